@@ -1,0 +1,109 @@
+"""Pins of the segmented primitives (Sections 4.1-4.2) against the worked
+example of Figure 1 and against brute-force definitions."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import segmented
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "figure1_flagpermute.txt")
+
+
+def _figure1():
+    rows = {}
+    with open(GOLDEN) as fh:
+        for line in fh:
+            if not line.strip() or line.startswith("#"):
+                continue
+            name, *vals = line.split()
+            rows[name] = np.array([int(v) for v in vals], np.int64)
+    return rows
+
+
+def test_figure1_rows():
+    fig = _figure1()
+    p, s_new, rows = segmented.flag_permute(fig["f"], fig["s"], 3)
+    for name in ["s_t", "s_h", "mask[0]", "scan[0]", "mask[1]", "scan[1]",
+                 "mask[2]", "scan[2]"]:
+        assert rows[name].tolist() == fig[name].tolist(), name
+    assert p.tolist() == fig["p"].tolist()
+    assert s_new.tolist() == fig["s'"].tolist()
+
+
+def test_figure1_printed_backscan_is_literal_exclusive_max():
+    fig = _figure1()
+    for i in (0, 1):
+        got = segmented.literal_backscan(fig["f"], fig["s"], i)
+        assert got.tolist() == fig[f"backscan[{i}]"].tolist()
+
+
+def _brute_partition(f, s, k):
+    """stable grouping by state inside every segment, by definition"""
+    n = len(f)
+    heads = [i for i in range(n) if s[i] == 1 or i == 0] + [n]
+    p = np.zeros(n, np.int64)
+    s_new = np.zeros(n, np.int64)
+    for a, b in zip(heads[:-1], heads[1:]):
+        pos = a
+        for st in range(k):
+            first = True
+            for i in range(a, b):
+                if f[i] == st:
+                    p[i] = pos
+                    if first:
+                        s_new[pos] = 1
+                        first = False
+                    pos += 1
+    return p, s_new
+
+
+@pytest.mark.parametrize("seed", range(200))
+def test_flag_permute_is_stable_partition(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 30))
+    k = int(rng.integers(1, 5))
+    f = rng.integers(0, k, size=n)
+    s = (rng.random(n) < 0.3).astype(np.int64)
+    s[0] = 1
+    p, s_new, _ = segmented.flag_permute(f, s, k)
+    bp, bs = _brute_partition(f, s, k)
+    assert p.tolist() == bp.tolist()
+    assert s_new.tolist() == bs.tolist()
+    assert sorted(p.tolist()) == list(range(n))
+
+
+def test_compact_scenarios():
+    # segment 0: first element dropped -> head moves to the first kept one;
+    # segment 1: every element dropped -> the segment and its head vanish;
+    # segment 2: all kept -> untouched.
+    s = np.array([1, 0, 0, 1, 0, 1, 0])
+    b = np.array([0, 1, 1, 0, 0, 1, 1])
+    p, n_new, sp, s_new = segmented.compact(b, s)
+    assert n_new == 4
+    assert [int(p[i]) for i in range(7) if b[i]] == [0, 1, 2, 3]
+    assert sp[0] == 0 and sp[3] == segmented.INF and sp[5] == 2
+    assert s_new.tolist() == [1, 0, 1, 0]
+
+
+@pytest.mark.parametrize("seed", range(200))
+def test_compact_brute(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 30))
+    s = (rng.random(n) < 0.3).astype(np.int64)
+    s[0] = 1
+    b = (rng.random(n) < 0.5).astype(np.int64)
+    p, n_new, sp, s_new = segmented.compact(b, s)
+    kept = [i for i in range(n) if b[i]]
+    assert n_new == len(kept)
+    assert [int(p[i]) for i in kept] == list(range(len(kept)))
+    heads = [i for i in range(n) if s[i] == 1] + [n]
+    exp_heads = np.zeros(len(kept), np.int64)
+    for a, c in zip(heads[:-1], heads[1:]):
+        ks = [i for i in range(a, c) if b[i]]
+        if ks:
+            assert sp[a] == p[ks[0]]
+            exp_heads[p[ks[0]]] = 1
+        else:
+            assert sp[a] == segmented.INF
+    assert s_new.tolist() == exp_heads.tolist()
