@@ -1,0 +1,144 @@
+/*
+ * qh.h -- segmented data-parallel Quickhull on AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of S. Tzeng and J. D. Owens, "Finding Convex Hulls Using
+ * Quickhull on the GPU": the recursion of Quickhull (Section 3.2, Algorithm
+ * 1) is replaced by rounds over one array of points grouped into segments
+ * (Section 3.1), and each round permutes the survivors into new segments and
+ * drops interior points (flagPermute and compact, Sections 4.1-4.2; the 2D
+ * driver is Algorithm 4).
+ *
+ * Conventions shared by every call below:
+ *
+ *  - Point data and outputs live in DEVICE memory (hipMalloc'd or torch
+ *    tensors on the GPU); counts returned "to the host" are written through
+ *    host pointers.  The caller owns every buffer it passes.  Inputs are never
+ *    modified.
+ *  - Points are integer-grid coordinates stored as planes (structure of
+ *    arrays): x[0..n) followed by y[0..n) (and z[0..n) in 3D).  All
+ *    orientation and distance decisions are exact: 2D needs |coord| <= 2^30-1,
+ *    3D |coord| <= 2^19, else QH_ERANGE.
+ *  - Reported hull vertices are the strictly convex ones (points exactly on
+ *    an edge or facet are not vertices).  Among exact duplicates the lowest
+ *    index is reported.
+ *  - Calls are host-synchronous: they enqueue work on opts->stream (NULL =
+ *    the null stream) and return when the outputs are complete.
+ *  - No call aborts or throws.  On error the outputs are unspecified and the
+ *    host counts are set to 0; the status says what went wrong.
+ *  - A context holds the device workspace (it grows on demand and is freed by
+ *    qh_ctx_destroy).  One context per host thread / stream at a time.
+ */
+#ifndef QH_H
+#define QH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QH_OK = 0,
+    QH_EINVAL = -1,       /* bad argument (null pointer, negative size, bad offsets) */
+    QH_ERANGE = -2,       /* a coordinate is outside the exact range */
+    QH_ENOMEM = -3,       /* device or host allocation failed */
+    QH_EDEGENERATE = -4,  /* 3D input has fewer than 4 affinely independent points */
+    QH_EDEVICE = -5,      /* a HIP runtime call failed */
+    QH_ECAPACITY = -6     /* an internal capacity was exceeded and could not grow */
+} qh_status;
+
+/* arithmetic of the distance tests (qh_opts.mode) */
+enum {
+    QH_EXACT_INT64 = 0,   /* every predicate in 64-bit integers */
+    QH_FP32_FILTER = 1    /* FP32 with a static forward error bound; only
+                             undecided signs / argmax candidates in int64.
+                             Same outputs as QH_EXACT_INT64, bit for bit. */
+};
+
+/* qh_opts.flags */
+enum {
+    QH_FLAG_TIMING = 1u   /* time every launch of the round kernel with HIP
+                             events (filled into qh_stats.round_kernel_ms) */
+};
+
+typedef struct qh_ctx qh_ctx;
+
+/* Counters of one call (all host values, filled when qh_opts.stats != NULL). */
+typedef struct qh_stats {
+    int64_t rounds;            /* Quickhull rounds, the first split included */
+    int64_t round_launches;    /* launches of the fused round kernel */
+    int64_t round_points_in;   /* points read by those launches, summed */
+    int64_t round_points_out;  /* survivors written by those launches, summed */
+    int64_t round_bytes;       /* algorithmic HBM bytes of those launches:
+                                  8 B per point read in the first split,
+                                  12 B per point read later, 12 B per survivor
+                                  written */
+    double round_kernel_ms;    /* summed device time of those launches
+                                  (QH_FLAG_TIMING only, else 0) */
+    int64_t filter_tests;      /* FP32 filter: sign tests made */
+    int64_t filter_fallbacks;  /* ... of which were undecided and redone in int64 */
+    int64_t argmax_candidates; /* points whose exact distance was needed by the
+                                  segmented argmax (FP32 filter) */
+    int64_t max_segments;      /* most segments alive in one round */
+    int64_t host_syncs;        /* device-to-host waits of the call */
+} qh_stats;
+
+typedef struct qh_opts {
+    void *stream;      /* hipStream_t, or NULL for the null stream */
+    uint32_t mode;     /* QH_EXACT_INT64 or QH_FP32_FILTER */
+    uint32_t flags;    /* QH_FLAG_* */
+    qh_ctx *ctx;       /* workspace; NULL = a temporary one for this call */
+    qh_stats *stats;   /* optional host output */
+} qh_opts;
+
+/* Create / destroy a workspace context bound to the current HIP device. */
+qh_status qh_ctx_create(qh_ctx **out);
+void qh_ctx_destroy(qh_ctx *ctx);
+
+/* Static text of a status code. */
+const char *qh_status_str(int status);
+
+/* Library version string. */
+const char *qh_version(void);
+
+/*
+ * 2D convex hull (Algorithm 4; Algorithm 1 with d = 2).
+ *
+ *   pts       device int32[2*n]: x[0..n) then y[0..n)
+ *   n         number of points, 0 <= n <= 2^31 - 2^16
+ *   hull_idx  device int32[n] (capacity n; n >= 1): hull vertex indices in
+ *             counter-clockwise order, starting at the lexicographically
+ *             smallest (x, y)
+ *   h         host: number of hull vertices written
+ *
+ * n = 0 gives h = 0; all points equal gives h = 1; all points collinear gives
+ * h = 2 (the lexicographic minimum and maximum).
+ */
+qh_status qh_hull2d(const int32_t *pts, int64_t n, int32_t *hull_idx, int64_t *h,
+                    const qh_opts *opts);
+
+/*
+ * Many independent 2D hulls in one call: instance i is the index range
+ * [offsets[i], offsets[i+1]) of one shared point array, and every instance
+ * becomes the initial segment of the permute-and-segment rounds
+ * (Section 3.1: segments keep subproblems of varying size in one array).
+ *
+ *   pts           device int32[2*n_total]: x planes then y planes
+ *   n_total       offsets[k] (host copy; checked on the device)
+ *   offsets       device int64[k+1], offsets[0] = 0, non-decreasing
+ *   k             number of instances, 1 <= k <= 2^24
+ *   hull_idx      device int32[n_total]: the hulls one after the other, each
+ *                 as in qh_hull2d, with indices LOCAL to the instance
+ *   hull_offsets  device int64[k+1]: instance i's hull is
+ *                 hull_idx[hull_offsets[i] .. hull_offsets[i+1])
+ *   h_total       host (may be NULL): hull_offsets[k]
+ */
+qh_status qh_hull2d_batched(const int32_t *pts, int64_t n_total, const int64_t *offsets,
+                            int32_t k, int32_t *hull_idx, int64_t *hull_offsets,
+                            int64_t *h_total, const qh_opts *opts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QH_H */

@@ -1,0 +1,387 @@
+// qh_api.hip -- the C ABI of include/qh.h: workspace context and the host
+// driver of the 2D rounds.
+//
+// The host enqueues the set-up kernels, the first split and then rounds in
+// batches (two launches per round).  Kernels read the round state from device
+// memory and do nothing once no segment is left, so a batch may overshoot the
+// last round; the host reads the small control block back once per batch
+// instead of once per round (the per-iteration read-back the paper names as
+// the cost of its GPU loop, Section 5).
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/qh.h"
+#include "qh2d.h"
+
+using namespace qh;
+
+struct qh_ctx {
+    int device = 0;
+    int cus = 256;
+    // capacities of the current allocation
+    int64_t cap_pts = 0;
+    int32_t scap = 0, hcap = 0, tcap = 0, s4cap = 0, kcap = 0;
+    // pending growth requests after a capacity overflow
+    int32_t want_scap = 0, want_hcap = 0;
+    void *dmem = nullptr;
+    size_t dbytes = 0;
+    Ws2 ws = {};
+    Control *ctl_host = nullptr;   // pinned copy of the control block
+    int64_t *h_host = nullptr;     // pinned: hull count of a single call
+    int64_t *single_off = nullptr; // device int64[2]
+    int64_t *single_hoff = nullptr;// device int64[2]
+    std::vector<hipEvent_t> ev;    // timing events (pairs)
+};
+
+namespace {
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Carve {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t count) {
+        off = align_up(off, 256);
+        T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// Lay the whole workspace out in one allocation (base == nullptr: size only).
+size_t carve(qh_ctx *c, char *base) {
+    Carve cv{base};
+    Ws2 &w = c->ws;
+    w.ctl = cv.take<Control>(1);
+    for (int p = 0; p < 2; ++p)
+        for (int r = 0; r < 2; ++r) {
+            w.px[p][r] = cv.take<int32_t>(c->cap_pts);
+            w.py[p][r] = cv.take<int32_t>(c->cap_pts);
+            w.pi[p][r] = cv.take<int32_t>(c->cap_pts);
+        }
+    for (int p = 0; p < 2; ++p)
+        for (int r = 0; r < 2; ++r) {
+            w.geo[p][r] = cv.take<SegGeo>(c->scap);
+            w.top[p][r] = cv.take<SegTop>(c->scap);
+            w.tmap[p][r] = cv.take<int32_t>(c->tcap);
+        }
+    w.pst = cv.take<int2>(2 * (size_t)c->scap);
+    w.pen = cv.take<int2>(2 * (size_t)c->scap);
+    w.adir = cv.take<Best>(4 * (size_t)c->scap);
+    w.recF = cv.take<Best>(2 * (size_t)c->tcap);
+    w.recL = cv.take<Best>(2 * (size_t)c->tcap);
+    for (int p = 0; p < 2; ++p) w.st2[p] = cv.take<uint64_t>(c->tcap + 4);
+    for (int p = 0; p < 2; ++p) w.st4[p] = cv.take<uint64_t>(c->s4cap);
+    w.recF0 = cv.take<Best>(2 * (size_t)c->tcap);
+    w.recL0 = cv.take<Best>(2 * (size_t)c->tcap);
+    w.dir0 = cv.take<Best>(2 * (size_t)c->kcap);
+    w.inst_rank = cv.take<int32_t>(c->kcap);
+    w.V = cv.take<int32_t>(c->hcap);
+    w.hinst = cv.take<int32_t>(c->hcap);
+    w.nxt = cv.take<int32_t>(c->hcap);
+    for (int p = 0; p < 2; ++p) {
+        w.succ[p] = cv.take<int32_t>(c->hcap);
+        w.dist[p] = cv.take<int32_t>(c->hcap);
+    }
+    w.cap_pts = c->cap_pts;
+    w.scap = c->scap;
+    w.hcap = c->hcap;
+    w.tcap = c->tcap;
+    w.s4cap = c->s4cap;
+    return align_up(cv.off, 256);
+}
+
+qh_status ensure(qh_ctx *c, int64_t n, int32_t k) {
+    const int64_t cap_pts = std::max<int64_t>(1, (n + kTile - 1) / kTile) * kTile;
+    const int32_t tcap = (int32_t)(cap_pts / kTile + 2);
+    const int64_t smax = n + k + 16;
+    int64_t scap = std::max<int64_t>({4096, n / 16 + 2 * (int64_t)k + 1024, c->want_scap});
+    scap = std::min(scap, std::max<int64_t>(smax, 4096));
+    int64_t hcap = std::max<int64_t>({(int64_t)2 * k + 4096, n / 16 + 2 * (int64_t)k + 1024,
+                                      c->want_hcap});
+    hcap = std::min(hcap, std::max<int64_t>(2 * (int64_t)k + n + 16, 4096));
+    const int32_t kcap = std::max(k, 1);
+    const int32_t s4cap = (int32_t)(2 * ((2 * scap + kSegBlock - 1) / kSegBlock) + 8);
+    if (c->dmem && cap_pts <= c->cap_pts && scap <= c->scap && hcap <= c->hcap && tcap <= c->tcap &&
+        kcap <= c->kcap)
+        return QH_OK;
+    if (c->dmem) {
+        (void)hipFree(c->dmem);
+        c->dmem = nullptr;
+    }
+    c->cap_pts = std::max(cap_pts, c->cap_pts);
+    c->tcap = std::max(tcap, c->tcap);
+    c->scap = std::max((int32_t)scap, c->scap);
+    c->hcap = std::max((int32_t)hcap, c->hcap);
+    c->kcap = std::max(kcap, c->kcap);
+    c->s4cap = std::max(s4cap, c->s4cap);
+    const size_t bytes = carve(c, nullptr);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        c->cap_pts = 0;
+        c->scap = c->hcap = c->tcap = c->kcap = c->s4cap = 0;
+        return QH_ENOMEM;
+    }
+    c->dmem = p;
+    c->dbytes = bytes;
+    carve(c, static_cast<char *>(p));
+    return QH_OK;
+}
+
+qh_status ctx_init(qh_ctx *c) {
+    if (hipGetDevice(&c->device) != hipSuccess) return QH_EDEVICE;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
+        cus > 0)
+        c->cus = cus;
+    if (hipHostMalloc((void **)&c->ctl_host, sizeof(Control), hipHostMallocDefault) != hipSuccess)
+        return QH_ENOMEM;
+    if (hipHostMalloc((void **)&c->h_host, sizeof(int64_t) * 2, hipHostMallocDefault) != hipSuccess)
+        return QH_ENOMEM;
+    if (hipMalloc((void **)&c->single_off, sizeof(int64_t) * 2) != hipSuccess) return QH_ENOMEM;
+    if (hipMalloc((void **)&c->single_hoff, sizeof(int64_t) * 2) != hipSuccess) return QH_ENOMEM;
+    return QH_OK;
+}
+
+void ctx_free(qh_ctx *c) {
+    if (!c) return;
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->dmem) (void)hipFree(c->dmem);
+    if (c->single_off) (void)hipFree(c->single_off);
+    if (c->single_hoff) (void)hipFree(c->single_hoff);
+    if (c->ctl_host) (void)hipHostFree(c->ctl_host);
+    if (c->h_host) (void)hipHostFree(c->h_host);
+    delete c;
+}
+
+#define QH_TRY(expr)                                  \
+    do {                                              \
+        if ((expr) != hipSuccess) {                   \
+            (void)hipGetLastError();                  \
+            return QH_EDEVICE;                        \
+        }                                             \
+    } while (0)
+
+struct Timing {
+    qh_ctx *c;
+    bool on;
+    size_t used = 0;
+    hipError_t before(hipStream_t st) {
+        if (!on) return hipSuccess;
+        if (used + 2 > c->ev.size()) {
+            for (int i = 0; i < 2; ++i) {
+                hipEvent_t e;
+                hipError_t err = hipEventCreate(&e);
+                if (err != hipSuccess) return err;
+                c->ev.push_back(e);
+            }
+        }
+        return hipEventRecord(c->ev[used], st);
+    }
+    hipError_t after(hipStream_t st) {
+        if (!on) return hipSuccess;
+        hipError_t err = hipEventRecord(c->ev[used + 1], st);
+        used += 2;
+        return err;
+    }
+    double total_ms() {
+        double t = 0;
+        for (size_t i = 0; i < used; i += 2) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess) t += ms;
+        }
+        return t;
+    }
+};
+
+qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets, int32_t k,
+                int32_t *hull_idx, int64_t *hull_offsets, int64_t *h_total, const qh_opts *o) {
+    hipStream_t st = o ? (hipStream_t)o->stream : nullptr;
+    const int mode = o ? (int)o->mode : 0;
+    const bool timing = o && (o->flags & QH_FLAG_TIMING);
+    qh_stats *stats = o ? o->stats : nullptr;
+    if (stats) memset(stats, 0, sizeof(*stats));
+    if (h_total) *h_total = 0;
+    if (mode != QH_EXACT_INT64 && mode != QH_FP32_FILTER) return QH_EINVAL;
+
+    const int32_t *x = pts;
+    const int32_t *y = pts + n;
+    const int32_t vec_ok = (((uintptr_t)pts & 15u) == 0 && (n & 3) == 0) ? 1 : 0;
+    int64_t syncs = 0;
+    int r = 0;
+    Timing tm{c, timing};
+
+    for (int attempt = 0;; ++attempt) {
+        qh_status s = ensure(c, n, k);
+        if (s != QH_OK) return s;
+        const Ws2 &ws = c->ws;
+        const int ntiles0 = (int)((n + kTile - 1) / kTile);
+        const int grid_round = std::max(1, std::min(c->tcap, c->cus * 4));
+        const int grid_seg = std::max(1, std::min((2 * c->scap + kSegBlock - 1) / kSegBlock, c->cus * 2));
+        const int grid_setup = std::max(1, std::min((c->tcap + 255) / 256 + 1, c->cus * 4));
+        tm.used = 0;
+        QH_TRY(launch_instances(ws, offsets, n, k, st));
+        QH_TRY(launch_setup(ws, offsets, k, ntiles0, grid_setup, st));
+        QH_TRY(launch_extremes(ws, x, y, (int32_t)n, vec_ok, grid_round, k, st));
+        QH_TRY(tm.before(st));
+        QH_TRY(launch_round(ws, 0, true, mode, x, y, vec_ok, grid_round, st));
+        QH_TRY(tm.after(st));
+        QH_TRY(launch_segments(ws, 0, grid_seg, st));
+        r = 1;
+        int batch = 6;
+        while (true) {
+            for (int j = 0; j < batch; ++j, ++r) {
+                QH_TRY(tm.before(st));
+                QH_TRY(launch_round(ws, r, false, mode, x, y, vec_ok, grid_round, st));
+                QH_TRY(tm.after(st));
+                QH_TRY(launch_segments(ws, r, grid_seg, st));
+            }
+            QH_TRY(hipMemcpyAsync(c->ctl_host, ws.ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
+            QH_TRY(hipStreamSynchronize(st));
+            ++syncs;
+            const Control &h = *c->ctl_host;
+            if (h.error) break;
+            const RoundState &rs = h.rs[r & 1];
+            if (rs.s[0] + rs.s[1] == 0) break;
+            batch = std::min(batch * 2, 48);
+        }
+        const int err = c->ctl_host->error;
+        if (err & kErrOffsets) return QH_EINVAL;
+        if (err & kErrRange) return QH_ERANGE;
+        if (err & (kErrSegCap | kErrHullCap)) {
+            if (attempt >= 8) return QH_ECAPACITY;
+            if (err & kErrSegCap) c->want_scap = (int32_t)std::min<int64_t>((int64_t)c->scap * 4, INT32_MAX / 2);
+            if (err & kErrHullCap) c->want_hcap = (int32_t)std::min<int64_t>((int64_t)c->hcap * 4, INT32_MAX / 2);
+            continue;
+        }
+        if (err) return QH_EDEVICE;
+        break;
+    }
+    const Control &h = *c->ctl_host;
+    const int32_t H = h.rs[r & 1].hbase;
+    QH_TRY(launch_output(c->ws, H, k, offsets, hull_offsets, hull_idx, n, st));
+    if (h_total || stats) {
+        QH_TRY(hipMemcpyAsync(c->h_host, hull_offsets + k, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        QH_TRY(hipStreamSynchronize(st));
+        ++syncs;
+        if (h_total) *h_total = *c->h_host;
+    } else {
+        QH_TRY(hipStreamSynchronize(st));
+    }
+    if (stats) {
+        stats->rounds = (int64_t)h.round_launches_work;
+        stats->round_launches = r;
+        stats->round_points_in = (int64_t)h.points_in;
+        stats->round_points_out = (int64_t)h.points_out;
+        stats->round_bytes = (int64_t)(8 * h.first_in + 12 * (h.points_in - h.first_in) + 12 * h.points_out);
+        stats->round_kernel_ms = timing ? tm.total_ms() : 0.0;
+        stats->filter_tests = (int64_t)h.filter_tests;
+        stats->filter_fallbacks = (int64_t)h.filter_fallbacks;
+        stats->argmax_candidates = (int64_t)h.candidates;
+        stats->max_segments = h.max_segments;
+        stats->host_syncs = syncs;
+    }
+    return QH_OK;
+}
+
+struct TempCtx {
+    qh_ctx *c = nullptr;
+    bool owned = false;
+    ~TempCtx() {
+        if (owned) ctx_free(c);
+    }
+};
+
+qh_status get_ctx(const qh_opts *o, TempCtx &t) {
+    if (o && o->ctx) {
+        t.c = o->ctx;
+        return QH_OK;
+    }
+    qh_ctx *c = new (std::nothrow) qh_ctx();
+    if (!c) return QH_ENOMEM;
+    t.c = c;
+    t.owned = true;
+    return ctx_init(c);
+}
+
+}  // namespace
+
+hipError_t qh_fill_offsets(int64_t *off, int64_t n, hipStream_t st);
+
+extern "C" {
+
+qh_status qh_ctx_create(qh_ctx **out) {
+    if (!out) return QH_EINVAL;
+    *out = nullptr;
+    qh_ctx *c = new (std::nothrow) qh_ctx();
+    if (!c) return QH_ENOMEM;
+    qh_status s = ctx_init(c);
+    if (s != QH_OK) {
+        ctx_free(c);
+        return s;
+    }
+    *out = c;
+    return QH_OK;
+}
+
+void qh_ctx_destroy(qh_ctx *ctx) { ctx_free(ctx); }
+
+const char *qh_status_str(int status) {
+    switch (status) {
+        case QH_OK: return "ok";
+        case QH_EINVAL: return "invalid argument";
+        case QH_ERANGE: return "coordinate out of the exact range";
+        case QH_ENOMEM: return "out of memory";
+        case QH_EDEGENERATE: return "degenerate input";
+        case QH_EDEVICE: return "HIP runtime error";
+        case QH_ECAPACITY: return "internal capacity exceeded";
+        default: return "unknown status";
+    }
+}
+
+const char *qh_version(void) { return "qh 0.1 (gfx950)"; }
+
+qh_status qh_hull2d(const int32_t *pts, int64_t n, int32_t *hull_idx, int64_t *h, const qh_opts *opts) {
+    if (h) *h = 0;
+    if (!h || n < 0 || n > (int64_t)INT32_MAX - 65536) return QH_EINVAL;
+    if (n > 0 && (!pts || !hull_idx)) return QH_EINVAL;
+    if (opts && opts->stats) memset(opts->stats, 0, sizeof(qh_stats));
+    if (n == 0) return QH_OK;
+    TempCtx t;
+    qh_status s = get_ctx(opts, t);
+    if (s != QH_OK) return s;
+    hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+    if (qh_fill_offsets(t.c->single_off, n, st) != hipSuccess) {
+        (void)hipGetLastError();
+        return QH_EDEVICE;
+    }
+    int64_t ht = 0;
+    s = run2d(t.c, pts, n, t.c->single_off, 1, hull_idx, t.c->single_hoff, &ht, opts);
+    if (s != QH_OK) return s;
+    *h = ht;
+    return QH_OK;
+}
+
+qh_status qh_hull2d_batched(const int32_t *pts, int64_t n_total, const int64_t *offsets, int32_t k,
+                            int32_t *hull_idx, int64_t *hull_offsets, int64_t *h_total,
+                            const qh_opts *opts) {
+    if (h_total) *h_total = 0;
+    if (k < 1 || k > (1 << 24) || n_total < 0 || n_total > (int64_t)INT32_MAX - 65536) return QH_EINVAL;
+    if (!offsets || !hull_offsets || (n_total > 0 && (!pts || !hull_idx))) return QH_EINVAL;
+    if (opts && opts->stats) memset(opts->stats, 0, sizeof(qh_stats));
+    TempCtx t;
+    qh_status s = get_ctx(opts, t);
+    if (s != QH_OK) return s;
+    return run2d(t.c, pts, n_total, offsets, k, hull_idx, hull_offsets, h_total, opts);
+}
+
+}  // extern "C"

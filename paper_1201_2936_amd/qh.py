@@ -1,0 +1,186 @@
+"""Thin ctypes binding of ``include/qh.h`` (argument marshalling only).
+
+Every step of the hull runs in the HIP library ``libqh.so``; PyTorch is used
+here only to own device memory and to name the current stream.  If the
+library is missing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqh.so")
+
+QH_OK = 0
+QH_EINVAL = -1
+QH_ERANGE = -2
+QH_ENOMEM = -3
+QH_EDEGENERATE = -4
+QH_EDEVICE = -5
+QH_ECAPACITY = -6
+
+QH_EXACT_INT64 = 0
+QH_FP32_FILTER = 1
+QH_FLAG_TIMING = 1
+
+EXPORTED = ["qh_ctx_create", "qh_ctx_destroy", "qh_status_str", "qh_version",
+            "qh_hull2d", "qh_hull2d_batched"]
+
+
+class QhStats(ctypes.Structure):
+    _fields_ = [
+        ("rounds", ctypes.c_int64),
+        ("round_launches", ctypes.c_int64),
+        ("round_points_in", ctypes.c_int64),
+        ("round_points_out", ctypes.c_int64),
+        ("round_bytes", ctypes.c_int64),
+        ("round_kernel_ms", ctypes.c_double),
+        ("filter_tests", ctypes.c_int64),
+        ("filter_fallbacks", ctypes.c_int64),
+        ("argmax_candidates", ctypes.c_int64),
+        ("max_segments", ctypes.c_int64),
+        ("host_syncs", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class QhOpts(ctypes.Structure):
+    _fields_ = [
+        ("stream", ctypes.c_void_p),
+        ("mode", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("ctx", ctypes.c_void_p),
+        ("stats", ctypes.POINTER(QhStats)),
+    ]
+
+
+class QhError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libqh.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing: run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    lib.qh_ctx_create.restype = ctypes.c_int
+    lib.qh_ctx_create.argtypes = [ctypes.POINTER(vp)]
+    lib.qh_ctx_destroy.restype = None
+    lib.qh_ctx_destroy.argtypes = [vp]
+    lib.qh_status_str.restype = ctypes.c_char_p
+    lib.qh_status_str.argtypes = [ctypes.c_int]
+    lib.qh_version.restype = ctypes.c_char_p
+    lib.qh_version.argtypes = []
+    lib.qh_hull2d.restype = ctypes.c_int
+    lib.qh_hull2d.argtypes = [vp, i64, vp, ctypes.POINTER(i64), ctypes.POINTER(QhOpts)]
+    lib.qh_hull2d_batched.restype = ctypes.c_int
+    lib.qh_hull2d_batched.argtypes = [vp, i64, vp, ctypes.c_int32, vp, vp,
+                                      ctypes.POINTER(i64), ctypes.POINTER(QhOpts)]
+    _lib = lib
+    return lib
+
+
+def status_str(status: int) -> str:
+    return load().qh_status_str(int(status)).decode()
+
+
+def version() -> str:
+    return load().qh_version().decode()
+
+
+class Context:
+    """A workspace context (device memory reused across calls)."""
+
+    def __init__(self):
+        lib = load()
+        p = ctypes.c_void_p()
+        st = lib.qh_ctx_create(ctypes.byref(p))
+        if st != QH_OK:
+            raise QhError(st, "qh_ctx_create")
+        self.ptr = p
+
+    def close(self):
+        if self.ptr is not None and self.ptr.value:
+            load().qh_ctx_destroy(self.ptr)
+        self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _opts(ctx, mode, timing, stream):
+    import torch
+    st = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    stats = QhStats()
+    o = QhOpts(ctypes.c_void_p(st), mode, QH_FLAG_TIMING if timing else 0,
+               ctx.ptr if ctx is not None else None, ctypes.pointer(stats))
+    return o, stats
+
+
+def _check_points(pts, dims):
+    import torch
+    if not isinstance(pts, torch.Tensor) or not pts.is_cuda:
+        raise TypeError("points must be a CUDA (HIP) tensor")
+    if pts.dtype != torch.int32 or pts.dim() != 2 or pts.shape[0] != dims:
+        raise TypeError(f"points must be int32 of shape ({dims}, n)")
+    return pts.contiguous()
+
+
+def qh_hull2d(pts, mode: int = QH_EXACT_INT64, ctx: Context | None = None,
+              timing: bool = False, stream=None):
+    """Counter-clockwise hull vertex indices (int32 tensor on the device) of
+    int32[2, n] device points; returns (indices, stats dict)."""
+    import torch
+    lib = load()
+    pts = _check_points(pts, 2)
+    n = pts.shape[1]
+    out = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
+    h = ctypes.c_int64(0)
+    o, stats = _opts(ctx, mode, timing, stream)
+    st = lib.qh_hull2d(ctypes.c_void_p(pts.data_ptr()), n, ctypes.c_void_p(out.data_ptr()),
+                       ctypes.byref(h), ctypes.byref(o))
+    if st != QH_OK:
+        raise QhError(st, "qh_hull2d")
+    return out[: h.value], stats.as_dict()
+
+
+def qh_hull2d_batched(pts, offsets, mode: int = QH_EXACT_INT64, ctx: Context | None = None,
+                      timing: bool = False, stream=None):
+    """Hulls of the instances [offsets[i], offsets[i+1]) of int32[2, N] device
+    points; offsets is an int64[k + 1] device tensor.  Returns (indices local
+    to each instance, int64[k + 1] device hull offsets, stats dict)."""
+    import torch
+    lib = load()
+    pts = _check_points(pts, 2)
+    if offsets.dtype != torch.int64 or not offsets.is_cuda or offsets.dim() != 1:
+        raise TypeError("offsets must be an int64 CUDA tensor of shape (k + 1,)")
+    offsets = offsets.contiguous()
+    k = offsets.shape[0] - 1
+    n = pts.shape[1]
+    out = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
+    hoff = torch.empty(k + 1, dtype=torch.int64, device=pts.device)
+    ht = ctypes.c_int64(0)
+    o, stats = _opts(ctx, mode, timing, stream)
+    st = lib.qh_hull2d_batched(ctypes.c_void_p(pts.data_ptr()), n,
+                               ctypes.c_void_p(offsets.data_ptr()), k,
+                               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(hoff.data_ptr()),
+                               ctypes.byref(ht), ctypes.byref(o))
+    if st != QH_OK:
+        raise QhError(st, "qh_hull2d_batched")
+    return out[: ht.value], hoff, stats.as_dict()

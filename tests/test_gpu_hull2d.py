@@ -1,0 +1,190 @@
+"""Parity of the HIP 2D path with the oracle (through the C ABI).
+
+Results must be identical element by element: the same hull vertex indices in
+the same counter-clockwise order.  Both arithmetic modes (exact int64 and the
+FP32 filter with int64 fallback) must give the oracle's output bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from hullcheck import check_hull2d
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MODES = [0, 1]
+
+
+@pytest.fixture(scope="module")
+def qhm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1201_2936_amd import qh
+    qh.load()
+    return qh
+
+
+@pytest.fixture(scope="module")
+def ctx(qhm):
+    c = qhm.Context()
+    yield c
+    c.close()
+
+
+def _gpu_hull(qhm, ctx, pts, mode):
+    t = torch.from_numpy(np.ascontiguousarray(pts)).to("cuda")
+    idx, stats = qhm.qh_hull2d(t, mode=mode, ctx=ctx)
+    return idx.cpu().numpy(), stats
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_tiny_cases(qhm, ctx, mode):
+    cases = [
+        np.array([[5], [7]], np.int32),
+        np.full((2, 9), 3, np.int32),
+        np.array([[4, 1, 4, 1], [0, 2, 0, 2]], np.int32),
+        np.array([[0, 10, 0], [0, 0, 10]], np.int32),
+        np.array([[0, 1, 2, 3, 4], [0, 1, 2, 3, 4]], np.int32),
+    ]
+    for pts in cases:
+        _say(f"tiny n={pts.shape[1]} mode={mode}")
+        got, _ = _gpu_hull(qhm, ctx, pts, mode)
+        assert got.tolist() == oracle.hull2d(pts).tolist()
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("seed", range(12))
+def test_random_small(qhm, ctx, mode, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 3000))
+    r = int(rng.choice([5, 100, 1 << 20, (1 << 30) - 1]))
+    pts = workloads.small_random(seed, n, r)
+    _say(f"random seed={seed} n={n} r={r} mode={mode}")
+    got, _ = _gpu_hull(qhm, ctx, pts, mode)
+    assert got.tolist() == oracle.hull2d(pts).tolist()
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("n", [2047, 2048, 2049, 4095, 4097, 6144 + 3, 20000, 65536 + 17])
+def test_tile_boundaries(qhm, ctx, mode, n):
+    pts = workloads.disk(workloads.rng_for(n), n, 1 << 20)
+    _say(f"disk n={n} mode={mode}")
+    got, _ = _gpu_hull(qhm, ctx, pts, mode)
+    assert got.tolist() == oracle.hull2d(pts).tolist()
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("seed", range(6))
+def test_grid_duplicates_collinear(qhm, ctx, mode, seed):
+    n = 5000 + 997 * seed
+    for pts in (workloads.small_grid(seed, n, 3 + seed),
+                workloads.small_collinear(seed, n, 400)):
+        _say(f"grid/collinear seed={seed} n={n} mode={mode}")
+        got, _ = _gpu_hull(qhm, ctx, pts, mode)
+        assert got.tolist() == oracle.hull2d(pts).tolist()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_many_segments(qhm, ctx, mode):
+    # every point on a parabola is a vertex: segments shrink to single points
+    x = np.arange(-30000, 30000, dtype=np.int64)
+    pts = np.stack([x, x * x // 1024]).astype(np.int32)
+    perm = np.random.default_rng(5).permutation(pts.shape[1])
+    pts = np.ascontiguousarray(pts[:, perm])
+    _say(f"parabola mode={mode}")
+    got, _ = _gpu_hull(qhm, ctx, pts, mode)
+    assert got.tolist() == oracle.hull2d(pts).tolist()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_circle_lattice(qhm, ctx, mode):
+    r = 801125
+    P = []
+    import math
+    for xx in range(-r, r + 1):
+        yy2 = r * r - xx * xx
+        yy = math.isqrt(yy2)
+        if yy * yy == yy2:
+            P.append((xx, yy))
+            if yy:
+                P.append((xx, -yy))
+    inner = workloads.disk(workloads.rng_for(9), 100000, r - 10)
+    pts = np.concatenate([np.array(P, np.int64).T.astype(np.int32), inner], axis=1)
+    perm = np.random.default_rng(6).permutation(pts.shape[1])
+    pts = np.ascontiguousarray(pts[:, perm])
+    _say(f"circle lattice mode={mode}")
+    got, _ = _gpu_hull(qhm, ctx, pts, mode)
+    want = oracle.hull2d(pts)
+    assert len(want) == 756
+    assert got.tolist() == want.tolist()
+
+
+def test_range_error(qhm, ctx):
+    pts = np.array([[0, 1 << 30, 5], [0, 0, 9]], np.int32)
+    with pytest.raises(qhm.QhError) as e:
+        _gpu_hull(qhm, ctx, pts, 0)
+    assert e.value.status == qhm.QH_ERANGE
+    # the context stays usable
+    ok, _ = _gpu_hull(qhm, ctx, np.array([[0, 3], [0, 4]], np.int32), 0)
+    assert ok.tolist() == [0, 1]
+
+
+def test_misaligned_and_odd_sizes(qhm, ctx):
+    # a view that starts one element in: not 16-byte aligned
+    base = workloads.disk(workloads.rng_for(12), 10001, 1 << 20)
+    t = torch.from_numpy(base).to("cuda")
+    for mode in MODES:
+        sub = t[:, 1:]
+        idx, _ = qhm.qh_hull2d(sub.contiguous(), mode=mode, ctx=ctx)
+        assert idx.cpu().numpy().tolist() == oracle.hull2d(base[:, 1:]).tolist()
+
+
+def test_deterministic_and_no_ctx(qhm):
+    pts = workloads.disk(workloads.rng_for(13), 50000, 1 << 20)
+    t = torch.from_numpy(pts).to("cuda")
+    a, _ = qhm.qh_hull2d(t, mode=1)
+    b, _ = qhm.qh_hull2d(t, mode=1)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_disk_65k(qhm, ctx, mode):
+    pts = workloads.disk_65k()
+    _say(f"disk_65k mode={mode}")
+    got, stats = _gpu_hull(qhm, ctx, pts, mode)
+    assert got.tolist() == oracle.hull2d(pts).tolist()
+    assert stats["rounds"] >= 2
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_square_16m(qhm, ctx, mode):
+    pts = workloads.square_16m()
+    _say(f"square_16m mode={mode}")
+    got, stats = _gpu_hull(qhm, ctx, pts, mode)
+    want = oracle.hull2d(pts)
+    assert got.tolist() == want.tolist()
+    if mode == 1:
+        assert stats["filter_tests"] > 0
+        _say(f"fallback rate {stats['filter_fallbacks'] / stats['filter_tests']:.3e}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_circle_mix_4m(qhm, ctx, mode):
+    pts = workloads.circle_mix_4m()
+    _say(f"circle_mix_4m mode={mode}")
+    got, stats = _gpu_hull(qhm, ctx, pts, mode)
+    want = oracle.hull2d(pts)
+    assert got.tolist() == want.tolist()
+    check_hull2d(pts, got)
+    if mode == 1:
+        # the exactly collinear support lines force undecided FP32 signs
+        assert stats["filter_fallbacks"] > 0
