@@ -1,0 +1,196 @@
+"""Benchmark of the segmented Quickhull on one MI355X.
+
+One step = one whole hull (extremes, first split, every round, output) of the
+2D workload of
+16,777,216 points uniform in [-2^20, 2^20]^2, with the points already resident
+in device memory, through the C ABI (qh_hull2d).  The headline form is the
+FP32 filter with exact int64 fallback (bit-exact); the plain exact-int64 form
+is timed beside it on the same data.
+
+Prints ONE JSON line.  ``roofline`` describes the round kernel (k_round: the
+first split and one launch per later round), the kernel that moves nearly all
+the bytes: algorithmic bytes per launch (first split 8 B per point read and 12
+B per survivor written; later rounds 12 B per point read and 12 B per survivor
+written) over its average launch duration, timed with HIP events around each
+launch on the stream it runs on.
+``cpu_baseline`` is the oracle (plain single-threaded C Quickhull) on the
+same points.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "square_16m"
+METRIC = "Mpoints/s per hull + HBM GB/s; FP32-filtered/batched vs exact-int64, bit-exact"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_round_square_16m.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1201_2936_amd", "csrc", "qh2d_kernels.hip")
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per round-kernel launch from the committed PMC summary, or
+    None when it is missing or was taken from another kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
+def cpu_baseline(pts, budget_s: float = 12.0):
+    import oracle
+    oracle.hull2d(pts[:, :1000])  # load / build outside the timing
+    n = pts.shape[1]
+    runs = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.hull2d(pts)
+        runs += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or runs >= 50:
+            break
+    return {"value": round(n * runs / el / 1e6, 3), "unit": "Mpoints/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{WORKLOAD} full ({n} points), {runs} runs in {el:.1f} s, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the hull of one point set "
+              "on one MI355X); --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1201_2936_amd import qh
+
+    qh.load()
+    pts_np = workloads.WORKLOADS[WORKLOAD]()
+    n = pts_np.shape[1]
+    dev = torch.device("cuda:0")
+    pts = torch.from_numpy(pts_np).to(dev)
+    ctx = qh.Context()
+
+    # headline: FP32 filter + int64 fallback
+    def run_filter():
+        return qh.qh_hull2d(pts, mode=qh.QH_FP32_FILTER, ctx=ctx)
+
+    def run_exact():
+        return qh.qh_hull2d(pts, mode=qh.QH_EXACT_INT64, ctx=ctx)
+
+    sec, (idx_f, st_f) = time_steps(run_filter, args.steps, args.warmup)
+    sec_x, (idx_x, st_x) = time_steps(run_exact, max(5, args.steps // 3), 2)
+
+    # kernel timing: HIP events around every launch (a separate pass of the
+    # same steps, so the events do not perturb the headline time)
+    agg = {k: 0.0 for k in ("round_kernel_bytes", "round_kernel_ms", "round_launches", "kernel_ms",
+                            "split_ms", "extremes_ms", "segment_ms", "hull_bytes")}
+    split_bytes = 0.0
+    for _ in range(args.steps):
+        _, s = qh.qh_hull2d(pts, mode=qh.QH_FP32_FILTER, ctx=ctx, timing=True)
+        for key in agg:
+            agg[key] += s[key]
+        split_bytes += 8 * n + 12 * s["split_points_out"]
+    torch.cuda.synchronize()
+    launches = agg["round_launches"]
+    avg_launch_ms = agg["round_kernel_ms"] / max(launches, 1)
+    bytes_per_launch = agg["round_kernel_bytes"] / max(launches, 1)
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if avg_launch_ms > 0 else 0.0
+
+    def gbs(nbytes, ms):
+        return round(nbytes / (ms * 1e-3) / 1e9, 1) if ms > 0 else None
+
+    later_ms = agg["round_kernel_ms"] - agg["split_ms"]
+    later_bytes = agg["round_kernel_bytes"] - split_bytes
+
+    import oracle  # checker only: parity of the timed output, and the CPU baseline
+    want = oracle.hull2d(pts_np)
+    parity = bool(np.array_equal(idx_f.cpu().numpy(), want) and
+                  np.array_equal(idx_x.cpu().numpy(), want))
+
+    traffic = load_traffic()
+    line = {
+        "metric": METRIC,
+        "value": round(n / sec / 1e6, 3),
+        "unit": "Mpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+i64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": n, "dims": 2,
+                   "coords": "int32 uniform in [-2^20, 2^20]^2", "form": "fp32_filter"},
+        "exact_int64": {"value": round(n / sec_x / 1e6, 3), "unit": "Mpoints/s",
+                        "ms_per_step": round(sec_x * 1e3, 4), "dtype": "i64"},
+        "hull_vertices": int(len(want)),
+        "parity_vs_oracle": parity,
+        "rounds": int(st_f["rounds"]),
+        "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"]
+                          if st_f["filter_tests"] else 0.0),
+        "argmax_candidates": int(st_f["argmax_candidates"]),
+        "round_kernel": {"name": "k_round (first split and every later round)",
+                         "launches_per_step": launches / args.steps,
+                         "avg_launch_us": round(avg_launch_ms * 1e3, 3),
+                         "bytes_per_launch": round(bytes_per_launch),
+                         "grid_blocks": int(st_f["grid_blocks"]),
+                         "first_split_us": round(agg["split_ms"] / args.steps * 1e3, 2),
+                         "first_split_GBs": gbs(split_bytes, agg["split_ms"]),
+                         "later_rounds_us": round(later_ms / args.steps * 1e3, 2),
+                         "later_rounds_GBs": gbs(later_bytes, later_ms)},
+        "device_time_us": {"all_kernels": round(agg["kernel_ms"] / args.steps * 1e3, 2),
+                           "extremes": round(agg["extremes_ms"] / args.steps * 1e3, 2),
+                           "segments": round(agg["segment_ms"] / args.steps * 1e3, 2)},
+        "hull_GBs_device": gbs(agg["hull_bytes"], agg["kernel_ms"]),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(pts_np)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

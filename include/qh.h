@@ -57,30 +57,43 @@ enum {
 
 /* qh_opts.flags */
 enum {
-    QH_FLAG_TIMING = 1u   /* time every launch of the round kernel with HIP
-                             events (filled into qh_stats.round_kernel_ms) */
+    QH_FLAG_TIMING = 1u   /* time every kernel launch of the call with HIP
+                             events (qh_stats) */
 };
 
 typedef struct qh_ctx qh_ctx;
 
 /* Counters of one call (all host values, filled when qh_opts.stats != NULL). */
 typedef struct qh_stats {
-    int64_t rounds;            /* Quickhull rounds, the first split included */
-    int64_t round_launches;    /* launches of the fused round kernel */
-    int64_t round_points_in;   /* points read by those launches, summed */
-    int64_t round_points_out;  /* survivors written by those launches, summed */
-    int64_t round_bytes;       /* algorithmic HBM bytes of those launches:
-                                  8 B per point read in the first split,
-                                  12 B per point read later, 12 B per survivor
-                                  written */
-    double round_kernel_ms;    /* summed device time of those launches
-                                  (QH_FLAG_TIMING only, else 0) */
-    int64_t filter_tests;      /* FP32 filter: sign tests made */
-    int64_t filter_fallbacks;  /* ... of which were undecided and redone in int64 */
-    int64_t argmax_candidates; /* points whose exact distance was needed by the
-                                  segmented argmax (FP32 filter) */
-    int64_t max_segments;      /* most segments alive in one round */
-    int64_t host_syncs;        /* device-to-host waits of the call */
+    int64_t rounds;             /* rounds that had points, first split included */
+    int64_t round_launches;     /* launches of the round kernel, first split
+                                   included (a batch of rounds may end with
+                                   launches that find nothing left to do) */
+    int64_t round_points_in;    /* points read by the rounds after the first split */
+    int64_t round_points_out;   /* survivors written by those rounds */
+    int64_t split_points_out;   /* survivors of the first split */
+    int64_t hull_bytes;         /* algorithmic HBM bytes of the whole call: the
+                                   extremes read 8 B per point; the first split
+                                   reads 8 B per point and writes 12 B per
+                                   survivor; every later round reads 12 B per
+                                   point (x, y, index) and writes 12 B per
+                                   survivor */
+    int64_t round_kernel_bytes; /* the part of hull_bytes moved by the round
+                                   kernel (first split and later rounds) */
+    double kernel_ms;           /* device time of all kernels of the call */
+    double round_kernel_ms;     /* ... of the round-kernel launches */
+    double split_ms;            /* ... of which the first split */
+    double extremes_ms;         /* ... of the extremes */
+    double segment_ms;          /* ... of the segment bookkeeping between rounds
+                                   (the five times: QH_FLAG_TIMING only, HIP
+                                   events around every launch, else 0) */
+    int64_t filter_tests;       /* FP32 filter: sign tests made */
+    int64_t filter_fallbacks;   /* ... of which were undecided and redone in int64 */
+    int64_t argmax_candidates;  /* points whose exact distance was needed by the
+                                   segmented argmax (FP32 filter) */
+    int64_t max_segments;       /* most segments alive in one round */
+    int64_t grid_blocks;        /* blocks of a round-kernel launch */
+    int64_t host_syncs;         /* device-to-host waits of the call */
 } qh_stats;
 
 typedef struct qh_opts {

@@ -5,34 +5,47 @@
 
 namespace qh {
 
-constexpr int kBlock = 256;              // threads of the round kernel
+constexpr int kBlock = 256;              // threads per block
 constexpr int kItems = 8;                // points per thread
 constexpr int kTile = kBlock * kItems;   // points per tile
-constexpr int kSlots = 256;              // segments per LDS window
-constexpr int kSegBlock = 256;           // threads (= segments) of the segment kernel
-constexpr int kRankSmallCap = 8192;      // hull ids ranked inside one block's LDS
+constexpr int kSlots = 128;              // segments per LDS window (multi-segment tiles)
+constexpr int kSegBlock = 256;           // segments per tile of the segment phase
+constexpr int kRankSmallCap = 4096;      // hull ids ranked inside one block's LDS
 constexpr int32_t kCoordMax2D = (1 << 30) - 1;
+constexpr int kMaxStamps = 256;
 
-// Device pointers of one workspace (passed by value to every kernel).
+// What a tile of the survivor array needs to know before it reads a point:
+// the segment holding its first point and, when that segment covers the whole
+// tile (the common case), its geometry.
+struct TileInfo {
+    int32_t seg;     // segment of the tile's first point (index in the region's table)
+    int32_t single;  // 1: that segment covers the whole tile
+    int32_t start, end;
+    int32_t ux, uy, fx, fy, vx, vy;
+    int32_t pad0, pad1;
+};
+
+// Device pointers of one workspace (passed by value to every kernel).  The
+// buffers indexed by round parity p and region r are laid out back to back
+// and addressed arithmetically, so no array of pointers is indexed at run
+// time (that would force a copy of this struct into scratch memory).
 struct Ws2 {
     Control *ctl;
-    // survivors: [round parity][region] planes x, y and input index
-    int32_t *px[2][2];
-    int32_t *py[2][2];
-    int32_t *pi[2][2];
-    // segment tables and tile maps: [round parity][region]
-    SegGeo *geo[2][2];
-    SegTop *top[2][2];
-    int32_t *tmap[2][2];
+    int32_t *pts_;      // survivors: [parity][region][plane x, y, index][cap_pts]
+    SegGeo *geo_;       // segment tables: [parity][region][scap]
+    SegTop *top_;       // [parity][region][scap]
+    TileInfo *tinfo_;   // tile records: [parity][region][tcap]
+    uint64_t *st2_;     // look-back words of the round phase: [parity][tcap + 4]
+    uint64_t *st4_;     // look-back words of the segment phase: [parity][s4cap]
+    int32_t *succ_;     // list ranking: [2][hcap]
+    int32_t *dist_;     // [2][hcap]
     // per segment of the current round (global id = region-0 ids, then region 1)
     int2 *pst;     // global offsets (child 0, child 1) at the segment's first point
     int2 *pen;     // ... after its last point
-    Best *adir;    // [seg][child] argmax of segments inside one tile
+    Best *adir;    // [seg][child] argmax of the segment
     // per tile of the current round
     Best *recF;    // [tile][child] partial argmax of the tile's first segment
     Best *recL;    // [tile][child] ... of its last segment
-    uint64_t *st2[2];  // look-back status of the round kernel, by parity
-    uint64_t *st4[2];  // look-back status of the segment kernel, by parity
     // extremes (set-up)
     Best *recF0, *recL0, *dir0;
     int32_t *inst_rank;
@@ -40,25 +53,45 @@ struct Ws2 {
     int32_t *V;       // input index of the vertex
     int32_t *hinst;   // its instance
     int32_t *nxt;     // next vertex counter-clockwise (-1 = unused id)
-    int32_t *succ[2];
-    int32_t *dist[2];
     int64_t cap_pts;  // points per survivor plane
     int32_t scap;     // segments per table
     int32_t hcap;     // compact hull ids
     int32_t tcap;     // tiles per round
-    int32_t s4cap;    // look-back words of the segment kernel
+    int32_t s4cap;    // look-back words of the segment phase
+
+    __host__ __device__ int32_t *px(int p, int r) const { return pts_ + (size_t)((p * 2 + r) * 3 + 0) * cap_pts; }
+    __host__ __device__ int32_t *py(int p, int r) const { return pts_ + (size_t)((p * 2 + r) * 3 + 1) * cap_pts; }
+    __host__ __device__ int32_t *pi(int p, int r) const { return pts_ + (size_t)((p * 2 + r) * 3 + 2) * cap_pts; }
+    __host__ __device__ SegGeo *geo(int p, int r) const { return geo_ + (size_t)(p * 2 + r) * scap; }
+    __host__ __device__ SegTop *top(int p, int r) const { return top_ + (size_t)(p * 2 + r) * scap; }
+    __host__ __device__ TileInfo *tinfo(int p, int r) const { return tinfo_ + (size_t)(p * 2 + r) * tcap; }
+    __host__ __device__ uint64_t *st2(int p) const { return st2_ + (size_t)p * (tcap + 4); }
+    __host__ __device__ uint64_t *st4(int p) const { return st4_ + (size_t)p * s4cap; }
+    __host__ __device__ int32_t *succ(int p) const { return succ_ + (size_t)p * hcap; }
+    __host__ __device__ int32_t *dist(int p) const { return dist_ + (size_t)p * hcap; }
 };
 
-hipError_t launch_instances(const Ws2 &ws, const int64_t *offsets, int64_t n_total, int32_t k,
-                            hipStream_t st);
-hipError_t launch_setup(const Ws2 &ws, const int64_t *offsets, int32_t k, int32_t ntiles, int grid,
+struct HullArgs {
+    const int32_t *x;
+    const int32_t *y;
+    const int64_t *offsets;
+    int32_t *hull_idx;
+    int64_t *hull_offsets;
+    int32_t n;
+    int32_t k;
+    int32_t vec_ok;
+    int32_t timing;
+    int32_t max_rounds;
+    int32_t pad;
+};
+
+hipError_t launch_setup(const Ws2 &ws, const HullArgs &a, int grid, hipStream_t st);
+hipError_t launch_extremes(const Ws2 &ws, const HullArgs &a, int grid, hipStream_t st);
+hipError_t launch_round(const Ws2 &ws, const HullArgs &a, int mode, int32_t r, int grid,
                         hipStream_t st);
-hipError_t launch_extremes(const Ws2 &ws, const int32_t *x, const int32_t *y, int32_t n,
-                           int32_t vec_ok, int grid, int32_t nseg_max, hipStream_t st);
-hipError_t launch_round(const Ws2 &ws, int32_t r, bool init, int mode, const int32_t *x,
-                        const int32_t *y, int32_t vec_ok, int grid, hipStream_t st);
-hipError_t launch_segments(const Ws2 &ws, int32_t r, int grid, hipStream_t st);
-hipError_t launch_output(const Ws2 &ws, int32_t H, int32_t k, const int64_t *offsets,
-                         int64_t *hull_offsets, int32_t *hull_idx, int64_t n_total, hipStream_t st);
+hipError_t launch_segments(const Ws2 &ws, const HullArgs &a, int32_t r, int grid, hipStream_t st);
+hipError_t launch_output(const Ws2 &ws, const HullArgs &a, int32_t H, hipStream_t st);
+// resident blocks of the round kernel on the whole device
+hipError_t round_grid(int mode, int cus, int *grid);
 
 }  // namespace qh

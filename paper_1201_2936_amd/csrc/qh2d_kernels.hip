@@ -1,26 +1,35 @@
-// qh2d_kernels.hip -- the 2D segmented Quickhull round on gfx950.
+// qh2d_kernels.hip -- the 2D segmented Quickhull on gfx950.
 //
-// One round of the permute-and-segment Quickhull (Tzeng & Owens, Section 3.1,
-// Algorithm 4's recursive step) is two launches:
+// The permute-and-segment Quickhull (Tzeng & Owens, Section 3.1; the 2D
+// driver of Algorithm 4) as a short sequence of kernels per call:
 //
-//   k_round     one pass over the survivors: every point is tested against
-//               the two new edges u->f and f->v of its segment (the triangle
-//               test and the "which edge" state of Algorithm 4), points
-//               inside the triangle are dropped (compact, Section 4.2), the
-//               others are written to the two child segments (a 2-state
-//               flagPermute, Section 4.1) with a single-pass decoupled
-//               look-back scan, and the farthest point of every child
-//               segment (the next apex) is found on the way;
-//   k_segments  one thread per segment: inserts the apex into the hull,
-//               finishes the argmax of segments that span several tiles and
-//               writes the child segment table of the next round.
+//   set-up       non-empty instances become the first segments, tile records
+//   extremes     lexicographic min / max of every instance (first split's
+//                extrema, Algorithm 4) and the coordinate range check
+//   round r      one pass over the survivors: each point is tested against the
+//                two new edges u->f and f->v of its segment (the triangle test
+//                and the "which edge" state), points inside the triangle are
+//                dropped (compact, Section 4.2), the others are written to the
+//                two child segments (a 2-state flagPermute, Section 4.1) using
+//                a single-pass decoupled look-back scan, and the farthest point
+//                of every child (next round's apex) is found on the way.
+//                Round 0 is the first split (its input is the caller's array).
+//   segments r   one thread per segment: the apex joins the hull, multi-tile
+//                argmax partials are merged, the next segment table is written
+//   output       list ranking of the hull cycles, CCW index lists
 //
-// Layout: survivors are structure-of-arrays int32 x[], y[], idx[] in two
-// regions per round (state-0 children and state-1 children), each region
-// filled front to back; a segment is a range [start, start+len) of one region.
-// Tiles of 4096 points are claimed from an atomic counter, which makes the
-// look-back safe without any assumption on the dispatch order.
+// Every kernel reads the round state from device memory and does nothing once
+// no segment is left, so the host enqueues rounds in batches and reads the
+// state back once per batch.
+//
+// Survivors are structure-of-arrays int32 x[], y[], idx[] in two regions per
+// round (children of state 0 and of state 1), each filled front to back; a
+// segment is a range [start, start+len) of one region.  Tiles of 2048 points
+// are claimed from an atomic counter, so the look-back needs no assumption on
+// the order in which blocks run.
 #include "qh2d.h"
+
+#include <algorithm>
 
 namespace qh {
 
@@ -28,7 +37,12 @@ namespace qh {
 // (|fl(a b)| + |fl(c d)|) for a, b, c, d rounded from int32 (eps = 2^-24);
 // 5 eps also covers the rounding of the bound itself.
 constexpr float kErrC = 5.0f / 16777216.0f;
+constexpr int kNW = kBlock / kWave;
+constexpr int kQ = kItems / 4;
 
+// ---------------------------------------------------------------------------
+// arithmetic
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t cross_i64(int32_t px, int32_t py, int32_t ax, int32_t ay,
                                              int32_t bx, int32_t by) {
     // (p - a) x (b - a): > 0 when p lies strictly right of a -> b
@@ -74,39 +88,142 @@ __device__ __forceinline__ int slot_of(const int32_t *s, int m, int32_t v) {
     return a;
 }
 
-__device__ __forceinline__ void store_best(Best *dst, const Best &b) { *dst = b; }
+__device__ __forceinline__ Best best_none() {
+    Best b;
+    b.key1 = 0;
+    b.key2 = ~0ull;
+    b.x = b.y = b.idx = b.pad = 0;
+    return b;
+}
 
 __device__ __forceinline__ void best_merge(Best &acc, const Best &b) {
     if (best_better(b, acc)) acc = b;
 }
 
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// butterfly all-reduce of a Best over the 64 lanes of a wave
+__device__ __forceinline__ void wave_best(Best &b) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        Best o;
+        o.key1 = shfl_xor_u64(b.key1, m);
+        o.key2 = shfl_xor_u64(b.key2, m);
+        o.x = __shfl_xor(b.x, m);
+        o.y = __shfl_xor(b.y, m);
+        o.idx = __shfl_xor(b.idx, m);
+        o.pad = 0;
+        if (best_better(o, b)) b = o;
+    }
+}
+
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m));
+    return v;
+}
+
+// candidate update of a running best with an exact distance d > 0
+__device__ __forceinline__ void best_offer(Best &b, uint64_t d, int32_t x, int32_t y, int32_t idx,
+                                           int32_t ex, int32_t ey) {
+    if (d < b.key1) return;
+    const uint64_t k2 = tie_key(x, y, idx, ex, ey);
+    if (d > b.key1 || k2 < b.key2) {
+        b.key1 = d;
+        b.key2 = k2;
+        b.x = x;
+        b.y = y;
+        b.idx = idx;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Set-up: compact the non-empty instances into the first segment table
-// (one block).
+// grid barrier of the cooperative kernel
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_instances(Ws2 ws, const int64_t *offsets, int64_t n_total,
-                                                    int32_t k) {
+// ---------------------------------------------------------------------------
+// LDS layouts of the phases (they share one buffer)
+// ---------------------------------------------------------------------------
+struct RoundSmem {
+    int32_t s_tile, s_next[2], s_m;
+    uint64_t s_ex;
+    float Mw[kNW][2];
+    uint32_t stat[4];
+    uint32_t scan[kQ * kNW];
+    Best red[kNW][2];
+    int32_t sstart[kTile + 4];
+    int32_t lgeo[kSlots][6];
+    uint64_t k1[2][kSlots];
+    uint64_t k2[2][kSlots];
+    uint32_t lm[2][kSlots];
+    int32_t res[2][kSlots][3];
+    uint64_t Dl[kTile];
+};
+
+struct ExtSmem {
+    int32_t s_m, pad;
+    Best red[kNW][2];
+    int32_t sstart[kTile + 4];
+    uint64_t kmin1[kSlots], kmin2[kSlots], kmax1[kSlots], kmax2[kSlots];
+    int32_t rmin[kSlots][3], rmax[kSlots][3];
+};
+
+struct SegSmem {
+    uint32_t scan[2 * (kSegBlock / kWave)];
+    int32_t s_tile, qn_apex, qn_map, pad;
+    uint64_t s_ex;
+    int16_t q_apex[kSegBlock];
+    int16_t q_map[2 * kSegBlock];
+    int32_t o_t0[kSegBlock], o_t1[kSegBlock];
+    int32_t o_ka[2 * kSegBlock], o_kb[2 * kSegBlock], o_id[2 * kSegBlock];
+    Best red[kNW];
+};
+
+struct RankSmem {
+    int32_t su[kRankSmallCap];
+    int32_t di[kRankSmallCap];
+};
+
+struct ScanSmem {
+    uint32_t scratch[32];
+    unsigned long long carry;
+    int32_t bad;
+};
+
+template <typename A, typename B>
+constexpr size_t cmax(A a, B b) { return a > b ? a : b; }
+constexpr size_t kSmemBytes =
+    cmax(cmax(cmax(sizeof(RoundSmem), sizeof(ExtSmem)), cmax(sizeof(SegSmem), sizeof(RankSmem))),
+         sizeof(ScanSmem));
+
+// ---------------------------------------------------------------------------
+// set-up
+// ---------------------------------------------------------------------------
+// block 0: compact the non-empty instances into the first segment table
+__device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a, char *smem) {
+    if (blockIdx.x != 0) return;
+    ScanSmem *sm = reinterpret_cast<ScanSmem *>(smem);
     Control *ctl = ws.ctl;
-    __shared__ uint32_t scratch[32];
-    __shared__ uint32_t carry;
-    __shared__ int32_t bad;
-    if (threadIdx.x == 0) { carry = 0; bad = 0; }
+    const int k = a.k;
+    if (threadIdx.x == 0) { sm->carry = 0; sm->bad = 0; }
     __syncthreads();
-    for (int base = 0; base < k; base += 1024) {
+    for (int base = 0; base < k; base += kBlock) {
         const int i = base + (int)threadIdx.x;
         int64_t lo = 0, hi = 0;
         bool ne = false;
         if (i < k) {
-            lo = offsets[i];
-            hi = offsets[i + 1];
-            if (lo < 0 || hi < lo || hi > n_total || (i == 0 && lo != 0) ||
-                (i == k - 1 && hi != n_total))
-                atomicOr(&bad, 1);
+            lo = a.offsets[i];
+            hi = a.offsets[i + 1];
+            if (lo < 0 || hi < lo || hi > a.n || (i == 0 && lo != 0) || (i == k - 1 && hi != a.n))
+                atomicOr(&sm->bad, 1);
             ne = hi > lo;
         }
         uint32_t v[1] = {ne ? 1u : 0u}, tot[1];
-        block_excl_scan<1024, 1>(v, tot, scratch);
-        const uint32_t j = carry + v[0];
+        block_excl_scan<kBlock, 1>(v, tot, sm->scratch);
+        const uint32_t j = (uint32_t)sm->carry + v[0];
         if (i < k) {
             ws.inst_rank[i] = ne ? (int32_t)j : -1;
             ws.nxt[i] = -1;
@@ -116,464 +233,429 @@ __global__ __launch_bounds__(1024) void k_instances(Ws2 ws, const int64_t *offse
                 g.start = (int32_t)lo;
                 g.len = (int32_t)(hi - lo);
                 g.ux = g.uy = g.fx = g.fy = g.vx = g.vy = 0;
-                ws.geo[0][0][j] = g;
+                ws.geo(0, 0)[j] = g;
                 SegTop t;
                 t.fidx = 0;
                 t.uc = i;
                 t.vc = i;
                 t.inst = i;
-                ws.top[0][0][j] = t;
+                ws.top(0, 0)[j] = t;
             }
         }
         __syncthreads();
-        if (threadIdx.x == 0) carry += tot[0];
+        if (threadIdx.x == 0) sm->carry += tot[0];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         RoundState z = {};
         ctl->rs[1] = z;
         RoundState r0 = {};
-        r0.n[0] = (int32_t)n_total;
+        r0.n[0] = a.n;
         r0.n[1] = 0;
-        r0.s[0] = (int32_t)carry;
+        r0.s[0] = (int32_t)sm->carry;
         r0.s[1] = 0;
         r0.hbase = k;
         ctl->rs[0] = r0;
-        ctl->error = bad ? kErrOffsets : 0;
+        ctl->error = sm->bad ? kErrOffsets : 0;
+        ctl->setup_error = sm->bad ? kErrOffsets : 0;
         ctl->rounds_done = 0;
-        ctl->max_segments = (int32_t)carry;
-        ctl->points_in = ctl->points_out = ctl->first_in = 0;
+        ctl->max_segments = (int32_t)sm->carry;
+        ctl->final_round = 0;
+        ctl->points_in = ctl->points_out = ctl->first_in = ctl->first_out = 0;
         ctl->filter_tests = ctl->filter_fallbacks = ctl->candidates = 0;
-        ctl->round_launches_work = 0;
+        ctl->rounds_with_work = 0;
+        ctl->H = 0;
+        ctl->h_total = 0;
     }
 }
 
-// Set-up: tile map of the original array (tile -> instance segment), and a
-// clean look-back status for both parities.
-__global__ void k_setup(Ws2 ws, const int64_t *offsets, int32_t k, int32_t ntiles) {
+// tile records of the input (tile -> instance segment) and clean look-back words
+__device__ __forceinline__ void phase_setup(const Ws2 &ws, const HullArgs &a) {
     const int stride = gridDim.x * blockDim.x;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     for (int i = tid; i < ws.tcap + 4; i += stride) {
-        ws.st2[0][i] = 0;
-        ws.st2[1][i] = 0;
+        ws.st2(0)[i] = 0;
+        ws.st2(1)[i] = 0;
     }
     for (int i = tid; i < ws.s4cap; i += stride) {
-        ws.st4[0][i] = 0;
-        ws.st4[1][i] = 0;
+        ws.st4(0)[i] = 0;
+        ws.st4(1)[i] = 0;
     }
     if (ws.ctl->error) return;
+    const int ntiles = (a.n + kTile - 1) / kTile;
     for (int t = tid; t < ntiles; t += stride) {
         const int64_t v = (int64_t)t * kTile;
         // largest i with offsets[i] <= v: that instance holds v and is non-empty
-        int a = 0, b = k;
-        while (b - a > 1) {
-            const int c = (a + b) >> 1;
-            if (offsets[c] <= v) a = c; else b = c;
+        int lo = 0, hi = a.k;
+        while (hi - lo > 1) {
+            const int c = (lo + hi) >> 1;
+            if (a.offsets[c] <= v) lo = c; else hi = c;
         }
-        ws.tmap[0][0][t] = ws.inst_rank[a];
+        const int64_t st = a.offsets[lo], en = a.offsets[lo + 1];
+        TileInfo ti = {};
+        ti.seg = ws.inst_rank[lo];
+        ti.start = (int32_t)st;
+        ti.end = (int32_t)en;
+        ti.single = en >= min(v + kTile, (int64_t)a.n) ? 1 : 0;
+        ws.tinfo(0, 0)[t] = ti;
     }
 }
 
 // ---------------------------------------------------------------------------
-// K0: lexicographic extremes of every instance and the coordinate range check
-// (first split of Algorithm 4: the extrema along x, ties by y then index).
+// extremes: lexicographic min and max of every instance, range check
 // ---------------------------------------------------------------------------
-template <int BLOCK, int ITEMS>
-__global__ __launch_bounds__(BLOCK) void k_extremes(Ws2 ws, const int32_t *in_x, const int32_t *in_y,
-                                                    int32_t n, int32_t vec_ok) {
-    constexpr int T = BLOCK * ITEMS;
-    constexpr int Q = ITEMS / 4;
+__device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a, char *smem) {
     Control *ctl = ws.ctl;
     if (ctl->error) return;
+    ExtSmem *sm = reinterpret_cast<ExtSmem *>(smem);
+    const int n = a.n;
     const int S = ctl->rs[0].s[0];
-    const int ntiles = (n + T - 1) / T;
-    const int tid = threadIdx.x;
-
-    __shared__ int32_t sstart[T + 1];
-    __shared__ uint64_t kmin1[kSlots], kmin2[kSlots], kmax1[kSlots], kmax2[kSlots];
-    __shared__ int32_t rmin[kSlots][3], rmax[kSlots][3];
-    __shared__ int32_t s_tile, s_m, s_bad;
-
+    const int ntiles = (n + kTile - 1) / kTile;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+    bool bad = false;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int lo = tile * T;
-        const int hi = min(lo + T, n);
-        int32_t X[ITEMS], Y[ITEMS];
+        const int lo = tile * kTile;
+        const int hi = min(lo + kTile, n);
+        int32_t X[kItems], Y[kItems];
 #pragma unroll
-        for (int qq = 0; qq < Q; ++qq) {
-            const int v0 = lo + qq * BLOCK * 4 + tid * 4;
-            if (vec_ok && v0 + 3 < hi) {
-                const int4 a = *reinterpret_cast<const int4 *>(in_x + v0);
-                const int4 b = *reinterpret_cast<const int4 *>(in_y + v0);
-                X[qq * 4 + 0] = a.x; X[qq * 4 + 1] = a.y; X[qq * 4 + 2] = a.z; X[qq * 4 + 3] = a.w;
-                Y[qq * 4 + 0] = b.x; Y[qq * 4 + 1] = b.y; Y[qq * 4 + 2] = b.z; Y[qq * 4 + 3] = b.w;
+        for (int qq = 0; qq < kQ; ++qq) {
+            const int v0 = lo + qq * kBlock * 4 + tid * 4;
+            if (a.vec_ok && v0 + 3 < hi) {
+                const int4 p = *reinterpret_cast<const int4 *>(a.x + v0);
+                const int4 q = *reinterpret_cast<const int4 *>(a.y + v0);
+                X[qq * 4 + 0] = p.x; X[qq * 4 + 1] = p.y; X[qq * 4 + 2] = p.z; X[qq * 4 + 3] = p.w;
+                Y[qq * 4 + 0] = q.x; Y[qq * 4 + 1] = q.y; Y[qq * 4 + 2] = q.z; Y[qq * 4 + 3] = q.w;
             } else {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int v = v0 + j;
-                    X[qq * 4 + j] = v < hi ? in_x[v] : 0;
-                    Y[qq * 4 + j] = v < hi ? in_y[v] : 0;
+                    X[qq * 4 + j] = v < hi ? a.x[v] : 0;
+                    Y[qq * 4 + j] = v < hi ? a.y[v] : 0;
                 }
             }
         }
-        // instances overlapping the tile
-        const int s0 = ws.tmap[0][0][tile];
-        if (tid == 0) { s_m = 0; s_bad = 0; }
+        const TileInfo ti = ws.tinfo(0, 0)[tile];
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+            if (v < hi)
+                bad |= (X[i] > kCoordMax2D) | (X[i] < -kCoordMax2D) | (Y[i] > kCoordMax2D) |
+                       (Y[i] < -kCoordMax2D);
+        }
+        if (ti.single) {
+            // one instance covers the tile: running min / max in registers
+            Best mn = best_none(), mx = best_none();
+#pragma unroll
+            for (int i = 0; i < kItems; ++i) {
+                const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                if (v >= hi) continue;
+                const uint64_t ck = coord_key(X[i], Y[i]);
+                Best c;
+                c.key1 = ~ck; c.key2 = (uint32_t)v; c.x = X[i]; c.y = Y[i]; c.idx = v; c.pad = 0;
+                best_merge(mn, c);
+                c.key1 = ck;
+                best_merge(mx, c);
+            }
+            wave_best(mn);
+            wave_best(mx);
+            if (lane == 0) { sm->red[wv][0] = mn; sm->red[wv][1] = mx; }
+            __syncthreads();
+            if (tid == 0) {
+                for (int w = 1; w < kNW; ++w) {
+                    best_merge(mn, sm->red[w][0]);
+                    best_merge(mx, sm->red[w][1]);
+                }
+                const bool inside = ti.start >= lo && ti.end <= hi;
+                if (inside) { ws.dir0[ti.seg * 2 + 0] = mn; ws.dir0[ti.seg * 2 + 1] = mx; }
+                ws.recF0[tile * 2 + 0] = mn; ws.recF0[tile * 2 + 1] = mx;
+                ws.recL0[tile * 2 + 0] = mn; ws.recL0[tile * 2 + 1] = mx;
+            }
+            __syncthreads();
+            continue;
+        }
+        // several instances in the tile: per-slot LDS reduction
+        const int s0 = ti.seg;
+        if (tid == 0) sm->s_m = 0;
         __syncthreads();
-        for (int b = 0; b <= T; b += BLOCK) {
+        for (int b = 0; b <= kTile; b += kBlock) {
             const int j = b + tid;
             bool in = false;
-            if (j <= T) {
+            if (j <= kTile) {
                 const int si = s0 + j;
-                const int st = si < S ? ws.geo[0][0][si].start : n;
-                sstart[j] = st;
+                const int st = si < S ? ws.geo(0, 0)[si].start : n;
+                sm->sstart[j] = st;
                 in = st < hi;
             }
             const int cnt = __syncthreads_count(in);
-            if (tid == 0) s_m += cnt;
-            if (cnt < BLOCK) break;
+            if (tid == 0) sm->s_m += cnt;
+            if (cnt < kBlock) break;
         }
         __syncthreads();
-        const int m = s_m;
-        // range check
-        bool bad = false;
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const int v = lo + (i >> 2) * BLOCK * 4 + tid * 4 + (i & 3);
-            if (v < hi) {
-                bad |= (X[i] > kCoordMax2D) | (X[i] < -kCoordMax2D) | (Y[i] > kCoordMax2D) |
-                       (Y[i] < -kCoordMax2D);
-            }
-        }
-        if (__syncthreads_or(bad) && tid == 0) atomicOr(&ctl->error, kErrRange);
-
+        const int m = sm->s_m;
         for (int w0 = 0; w0 < m; w0 += kSlots) {
             const int wn = min(kSlots, m - w0);
-            for (int j = tid; j < kSlots; j += BLOCK) {
-                kmin1[j] = 0; kmin2[j] = ~0ull; kmax1[j] = 0; kmax2[j] = ~0ull;
+            for (int j = tid; j < kSlots; j += kBlock) {
+                sm->kmin1[j] = 0; sm->kmin2[j] = ~0ull; sm->kmax1[j] = 0; sm->kmax2[j] = ~0ull;
             }
             __syncthreads();
-            // phase 1: best coordinate key per slot (min as max of complement)
-            int cur = -1;
-            uint64_t bmin = 0, bmax = 0;
 #pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const int v = lo + (i >> 2) * BLOCK * 4 + tid * 4 + (i & 3);
+            for (int i = 0; i < kItems; ++i) {
+                const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
                 if (v >= hi) continue;
-                const int sl = (m == 1) ? 0 : slot_of(sstart, m, v);
-                if (sl < w0 || sl >= w0 + wn) continue;
-                if (sl != cur) {
-                    if (cur >= 0) {
-                        atomicMax(&kmin1[cur - w0], bmin);
-                        atomicMax(&kmax1[cur - w0], bmax);
-                    }
-                    cur = sl;
-                    bmin = 0;
-                    bmax = 0;
-                }
-                const uint64_t ck = coord_key(X[i], Y[i]);
-                bmin = max(bmin, ~ck);
-                bmax = max(bmax, ck);
-            }
-            if (cur >= 0) {
-                atomicMax(&kmin1[cur - w0], bmin);
-                atomicMax(&kmax1[cur - w0], bmax);
-            }
-            __syncthreads();
-            // phase 2: lowest index among the points with that key
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const int v = lo + (i >> 2) * BLOCK * 4 + tid * 4 + (i & 3);
-                if (v >= hi) continue;
-                const int sl = (m == 1) ? 0 : slot_of(sstart, m, v);
+                const int sl = slot_of(sm->sstart, m, v);
                 if (sl < w0 || sl >= w0 + wn) continue;
                 const uint64_t ck = coord_key(X[i], Y[i]);
-                if (~ck == kmin1[sl - w0]) atomicMin(&kmin2[sl - w0], (uint64_t)(uint32_t)v);
-                if (ck == kmax1[sl - w0]) atomicMin(&kmax2[sl - w0], (uint64_t)(uint32_t)v);
+                atomicMax(&sm->kmin1[sl - w0], ~ck);
+                atomicMax(&sm->kmax1[sl - w0], ck);
             }
             __syncthreads();
 #pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const int v = lo + (i >> 2) * BLOCK * 4 + tid * 4 + (i & 3);
+            for (int i = 0; i < kItems; ++i) {
+                const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
                 if (v >= hi) continue;
-                const int sl = (m == 1) ? 0 : slot_of(sstart, m, v);
+                const int sl = slot_of(sm->sstart, m, v);
                 if (sl < w0 || sl >= w0 + wn) continue;
-                if ((uint64_t)(uint32_t)v == kmin2[sl - w0]) {
-                    rmin[sl - w0][0] = X[i]; rmin[sl - w0][1] = Y[i]; rmin[sl - w0][2] = v;
+                const uint64_t ck = coord_key(X[i], Y[i]);
+                if (~ck == sm->kmin1[sl - w0]) atomicMin(&sm->kmin2[sl - w0], (uint64_t)(uint32_t)v);
+                if (ck == sm->kmax1[sl - w0]) atomicMin(&sm->kmax2[sl - w0], (uint64_t)(uint32_t)v);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < kItems; ++i) {
+                const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                if (v >= hi) continue;
+                const int sl = slot_of(sm->sstart, m, v);
+                if (sl < w0 || sl >= w0 + wn) continue;
+                if ((uint64_t)(uint32_t)v == sm->kmin2[sl - w0]) {
+                    sm->rmin[sl - w0][0] = X[i]; sm->rmin[sl - w0][1] = Y[i]; sm->rmin[sl - w0][2] = v;
                 }
-                if ((uint64_t)(uint32_t)v == kmax2[sl - w0]) {
-                    rmax[sl - w0][0] = X[i]; rmax[sl - w0][1] = Y[i]; rmax[sl - w0][2] = v;
+                if ((uint64_t)(uint32_t)v == sm->kmax2[sl - w0]) {
+                    sm->rmax[sl - w0][0] = X[i]; sm->rmax[sl - w0][1] = Y[i]; sm->rmax[sl - w0][2] = v;
                 }
             }
             __syncthreads();
-            for (int j = tid; j < wn; j += BLOCK) {
+            for (int j = tid; j < wn; j += kBlock) {
                 const int sl = w0 + j;
                 Best bmn, bmx;
-                bmn.key1 = kmin1[j]; bmn.key2 = kmin2[j];
-                bmn.x = rmin[j][0]; bmn.y = rmin[j][1]; bmn.idx = rmin[j][2]; bmn.pad = 0;
-                bmx.key1 = kmax1[j]; bmx.key2 = kmax2[j];
-                bmx.x = rmax[j][0]; bmx.y = rmax[j][1]; bmx.idx = rmax[j][2]; bmx.pad = 0;
-                const bool inside = sstart[sl] >= lo && sstart[sl + 1] <= hi;
+                bmn.key1 = sm->kmin1[j]; bmn.key2 = sm->kmin2[j];
+                bmn.x = sm->rmin[j][0]; bmn.y = sm->rmin[j][1]; bmn.idx = sm->rmin[j][2]; bmn.pad = 0;
+                bmx.key1 = sm->kmax1[j]; bmx.key2 = sm->kmax2[j];
+                bmx.x = sm->rmax[j][0]; bmx.y = sm->rmax[j][1]; bmx.idx = sm->rmax[j][2]; bmx.pad = 0;
+                const bool inside = sm->sstart[sl] >= lo && sm->sstart[sl + 1] <= hi;
                 if (inside) {
                     ws.dir0[(s0 + sl) * 2 + 0] = bmn;
                     ws.dir0[(s0 + sl) * 2 + 1] = bmx;
                 }
-                if (sl == 0) {
-                    ws.recF0[tile * 2 + 0] = bmn;
-                    ws.recF0[tile * 2 + 1] = bmx;
-                }
-                if (sl == m - 1) {
-                    ws.recL0[tile * 2 + 0] = bmn;
-                    ws.recL0[tile * 2 + 1] = bmx;
-                }
+                if (sl == 0) { ws.recF0[tile * 2 + 0] = bmn; ws.recF0[tile * 2 + 1] = bmx; }
+                if (sl == m - 1) { ws.recL0[tile * 2 + 0] = bmn; ws.recL0[tile * 2 + 1] = bmx; }
             }
             __syncthreads();
         }
     }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) {
+        atomicOr(&ctl->error, kErrRange);
+        atomicOr(&ctl->setup_error, kErrRange);
+    }
 }
 
-// K0f: one block per instance segment: finish the extremes over the tiles it
-// spans and write the first-split segment (edge a -> a with apex b, so the
-// round kernel splits the points by the line ab).
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_extremes_final(Ws2 ws) {
+// Merge the per-tile partials of one segment over tiles t0 .. t1 (the whole
+// block cooperates; every thread gets the result).  In tile t0 the segment is
+// the tile's last one, in the later tiles its first one.
+__device__ __forceinline__ Best block_merge_tiles(const Best *recF, const Best *recL, int t0, int t1, int c,
+                                  Best *red) {
+    Best acc = best_none();
+    for (int t = t0 + (int)threadIdx.x; t <= t1; t += 4 * kBlock) {
+        Best b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int tt = t + u * kBlock;
+            b[u] = tt <= t1 ? (tt == t0 ? recL[tt * 2 + c] : recF[tt * 2 + c]) : best_none();
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) best_merge(acc, b[u]);
+    }
+    wave_best(acc);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    Best r = red[0];
+    for (int w = 1; w < kNW; ++w) best_merge(r, red[w]);
+    __syncthreads();
+    return r;
+}
+
+// Every instance segment: finish its extremes, write the first-split segment
+// (edge a -> a with apex b, so the round splits the points by the line ab) and
+// the geometry of its tiles.
+__device__ __forceinline__ void phase_extremes_final(const Ws2 &ws, const HullArgs &a, char *smem) {
     Control *ctl = ws.ctl;
     if (ctl->error) return;
+    SegSmem *sm = reinterpret_cast<SegSmem *>(smem);
     const int S = ctl->rs[0].s[0];
-    const int s = blockIdx.x;
-    if (s >= S) return;
-    __shared__ Best red[2][BLOCK];
-    SegGeo g = ws.geo[0][0][s];
-    const SegTop tp = ws.top[0][0][s];
-    const int t0 = g.start / kTile;
-    const int t1 = (g.start + g.len - 1) / kTile;
-    Best b[2];
-    if (t0 == t1) {
-        b[0] = ws.dir0[s * 2 + 0];
-        b[1] = ws.dir0[s * 2 + 1];
-    } else {
-        for (int c = 0; c < 2; ++c) {
-            Best acc;
-            acc.key1 = 0; acc.key2 = ~0ull; acc.x = acc.y = acc.idx = acc.pad = 0;
-            for (int t = t0 + (int)threadIdx.x; t <= t1; t += BLOCK)
-                best_merge(acc, t == t0 ? ws.recL0[t * 2 + c] : ws.recF0[t * 2 + c]);
-            red[c][threadIdx.x] = acc;
+    for (int s = blockIdx.x; s < S; s += gridDim.x) {
+        SegGeo g = ws.geo(0, 0)[s];
+        const SegTop tp = ws.top(0, 0)[s];
+        const int t0 = g.start / kTile;
+        const int t1 = (g.start + g.len - 1) / kTile;
+        Best mn, mx;
+        if (t0 == t1) {
+            mn = ws.dir0[s * 2 + 0];
+            mx = ws.dir0[s * 2 + 1];
+        } else {
+            mn = block_merge_tiles(ws.recF0, ws.recL0, t0, t1, 0, sm->red);
+            mx = block_merge_tiles(ws.recF0, ws.recL0, t0, t1, 1, sm->red);
         }
-        __syncthreads();
-        for (int w = BLOCK / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) {
-                for (int c = 0; c < 2; ++c) {
-                    Best o = red[c][threadIdx.x + w];
-                    if (best_better(o, red[c][threadIdx.x])) red[c][threadIdx.x] = o;
-                }
-            }
-            __syncthreads();
+        // tiles that start inside this instance
+        const int ka = (g.start + kTile - 1) / kTile;
+        const int kb = (g.start + g.len + kTile - 1) / kTile;
+        for (int kk = ka + (int)threadIdx.x; kk < kb; kk += kBlock) {
+            TileInfo ti;
+            ti.seg = s;
+            ti.start = g.start;
+            ti.end = g.start + g.len;
+            ti.single = (int64_t)ti.end >= min((int64_t)(kk + 1) * kTile, (int64_t)a.n) ? 1 : 0;
+            ti.ux = mn.x; ti.uy = mn.y;
+            ti.fx = mx.x; ti.fy = mx.y;
+            ti.vx = mn.x; ti.vy = mn.y;
+            ti.pad0 = ti.pad1 = 0;
+            ws.tinfo(0, 0)[kk] = ti;
         }
-        b[0] = red[0][0];
-        b[1] = red[1][0];
+        if (threadIdx.x == 0) {
+            g.ux = mn.x; g.uy = mn.y;
+            g.vx = mn.x; g.vy = mn.y;
+            g.fx = mx.x; g.fy = mx.y;
+            ws.geo(0, 0)[s] = g;
+            SegTop t = tp;
+            t.fidx = mx.idx;
+            ws.top(0, 0)[s] = t;
+            ws.V[tp.uc] = mn.idx;
+            ws.hinst[tp.uc] = tp.inst;
+        }
     }
-    if (threadIdx.x != 0) return;
-    g.ux = b[0].x; g.uy = b[0].y;
-    g.vx = b[0].x; g.vy = b[0].y;
-    g.fx = b[1].x; g.fy = b[1].y;
-    ws.geo[0][0][s] = g;
-    SegTop t = tp;
-    t.fidx = b[1].idx;
-    ws.top[0][0][s] = t;
-    ws.V[tp.uc] = b[0].idx;
-    ws.hinst[tp.uc] = tp.inst;
 }
 
 // ---------------------------------------------------------------------------
-// The fused round kernel.
+// one round over the survivors
 // ---------------------------------------------------------------------------
-template <bool INIT, int MODE, int BLOCK, int ITEMS>
-__global__ __launch_bounds__(BLOCK) void k_round(Ws2 ws, int32_t r, const int32_t *in_x,
-                                                 const int32_t *in_y, int32_t vec_ok) {
-    constexpr int T = BLOCK * ITEMS;
-    constexpr int Q = ITEMS / 4;
-    constexpr int NW = BLOCK / kWave;
-    static_assert(T == kTile, "tile size");
+template <int MODE>
+__device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, int r, char *smem) {
+    const bool INIT = r == 0;  // the first split reads the input (index = position)
     Control *ctl = ws.ctl;
-    if (ctl->error) return;
+    RoundSmem *sm = reinterpret_cast<RoundSmem *>(smem);
     const int p = r & 1, q = p ^ 1;
     RoundState *rs = &ctl->rs[p];
     RoundState *rn = &ctl->rs[q];
     const int n0 = rs->n[0], n1 = rs->n[1];
-    const int S0 = rs->s[0];
-    const int S1 = rs->s[1];
-    const int nt0 = (n0 + T - 1) / T, nt1 = (n1 + T - 1) / T;
+    const int S0 = rs->s[0], S1 = rs->s[1];
+    const int nt0 = (n0 + kTile - 1) / kTile, nt1 = (n1 + kTile - 1) / kTile;
     const int ntiles = nt0 + nt1;
-    const int tid = threadIdx.x;
-    const int lane = lane_id();
-    const int wv = tid / kWave;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
 
     // house-keeping for the next round
     if (blockIdx.x == 0 && tid == 0) rn->tile_ctr = 0;
-    for (int i = blockIdx.x * BLOCK + tid; i < ntiles + 2 && i < ws.tcap + 4; i += gridDim.x * BLOCK)
-        ws.st2[q][i] = 0;
+    for (int i = blockIdx.x * kBlock + tid; i < ntiles + 2 && i < ws.tcap + 4; i += gridDim.x * kBlock)
+        ws.st2(q)[i] = 0;
     if (ntiles == 0) {
         if (blockIdx.x == 0 && tid == 0) { rn->n[0] = 0; rn->n[1] = 0; }
         return;
     }
 
-    __shared__ int32_t sstart[T + 1];
-    __shared__ int32_t lgeo[kSlots][6];
-    __shared__ uint64_t k1[2][kSlots];
-    __shared__ uint64_t k2[2][kSlots];
-    __shared__ uint32_t lm[2][kSlots];
-    __shared__ int32_t res[2][kSlots][3];
-    __shared__ uint32_t scan_scr[Q * NW];
-    __shared__ int32_t s_tile, s_m;
-    __shared__ uint64_t s_ex;
-
-    while (true) {
-        if (tid == 0) s_tile = (int32_t)atomicAdd(&rs->tile_ctr, 1u);
-        __syncthreads();
-        const int tile = s_tile;
-        if (tile >= ntiles) break;
+    uint32_t ntests = 0, nfall = 0, ncand = 0;
+    if (tid == 0) sm->s_tile = (int32_t)atomicAdd(&rs->tile_ctr, 1u);
+    __syncthreads();
+    int tile = sm->s_tile;
+    int it = 0;
+    while (tile < ntiles) {
+        if (tid == 0) sm->s_next[it & 1] = (int32_t)atomicAdd(&rs->tile_ctr, 1u);
         const int R = tile < nt0 ? 0 : 1;
         const int lt = tile - (R ? nt0 : 0);
         const int NR = R ? n1 : n0;
         const int SR = R ? S1 : S0;
         const int gbase = R ? S0 : 0;
-        const int lo = lt * T;
-        const int hi = min(lo + T, NR);
-        const SegGeo *geo = ws.geo[p][R];
+        const int lo = lt * kTile;
+        const int hi = min(lo + kTile, NR);
 
         // 1. the tile's points (structure of arrays, 16-byte loads)
-        int32_t X[ITEMS], Y[ITEMS], I[ITEMS];
+        int32_t X[kItems], Y[kItems], I[kItems];
 #pragma unroll
-        for (int qq = 0; qq < Q; ++qq) {
-            const int v0 = lo + qq * BLOCK * 4 + tid * 4;
+        for (int qq = 0; qq < kQ; ++qq) {
+            const int v0 = lo + qq * kBlock * 4 + tid * 4;
             if (INIT) {
-                if (vec_ok && v0 + 3 < hi) {
-                    const int4 a = *reinterpret_cast<const int4 *>(in_x + v0);
-                    const int4 b = *reinterpret_cast<const int4 *>(in_y + v0);
-                    X[qq * 4 + 0] = a.x; X[qq * 4 + 1] = a.y; X[qq * 4 + 2] = a.z; X[qq * 4 + 3] = a.w;
-                    Y[qq * 4 + 0] = b.x; Y[qq * 4 + 1] = b.y; Y[qq * 4 + 2] = b.z; Y[qq * 4 + 3] = b.w;
+                if (a.vec_ok && v0 + 3 < hi) {
+                    const int4 pa = *reinterpret_cast<const int4 *>(a.x + v0);
+                    const int4 pb = *reinterpret_cast<const int4 *>(a.y + v0);
+                    X[qq * 4 + 0] = pa.x; X[qq * 4 + 1] = pa.y; X[qq * 4 + 2] = pa.z; X[qq * 4 + 3] = pa.w;
+                    Y[qq * 4 + 0] = pb.x; Y[qq * 4 + 1] = pb.y; Y[qq * 4 + 2] = pb.z; Y[qq * 4 + 3] = pb.w;
                 } else {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int v = v0 + j;
-                        X[qq * 4 + j] = v < hi ? in_x[v] : 0;
-                        Y[qq * 4 + j] = v < hi ? in_y[v] : 0;
+                        X[qq * 4 + j] = v < hi ? a.x[v] : 0;
+                        Y[qq * 4 + j] = v < hi ? a.y[v] : 0;
                     }
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j) I[qq * 4 + j] = v0 + j;
             } else {
-                const int4 a = *reinterpret_cast<const int4 *>(ws.px[p][R] + v0);
-                const int4 b = *reinterpret_cast<const int4 *>(ws.py[p][R] + v0);
-                const int4 c = *reinterpret_cast<const int4 *>(ws.pi[p][R] + v0);
-                X[qq * 4 + 0] = a.x; X[qq * 4 + 1] = a.y; X[qq * 4 + 2] = a.z; X[qq * 4 + 3] = a.w;
-                Y[qq * 4 + 0] = b.x; Y[qq * 4 + 1] = b.y; Y[qq * 4 + 2] = b.z; Y[qq * 4 + 3] = b.w;
-                I[qq * 4 + 0] = c.x; I[qq * 4 + 1] = c.y; I[qq * 4 + 2] = c.z; I[qq * 4 + 3] = c.w;
+                const int4 pa = *reinterpret_cast<const int4 *>(ws.px(p, R) + v0);
+                const int4 pb = *reinterpret_cast<const int4 *>(ws.py(p, R) + v0);
+                const int4 pc = *reinterpret_cast<const int4 *>(ws.pi(p, R) + v0);
+                X[qq * 4 + 0] = pa.x; X[qq * 4 + 1] = pa.y; X[qq * 4 + 2] = pa.z; X[qq * 4 + 3] = pa.w;
+                Y[qq * 4 + 0] = pb.x; Y[qq * 4 + 1] = pb.y; Y[qq * 4 + 2] = pb.z; Y[qq * 4 + 3] = pb.w;
+                I[qq * 4 + 0] = pc.x; I[qq * 4 + 1] = pc.y; I[qq * 4 + 2] = pc.z; I[qq * 4 + 3] = pc.w;
             }
         }
+        const TileInfo ti = ws.tinfo(p, R)[lt];
+        const int s0 = ti.seg;
 
-        // 2. the segments overlapping the tile: starts into LDS
-        const int s0 = ws.tmap[p][R][lt];
-        if (tid == 0) s_m = 0;
-        __syncthreads();
-        for (int b = 0; b <= T; b += BLOCK) {
-            const int j = b + tid;
-            bool in = false;
-            if (j <= T) {
-                const int si = s0 + j;
-                const int st = si < SR ? geo[si].start : NR;
-                sstart[j] = st;
-                in = st < hi;
-            }
-            const int cnt = __syncthreads_count(in);
-            if (tid == 0) s_m += cnt;
-            if (cnt < BLOCK) break;
-        }
-        __syncthreads();
-        const int m = s_m;
-
-        // slot of every point (16 bits each)
-        uint32_t slotpk[ITEMS / 2];
+        uint32_t stbits = 0xaaaaaaaau;  // 2 bits per point: 0, 1 = child, 2 = dropped
+        // slot of every point inside the tile's segment list (16 bits each)
+        uint32_t slotpk[kItems / 2];
 #pragma unroll
-        for (int i = 0; i < ITEMS; i += 2) {
-            const int va = lo + (i >> 2) * BLOCK * 4 + tid * 4 + (i & 3);
-            const int sa = (m == 1 || va >= hi) ? 0 : slot_of(sstart, m, va);
-            const int sb = (m == 1 || va + 1 >= hi) ? 0 : slot_of(sstart, m, va + 1);
-            slotpk[i >> 1] = (uint32_t)sa | ((uint32_t)sb << 16);
-        }
-        auto SLOT = [&](int i) -> int { return (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu); };
-        auto VOF = [&](int i) -> int { return lo + (i >> 2) * BLOCK * 4 + tid * 4 + (i & 3); };
+        for (int i = 0; i < kItems / 2; ++i) slotpk[i] = 0;
 
-        uint32_t stbits = 0;        // 2 bits per point: 0, 1 = child, 2 = dropped
-        uint64_t D[ITEMS];          // exact distance to the child edge (argmax key)
-        float U[ITEMS];             // FP32 filter: upper bound of that distance
-        uint32_t ntests = 0, nfall = 0, ncand = 0;
+        if (ti.single) {
+            // 2a. one segment covers the tile: its geometry is uniform
+            const int ux = ti.ux, uy = ti.uy, fx = ti.fx, fy = ti.fy, vx = ti.vx, vy = ti.vy;
+            const int e0x = fx - ux, e0y = fy - uy, e1x = vx - fx, e1y = vy - fy;
+            Best b0 = best_none(), b1 = best_none();
+            if (MODE == 0) {
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) { D[i] = 0; U[i] = 0.f; }
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) stbits |= 2u << (2 * i);
-
-        for (int w0 = 0; w0 < m; w0 += kSlots) {
-            const int wn = min(kSlots, m - w0);
-            for (int j = tid; j < wn; j += BLOCK) {
-                const SegGeo g = geo[s0 + w0 + j];
-                lgeo[j][0] = g.ux; lgeo[j][1] = g.uy;
-                lgeo[j][2] = g.fx; lgeo[j][3] = g.fy;
-                lgeo[j][4] = g.vx; lgeo[j][5] = g.vy;
-            }
-            for (int j = tid; j < 2 * kSlots; j += BLOCK) {
-                (&k1[0][0])[j] = 0;
-                (&k2[0][0])[j] = ~0ull;
-                (&lm[0][0])[j] = 0;
-            }
-            __syncthreads();
-
-            // 3. classify against u->f and f->v; running max per (slot, child)
-            int cur = -1;
-            uint64_t rb0 = 0, rb1 = 0;     // exact: max distance
-            uint32_t rl0 = 0, rl1 = 0;     // filter: max lower bound (ordered key)
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const int v = VOF(i);
-                const int sl = SLOT(i);
-                if (v >= hi || sl < w0 || sl >= w0 + wn) continue;
-                const int ls = sl - w0;
-                const int ux = lgeo[ls][0], uy = lgeo[ls][1];
-                const int fx = lgeo[ls][2], fy = lgeo[ls][3];
-                const int vx = lgeo[ls][4], vy = lgeo[ls][5];
-                uint32_t st = 2;
-                if (MODE == 0) {
+                for (int i = 0; i < kItems; ++i) {
+                    const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                    if (v >= hi) continue;
                     const int64_t d0 = cross_i64(X[i], Y[i], ux, uy, fx, fy);
+                    uint32_t st = 2;
                     if (d0 > 0) {
                         st = 0;
-                        D[i] = (uint64_t)d0;
+                        best_offer(b0, (uint64_t)d0, X[i], Y[i], I[i], e0x, e0y);
                     } else {
                         const int64_t d1 = cross_i64(X[i], Y[i], fx, fy, vx, vy);
                         if (d1 > 0) {
                             st = 1;
-                            D[i] = (uint64_t)d1;
+                            best_offer(b1, (uint64_t)d1, X[i], Y[i], I[i], e1x, e1y);
                         }
                     }
-                } else {
-                    float B0, B1;
+                    stbits ^= (st ^ 2u) << (2 * i);
+                }
+            } else {
+                float l0 = -INFINITY, l1 = -INFINITY;
+#pragma unroll
+                for (int i = 0; i < kItems; ++i) {
+                    const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                    if (v >= hi) continue;
+                    float B0;
                     const float e0 = cross_f32(X[i], Y[i], ux, uy, fx, fy, B0);
                     ntests++;
                     bool out0;
                     if (e0 > B0) out0 = true;
                     else if (e0 < -B0) out0 = false;
                     else { nfall++; out0 = cross_i64(X[i], Y[i], ux, uy, fx, fy) > 0; }
+                    uint32_t st = 2;
                     if (out0) {
                         st = 0;
-                        U[i] = __fadd_rn(e0, 2.f * B0);
-                        const float L = __fsub_rn(e0, 2.f * B0);
-                        if (sl != cur) {
-                            if (cur >= 0) {
-                                if (rl0) atomicMax(&lm[0][cur - w0], rl0);
-                                if (rl1) atomicMax(&lm[1][cur - w0], rl1);
-                            }
-                            cur = sl; rl0 = 0; rl1 = 0;
-                        }
-                        rl0 = max(rl0, fkey(L));
+                        l0 = fmaxf(l0, __fsub_rn(e0, 2.f * B0));
                     } else {
+                        float B1;
                         const float e1 = cross_f32(X[i], Y[i], fx, fy, vx, vy, B1);
                         ntests++;
                         bool out1;
@@ -582,132 +664,228 @@ __global__ __launch_bounds__(BLOCK) void k_round(Ws2 ws, int32_t r, const int32_
                         else { nfall++; out1 = cross_i64(X[i], Y[i], fx, fy, vx, vy) > 0; }
                         if (out1) {
                             st = 1;
-                            U[i] = __fadd_rn(e1, 2.f * B1);
-                            const float L = __fsub_rn(e1, 2.f * B1);
-                            if (sl != cur) {
-                                if (cur >= 0) {
-                                    if (rl0) atomicMax(&lm[0][cur - w0], rl0);
-                                    if (rl1) atomicMax(&lm[1][cur - w0], rl1);
-                                }
-                                cur = sl; rl0 = 0; rl1 = 0;
-                            }
-                            rl1 = max(rl1, fkey(L));
+                            l1 = fmaxf(l1, __fsub_rn(e1, 2.f * B1));
                         }
                     }
+                    stbits ^= (st ^ 2u) << (2 * i);
                 }
-                stbits = (stbits & ~(3u << (2 * i))) | (st << (2 * i));
-                if (MODE == 0 && st < 2) {
-                    if (sl != cur) {
-                        if (cur >= 0) {
-                            if (rb0) atomicMax(&k1[0][cur - w0], rb0);
-                            if (rb1) atomicMax(&k1[1][cur - w0], rb1);
-                        }
-                        cur = sl; rb0 = 0; rb1 = 0;
-                    }
-                    if (st == 0) rb0 = max(rb0, D[i]); else rb1 = max(rb1, D[i]);
+                // the best lower bound of each child over the tile
+                l0 = wave_max_f(l0);
+                l1 = wave_max_f(l1);
+                if (lane == 0) { sm->Mw[wv][0] = l0; sm->Mw[wv][1] = l1; }
+                __syncthreads();
+                float M0 = sm->Mw[0][0], M1 = sm->Mw[0][1];
+#pragma unroll
+                for (int w = 1; w < kNW; ++w) { M0 = fmaxf(M0, sm->Mw[w][0]); M1 = fmaxf(M1, sm->Mw[w][1]); }
+                // only points whose upper bound reaches it can be the argmax
+#pragma unroll
+                for (int i = 0; i < kItems; ++i) {
+                    const uint32_t st = (stbits >> (2 * i)) & 3u;
+                    if (st > 1) continue;
+                    float B;
+                    const float e = st == 0 ? cross_f32(X[i], Y[i], ux, uy, fx, fy, B)
+                                            : cross_f32(X[i], Y[i], fx, fy, vx, vy, B);
+                    const float U = __fadd_rn(e, 2.f * B);
+                    if (U < (st == 0 ? M0 : M1)) continue;
+                    ncand++;
+                    if (st == 0)
+                        best_offer(b0, (uint64_t)cross_i64(X[i], Y[i], ux, uy, fx, fy), X[i], Y[i], I[i], e0x, e0y);
+                    else
+                        best_offer(b1, (uint64_t)cross_i64(X[i], Y[i], fx, fy, vx, vy), X[i], Y[i], I[i], e1x, e1y);
                 }
             }
-            if (cur >= 0) {
-                if (MODE == 0) {
-                    if (rb0) atomicMax(&k1[0][cur - w0], rb0);
-                    if (rb1) atomicMax(&k1[1][cur - w0], rb1);
-                } else {
-                    if (rl0) atomicMax(&lm[0][cur - w0], rl0);
-                    if (rl1) atomicMax(&lm[1][cur - w0], rl1);
+            wave_best(b0);
+            wave_best(b1);
+            if (lane == 0) { sm->red[wv][0] = b0; sm->red[wv][1] = b1; }
+            __syncthreads();
+            if (tid == 0) {
+                for (int w = 1; w < kNW; ++w) {
+                    best_merge(b0, sm->red[w][0]);
+                    best_merge(b1, sm->red[w][1]);
                 }
+                const int g = gbase + s0;
+                const bool inside = ti.start >= lo && ti.end <= hi;
+                if (inside) { ws.adir[g * 2 + 0] = b0; ws.adir[g * 2 + 1] = b1; }
+                ws.recF[tile * 2 + 0] = b0; ws.recF[tile * 2 + 1] = b1;
+                ws.recL[tile * 2 + 0] = b0; ws.recL[tile * 2 + 1] = b1;
+                sm->sstart[0] = ti.start;
+                sm->sstart[1] = ti.end;
+            }
+        } else {
+            // 2b. several segments: starts into LDS, per-slot reductions
+            const SegGeo *geo = ws.geo(p, R);
+            if (tid == 0) sm->s_m = 0;
+            __syncthreads();
+            for (int b = 0; b <= kTile; b += kBlock) {
+                const int j = b + tid;
+                bool in = false;
+                if (j <= kTile) {
+                    const int si = s0 + j;
+                    const int st = si < SR ? geo[si].start : NR;
+                    sm->sstart[j] = st;
+                    in = st < hi;
+                }
+                const int cnt = __syncthreads_count(in);
+                if (tid == 0) sm->s_m += cnt;
+                if (cnt < kBlock) break;
             }
             __syncthreads();
-
-            if (MODE != 0) {
-                // 3b. filter: points whose upper bound reaches the best lower
-                // bound are the only possible argmax; they get exact keys
-                cur = -1;
-                uint64_t cb0 = 0, cb1 = 0;
+            const int m = sm->s_m;
 #pragma unroll
-                for (int i = 0; i < ITEMS; ++i) {
-                    const int v = VOF(i);
-                    const int sl = SLOT(i);
+            for (int i = 0; i < kItems; i += 2) {
+                const int va = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                const int sa = (va >= hi) ? 0 : slot_of(sm->sstart, m, va);
+                const int sb = (va + 1 >= hi) ? 0 : slot_of(sm->sstart, m, va + 1);
+                slotpk[i >> 1] = (uint32_t)sa | ((uint32_t)sb << 16);
+            }
+            for (int w0 = 0; w0 < m; w0 += kSlots) {
+                const int wn = min(kSlots, m - w0);
+                for (int j = tid; j < wn; j += kBlock) {
+                    const SegGeo g = geo[s0 + w0 + j];
+                    sm->lgeo[j][0] = g.ux; sm->lgeo[j][1] = g.uy;
+                    sm->lgeo[j][2] = g.fx; sm->lgeo[j][3] = g.fy;
+                    sm->lgeo[j][4] = g.vx; sm->lgeo[j][5] = g.vy;
+                }
+                for (int j = tid; j < 2 * kSlots; j += kBlock) {
+                    (&sm->k1[0][0])[j] = 0;
+                    (&sm->k2[0][0])[j] = ~0ull;
+                    (&sm->lm[0][0])[j] = 0;
+                }
+                __syncthreads();
+                // classify; exact distances of survivors (exact mode) into LDS
+#pragma unroll
+                for (int i = 0; i < kItems; ++i) {
+                    const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                    const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
+                    if (v >= hi || sl < w0 || sl >= w0 + wn) continue;
+                    const int ls = sl - w0;
+                    const int ux = sm->lgeo[ls][0], uy = sm->lgeo[ls][1];
+                    const int fx = sm->lgeo[ls][2], fy = sm->lgeo[ls][3];
+                    const int vx = sm->lgeo[ls][4], vy = sm->lgeo[ls][5];
+                    const int e = v - lo;
+                    uint32_t st = 2;
+                    if (MODE == 0) {
+                        const int64_t d0 = cross_i64(X[i], Y[i], ux, uy, fx, fy);
+                        if (d0 > 0) {
+                            st = 0;
+                            sm->Dl[e] = (uint64_t)d0;
+                            atomicMax(&sm->k1[0][ls], (uint64_t)d0);
+                        } else {
+                            const int64_t d1 = cross_i64(X[i], Y[i], fx, fy, vx, vy);
+                            if (d1 > 0) {
+                                st = 1;
+                                sm->Dl[e] = (uint64_t)d1;
+                                atomicMax(&sm->k1[1][ls], (uint64_t)d1);
+                            }
+                        }
+                    } else {
+                        float B0;
+                        const float e0 = cross_f32(X[i], Y[i], ux, uy, fx, fy, B0);
+                        ntests++;
+                        bool out0;
+                        if (e0 > B0) out0 = true;
+                        else if (e0 < -B0) out0 = false;
+                        else { nfall++; out0 = cross_i64(X[i], Y[i], ux, uy, fx, fy) > 0; }
+                        if (out0) {
+                            st = 0;
+                            atomicMax(&sm->lm[0][ls], fkey(__fsub_rn(e0, 2.f * B0)));
+                        } else {
+                            float B1;
+                            const float e1 = cross_f32(X[i], Y[i], fx, fy, vx, vy, B1);
+                            ntests++;
+                            bool out1;
+                            if (e1 > B1) out1 = true;
+                            else if (e1 < -B1) out1 = false;
+                            else { nfall++; out1 = cross_i64(X[i], Y[i], fx, fy, vx, vy) > 0; }
+                            if (out1) {
+                                st = 1;
+                                atomicMax(&sm->lm[1][ls], fkey(__fsub_rn(e1, 2.f * B1)));
+                            }
+                        }
+                    }
+                    stbits ^= (st ^ 2u) << (2 * i);
+                }
+                __syncthreads();
+                if (MODE != 0) {
+                    // candidates of the argmax get exact distances
+#pragma unroll
+                    for (int i = 0; i < kItems; ++i) {
+                        const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                        const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
+                        const uint32_t st = (stbits >> (2 * i)) & 3u;
+                        if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
+                        const int ls = sl - w0;
+                        const int ax = st == 0 ? sm->lgeo[ls][0] : sm->lgeo[ls][2];
+                        const int ay = st == 0 ? sm->lgeo[ls][1] : sm->lgeo[ls][3];
+                        const int bx = st == 0 ? sm->lgeo[ls][2] : sm->lgeo[ls][4];
+                        const int by = st == 0 ? sm->lgeo[ls][3] : sm->lgeo[ls][5];
+                        float B;
+                        const float e = cross_f32(X[i], Y[i], ax, ay, bx, by, B);
+                        uint64_t d = 0;
+                        if (fkey(__fadd_rn(e, 2.f * B)) >= sm->lm[st][ls]) {
+                            ncand++;
+                            d = (uint64_t)cross_i64(X[i], Y[i], ax, ay, bx, by);
+                            atomicMax(&sm->k1[st][ls], d);
+                        }
+                        sm->Dl[v - lo] = d;
+                    }
+                    __syncthreads();
+                }
+                // tie-break among the farthest points, then the winner
+#pragma unroll
+                for (int i = 0; i < kItems; ++i) {
+                    const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                    const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
                     const uint32_t st = (stbits >> (2 * i)) & 3u;
                     if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
                     const int ls = sl - w0;
-                    if (fkey(U[i]) < lm[st][ls]) continue;
-                    ncand++;
-                    int64_t d;
-                    if (st == 0) d = cross_i64(X[i], Y[i], lgeo[ls][0], lgeo[ls][1], lgeo[ls][2], lgeo[ls][3]);
-                    else d = cross_i64(X[i], Y[i], lgeo[ls][2], lgeo[ls][3], lgeo[ls][4], lgeo[ls][5]);
-                    D[i] = (uint64_t)d;
-                    if (sl != cur) {
-                        if (cur >= 0) {
-                            if (cb0) atomicMax(&k1[0][cur - w0], cb0);
-                            if (cb1) atomicMax(&k1[1][cur - w0], cb1);
-                        }
-                        cur = sl; cb0 = 0; cb1 = 0;
-                    }
-                    if (st == 0) cb0 = max(cb0, D[i]); else cb1 = max(cb1, D[i]);
+                    if (sm->Dl[v - lo] != sm->k1[st][ls]) continue;
+                    const int ex = st == 0 ? sm->lgeo[ls][2] - sm->lgeo[ls][0] : sm->lgeo[ls][4] - sm->lgeo[ls][2];
+                    const int ey = st == 0 ? sm->lgeo[ls][3] - sm->lgeo[ls][1] : sm->lgeo[ls][5] - sm->lgeo[ls][3];
+                    atomicMin(&sm->k2[st][ls], tie_key(X[i], Y[i], I[i], ex, ey));
                 }
-                if (cur >= 0) {
-                    if (cb0) atomicMax(&k1[0][cur - w0], cb0);
-                    if (cb1) atomicMax(&k1[1][cur - w0], cb1);
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < kItems; ++i) {
+                    const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                    const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
+                    const uint32_t st = (stbits >> (2 * i)) & 3u;
+                    if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
+                    const int ls = sl - w0;
+                    if (sm->Dl[v - lo] != sm->k1[st][ls]) continue;
+                    const int ex = st == 0 ? sm->lgeo[ls][2] - sm->lgeo[ls][0] : sm->lgeo[ls][4] - sm->lgeo[ls][2];
+                    const int ey = st == 0 ? sm->lgeo[ls][3] - sm->lgeo[ls][1] : sm->lgeo[ls][5] - sm->lgeo[ls][3];
+                    if (tie_key(X[i], Y[i], I[i], ex, ey) == sm->k2[st][ls]) {
+                        sm->res[st][ls][0] = X[i]; sm->res[st][ls][1] = Y[i]; sm->res[st][ls][2] = I[i];
+                    }
+                }
+                __syncthreads();
+                // whole segments directly, the tile's first and last as partials
+                for (int j = tid; j < wn; j += kBlock) {
+                    const int sl = w0 + j;
+                    const int g = gbase + s0 + sl;
+                    const bool inside = sm->sstart[sl] >= lo && sm->sstart[sl + 1] <= hi;
+                    for (int c = 0; c < 2; ++c) {
+                        Best b;
+                        b.key1 = sm->k1[c][j];
+                        b.key2 = sm->k2[c][j];
+                        b.x = b.key1 ? sm->res[c][j][0] : 0;
+                        b.y = b.key1 ? sm->res[c][j][1] : 0;
+                        b.idx = b.key1 ? sm->res[c][j][2] : 0;
+                        b.pad = 0;
+                        if (inside) ws.adir[g * 2 + c] = b;
+                        if (sl == 0) ws.recF[tile * 2 + c] = b;
+                        if (sl == m - 1) ws.recL[tile * 2 + c] = b;
+                    }
                 }
                 __syncthreads();
             }
-
-            // 4. tie-break among the farthest points, then the winner
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const int v = VOF(i);
-                const int sl = SLOT(i);
-                const uint32_t st = (stbits >> (2 * i)) & 3u;
-                if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
-                const int ls = sl - w0;
-                if (D[i] != k1[st][ls]) continue;
-                const int ex = st == 0 ? lgeo[ls][2] - lgeo[ls][0] : lgeo[ls][4] - lgeo[ls][2];
-                const int ey = st == 0 ? lgeo[ls][3] - lgeo[ls][1] : lgeo[ls][5] - lgeo[ls][3];
-                atomicMin(&k2[st][ls], tie_key(X[i], Y[i], I[i], ex, ey));
-            }
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const int v = VOF(i);
-                const int sl = SLOT(i);
-                const uint32_t st = (stbits >> (2 * i)) & 3u;
-                if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
-                const int ls = sl - w0;
-                if (D[i] != k1[st][ls]) continue;
-                const int ex = st == 0 ? lgeo[ls][2] - lgeo[ls][0] : lgeo[ls][4] - lgeo[ls][2];
-                const int ey = st == 0 ? lgeo[ls][3] - lgeo[ls][1] : lgeo[ls][5] - lgeo[ls][3];
-                if (tie_key(X[i], Y[i], I[i], ex, ey) == k2[st][ls]) {
-                    res[st][ls][0] = X[i]; res[st][ls][1] = Y[i]; res[st][ls][2] = I[i];
-                }
-            }
-            __syncthreads();
-
-            // 5. per-slot results: whole segments directly, the first and the
-            // last segment of the tile as partial records
-            for (int j = tid; j < wn; j += BLOCK) {
-                const int sl = w0 + j;
-                const int g = gbase + s0 + sl;
-                const bool inside = sstart[sl] >= lo && sstart[sl + 1] <= hi;
-                for (int c = 0; c < 2; ++c) {
-                    Best b;
-                    b.key1 = k1[c][j];
-                    b.key2 = k2[c][j];
-                    b.x = b.key1 ? res[c][j][0] : 0;
-                    b.y = b.key1 ? res[c][j][1] : 0;
-                    b.idx = b.key1 ? res[c][j][2] : 0;
-                    b.pad = 0;
-                    if (inside) ws.adir[g * 2 + c] = b;
-                    if (sl == 0) ws.recF[tile * 2 + c] = b;
-                    if (sl == m - 1) ws.recL[tile * 2 + c] = b;
-                }
-            }
-            __syncthreads();
         }
 
-        // 6. ranks of the survivors inside the tile (point order), per child
-        uint32_t cnt[Q], tot[Q];
+        // 3. ranks of the survivors inside the tile (point order), per child
+        uint32_t cnt[kQ], tot[kQ];
 #pragma unroll
-        for (int qq = 0; qq < Q; ++qq) {
+        for (int qq = 0; qq < kQ; ++qq) {
             uint32_t c = 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -716,88 +894,94 @@ __global__ __launch_bounds__(BLOCK) void k_round(Ws2 ws, int32_t r, const int32_
             }
             cnt[qq] = c;
         }
-        block_excl_scan<BLOCK, Q>(cnt, tot, scan_scr);
-        uint32_t rowbase[Q];
+        block_excl_scan<kBlock, kQ>(cnt, tot, sm->scan);
+        uint32_t rowbase[kQ];
         uint32_t acc = 0;
 #pragma unroll
-        for (int qq = 0; qq < Q; ++qq) { rowbase[qq] = acc; acc += tot[qq]; }
+        for (int qq = 0; qq < kQ; ++qq) { rowbase[qq] = acc; acc += tot[qq]; }
         const uint32_t c0 = acc & 0xffffu, c1 = acc >> 16;
 
-        // 7. decoupled look-back: global offsets of this tile's survivors
+        // 4. decoupled look-back: global offsets of this tile's survivors
         if (wv == 0) {
-            const uint64_t ex = lookback_excl(ws.st2[p], tile, pack2(c0, c1), &ctl->error);
-            if (lane == 0) s_ex = ex;
+            const uint64_t ex = lookback_excl(ws.st2(p), tile, pack2(c0, c1), &ctl->error);
+            if (lane == 0) sm->s_ex = ex;
         }
         __syncthreads();
-        const uint32_t E0 = unpackA(s_ex), E1 = unpackB(s_ex);
+        const uint32_t E0 = unpackA(sm->s_ex), E1 = unpackB(sm->s_ex);
 
-        // 8. scatter the survivors into the two child regions; segment
+        // 5. scatter the survivors into the two child regions; segment
         // boundaries record their global offsets
-        int32_t *ox0 = ws.px[q][0], *oy0 = ws.py[q][0], *oi0 = ws.pi[q][0];
-        int32_t *ox1 = ws.px[q][1], *oy1 = ws.py[q][1], *oi1 = ws.pi[q][1];
+        int32_t *ox0 = ws.px(q, 0), *oy0 = ws.py(q, 0), *oi0 = ws.pi(q, 0);
+        int32_t *ox1 = ws.px(q, 1), *oy1 = ws.py(q, 1), *oi1 = ws.pi(q, 1);
+        const uint32_t cap = (uint32_t)ws.cap_pts;
+        bool oob = false;
 #pragma unroll
-        for (int qq = 0; qq < Q; ++qq) {
+        for (int qq = 0; qq < kQ; ++qq) {
             uint32_t run = rowbase[qq] + cnt[qq];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int i = qq * 4 + j;
-                const int v = VOF(i);
+                const int v = lo + qq * kBlock * 4 + tid * 4 + j;
                 const uint32_t st = (stbits >> (2 * i)) & 3u;
                 const uint32_t e0 = E0 + (run & 0xffffu);
                 const uint32_t e1 = E1 + (run >> 16);
                 if (v < hi) {
-                    const int sl = SLOT(i);
+                    const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
                     const int g = gbase + s0 + sl;
-                    if (v == sstart[sl]) ws.pst[g] = make_int2((int)e0, (int)e1);
+                    if (v == sm->sstart[sl]) ws.pst[g] = make_int2((int)e0, (int)e1);
                     if (st == 0) {
-                        if (e0 < (uint32_t)ws.cap_pts) {
-                            ox0[e0] = X[i]; oy0[e0] = Y[i]; oi0[e0] = I[i];
-                        } else {
-                            atomicOr(&ctl->error, kErrInternal);
-                        }
+                        if (e0 < cap) { ox0[e0] = X[i]; oy0[e0] = Y[i]; oi0[e0] = I[i]; } else oob = true;
                     } else if (st == 1) {
-                        if (e1 < (uint32_t)ws.cap_pts) {
-                            ox1[e1] = X[i]; oy1[e1] = Y[i]; oi1[e1] = I[i];
-                        } else {
-                            atomicOr(&ctl->error, kErrInternal);
-                        }
+                        if (e1 < cap) { ox1[e1] = X[i]; oy1[e1] = Y[i]; oi1[e1] = I[i]; } else oob = true;
                     }
                     const uint32_t run2 = run + (st == 0 ? 1u : (st == 1 ? 0x10000u : 0u));
-                    if (v == sstart[sl + 1] - 1)
+                    if (v == sm->sstart[sl + 1] - 1)
                         ws.pen[g] = make_int2((int)(E0 + (run2 & 0xffffu)), (int)(E1 + (run2 >> 16)));
                     run = run2;
                 }
             }
         }
-        if (MODE != 0) {
-            const uint32_t a = wave_sum(ntests), b = wave_sum(nfall), c = wave_sum(ncand);
-            if (lane == 0) {
-                atomicAdd(&ctl->filter_tests, (unsigned long long)a);
-                atomicAdd(&ctl->filter_fallbacks, (unsigned long long)b);
-                atomicAdd(&ctl->candidates, (unsigned long long)c);
-            }
-            ntests = nfall = ncand = 0;
-        }
+        if (oob) atomicOr(&ctl->error, kErrInternal);
         if (tile == ntiles - 1 && tid == 0) {
             rn->n[0] = (int32_t)(E0 + c0);
             rn->n[1] = (int32_t)(E1 + c1);
-            atomicAdd(&ctl->points_in, (unsigned long long)(n0 + n1));
-            atomicAdd(&ctl->points_out, (unsigned long long)(E0 + c0 + E1 + c1));
-            if (INIT) atomicAdd(&ctl->first_in, (unsigned long long)(n0 + n1));
-            atomicAdd(&ctl->round_launches_work, 1ull);
+            if (INIT) {
+                ctl->first_in += (unsigned long long)(n0 + n1);
+                ctl->first_out += (unsigned long long)(E0 + c0 + E1 + c1);
+            } else {
+                ctl->points_in += (unsigned long long)(n0 + n1);
+                ctl->points_out += (unsigned long long)(E0 + c0 + E1 + c1);
+            }
+            ctl->rounds_with_work += 1ull;
         }
         __syncthreads();
+        tile = sm->s_next[it & 1];
+        ++it;
+    }
+    if (MODE != 0) {
+        if (tid == 0) { sm->stat[0] = 0; sm->stat[1] = 0; sm->stat[2] = 0; }
+        __syncthreads();
+        const uint32_t t = wave_sum(ntests), f = wave_sum(nfall), c = wave_sum(ncand);
+        if (lane == 0) {
+            atomicAdd(&sm->stat[0], t);
+            atomicAdd(&sm->stat[1], f);
+            atomicAdd(&sm->stat[2], c);
+        }
+        __syncthreads();
+        if (tid == 0 && sm->stat[0]) {
+            atomicAdd(&ctl->filter_tests, (unsigned long long)sm->stat[0]);
+            atomicAdd(&ctl->filter_fallbacks, (unsigned long long)sm->stat[1]);
+            atomicAdd(&ctl->candidates, (unsigned long long)sm->stat[2]);
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// The segment kernel: hull insertion, argmax finish, next segment table.
+// segments: hull insertion, multi-tile argmax, next segment table
 // ---------------------------------------------------------------------------
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_segments(Ws2 ws, int32_t r) {
-    constexpr int NW = BLOCK / kWave;
+__device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a, int r, char *smem) {
     Control *ctl = ws.ctl;
-    if (ctl->error) return;
+    SegSmem *sm = reinterpret_cast<SegSmem *>(smem);
     const int p = r & 1, q = p ^ 1;
     RoundState *rs = &ctl->rs[p];
     RoundState *rn = &ctl->rs[q];
@@ -805,52 +989,40 @@ __global__ __launch_bounds__(BLOCK) void k_segments(Ws2 ws, int32_t r) {
     const int Stot = S0 + S1;
     const int hbase = rs->hbase;
     const int nt0 = (rs->n[0] + kTile - 1) / kTile;
-    const int nsegt = (Stot + BLOCK - 1) / BLOCK;
-    const int tid = threadIdx.x;
-    const int lane = lane_id();
-    const int wv = tid / kWave;
+    const int Nn0 = rn->n[0], Nn1 = rn->n[1];
+    const int nsegt = (Stot + kSegBlock - 1) / kSegBlock;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
 
     if (blockIdx.x == 0 && tid == 0) rn->seg_ctr = 0;
-    for (int i = blockIdx.x * BLOCK + tid; i < 2 * nsegt + 4 && i < ws.s4cap; i += gridDim.x * BLOCK)
-        ws.st4[q][i] = 0;
-    if (Stot == 0) {
+    for (int i = blockIdx.x * kSegBlock + tid; i < 2 * nsegt + 4 && i < ws.s4cap; i += gridDim.x * kSegBlock)
+        ws.st4(q)[i] = 0;
+    if (Stot == 0 || ctl->error) {
         if (blockIdx.x == 0 && tid == 0) {
             rn->s[0] = 0; rn->s[1] = 0; rn->hbase = hbase;
         }
         return;
     }
 
-    __shared__ uint32_t scan_scr[2 * NW];
-    __shared__ int32_t s_tile;
-    __shared__ uint64_t s_ex;
-    __shared__ int32_t qn_apex, qn_map;
-    __shared__ int16_t q_apex[BLOCK], q_map[2 * BLOCK];
-    __shared__ int32_t o_t0[BLOCK], o_t1[BLOCK];
-    __shared__ int32_t o_mst[2 * BLOCK], o_mlen[2 * BLOCK], o_mid[2 * BLOCK];
-    __shared__ Best red[2][BLOCK];
-    __shared__ Best o_best[2][BLOCK];
-
     while (true) {
         if (tid == 0) {
-            s_tile = (int32_t)atomicAdd(&rs->seg_ctr, 1u);
-            qn_apex = 0;
-            qn_map = 0;
+            sm->s_tile = (int32_t)atomicAdd(&rs->seg_ctr, 1u);
+            sm->qn_apex = 0;
+            sm->qn_map = 0;
         }
         __syncthreads();
-        const int tile = s_tile;
+        const int tile = sm->s_tile;
         if (tile >= nsegt) break;
-        const int g = tile * BLOCK + tid;
+        const int g = tile * kSegBlock + tid;
         const bool valid = g < Stot;
         const int R = g < S0 ? 0 : 1;
         const int s = g - (R ? S0 : 0);
         SegGeo G = {};
         SegTop Tp = {};
         int2 ps = make_int2(0, 0), pe = make_int2(0, 0);
-        int c0 = 0, c1 = 0;
-        int fc = 0;
+        int c0 = 0, c1 = 0, fc = 0;
         if (valid) {
-            G = ws.geo[p][R][s];
-            Tp = ws.top[p][R][s];
+            G = ws.geo(p, R)[s];
+            Tp = ws.top(p, R)[s];
             ps = ws.pst[g];
             pe = ws.pen[g];
             c0 = pe.x - ps.x;
@@ -871,23 +1043,23 @@ __global__ __launch_bounds__(BLOCK) void k_segments(Ws2 ws, int32_t r) {
         }
         const bool has0 = valid && c0 > 0, has1 = valid && c1 > 0;
         uint32_t v[2] = {has0 ? 1u : 0u, has1 ? 1u : 0u}, tot[2];
-        block_excl_scan<BLOCK, 2>(v, tot, scan_scr);
+        block_excl_scan<kSegBlock, 2>(v, tot, sm->scan);
         if (wv == 0) {
-            const uint64_t ex = lookback_excl(ws.st4[p], tile, pack2(tot[0], tot[1]), &ctl->error);
-            if (lane == 0) s_ex = ex;
+            const uint64_t ex = lookback_excl(ws.st4(p), tile, pack2(tot[0], tot[1]), &ctl->error);
+            if (lane == 0) sm->s_ex = ex;
         }
         __syncthreads();
-        const int id0 = (int)(unpackA(s_ex) + v[0]);
-        const int id1 = (int)(unpackB(s_ex) + v[1]);
-        if ((has0 && id0 >= ws.scap) || (has1 && id1 >= ws.scap)) atomicOr(&ctl->error, kErrSegCap);
+        const int id0 = (int)(unpackA(sm->s_ex) + v[0]);
+        const int id1 = (int)(unpackB(sm->s_ex) + v[1]);
+        const bool ok0 = has0 && id0 < ws.scap, ok1 = has1 && id1 < ws.scap;
+        if ((has0 && !ok0) || (has1 && !ok1)) atomicOr(&ctl->error, kErrSegCap);
 
         // apexes of the two children
-        Best b0, b1;
-        b0.key1 = 0; b0.key2 = ~0ull; b0.x = b0.y = b0.idx = b0.pad = 0;
-        b1 = b0;
+        Best b0 = best_none(), b1 = best_none();
         const int t0 = (R ? nt0 : 0) + G.start / kTile;
         const int t1 = (R ? nt0 : 0) + (G.start + G.len - 1) / kTile;
-        if (valid && (has0 || has1)) {
+        const bool want = valid && (has0 || has1);
+        if (want) {
             if (t0 == t1) {
                 b0 = ws.adir[g * 2 + 0];
                 b1 = ws.adir[g * 2 + 1];
@@ -899,259 +1071,270 @@ __global__ __launch_bounds__(BLOCK) void k_segments(Ws2 ws, int32_t r) {
                     best_merge(b1, ws.recF[t * 2 + 1]);
                 }
             } else {
-                const int qi = atomicAdd(&qn_apex, 1);
-                q_apex[qi] = (int16_t)tid;
-                o_t0[tid] = t0;
-                o_t1[tid] = t1;
+                const int qi = atomicAdd(&sm->qn_apex, 1);
+                sm->q_apex[qi] = (int16_t)tid;
+                sm->o_t0[tid] = t0;
+                sm->o_t1[tid] = t1;
             }
         }
         __syncthreads();
-        const int nqa = qn_apex;
+        const int nqa = sm->qn_apex;
         for (int qi = 0; qi < nqa; ++qi) {
-            const int own = q_apex[qi];
-            const int a0 = o_t0[own], a1 = o_t1[own];
-            for (int c = 0; c < 2; ++c) {
-                Best acc;
-                acc.key1 = 0; acc.key2 = ~0ull; acc.x = acc.y = acc.idx = acc.pad = 0;
-                for (int t = a0 + tid; t <= a1; t += BLOCK)
-                    best_merge(acc, t == a0 ? ws.recL[t * 2 + c] : ws.recF[t * 2 + c]);
-                red[c][tid] = acc;
-            }
-            __syncthreads();
-            for (int w = BLOCK / 2; w > 0; w >>= 1) {
-                if (tid < w) {
-                    for (int c = 0; c < 2; ++c) {
-                        const Best o = red[c][tid + w];
-                        if (best_better(o, red[c][tid])) red[c][tid] = o;
-                    }
-                }
-                __syncthreads();
-            }
-            if (tid == 0) {
-                o_best[0][own] = red[0][0];
-                o_best[1][own] = red[1][0];
-            }
-            __syncthreads();
-        }
-        if (valid && (has0 || has1) && t1 - t0 > 8) {
-            b0 = o_best[0][tid];
-            b1 = o_best[1][tid];
+            const int own = sm->q_apex[qi];
+            const int a0 = sm->o_t0[own], a1 = sm->o_t1[own];
+            const Best r0 = block_merge_tiles(ws.recF, ws.recL, a0, a1, 0, sm->red);
+            const Best r1 = block_merge_tiles(ws.recF, ws.recL, a0, a1, 1, sm->red);
+            if (tid == own) { b0 = r0; b1 = r1; }
         }
 
         // child segments of the next round
-        if (has0 && id0 < ws.scap) {
+        if (ok0) {
             SegGeo cg;
             cg.start = ps.x; cg.len = c0;
             cg.ux = G.ux; cg.uy = G.uy;
             cg.fx = b0.x; cg.fy = b0.y;
             cg.vx = G.fx; cg.vy = G.fy;
-            ws.geo[q][0][id0] = cg;
+            ws.geo(q, 0)[id0] = cg;
             SegTop ct;
             ct.fidx = b0.idx; ct.uc = Tp.uc; ct.vc = fc; ct.inst = Tp.inst;
-            ws.top[q][0][id0] = ct;
+            ws.top(q, 0)[id0] = ct;
         }
-        if (has1 && id1 < ws.scap) {
+        if (ok1) {
             SegGeo cg;
             cg.start = ps.y; cg.len = c1;
             cg.ux = G.fx; cg.uy = G.fy;
             cg.fx = b1.x; cg.fy = b1.y;
             cg.vx = G.vx; cg.vy = G.vy;
-            ws.geo[q][1][id1] = cg;
+            ws.geo(q, 1)[id1] = cg;
             SegTop ct;
             ct.fidx = b1.idx; ct.uc = fc; ct.vc = Tp.vc; ct.inst = Tp.inst;
-            ws.top[q][1][id1] = ct;
+            ws.top(q, 1)[id1] = ct;
         }
-        // tile maps of the next round: tiles whose first point lies in a child
+        // tile records of the next round: tiles whose first point lies in a
+        // child; a child over many tiles is written by the whole block
         for (int c = 0; c < 2; ++c) {
-            const bool h = c == 0 ? has0 : has1;
+            const bool ok = c == 0 ? ok0 : ok1;
+            if (!ok) continue;
             const int id = c == 0 ? id0 : id1;
-            if (!h || id >= ws.scap) continue;
             const int st = c == 0 ? ps.x : ps.y;
             const int ln = c == 0 ? c0 : c1;
             const int ka = (st + kTile - 1) / kTile;
             const int kb = (st + ln + kTile - 1) / kTile;
-            if (kb - ka <= 8) {
-                for (int kk = ka; kk < kb; ++kk) ws.tmap[q][c][kk] = id;
+            if (kb - ka <= 4) {
+                TileInfo ti;
+                ti.seg = id;
+                ti.start = st;
+                ti.end = st + ln;
+                ti.ux = c == 0 ? G.ux : G.fx; ti.uy = c == 0 ? G.uy : G.fy;
+                ti.fx = c == 0 ? b0.x : b1.x; ti.fy = c == 0 ? b0.y : b1.y;
+                ti.vx = c == 0 ? G.fx : G.vx; ti.vy = c == 0 ? G.fy : G.vy;
+                ti.pad0 = ti.pad1 = 0;
+                for (int kk = ka; kk < kb; ++kk) {
+                    ti.single = ti.end >= min((kk + 1) * kTile, c == 0 ? Nn0 : Nn1) ? 1 : 0;
+                    ws.tinfo(q, c)[kk] = ti;
+                }
             } else {
-                const int qi = atomicAdd(&qn_map, 1);
-                q_map[qi] = (int16_t)(tid * 2 + c);
-                o_mst[tid * 2 + c] = ka;
-                o_mlen[tid * 2 + c] = kb;
-                o_mid[tid * 2 + c] = id;
+                const int qi = atomicAdd(&sm->qn_map, 1);
+                sm->q_map[qi] = (int16_t)(tid * 2 + c);
+                sm->o_ka[tid * 2 + c] = ka;
+                sm->o_kb[tid * 2 + c] = kb;
+                sm->o_id[tid * 2 + c] = id;
             }
         }
         __syncthreads();
-        const int nqm = qn_map;
+        const int nqm = sm->qn_map;
         for (int qi = 0; qi < nqm; ++qi) {
-            const int o = q_map[qi];
+            const int o = sm->q_map[qi];
             const int c = o & 1;
-            const int ka = o_mst[o], kb = o_mlen[o], id = o_mid[o];
-            for (int kk = ka + tid; kk < kb; kk += BLOCK) ws.tmap[q][c][kk] = id;
+            const int ka = sm->o_ka[o], kb = sm->o_kb[o], id = sm->o_id[o];
+            // the owner wrote the child's table entry before the barrier
+            const SegGeo cg = ws.geo(q, c)[id];
+            TileInfo ti;
+            ti.seg = id;
+            ti.start = cg.start;
+            ti.end = cg.start + cg.len;
+            ti.ux = cg.ux; ti.uy = cg.uy; ti.fx = cg.fx; ti.fy = cg.fy; ti.vx = cg.vx; ti.vy = cg.vy;
+            ti.pad0 = ti.pad1 = 0;
+            for (int kk = ka + tid; kk < kb; kk += kSegBlock) {
+                ti.single = ti.end >= min((kk + 1) * kTile, c == 0 ? Nn0 : Nn1) ? 1 : 0;
+                ws.tinfo(q, c)[kk] = ti;
+            }
         }
         if (tile == nsegt - 1 && tid == 0) {
-            const int n0n = (int)(unpackA(s_ex) + tot[0]);
-            const int n1n = (int)(unpackB(s_ex) + tot[1]);
-            rn->s[0] = n0n;
-            rn->s[1] = n1n;
+            const int n0n = (int)(unpackA(sm->s_ex) + tot[0]);
+            const int n1n = (int)(unpackB(sm->s_ex) + tot[1]);
+            const bool capbad = hbase + Stot > ws.hcap || n0n > ws.scap || n1n > ws.scap;
+            if (capbad) atomicOr(&ctl->error, kErrHullCap);
+            rn->s[0] = capbad ? 0 : n0n;
+            rn->s[1] = capbad ? 0 : n1n;
             rn->hbase = hbase + Stot;
-            if (hbase + Stot > ws.hcap) atomicOr(&ctl->error, kErrHullCap);
             atomicMax(&ctl->max_segments, n0n + n1n);
-            atomicAdd(&ctl->rounds_done, 1);
+            ctl->rounds_done += 1;
         }
         __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// Output: rank the hull cycles (pointer jumping) and write CCW index lists.
+// output: rank the hull cycles (pointer jumping), CCW index lists
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void rank_init_one(const Ws2 &ws, int x, int32_t &su, int32_t &di) {
+    const int nx = ws.nxt[x];
+    if (nx < 0) { su = x; di = 0; return; }
+    const bool term = (nx == ws.hinst[x]);   // next is the instance's first vertex
+    su = term ? x : nx;
+    di = term ? 0 : 1;
+}
+
+// ---------------------------------------------------------------------------
+// output kernels
+// ---------------------------------------------------------------------------
+// small hulls: pointer jumping in one block's LDS
+__global__ __launch_bounds__(kBlock) void k_rank_small(Ws2 ws, int32_t H, int32_t steps) {
+    __shared__ RankSmem sm;
+    for (int x = threadIdx.x; x < H; x += kBlock) rank_init_one(ws, x, sm.su[x], sm.di[x]);
+    __syncthreads();
+    constexpr int PER = kRankSmallCap / kBlock;
+    for (int itr = 0; itr < steps; ++itr) {
+        int ns[PER], nd[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int x = threadIdx.x + j * kBlock;
+            if (x < H) {
+                const int s = sm.su[x];
+                nd[j] = sm.di[x] + sm.di[s];
+                ns[j] = sm.su[s];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int x = threadIdx.x + j * kBlock;
+            if (x < H) { sm.su[x] = ns[j]; sm.di[x] = nd[j]; }
+        }
+        __syncthreads();
+    }
+    for (int x = threadIdx.x; x < H; x += kBlock) ws.dist(0)[x] = sm.di[x];
+}
+
 __global__ void k_rank_init(Ws2 ws, int32_t H) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= H) return;
-    const int nx = ws.nxt[x];
-    if (nx < 0) { ws.succ[0][x] = x; ws.dist[0][x] = 0; return; }
-    const bool term = (nx == ws.hinst[x]);   // next is the instance's first vertex
-    ws.succ[0][x] = term ? x : nx;
-    ws.dist[0][x] = term ? 0 : 1;
+    if (x < H) rank_init_one(ws, x, ws.succ(0)[x], ws.dist(0)[x]);
 }
 
 __global__ void k_rank_step(Ws2 ws, int32_t H, int32_t src) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= H) return;
-    const int s = ws.succ[src][x];
-    ws.dist[src ^ 1][x] = ws.dist[src][x] + ws.dist[src][s];
-    ws.succ[src ^ 1][x] = ws.succ[src][s];
-}
-
-// small hulls: all pointer jumping in LDS by one block
-template <int BLOCK, int CAP>
-__global__ __launch_bounds__(BLOCK) void k_rank_small(Ws2 ws, int32_t H, int32_t steps) {
-    __shared__ int32_t su[CAP], di[CAP];
-    for (int x = threadIdx.x; x < H; x += BLOCK) {
-        const int nx = ws.nxt[x];
-        if (nx < 0) { su[x] = x; di[x] = 0; continue; }
-        const bool term = (nx == ws.hinst[x]);
-        su[x] = term ? x : nx;
-        di[x] = term ? 0 : 1;
-    }
-    __syncthreads();
-    constexpr int PER = CAP / BLOCK;
-    for (int it = 0; it < steps; ++it) {
-        int ns[PER], nd[PER];
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int x = threadIdx.x + j * BLOCK;
-            if (x < H) {
-                const int s = su[x];
-                nd[j] = di[x] + di[s];
-                ns[j] = su[s];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int x = threadIdx.x + j * BLOCK;
-            if (x < H) { su[x] = ns[j]; di[x] = nd[j]; }
-        }
-        __syncthreads();
-    }
-    for (int x = threadIdx.x; x < H; x += BLOCK) ws.dist[0][x] = di[x];
+    const int s = ws.succ(src)[x];
+    ws.dist(src ^ 1)[x] = ws.dist(src)[x] + ws.dist(src)[s];
+    ws.succ(src ^ 1)[x] = ws.succ(src)[s];
 }
 
 // hull sizes per instance and their exclusive scan (one block)
-__global__ __launch_bounds__(1024) void k_hull_offsets(Ws2 ws, int32_t k, int32_t src,
-                                                       int64_t *hull_offsets) {
-    __shared__ uint32_t scratch[32];
-    __shared__ uint64_t carry;
-    if (threadIdx.x == 0) carry = 0;
+__global__ __launch_bounds__(kBlock) void k_hull_offsets(Ws2 ws, HullArgs a, int32_t src) {
+    __shared__ ScanSmem sm;
+    Control *ctl = ws.ctl;
+    if (threadIdx.x == 0) sm.carry = 0;
     __syncthreads();
-    for (int base = 0; base < k; base += 1024) {
+    for (int base = 0; base < a.k; base += kBlock) {
         const int i = base + (int)threadIdx.x;
         uint32_t h = 0;
-        if (i < k && ws.nxt[i] >= 0) h = (uint32_t)ws.dist[src][i] + 1u;
+        if (i < a.k && ws.nxt[i] >= 0) h = (uint32_t)ws.dist(src)[i] + 1u;
         uint32_t v[1] = {h}, tot[1];
-        block_excl_scan<1024, 1>(v, tot, scratch);
-        if (i < k) hull_offsets[i] = (int64_t)(carry + v[0]);
+        block_excl_scan<kBlock, 1>(v, tot, sm.scratch);
+        if (i < a.k) a.hull_offsets[i] = (int64_t)(sm.carry + v[0]);
         __syncthreads();
-        if (threadIdx.x == 0) carry += tot[0];
+        if (threadIdx.x == 0) sm.carry += tot[0];
         __syncthreads();
     }
-    if (threadIdx.x == 0) hull_offsets[k] = (int64_t)carry;
+    if (threadIdx.x == 0) {
+        a.hull_offsets[a.k] = (int64_t)sm.carry;
+        ctl->h_total = (long long)sm.carry;
+    }
 }
 
-__global__ void k_emit(Ws2 ws, int32_t H, int32_t src, const int64_t *offsets,
-                       const int64_t *hull_offsets, int32_t *hull_idx, int64_t n_total) {
+__global__ void k_emit(Ws2 ws, HullArgs a, int32_t H, int32_t src) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= H) return;
-    if (ws.nxt[x] < 0) return;
+    if (x >= H || ws.nxt[x] < 0) return;
     const int i = ws.hinst[x];
-    const int64_t base = hull_offsets[i];
-    const int64_t h = hull_offsets[i + 1] - base;
-    const int64_t pos = base + (h - 1 - ws.dist[src][x]);
-    if (pos < base || pos >= base + h || pos >= n_total) {
+    const int64_t base = a.hull_offsets[i];
+    const int64_t h = a.hull_offsets[i + 1] - base;
+    const int64_t pos = base + (h - 1 - ws.dist(src)[x]);
+    if (pos < base || pos >= base + h || pos >= a.n) {
         atomicOr(&ws.ctl->error, kErrInternal);
         return;
     }
-    hull_idx[pos] = (int32_t)(ws.V[x] - offsets[i]);
+    a.hull_idx[pos] = (int32_t)(ws.V[x] - a.offsets[i]);
+}
+
+// ---------------------------------------------------------------------------
+// the other kernels: one phase each
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_instances(Ws2 ws, HullArgs a) {
+    __shared__ ScanSmem sm;
+    phase_instances(ws, a, reinterpret_cast<char *>(&sm));
+}
+
+__global__ __launch_bounds__(kBlock) void k_setup(Ws2 ws, HullArgs a) { phase_setup(ws, a); }
+
+__global__ __launch_bounds__(kBlock) void k_extremes(Ws2 ws, HullArgs a) {
+    __shared__ ExtSmem sm;
+    phase_extremes(ws, a, reinterpret_cast<char *>(&sm));
+}
+
+__global__ __launch_bounds__(kBlock) void k_extremes_final(Ws2 ws, HullArgs a) {
+    __shared__ SegSmem sm;
+    phase_extremes_final(ws, a, reinterpret_cast<char *>(&sm));
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_round(Ws2 ws, HullArgs a, int32_t r) {
+    __shared__ RoundSmem sm;
+    if (ws.ctl->setup_error) return;
+    phase_round<MODE>(ws, a, r, reinterpret_cast<char *>(&sm));
+}
+
+__global__ __launch_bounds__(kSegBlock) void k_segments(Ws2 ws, HullArgs a, int32_t r) {
+    __shared__ SegSmem sm;
+    phase_segments(ws, a, r, reinterpret_cast<char *>(&sm));
 }
 
 // ---------------------------------------------------------------------------
 // host-side launch wrappers
 // ---------------------------------------------------------------------------
-hipError_t launch_instances(const Ws2 &ws, const int64_t *offsets, int64_t n_total, int32_t k,
-                            hipStream_t st) {
-    hipLaunchKernelGGL(k_instances, dim3(1), dim3(1024), 0, st, ws, offsets, n_total, k);
+hipError_t launch_setup(const Ws2 &ws, const HullArgs &a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_instances, dim3(1), dim3(kBlock), 0, st, ws, a);
+    hipLaunchKernelGGL(k_setup, dim3(grid), dim3(kBlock), 0, st, ws, a);
     return hipGetLastError();
 }
 
-hipError_t launch_setup(const Ws2 &ws, const int64_t *offsets, int32_t k, int32_t ntiles,
-                        int grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_setup, dim3(grid), dim3(256), 0, st, ws, offsets, k, ntiles);
+hipError_t launch_extremes(const Ws2 &ws, const HullArgs &a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_extremes, dim3(grid), dim3(kBlock), 0, st, ws, a);
+    hipLaunchKernelGGL(k_extremes_final, dim3(std::max(1, std::min(a.k, grid))), dim3(kBlock), 0, st, ws, a);
     return hipGetLastError();
 }
 
-hipError_t launch_extremes(const Ws2 &ws, const int32_t *x, const int32_t *y, int32_t n,
-                           int32_t vec_ok, int grid, int32_t nseg_max, hipStream_t st) {
-    hipLaunchKernelGGL((k_extremes<kBlock, kItems>), dim3(grid), dim3(kBlock), 0, st, ws, x, y, n,
-                       vec_ok);
-    hipLaunchKernelGGL((k_extremes_final<kBlock>), dim3(nseg_max), dim3(kBlock), 0, st, ws);
+hipError_t launch_round(const Ws2 &ws, const HullArgs &a, int mode, int32_t r, int grid,
+                        hipStream_t st) {
+    if (mode == 0)
+        hipLaunchKernelGGL(k_round<0>, dim3(grid), dim3(kBlock), 0, st, ws, a, r);
+    else
+        hipLaunchKernelGGL(k_round<1>, dim3(grid), dim3(kBlock), 0, st, ws, a, r);
     return hipGetLastError();
 }
 
-hipError_t launch_round(const Ws2 &ws, int32_t r, bool init, int mode, const int32_t *x,
-                        const int32_t *y, int32_t vec_ok, int grid, hipStream_t st) {
-    if (init) {
-        if (mode == 0)
-            hipLaunchKernelGGL((k_round<true, 0, kBlock, kItems>), dim3(grid), dim3(kBlock), 0, st,
-                               ws, r, x, y, vec_ok);
-        else
-            hipLaunchKernelGGL((k_round<true, 1, kBlock, kItems>), dim3(grid), dim3(kBlock), 0, st,
-                               ws, r, x, y, vec_ok);
-    } else {
-        if (mode == 0)
-            hipLaunchKernelGGL((k_round<false, 0, kBlock, kItems>), dim3(grid), dim3(kBlock), 0,
-                               st, ws, r, x, y, vec_ok);
-        else
-            hipLaunchKernelGGL((k_round<false, 1, kBlock, kItems>), dim3(grid), dim3(kBlock), 0,
-                               st, ws, r, x, y, vec_ok);
-    }
+hipError_t launch_segments(const Ws2 &ws, const HullArgs &a, int32_t r, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_segments, dim3(grid), dim3(kSegBlock), 0, st, ws, a, r);
     return hipGetLastError();
 }
 
-hipError_t launch_segments(const Ws2 &ws, int32_t r, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_segments<kSegBlock>), dim3(grid), dim3(kSegBlock), 0, st, ws, r);
-    return hipGetLastError();
-}
-
-hipError_t launch_output(const Ws2 &ws, int32_t H, int32_t k, const int64_t *offsets,
-                         int64_t *hull_offsets, int32_t *hull_idx, int64_t n_total, hipStream_t st) {
+hipError_t launch_output(const Ws2 &ws, const HullArgs &a, int32_t H, hipStream_t st) {
     int steps = 0;
     while ((1ll << steps) < (int64_t)H + 1) ++steps;
     int src = 0;
     if (H > 0) {
         if (H <= kRankSmallCap) {
-            hipLaunchKernelGGL((k_rank_small<1024, kRankSmallCap>), dim3(1), dim3(1024), 0, st, ws,
-                               H, steps);
+            hipLaunchKernelGGL(k_rank_small, dim3(1), dim3(kBlock), 0, st, ws, H, steps);
         } else {
             const int grid = (H + 255) / 256;
             hipLaunchKernelGGL(k_rank_init, dim3(grid), dim3(256), 0, st, ws, H);
@@ -1161,12 +1344,9 @@ hipError_t launch_output(const Ws2 &ws, int32_t H, int32_t k, const int64_t *off
             }
         }
     }
-    hipLaunchKernelGGL(k_hull_offsets, dim3(1), dim3(1024), 0, st, ws, k, src, hull_offsets);
-    if (H > 0) {
-        const int grid = (H + 255) / 256;
-        hipLaunchKernelGGL(k_emit, dim3(grid), dim3(256), 0, st, ws, H, src, offsets, hull_offsets,
-                           hull_idx, n_total);
-    }
+    hipLaunchKernelGGL(k_hull_offsets, dim3(1), dim3(kBlock), 0, st, ws, a, src);
+    if (H > 0)
+        hipLaunchKernelGGL(k_emit, dim3((H + 255) / 256), dim3(256), 0, st, ws, a, H, src);
     return hipGetLastError();
 }
 
@@ -1174,9 +1354,19 @@ __global__ void k_fill_offsets(int64_t *off, int64_t n) {
     if (threadIdx.x == 0) { off[0] = 0; off[1] = n; }
 }
 
-}  // namespace qh
-
-hipError_t qh_fill_offsets(int64_t *off, int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(qh::k_fill_offsets, dim3(1), dim3(64), 0, st, off, n);
+hipError_t fill_single_offsets(int64_t *off, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_offsets, dim3(1), dim3(64), 0, st, off, n);
     return hipGetLastError();
 }
+
+hipError_t round_grid(int mode, int cus, int *grid) {
+    int per = 0;
+    const void *f = mode == 0 ? reinterpret_cast<const void *>(&k_round<0>)
+                              : reinterpret_cast<const void *>(&k_round<1>);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kBlock, 0);
+    if (e != hipSuccess) return e;
+    *grid = std::max(1, per) * cus;
+    return hipSuccess;
+}
+
+}  // namespace qh

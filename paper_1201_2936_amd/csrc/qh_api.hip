@@ -1,12 +1,15 @@
 // qh_api.hip -- the C ABI of include/qh.h: workspace context and the host
-// driver of the 2D rounds.
+// driver of a call.
 //
-// The host enqueues the set-up kernels, the first split and then rounds in
-// batches (two launches per round).  Kernels read the round state from device
-// memory and do nothing once no segment is left, so a batch may overshoot the
-// last round; the host reads the small control block back once per batch
-// instead of once per round (the per-iteration read-back the paper names as
-// the cost of its GPU loop, Section 5).
+// A call enqueues the set-up and extremes kernels, the first split, and then
+// Quickhull rounds in batches (two launches per round).  Every kernel reads the
+// round state from device memory and does nothing once no segment is left,
+// so a batch may overshoot the last round; the host reads the small control
+// block back once per batch instead of once per round, which is what the
+// paper's GPU loop paid for (Section 5).  Back-to-back launches were chosen
+// over a persistent kernel with grid barriers: on MI355X a grid-wide barrier
+// (with the cross-XCD fences it needs) costs tens of microseconds, a
+// dependent launch a few.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -21,6 +24,10 @@
 #include "qh2d.h"
 
 using namespace qh;
+
+namespace qh {
+hipError_t fill_single_offsets(int64_t *off, int64_t n, hipStream_t st);
+}
 
 struct qh_ctx {
     int device = 0;
@@ -38,6 +45,7 @@ struct qh_ctx {
     int64_t *single_off = nullptr; // device int64[2]
     int64_t *single_hoff = nullptr;// device int64[2]
     std::vector<hipEvent_t> ev;    // timing events (pairs)
+    int grid[2] = {0, 0};          // resident blocks of the round kernel, per mode
 };
 
 namespace {
@@ -61,25 +69,17 @@ size_t carve(qh_ctx *c, char *base) {
     Carve cv{base};
     Ws2 &w = c->ws;
     w.ctl = cv.take<Control>(1);
-    for (int p = 0; p < 2; ++p)
-        for (int r = 0; r < 2; ++r) {
-            w.px[p][r] = cv.take<int32_t>(c->cap_pts);
-            w.py[p][r] = cv.take<int32_t>(c->cap_pts);
-            w.pi[p][r] = cv.take<int32_t>(c->cap_pts);
-        }
-    for (int p = 0; p < 2; ++p)
-        for (int r = 0; r < 2; ++r) {
-            w.geo[p][r] = cv.take<SegGeo>(c->scap);
-            w.top[p][r] = cv.take<SegTop>(c->scap);
-            w.tmap[p][r] = cv.take<int32_t>(c->tcap);
-        }
+    w.pts_ = cv.take<int32_t>((size_t)12 * c->cap_pts);
+    w.geo_ = cv.take<SegGeo>((size_t)4 * c->scap);
+    w.top_ = cv.take<SegTop>((size_t)4 * c->scap);
+    w.tinfo_ = cv.take<TileInfo>((size_t)4 * c->tcap);
     w.pst = cv.take<int2>(2 * (size_t)c->scap);
     w.pen = cv.take<int2>(2 * (size_t)c->scap);
     w.adir = cv.take<Best>(4 * (size_t)c->scap);
     w.recF = cv.take<Best>(2 * (size_t)c->tcap);
     w.recL = cv.take<Best>(2 * (size_t)c->tcap);
-    for (int p = 0; p < 2; ++p) w.st2[p] = cv.take<uint64_t>(c->tcap + 4);
-    for (int p = 0; p < 2; ++p) w.st4[p] = cv.take<uint64_t>(c->s4cap);
+    w.st2_ = cv.take<uint64_t>((size_t)2 * (c->tcap + 4));
+    w.st4_ = cv.take<uint64_t>((size_t)2 * c->s4cap);
     w.recF0 = cv.take<Best>(2 * (size_t)c->tcap);
     w.recL0 = cv.take<Best>(2 * (size_t)c->tcap);
     w.dir0 = cv.take<Best>(2 * (size_t)c->kcap);
@@ -87,10 +87,8 @@ size_t carve(qh_ctx *c, char *base) {
     w.V = cv.take<int32_t>(c->hcap);
     w.hinst = cv.take<int32_t>(c->hcap);
     w.nxt = cv.take<int32_t>(c->hcap);
-    for (int p = 0; p < 2; ++p) {
-        w.succ[p] = cv.take<int32_t>(c->hcap);
-        w.dist[p] = cv.take<int32_t>(c->hcap);
-    }
+    w.succ_ = cv.take<int32_t>((size_t)2 * c->hcap);
+    w.dist_ = cv.take<int32_t>((size_t)2 * c->hcap);
     w.cap_pts = c->cap_pts;
     w.scap = c->scap;
     w.hcap = c->hcap;
@@ -143,12 +141,15 @@ qh_status ctx_init(qh_ctx *c) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
         cus > 0)
         c->cus = cus;
+    for (int m = 0; m < 2; ++m)
+        if (round_grid(m, c->cus, &c->grid[m]) != hipSuccess || c->grid[m] <= 0) return QH_EDEVICE;
     if (hipHostMalloc((void **)&c->ctl_host, sizeof(Control), hipHostMallocDefault) != hipSuccess)
         return QH_ENOMEM;
     if (hipHostMalloc((void **)&c->h_host, sizeof(int64_t) * 2, hipHostMallocDefault) != hipSuccess)
         return QH_ENOMEM;
     if (hipMalloc((void **)&c->single_off, sizeof(int64_t) * 2) != hipSuccess) return QH_ENOMEM;
     if (hipMalloc((void **)&c->single_hoff, sizeof(int64_t) * 2) != hipSuccess) return QH_ENOMEM;
+
     return QH_OK;
 }
 
@@ -158,6 +159,7 @@ void ctx_free(qh_ctx *c) {
     if (c->dmem) (void)hipFree(c->dmem);
     if (c->single_off) (void)hipFree(c->single_off);
     if (c->single_hoff) (void)hipFree(c->single_hoff);
+
     if (c->ctl_host) (void)hipHostFree(c->ctl_host);
     if (c->h_host) (void)hipHostFree(c->h_host);
     delete c;
@@ -171,40 +173,42 @@ void ctx_free(qh_ctx *c) {
         }                                             \
     } while (0)
 
+
+
+// HIP events around launches (QH_FLAG_TIMING), summed per kind of kernel
 struct Timing {
+    enum Kind { kSetup = 0, kExtremes, kSplit, kRound, kSegments, kOutput, kKinds };
     qh_ctx *c;
     bool on;
-    size_t used = 0;
-    hipError_t before(hipStream_t st) {
+    std::vector<int> kind;
+    hipError_t before(hipStream_t st, int k) {
         if (!on) return hipSuccess;
-        if (used + 2 > c->ev.size()) {
-            for (int i = 0; i < 2; ++i) {
-                hipEvent_t e;
-                hipError_t err = hipEventCreate(&e);
-                if (err != hipSuccess) return err;
-                c->ev.push_back(e);
-            }
+        const size_t i = kind.size() * 2;
+        while (c->ev.size() < i + 2) {
+            hipEvent_t e;
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) return err;
+            c->ev.push_back(e);
         }
-        return hipEventRecord(c->ev[used], st);
+        kind.push_back(k);
+        return hipEventRecord(c->ev[i], st);
     }
     hipError_t after(hipStream_t st) {
         if (!on) return hipSuccess;
-        hipError_t err = hipEventRecord(c->ev[used + 1], st);
-        used += 2;
-        return err;
+        return hipEventRecord(c->ev[kind.size() * 2 - 1], st);
     }
-    double total_ms() {
-        double t = 0;
-        for (size_t i = 0; i < used; i += 2) {
-            float ms = 0;
-            if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess) t += ms;
+    void totals(double (&ms)[kKinds]) {
+        for (double &m : ms) m = 0;
+        for (size_t j = 0; j < kind.size(); ++j) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, c->ev[2 * j], c->ev[2 * j + 1]) == hipSuccess) ms[kind[j]] += t;
         }
-        return t;
     }
 };
 
 qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets, int32_t k,
-                int32_t *hull_idx, int64_t *hull_offsets, int64_t *h_total, const qh_opts *o) {
+                int32_t *hull_idx, int64_t *hull_offsets, int64_t *h_total, int64_t *single_off,
+                const qh_opts *o) {
     hipStream_t st = o ? (hipStream_t)o->stream : nullptr;
     const int mode = o ? (int)o->mode : 0;
     const bool timing = o && (o->flags & QH_FLAG_TIMING);
@@ -213,81 +217,101 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
     if (h_total) *h_total = 0;
     if (mode != QH_EXACT_INT64 && mode != QH_FP32_FILTER) return QH_EINVAL;
 
-    const int32_t *x = pts;
-    const int32_t *y = pts + n;
-    const int32_t vec_ok = (((uintptr_t)pts & 15u) == 0 && (n & 3) == 0) ? 1 : 0;
+    HullArgs args = {};
+    args.x = pts;
+    args.y = pts + n;
+    args.offsets = offsets;
+    args.hull_idx = hull_idx;
+    args.hull_offsets = hull_offsets;
+    args.n = (int32_t)n;
+    args.k = k;
+    args.vec_ok = (((uintptr_t)pts & 15u) == 0 && (n & 3) == 0) ? 1 : 0;
+    const int grid = c->grid[mode];
     int64_t syncs = 0;
     int r = 0;
-    Timing tm{c, timing};
+    Timing tm{c, timing, {}};
 
     for (int attempt = 0;; ++attempt) {
         qh_status s = ensure(c, n, k);
         if (s != QH_OK) return s;
         const Ws2 &ws = c->ws;
-        const int ntiles0 = (int)((n + kTile - 1) / kTile);
-        const int grid_round = std::max(1, std::min(c->tcap, c->cus * 4));
         const int grid_seg = std::max(1, std::min((2 * c->scap + kSegBlock - 1) / kSegBlock, c->cus * 2));
-        const int grid_setup = std::max(1, std::min((c->tcap + 255) / 256 + 1, c->cus * 4));
-        tm.used = 0;
-        QH_TRY(launch_instances(ws, offsets, n, k, st));
-        QH_TRY(launch_setup(ws, offsets, k, ntiles0, grid_setup, st));
-        QH_TRY(launch_extremes(ws, x, y, (int32_t)n, vec_ok, grid_round, k, st));
-        QH_TRY(tm.before(st));
-        QH_TRY(launch_round(ws, 0, true, mode, x, y, vec_ok, grid_round, st));
+        tm.kind.clear();
+        if (single_off) QH_TRY(fill_single_offsets(single_off, n, st));
+        QH_TRY(tm.before(st, Timing::kSetup));
+        QH_TRY(launch_setup(ws, args, grid, st));
         QH_TRY(tm.after(st));
-        QH_TRY(launch_segments(ws, 0, grid_seg, st));
-        r = 1;
-        int batch = 6;
+        QH_TRY(tm.before(st, Timing::kExtremes));
+        QH_TRY(launch_extremes(ws, args, grid, st));
+        QH_TRY(tm.after(st));
+        r = 0;
+        int batch = 9;  // the first split and 8 rounds, then 8 rounds per batch
         while (true) {
             for (int j = 0; j < batch; ++j, ++r) {
-                QH_TRY(tm.before(st));
-                QH_TRY(launch_round(ws, r, false, mode, x, y, vec_ok, grid_round, st));
+                QH_TRY(tm.before(st, r == 0 ? Timing::kSplit : Timing::kRound));
+                QH_TRY(launch_round(ws, args, mode, r, grid, st));
                 QH_TRY(tm.after(st));
-                QH_TRY(launch_segments(ws, r, grid_seg, st));
+                QH_TRY(tm.before(st, Timing::kSegments));
+                QH_TRY(launch_segments(ws, args, r, grid_seg, st));
+                QH_TRY(tm.after(st));
             }
             QH_TRY(hipMemcpyAsync(c->ctl_host, ws.ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
             QH_TRY(hipStreamSynchronize(st));
             ++syncs;
-            const Control &h = *c->ctl_host;
-            if (h.error) break;
-            const RoundState &rs = h.rs[r & 1];
+            const Control &hc = *c->ctl_host;
+            if (hc.error) break;
+            const RoundState &rs = hc.rs[r & 1];
             if (rs.s[0] + rs.s[1] == 0) break;
-            batch = std::min(batch * 2, 48);
+            batch = 8;
         }
         const int err = c->ctl_host->error;
         if (err & kErrOffsets) return QH_EINVAL;
         if (err & kErrRange) return QH_ERANGE;
         if (err & (kErrSegCap | kErrHullCap)) {
             if (attempt >= 8) return QH_ECAPACITY;
-            if (err & kErrSegCap) c->want_scap = (int32_t)std::min<int64_t>((int64_t)c->scap * 4, INT32_MAX / 2);
-            if (err & kErrHullCap) c->want_hcap = (int32_t)std::min<int64_t>((int64_t)c->hcap * 4, INT32_MAX / 2);
+            if (err & kErrSegCap)
+                c->want_scap = (int32_t)std::min<int64_t>((int64_t)c->scap * 4, INT32_MAX / 2);
+            if (err & kErrHullCap)
+                c->want_hcap = (int32_t)std::min<int64_t>((int64_t)c->hcap * 4, INT32_MAX / 2);
             continue;
         }
         if (err) return QH_EDEVICE;
         break;
     }
+    const int32_t H = c->ctl_host->rs[r & 1].hbase;
+    QH_TRY(tm.before(st, Timing::kOutput));
+    QH_TRY(launch_output(c->ws, args, H, st));
+    QH_TRY(tm.after(st));
+    QH_TRY(hipMemcpyAsync(c->ctl_host, c->ws.ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
+    QH_TRY(hipStreamSynchronize(st));
+    ++syncs;
     const Control &h = *c->ctl_host;
-    const int32_t H = h.rs[r & 1].hbase;
-    QH_TRY(launch_output(c->ws, H, k, offsets, hull_offsets, hull_idx, n, st));
-    if (h_total || stats) {
-        QH_TRY(hipMemcpyAsync(c->h_host, hull_offsets + k, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        QH_TRY(hipStreamSynchronize(st));
-        ++syncs;
-        if (h_total) *h_total = *c->h_host;
-    } else {
-        QH_TRY(hipStreamSynchronize(st));
-    }
+    if (h.error) return QH_EDEVICE;
+    if (h_total) *h_total = h.h_total;
     if (stats) {
-        stats->rounds = (int64_t)h.round_launches_work;
+        stats->rounds = (int64_t)h.rounds_with_work;
         stats->round_launches = r;
         stats->round_points_in = (int64_t)h.points_in;
         stats->round_points_out = (int64_t)h.points_out;
-        stats->round_bytes = (int64_t)(8 * h.first_in + 12 * (h.points_in - h.first_in) + 12 * h.points_out);
-        stats->round_kernel_ms = timing ? tm.total_ms() : 0.0;
+        stats->split_points_out = (int64_t)h.first_out;
+        const int64_t split_bytes = (int64_t)(8 * h.first_in + 12 * h.first_out);
+        const int64_t later = (int64_t)(12 * h.points_in + 12 * h.points_out);
+        stats->round_kernel_bytes = split_bytes + later;
+        stats->hull_bytes = 8 * n + split_bytes + later;
+        if (timing) {
+            double ms[Timing::kKinds];
+            tm.totals(ms);
+            stats->kernel_ms = ms[0] + ms[1] + ms[2] + ms[3] + ms[4] + ms[5];
+            stats->round_kernel_ms = ms[Timing::kSplit] + ms[Timing::kRound];
+            stats->split_ms = ms[Timing::kSplit];
+            stats->extremes_ms = ms[Timing::kExtremes];
+            stats->segment_ms = ms[Timing::kSegments];
+        }
         stats->filter_tests = (int64_t)h.filter_tests;
         stats->filter_fallbacks = (int64_t)h.filter_fallbacks;
         stats->argmax_candidates = (int64_t)h.candidates;
         stats->max_segments = h.max_segments;
+        stats->grid_blocks = grid;
         stats->host_syncs = syncs;
     }
     return QH_OK;
@@ -314,8 +338,6 @@ qh_status get_ctx(const qh_opts *o, TempCtx &t) {
 }
 
 }  // namespace
-
-hipError_t qh_fill_offsets(int64_t *off, int64_t n, hipStream_t st);
 
 extern "C" {
 
@@ -359,13 +381,8 @@ qh_status qh_hull2d(const int32_t *pts, int64_t n, int32_t *hull_idx, int64_t *h
     TempCtx t;
     qh_status s = get_ctx(opts, t);
     if (s != QH_OK) return s;
-    hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
-    if (qh_fill_offsets(t.c->single_off, n, st) != hipSuccess) {
-        (void)hipGetLastError();
-        return QH_EDEVICE;
-    }
     int64_t ht = 0;
-    s = run2d(t.c, pts, n, t.c->single_off, 1, hull_idx, t.c->single_hoff, &ht, opts);
+    s = run2d(t.c, pts, n, t.c->single_off, 1, hull_idx, t.c->single_hoff, &ht, t.c->single_off, opts);
     if (s != QH_OK) return s;
     *h = ht;
     return QH_OK;
@@ -381,7 +398,7 @@ qh_status qh_hull2d_batched(const int32_t *pts, int64_t n_total, const int64_t *
     TempCtx t;
     qh_status s = get_ctx(opts, t);
     if (s != QH_OK) return s;
-    return run2d(t.c, pts, n_total, offsets, k, hull_idx, hull_offsets, h_total, opts);
+    return run2d(t.c, pts, n_total, offsets, k, hull_idx, hull_offsets, h_total, nullptr, opts);
 }
 
 }  // extern "C"

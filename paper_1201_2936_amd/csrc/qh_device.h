@@ -201,14 +201,21 @@ struct Control {
     int32_t error;
     int32_t rounds_done;
     int32_t max_segments;
-    int32_t pad;
-    unsigned long long points_in;     // summed over round-kernel launches
-    unsigned long long points_out;
+    int32_t final_round;              // parity source of the final state
+    unsigned long long points_in;     // points read by the rounds after the first split
+    unsigned long long points_out;    // survivors written by those rounds
     unsigned long long first_in;      // points read by the first split
+    unsigned long long first_out;     // survivors written by the first split
     unsigned long long filter_tests;
     unsigned long long filter_fallbacks;
     unsigned long long candidates;
-    unsigned long long round_launches_work;  // launches that had work
+    unsigned long long rounds_with_work;
+    unsigned int bar;                 // grid barrier arrivals (reset before each launch)
+    int32_t H;                        // compact hull ids used
+    long long h_total;                // hull vertices of all instances
+    int32_t nstamps;
+    int32_t setup_error;              // errors of the set-up phases only
+    long long stamps[256];            // wall-clock stamps at phase ends (timing only)
 };
 
 }  // namespace qh

@@ -34,12 +34,19 @@ class QhStats(ctypes.Structure):
         ("round_launches", ctypes.c_int64),
         ("round_points_in", ctypes.c_int64),
         ("round_points_out", ctypes.c_int64),
-        ("round_bytes", ctypes.c_int64),
+        ("split_points_out", ctypes.c_int64),
+        ("hull_bytes", ctypes.c_int64),
+        ("round_kernel_bytes", ctypes.c_int64),
+        ("kernel_ms", ctypes.c_double),
         ("round_kernel_ms", ctypes.c_double),
+        ("split_ms", ctypes.c_double),
+        ("extremes_ms", ctypes.c_double),
+        ("segment_ms", ctypes.c_double),
         ("filter_tests", ctypes.c_int64),
         ("filter_fallbacks", ctypes.c_int64),
         ("argmax_candidates", ctypes.c_int64),
         ("max_segments", ctypes.c_int64),
+        ("grid_blocks", ctypes.c_int64),
         ("host_syncs", ctypes.c_int64),
     ]
 
