@@ -9,6 +9,7 @@ constexpr int kBlock = 256;              // threads per block
 constexpr int kItems = 8;                // points per thread
 constexpr int kTile = kBlock * kItems;   // points per tile
 constexpr int kSlots = 128;              // segments per LDS window (multi-segment tiles)
+constexpr int kChunk = 8;                // tiles per chunk of the round (one look-back each)
 constexpr int kSegBlock = 256;           // segments per tile of the segment phase
 constexpr int kRankSmallCap = 4096;      // hull ids ranked inside one block's LDS
 constexpr int32_t kCoordMax2D = (1 << 30) - 1;
@@ -37,11 +38,10 @@ struct Ws2 {
     TileInfo *tinfo_;   // tile records: [parity][region][tcap]
     uint64_t *st2_;     // look-back words of the round phase: [parity][tcap + 4]
     uint64_t *st4_;     // look-back words of the segment phase: [parity][s4cap]
+    uint64_t *st4b_;    // ... of its second scan (child offsets): [parity][s4cap]
     int32_t *succ_;     // list ranking: [2][hcap]
     int32_t *dist_;     // [2][hcap]
     // per segment of the current round (global id = region-0 ids, then region 1)
-    int2 *pst;     // global offsets (child 0, child 1) at the segment's first point
-    int2 *pen;     // ... after its last point
     Best *adir;    // [seg][child] argmax of the segment
     // per tile of the current round
     Best *recF;    // [tile][child] partial argmax of the tile's first segment
@@ -67,6 +67,7 @@ struct Ws2 {
     __host__ __device__ TileInfo *tinfo(int p, int r) const { return tinfo_ + (size_t)(p * 2 + r) * tcap; }
     __host__ __device__ uint64_t *st2(int p) const { return st2_ + (size_t)p * (tcap + 4); }
     __host__ __device__ uint64_t *st4(int p) const { return st4_ + (size_t)p * s4cap; }
+    __host__ __device__ uint64_t *st4b(int p) const { return st4b_ + (size_t)p * s4cap; }
     __host__ __device__ int32_t *succ(int p) const { return succ_ + (size_t)p * hcap; }
     __host__ __device__ int32_t *dist(int p) const { return dist_ + (size_t)p * hcap; }
 };

@@ -92,12 +92,32 @@ __device__ __forceinline__ Best best_none() {
     Best b;
     b.key1 = 0;
     b.key2 = ~0ull;
-    b.x = b.y = b.idx = b.pad = 0;
+    b.x = b.y = b.idx = b.cnt = 0;
     return b;
 }
 
 __device__ __forceinline__ void best_merge(Best &acc, const Best &b) {
-    if (best_better(b, acc)) acc = b;
+    if (best_better(b, acc)) {
+        acc.key1 = b.key1;
+        acc.key2 = b.key2;
+        acc.x = b.x;
+        acc.y = b.y;
+        acc.idx = b.idx;
+        acc.cnt = b.cnt;
+    }
+}
+
+// merge of argmax records that also sums the child counts
+__device__ __forceinline__ void rec_merge(Best &acc, const Best &b) {
+    const int32_t c = acc.cnt + b.cnt;
+    if (best_better(b, acc)) {
+        acc.key1 = b.key1;
+        acc.key2 = b.key2;
+        acc.x = b.x;
+        acc.y = b.y;
+        acc.idx = b.idx;
+    }
+    acc.cnt = c;
 }
 
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
@@ -116,8 +136,22 @@ __device__ __forceinline__ void wave_best(Best &b) {
         o.x = __shfl_xor(b.x, m);
         o.y = __shfl_xor(b.y, m);
         o.idx = __shfl_xor(b.idx, m);
-        o.pad = 0;
+        o.cnt = 0;
         if (best_better(o, b)) b = o;
+    }
+}
+
+__device__ __forceinline__ void wave_rec(Best &b) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        Best o;
+        o.key1 = shfl_xor_u64(b.key1, m);
+        o.key2 = shfl_xor_u64(b.key2, m);
+        o.x = __shfl_xor(b.x, m);
+        o.y = __shfl_xor(b.y, m);
+        o.idx = __shfl_xor(b.idx, m);
+        o.cnt = __shfl_xor(b.cnt, m);
+        rec_merge(b, o);
     }
 }
 
@@ -148,19 +182,23 @@ __device__ __forceinline__ void best_offer(Best &b, uint64_t d, int32_t x, int32
 // LDS layouts of the phases (they share one buffer)
 // ---------------------------------------------------------------------------
 struct RoundSmem {
-    int32_t s_tile, s_next[2], s_m;
+    int32_t s_tile, s_m;
+    uint32_t s_tot;
     uint64_t s_ex;
-    float Mw[kNW][2];
     uint32_t stat[4];
     uint32_t scan[kQ * kNW];
-    Best red[kNW][2];
     int32_t sstart[kTile + 4];
     int32_t lgeo[kSlots][6];
     uint64_t k1[2][kSlots];
     uint64_t k2[2][kSlots];
     uint32_t lm[2][kSlots];
+    uint32_t scnt[2][kSlots];
     int32_t res[2][kSlots][3];
-    uint64_t Dl[kTile];
+    Best wrec[kChunk][kNW][2];      // per-wave argmax records of one-segment tiles
+    uint32_t wcnt[kChunk][kNW];     // per-wave survivor counts (child 0 | child 1 << 16)
+    uint32_t woff[kChunk][kNW];     // their chunk-local offsets
+    int32_t tgen[kChunk];           // tile has several segments
+    uint32_t stc[kChunk][kBlock];   // 2-bit states of the chunk's tiles, pass 1 -> pass 2
 };
 
 struct ExtSmem {
@@ -173,8 +211,9 @@ struct ExtSmem {
 
 struct SegSmem {
     uint32_t scan[2 * (kSegBlock / kWave)];
+    uint32_t scan2[2 * (kSegBlock / kWave)];
     int32_t s_tile, qn_apex, qn_map, pad;
-    uint64_t s_ex;
+    uint64_t s_ex, s_ex2;
     int16_t q_apex[kSegBlock];
     int16_t q_map[2 * kSegBlock];
     int32_t o_t0[kSegBlock], o_t1[kSegBlock];
@@ -280,6 +319,8 @@ __device__ __forceinline__ void phase_setup(const Ws2 &ws, const HullArgs &a) {
     for (int i = tid; i < ws.s4cap; i += stride) {
         ws.st4(0)[i] = 0;
         ws.st4(1)[i] = 0;
+        ws.st4b(0)[i] = 0;
+        ws.st4b(1)[i] = 0;
     }
     if (ws.ctl->error) return;
     const int ntiles = (a.n + kTile - 1) / kTile;
@@ -351,7 +392,7 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
                 if (v >= hi) continue;
                 const uint64_t ck = coord_key(X[i], Y[i]);
                 Best c;
-                c.key1 = ~ck; c.key2 = (uint32_t)v; c.x = X[i]; c.y = Y[i]; c.idx = v; c.pad = 0;
+                c.key1 = ~ck; c.key2 = (uint32_t)v; c.x = X[i]; c.y = Y[i]; c.idx = v; c.cnt = 0;
                 best_merge(mn, c);
                 c.key1 = ck;
                 best_merge(mx, c);
@@ -438,9 +479,9 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
                 const int sl = w0 + j;
                 Best bmn, bmx;
                 bmn.key1 = sm->kmin1[j]; bmn.key2 = sm->kmin2[j];
-                bmn.x = sm->rmin[j][0]; bmn.y = sm->rmin[j][1]; bmn.idx = sm->rmin[j][2]; bmn.pad = 0;
+                bmn.x = sm->rmin[j][0]; bmn.y = sm->rmin[j][1]; bmn.idx = sm->rmin[j][2]; bmn.cnt = 0;
                 bmx.key1 = sm->kmax1[j]; bmx.key2 = sm->kmax2[j];
-                bmx.x = sm->rmax[j][0]; bmx.y = sm->rmax[j][1]; bmx.idx = sm->rmax[j][2]; bmx.pad = 0;
+                bmx.x = sm->rmax[j][0]; bmx.y = sm->rmax[j][1]; bmx.idx = sm->rmax[j][2]; bmx.cnt = 0;
                 const bool inside = sm->sstart[sl] >= lo && sm->sstart[sl + 1] <= hi;
                 if (inside) {
                     ws.dir0[(s0 + sl) * 2 + 0] = bmn;
@@ -472,13 +513,13 @@ __device__ __forceinline__ Best block_merge_tiles(const Best *recF, const Best *
             b[u] = tt <= t1 ? (tt == t0 ? recL[tt * 2 + c] : recF[tt * 2 + c]) : best_none();
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) best_merge(acc, b[u]);
+        for (int u = 0; u < 4; ++u) rec_merge(acc, b[u]);
     }
-    wave_best(acc);
+    wave_rec(acc);
     if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
     __syncthreads();
     Best r = red[0];
-    for (int w = 1; w < kNW; ++w) best_merge(r, red[w]);
+    for (int w = 1; w < kNW; ++w) rec_merge(r, red[w]);
     __syncthreads();
     return r;
 }
@@ -536,6 +577,91 @@ __device__ __forceinline__ void phase_extremes_final(const Ws2 &ws, const HullAr
 // ---------------------------------------------------------------------------
 // one round over the survivors
 // ---------------------------------------------------------------------------
+// The tiles of a round are grouped into chunks of up to kChunk tiles, claimed
+// in order from an atomic counter.  Pass 1 classifies every tile of the chunk
+// and produces its argmax records (with the child counts); one look-back gives
+// the chunk its global offsets; pass 2 reads the chunk's points again (from L2
+// / Infinity Cache) and scatters the survivors.  A tile covered by one segment
+// (the common case) is processed by each wave on its own quarter, without
+// block barriers; a tile with several segments is processed by the whole
+// block in point order.
+
+__device__ __forceinline__ void load_tile(const Ws2 &ws, const HullArgs &a, bool init, int p, int R,
+                                          int lo, int hi, int32_t (&X)[kItems], int32_t (&Y)[kItems],
+                                          int32_t (&I)[kItems]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int qq = 0; qq < kQ; ++qq) {
+        const int v0 = lo + qq * kBlock * 4 + tid * 4;
+        if (init) {
+            if (a.vec_ok && v0 + 3 < hi) {
+                const int4 pa = *reinterpret_cast<const int4 *>(a.x + v0);
+                const int4 pb = *reinterpret_cast<const int4 *>(a.y + v0);
+                X[qq * 4 + 0] = pa.x; X[qq * 4 + 1] = pa.y; X[qq * 4 + 2] = pa.z; X[qq * 4 + 3] = pa.w;
+                Y[qq * 4 + 0] = pb.x; Y[qq * 4 + 1] = pb.y; Y[qq * 4 + 2] = pb.z; Y[qq * 4 + 3] = pb.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int v = v0 + j;
+                    X[qq * 4 + j] = v < hi ? a.x[v] : 0;
+                    Y[qq * 4 + j] = v < hi ? a.y[v] : 0;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) I[qq * 4 + j] = v0 + j;
+        } else {
+            const int4 pa = *reinterpret_cast<const int4 *>(ws.px(p, R) + v0);
+            const int4 pb = *reinterpret_cast<const int4 *>(ws.py(p, R) + v0);
+            const int4 pc = *reinterpret_cast<const int4 *>(ws.pi(p, R) + v0);
+            X[qq * 4 + 0] = pa.x; X[qq * 4 + 1] = pa.y; X[qq * 4 + 2] = pa.z; X[qq * 4 + 3] = pa.w;
+            Y[qq * 4 + 0] = pb.x; Y[qq * 4 + 1] = pb.y; Y[qq * 4 + 2] = pb.z; Y[qq * 4 + 3] = pb.w;
+            I[qq * 4 + 0] = pc.x; I[qq * 4 + 1] = pc.y; I[qq * 4 + 2] = pc.z; I[qq * 4 + 3] = pc.w;
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t row_count(uint32_t stbits, int qq) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t st = (stbits >> (2 * (qq * 4 + j))) & 3u;
+        c += st == 0 ? 1u : (st == 1 ? 0x10000u : 0u);
+    }
+    return c;
+}
+
+// exclusive in-tile ranks of the survivors of both children in point order
+// (packed child 0 | child 1 << 16): cnt[qq] before this thread's group of
+// row qq, rowbase[qq] before row qq; returns the tile totals
+__device__ __forceinline__ uint32_t tile_ranks(uint32_t stbits, uint32_t (&cnt)[kQ],
+                                               uint32_t (&rowbase)[kQ], uint32_t *scan) {
+    uint32_t tot[kQ];
+#pragma unroll
+    for (int qq = 0; qq < kQ; ++qq) cnt[qq] = row_count(stbits, qq);
+    block_excl_scan<kBlock, kQ>(cnt, tot, scan);
+    uint32_t acc = 0;
+#pragma unroll
+    for (int qq = 0; qq < kQ; ++qq) { rowbase[qq] = acc; acc += tot[qq]; }
+    return acc;
+}
+
+// exact distance of a point to its child's edge (child 0: u->f, 1: f->v)
+__device__ __forceinline__ int64_t child_d(int32_t x, int32_t y, uint32_t st, const int32_t *g) {
+    return st == 0 ? cross_i64(x, y, g[0], g[1], g[2], g[3]) : cross_i64(x, y, g[2], g[3], g[4], g[5]);
+}
+
+// FP32 filter: is the point a possible argmax of its child (upper bound of its
+// distance reaches the best lower bound lmk of the child)?
+__device__ __forceinline__ bool filter_cand(int32_t x, int32_t y, uint32_t st, const int32_t *g,
+                                            uint32_t lmk) {
+    float B;
+    const float e = st == 0 ? cross_f32(x, y, g[0], g[1], g[2], g[3], B)
+                            : cross_f32(x, y, g[2], g[3], g[4], g[5], B);
+    return fkey(__fadd_rn(e, 2.f * B)) >= lmk;
+}
+
+
+
 template <int MODE>
 __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, int r, char *smem) {
     const bool INIT = r == 0;  // the first split reads the input (index = position)
@@ -548,6 +674,9 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
     const int S0 = rs->s[0], S1 = rs->s[1];
     const int nt0 = (n0 + kTile - 1) / kTile, nt1 = (n1 + kTile - 1) / kTile;
     const int ntiles = nt0 + nt1;
+    const int C = max(1, min(kChunk, ntiles / (2 * (int)gridDim.x)));
+    const int nc0 = (nt0 + C - 1) / C, nc1 = (nt1 + C - 1) / C;
+    const int nchunks = nc0 + nc1;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
 
     // house-keeping for the next round
@@ -560,225 +689,64 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
     }
 
     uint32_t ntests = 0, nfall = 0, ncand = 0;
-    if (tid == 0) sm->s_tile = (int32_t)atomicAdd(&rs->tile_ctr, 1u);
-    __syncthreads();
-    int tile = sm->s_tile;
-    int it = 0;
-    while (tile < ntiles) {
-        if (tid == 0) sm->s_next[it & 1] = (int32_t)atomicAdd(&rs->tile_ctr, 1u);
-        const int R = tile < nt0 ? 0 : 1;
-        const int lt = tile - (R ? nt0 : 0);
+    while (true) {
+        if (tid == 0) sm->s_tile = (int32_t)atomicAdd(&rs->tile_ctr, 1u);
+        __syncthreads();
+        const int ch = __builtin_amdgcn_readfirstlane(sm->s_tile);  // uniform: scalar registers
+        if (ch >= nchunks) break;
+        const int R = ch < nc0 ? 0 : 1;
+        const int lc = ch - (R ? nc0 : 0);
         const int NR = R ? n1 : n0;
         const int SR = R ? S1 : S0;
+        const int ntR = R ? nt1 : nt0;
         const int gbase = R ? S0 : 0;
-        const int lo = lt * kTile;
-        const int hi = min(lo + kTile, NR);
+        const int t_first = lc * C;
+        const int tcount = min(C, ntR - t_first);
 
-        // 1. the tile's points (structure of arrays, 16-byte loads)
-        int32_t X[kItems], Y[kItems], I[kItems];
-#pragma unroll
-        for (int qq = 0; qq < kQ; ++qq) {
-            const int v0 = lo + qq * kBlock * 4 + tid * 4;
-            if (INIT) {
-                if (a.vec_ok && v0 + 3 < hi) {
-                    const int4 pa = *reinterpret_cast<const int4 *>(a.x + v0);
-                    const int4 pb = *reinterpret_cast<const int4 *>(a.y + v0);
-                    X[qq * 4 + 0] = pa.x; X[qq * 4 + 1] = pa.y; X[qq * 4 + 2] = pa.z; X[qq * 4 + 3] = pa.w;
-                    Y[qq * 4 + 0] = pb.x; Y[qq * 4 + 1] = pb.y; Y[qq * 4 + 2] = pb.z; Y[qq * 4 + 3] = pb.w;
-                } else {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int v = v0 + j;
-                        X[qq * 4 + j] = v < hi ? a.x[v] : 0;
-                        Y[qq * 4 + j] = v < hi ? a.y[v] : 0;
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) I[qq * 4 + j] = v0 + j;
-            } else {
-                const int4 pa = *reinterpret_cast<const int4 *>(ws.px(p, R) + v0);
-                const int4 pb = *reinterpret_cast<const int4 *>(ws.py(p, R) + v0);
-                const int4 pc = *reinterpret_cast<const int4 *>(ws.pi(p, R) + v0);
-                X[qq * 4 + 0] = pa.x; X[qq * 4 + 1] = pa.y; X[qq * 4 + 2] = pa.z; X[qq * 4 + 3] = pa.w;
-                Y[qq * 4 + 0] = pb.x; Y[qq * 4 + 1] = pb.y; Y[qq * 4 + 2] = pb.z; Y[qq * 4 + 3] = pb.w;
-                I[qq * 4 + 0] = pc.x; I[qq * 4 + 1] = pc.y; I[qq * 4 + 2] = pc.z; I[qq * 4 + 3] = pc.w;
-            }
-        }
-        const TileInfo ti = ws.tinfo(p, R)[lt];
-        const int s0 = ti.seg;
+        // ---------------- pass 1: classify every tile of the chunk
+        for (int it = 0; it < tcount; ++it) {
+            const int lt = t_first + it;
+            const int tile = (R ? nt0 : 0) + lt;
+            const int lo = lt * kTile;
+            const int hi = min(lo + kTile, NR);
+            int32_t X[kItems], Y[kItems], I[kItems];
+            load_tile(ws, a, INIT, p, R, lo, hi, X, Y, I);
+            const TileInfo ti = ws.tinfo(p, R)[lt];
+            const int s0 = ti.seg;
+            uint32_t stbits = 0xaaaaaaaau;  // 2 bits per point: 0, 1 = child, 2 = dropped
 
-        uint32_t stbits = 0xaaaaaaaau;  // 2 bits per point: 0, 1 = child, 2 = dropped
-        // slot of every point inside the tile's segment list (16 bits each)
-        uint32_t slotpk[kItems / 2];
+            if (ti.single) {
+                // one segment covers the tile: uniform geometry, every wave on its own
+                const int ux = ti.ux, uy = ti.uy, fx = ti.fx, fy = ti.fy, vx = ti.vx, vy = ti.vy;
+                const int e0x = fx - ux, e0y = fy - uy, e1x = vx - fx, e1y = vy - fy;
+                Best b0 = best_none(), b1 = best_none();
+                if (MODE == 0) {
 #pragma unroll
-        for (int i = 0; i < kItems / 2; ++i) slotpk[i] = 0;
-
-        if (ti.single) {
-            // 2a. one segment covers the tile: its geometry is uniform
-            const int ux = ti.ux, uy = ti.uy, fx = ti.fx, fy = ti.fy, vx = ti.vx, vy = ti.vy;
-            const int e0x = fx - ux, e0y = fy - uy, e1x = vx - fx, e1y = vy - fy;
-            Best b0 = best_none(), b1 = best_none();
-            if (MODE == 0) {
-#pragma unroll
-                for (int i = 0; i < kItems; ++i) {
-                    const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-                    if (v >= hi) continue;
-                    const int64_t d0 = cross_i64(X[i], Y[i], ux, uy, fx, fy);
-                    uint32_t st = 2;
-                    if (d0 > 0) {
-                        st = 0;
-                        best_offer(b0, (uint64_t)d0, X[i], Y[i], I[i], e0x, e0y);
-                    } else {
-                        const int64_t d1 = cross_i64(X[i], Y[i], fx, fy, vx, vy);
-                        if (d1 > 0) {
-                            st = 1;
-                            best_offer(b1, (uint64_t)d1, X[i], Y[i], I[i], e1x, e1y);
-                        }
-                    }
-                    stbits ^= (st ^ 2u) << (2 * i);
-                }
-            } else {
-                float l0 = -INFINITY, l1 = -INFINITY;
-#pragma unroll
-                for (int i = 0; i < kItems; ++i) {
-                    const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-                    if (v >= hi) continue;
-                    float B0;
-                    const float e0 = cross_f32(X[i], Y[i], ux, uy, fx, fy, B0);
-                    ntests++;
-                    bool out0;
-                    if (e0 > B0) out0 = true;
-                    else if (e0 < -B0) out0 = false;
-                    else { nfall++; out0 = cross_i64(X[i], Y[i], ux, uy, fx, fy) > 0; }
-                    uint32_t st = 2;
-                    if (out0) {
-                        st = 0;
-                        l0 = fmaxf(l0, __fsub_rn(e0, 2.f * B0));
-                    } else {
-                        float B1;
-                        const float e1 = cross_f32(X[i], Y[i], fx, fy, vx, vy, B1);
-                        ntests++;
-                        bool out1;
-                        if (e1 > B1) out1 = true;
-                        else if (e1 < -B1) out1 = false;
-                        else { nfall++; out1 = cross_i64(X[i], Y[i], fx, fy, vx, vy) > 0; }
-                        if (out1) {
-                            st = 1;
-                            l1 = fmaxf(l1, __fsub_rn(e1, 2.f * B1));
-                        }
-                    }
-                    stbits ^= (st ^ 2u) << (2 * i);
-                }
-                // the best lower bound of each child over the tile
-                l0 = wave_max_f(l0);
-                l1 = wave_max_f(l1);
-                if (lane == 0) { sm->Mw[wv][0] = l0; sm->Mw[wv][1] = l1; }
-                __syncthreads();
-                float M0 = sm->Mw[0][0], M1 = sm->Mw[0][1];
-#pragma unroll
-                for (int w = 1; w < kNW; ++w) { M0 = fmaxf(M0, sm->Mw[w][0]); M1 = fmaxf(M1, sm->Mw[w][1]); }
-                // only points whose upper bound reaches it can be the argmax
-#pragma unroll
-                for (int i = 0; i < kItems; ++i) {
-                    const uint32_t st = (stbits >> (2 * i)) & 3u;
-                    if (st > 1) continue;
-                    float B;
-                    const float e = st == 0 ? cross_f32(X[i], Y[i], ux, uy, fx, fy, B)
-                                            : cross_f32(X[i], Y[i], fx, fy, vx, vy, B);
-                    const float U = __fadd_rn(e, 2.f * B);
-                    if (U < (st == 0 ? M0 : M1)) continue;
-                    ncand++;
-                    if (st == 0)
-                        best_offer(b0, (uint64_t)cross_i64(X[i], Y[i], ux, uy, fx, fy), X[i], Y[i], I[i], e0x, e0y);
-                    else
-                        best_offer(b1, (uint64_t)cross_i64(X[i], Y[i], fx, fy, vx, vy), X[i], Y[i], I[i], e1x, e1y);
-                }
-            }
-            wave_best(b0);
-            wave_best(b1);
-            if (lane == 0) { sm->red[wv][0] = b0; sm->red[wv][1] = b1; }
-            __syncthreads();
-            if (tid == 0) {
-                for (int w = 1; w < kNW; ++w) {
-                    best_merge(b0, sm->red[w][0]);
-                    best_merge(b1, sm->red[w][1]);
-                }
-                const int g = gbase + s0;
-                const bool inside = ti.start >= lo && ti.end <= hi;
-                if (inside) { ws.adir[g * 2 + 0] = b0; ws.adir[g * 2 + 1] = b1; }
-                ws.recF[tile * 2 + 0] = b0; ws.recF[tile * 2 + 1] = b1;
-                ws.recL[tile * 2 + 0] = b0; ws.recL[tile * 2 + 1] = b1;
-                sm->sstart[0] = ti.start;
-                sm->sstart[1] = ti.end;
-            }
-        } else {
-            // 2b. several segments: starts into LDS, per-slot reductions
-            const SegGeo *geo = ws.geo(p, R);
-            if (tid == 0) sm->s_m = 0;
-            __syncthreads();
-            for (int b = 0; b <= kTile; b += kBlock) {
-                const int j = b + tid;
-                bool in = false;
-                if (j <= kTile) {
-                    const int si = s0 + j;
-                    const int st = si < SR ? geo[si].start : NR;
-                    sm->sstart[j] = st;
-                    in = st < hi;
-                }
-                const int cnt = __syncthreads_count(in);
-                if (tid == 0) sm->s_m += cnt;
-                if (cnt < kBlock) break;
-            }
-            __syncthreads();
-            const int m = sm->s_m;
-#pragma unroll
-            for (int i = 0; i < kItems; i += 2) {
-                const int va = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-                const int sa = (va >= hi) ? 0 : slot_of(sm->sstart, m, va);
-                const int sb = (va + 1 >= hi) ? 0 : slot_of(sm->sstart, m, va + 1);
-                slotpk[i >> 1] = (uint32_t)sa | ((uint32_t)sb << 16);
-            }
-            for (int w0 = 0; w0 < m; w0 += kSlots) {
-                const int wn = min(kSlots, m - w0);
-                for (int j = tid; j < wn; j += kBlock) {
-                    const SegGeo g = geo[s0 + w0 + j];
-                    sm->lgeo[j][0] = g.ux; sm->lgeo[j][1] = g.uy;
-                    sm->lgeo[j][2] = g.fx; sm->lgeo[j][3] = g.fy;
-                    sm->lgeo[j][4] = g.vx; sm->lgeo[j][5] = g.vy;
-                }
-                for (int j = tid; j < 2 * kSlots; j += kBlock) {
-                    (&sm->k1[0][0])[j] = 0;
-                    (&sm->k2[0][0])[j] = ~0ull;
-                    (&sm->lm[0][0])[j] = 0;
-                }
-                __syncthreads();
-                // classify; exact distances of survivors (exact mode) into LDS
-#pragma unroll
-                for (int i = 0; i < kItems; ++i) {
-                    const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-                    const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
-                    if (v >= hi || sl < w0 || sl >= w0 + wn) continue;
-                    const int ls = sl - w0;
-                    const int ux = sm->lgeo[ls][0], uy = sm->lgeo[ls][1];
-                    const int fx = sm->lgeo[ls][2], fy = sm->lgeo[ls][3];
-                    const int vx = sm->lgeo[ls][4], vy = sm->lgeo[ls][5];
-                    const int e = v - lo;
-                    uint32_t st = 2;
-                    if (MODE == 0) {
+                    for (int i = 0; i < kItems; ++i) {
+                        const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                        if (v >= hi) continue;
                         const int64_t d0 = cross_i64(X[i], Y[i], ux, uy, fx, fy);
+                        uint32_t st = 2;
                         if (d0 > 0) {
                             st = 0;
-                            sm->Dl[e] = (uint64_t)d0;
-                            atomicMax(&sm->k1[0][ls], (uint64_t)d0);
+                            b0.cnt++;
+                            best_offer(b0, (uint64_t)d0, X[i], Y[i], I[i], e0x, e0y);
                         } else {
                             const int64_t d1 = cross_i64(X[i], Y[i], fx, fy, vx, vy);
                             if (d1 > 0) {
                                 st = 1;
-                                sm->Dl[e] = (uint64_t)d1;
-                                atomicMax(&sm->k1[1][ls], (uint64_t)d1);
+                                b1.cnt++;
+                                best_offer(b1, (uint64_t)d1, X[i], Y[i], I[i], e1x, e1y);
                             }
                         }
-                    } else {
+                        stbits ^= (st ^ 2u) << (2 * i);
+                    }
+                } else {
+                    float l0 = -INFINITY, l1 = -INFINITY;
+#pragma unroll
+                    for (int i = 0; i < kItems; ++i) {
+                        const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                        if (v >= hi) continue;
                         float B0;
                         const float e0 = cross_f32(X[i], Y[i], ux, uy, fx, fy, B0);
                         ntests++;
@@ -786,9 +754,11 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
                         if (e0 > B0) out0 = true;
                         else if (e0 < -B0) out0 = false;
                         else { nfall++; out0 = cross_i64(X[i], Y[i], ux, uy, fx, fy) > 0; }
+                        uint32_t st = 2;
                         if (out0) {
                             st = 0;
-                            atomicMax(&sm->lm[0][ls], fkey(__fsub_rn(e0, 2.f * B0)));
+                            b0.cnt++;
+                            l0 = fmaxf(l0, __fsub_rn(e0, 2.f * B0));
                         } else {
                             float B1;
                             const float e1 = cross_f32(X[i], Y[i], fx, fy, vx, vy, B1);
@@ -799,15 +769,151 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
                             else { nfall++; out1 = cross_i64(X[i], Y[i], fx, fy, vx, vy) > 0; }
                             if (out1) {
                                 st = 1;
-                                atomicMax(&sm->lm[1][ls], fkey(__fsub_rn(e1, 2.f * B1)));
+                                b1.cnt++;
+                                l1 = fmaxf(l1, __fsub_rn(e1, 2.f * B1));
                             }
                         }
+                        stbits ^= (st ^ 2u) << (2 * i);
                     }
-                    stbits ^= (st ^ 2u) << (2 * i);
+                    // the wave's best lower bound per child; only points whose
+                    // upper bound reaches it can be the argmax
+                    const float M0 = wave_max_f(l0), M1 = wave_max_f(l1);
+#pragma unroll
+                    for (int i = 0; i < kItems; ++i) {
+                        const uint32_t st = (stbits >> (2 * i)) & 3u;
+                        if (st > 1) continue;
+                        float B;
+                        const float e = st == 0 ? cross_f32(X[i], Y[i], ux, uy, fx, fy, B)
+                                                : cross_f32(X[i], Y[i], fx, fy, vx, vy, B);
+                        const float U = __fadd_rn(e, 2.f * B);
+                        if (U < (st == 0 ? M0 : M1)) continue;
+                        ncand++;
+                        if (st == 0)
+                            best_offer(b0, (uint64_t)cross_i64(X[i], Y[i], ux, uy, fx, fy), X[i], Y[i], I[i], e0x, e0y);
+                        else
+                            best_offer(b1, (uint64_t)cross_i64(X[i], Y[i], fx, fy, vx, vy), X[i], Y[i], I[i], e1x, e1y);
+                    }
+                }
+                wave_rec(b0);
+                wave_rec(b1);
+                if (lane == 0) {
+                    sm->wrec[it][wv][0] = b0;
+                    sm->wrec[it][wv][1] = b1;
+                    sm->wcnt[it][wv] = (uint32_t)b0.cnt | ((uint32_t)b1.cnt << 16);
+                }
+                if (tid == 0) sm->tgen[it] = 0;
+            } else {
+                // several segments: starts into LDS, per-slot reductions (point order)
+                const SegGeo *geo = ws.geo(p, R);
+                if (tid == 0) sm->s_m = 0;
+                __syncthreads();
+                for (int b = 0; b <= kTile; b += kBlock) {
+                    const int j = b + tid;
+                    bool in = false;
+                    if (j <= kTile) {
+                        const int si = s0 + j;
+                        const int st = si < SR ? geo[si].start : NR;
+                        sm->sstart[j] = st;
+                        in = st < hi;
+                    }
+                    const int cnt = __syncthreads_count(in);
+                    if (tid == 0) sm->s_m += cnt;
+                    if (cnt < kBlock) break;
                 }
                 __syncthreads();
-                if (MODE != 0) {
-                    // candidates of the argmax get exact distances
+                const int m = sm->s_m;
+                uint32_t slotpk[kItems / 2];
+#pragma unroll
+                for (int i = 0; i < kItems; i += 2) {
+                    const int va = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                    const int sa = (va >= hi) ? 0 : slot_of(sm->sstart, m, va);
+                    const int sb = (va + 1 >= hi) ? 0 : slot_of(sm->sstart, m, va + 1);
+                    slotpk[i >> 1] = (uint32_t)sa | ((uint32_t)sb << 16);
+                }
+                for (int w0 = 0; w0 < m; w0 += kSlots) {
+                    const int wn = min(kSlots, m - w0);
+                    for (int j = tid; j < wn; j += kBlock) {
+                        const SegGeo g = geo[s0 + w0 + j];
+                        sm->lgeo[j][0] = g.ux; sm->lgeo[j][1] = g.uy;
+                        sm->lgeo[j][2] = g.fx; sm->lgeo[j][3] = g.fy;
+                        sm->lgeo[j][4] = g.vx; sm->lgeo[j][5] = g.vy;
+                    }
+                    for (int j = tid; j < 2 * kSlots; j += kBlock) {
+                        (&sm->k1[0][0])[j] = 0;
+                        (&sm->k2[0][0])[j] = ~0ull;
+                        (&sm->lm[0][0])[j] = 0;
+                        (&sm->scnt[0][0])[j] = 0;
+                    }
+                    __syncthreads();
+                    // classify; the best distance (exact) or lower bound (filter) per slot
+#pragma unroll
+                    for (int i = 0; i < kItems; ++i) {
+                        const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                        const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
+                        if (v >= hi || sl < w0 || sl >= w0 + wn) continue;
+                        const int ls = sl - w0;
+                        const int ux = sm->lgeo[ls][0], uy = sm->lgeo[ls][1];
+                        const int fx = sm->lgeo[ls][2], fy = sm->lgeo[ls][3];
+                        const int vx = sm->lgeo[ls][4], vy = sm->lgeo[ls][5];
+                        uint32_t st = 2;
+                        if (MODE == 0) {
+                            const int64_t d0 = cross_i64(X[i], Y[i], ux, uy, fx, fy);
+                            if (d0 > 0) {
+                                st = 0;
+                                atomicMax(&sm->k1[0][ls], (uint64_t)d0);
+                            } else {
+                                const int64_t d1 = cross_i64(X[i], Y[i], fx, fy, vx, vy);
+                                if (d1 > 0) {
+                                    st = 1;
+                                    atomicMax(&sm->k1[1][ls], (uint64_t)d1);
+                                }
+                            }
+                        } else {
+                            float B0;
+                            const float e0 = cross_f32(X[i], Y[i], ux, uy, fx, fy, B0);
+                            ntests++;
+                            bool out0;
+                            if (e0 > B0) out0 = true;
+                            else if (e0 < -B0) out0 = false;
+                            else { nfall++; out0 = cross_i64(X[i], Y[i], ux, uy, fx, fy) > 0; }
+                            if (out0) {
+                                st = 0;
+                                atomicMax(&sm->lm[0][ls], fkey(__fsub_rn(e0, 2.f * B0)));
+                            } else {
+                                float B1;
+                                const float e1 = cross_f32(X[i], Y[i], fx, fy, vx, vy, B1);
+                                ntests++;
+                                bool out1;
+                                if (e1 > B1) out1 = true;
+                                else if (e1 < -B1) out1 = false;
+                                else { nfall++; out1 = cross_i64(X[i], Y[i], fx, fy, vx, vy) > 0; }
+                                if (out1) {
+                                    st = 1;
+                                    atomicMax(&sm->lm[1][ls], fkey(__fsub_rn(e1, 2.f * B1)));
+                                }
+                            }
+                        }
+                        if (st < 2) atomicAdd(&sm->scnt[st][ls], 1u);
+                        stbits ^= (st ^ 2u) << (2 * i);
+                    }
+                    __syncthreads();
+                    if (MODE != 0) {
+                        // candidates of the argmax get exact distances
+#pragma unroll
+                        for (int i = 0; i < kItems; ++i) {
+                            const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                            const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
+                            const uint32_t st = (stbits >> (2 * i)) & 3u;
+                            if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
+                            const int ls = sl - w0;
+                            if (!filter_cand(X[i], Y[i], st, sm->lgeo[ls], sm->lm[st][ls])) continue;
+                            ncand++;
+                            atomicMax(&sm->k1[st][ls], (uint64_t)child_d(X[i], Y[i], st, sm->lgeo[ls]));
+                        }
+                        __syncthreads();
+                    }
+                    // tie-break among the farthest points, then the winner (the
+                    // exact distances are recomputed rather than kept)
 #pragma unroll
                     for (int i = 0; i < kItems; ++i) {
                         const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
@@ -815,134 +921,152 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
                         const uint32_t st = (stbits >> (2 * i)) & 3u;
                         if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
                         const int ls = sl - w0;
-                        const int ax = st == 0 ? sm->lgeo[ls][0] : sm->lgeo[ls][2];
-                        const int ay = st == 0 ? sm->lgeo[ls][1] : sm->lgeo[ls][3];
-                        const int bx = st == 0 ? sm->lgeo[ls][2] : sm->lgeo[ls][4];
-                        const int by = st == 0 ? sm->lgeo[ls][3] : sm->lgeo[ls][5];
-                        float B;
-                        const float e = cross_f32(X[i], Y[i], ax, ay, bx, by, B);
-                        uint64_t d = 0;
-                        if (fkey(__fadd_rn(e, 2.f * B)) >= sm->lm[st][ls]) {
-                            ncand++;
-                            d = (uint64_t)cross_i64(X[i], Y[i], ax, ay, bx, by);
-                            atomicMax(&sm->k1[st][ls], d);
+                        if (MODE != 0 && !filter_cand(X[i], Y[i], st, sm->lgeo[ls], sm->lm[st][ls])) continue;
+                        if ((uint64_t)child_d(X[i], Y[i], st, sm->lgeo[ls]) != sm->k1[st][ls]) continue;
+                        const int ex = st == 0 ? sm->lgeo[ls][2] - sm->lgeo[ls][0] : sm->lgeo[ls][4] - sm->lgeo[ls][2];
+                        const int ey = st == 0 ? sm->lgeo[ls][3] - sm->lgeo[ls][1] : sm->lgeo[ls][5] - sm->lgeo[ls][3];
+                        atomicMin(&sm->k2[st][ls], tie_key(X[i], Y[i], I[i], ex, ey));
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int i = 0; i < kItems; ++i) {
+                        const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
+                        const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
+                        const uint32_t st = (stbits >> (2 * i)) & 3u;
+                        if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
+                        const int ls = sl - w0;
+                        if (MODE != 0 && !filter_cand(X[i], Y[i], st, sm->lgeo[ls], sm->lm[st][ls])) continue;
+                        if ((uint64_t)child_d(X[i], Y[i], st, sm->lgeo[ls]) != sm->k1[st][ls]) continue;
+                        const int ex = st == 0 ? sm->lgeo[ls][2] - sm->lgeo[ls][0] : sm->lgeo[ls][4] - sm->lgeo[ls][2];
+                        const int ey = st == 0 ? sm->lgeo[ls][3] - sm->lgeo[ls][1] : sm->lgeo[ls][5] - sm->lgeo[ls][3];
+                        if (tie_key(X[i], Y[i], I[i], ex, ey) == sm->k2[st][ls]) {
+                            sm->res[st][ls][0] = X[i]; sm->res[st][ls][1] = Y[i]; sm->res[st][ls][2] = I[i];
                         }
-                        sm->Dl[v - lo] = d;
+                    }
+                    __syncthreads();
+                    // whole segments directly, the tile's first and last as partials
+                    for (int j = tid; j < wn; j += kBlock) {
+                        const int sl = w0 + j;
+                        const int g = gbase + s0 + sl;
+                        const bool inside = sm->sstart[sl] >= lo && sm->sstart[sl + 1] <= hi;
+                        for (int c = 0; c < 2; ++c) {
+                            Best b;
+                            b.key1 = sm->k1[c][j];
+                            b.key2 = sm->k2[c][j];
+                            b.x = b.key1 ? sm->res[c][j][0] : 0;
+                            b.y = b.key1 ? sm->res[c][j][1] : 0;
+                            b.idx = b.key1 ? sm->res[c][j][2] : 0;
+                            b.cnt = (int32_t)sm->scnt[c][j];
+                            if (inside) ws.adir[g * 2 + c] = b;
+                            if (sl == 0) ws.recF[tile * 2 + c] = b;
+                            if (sl == m - 1) ws.recL[tile * 2 + c] = b;
+                        }
                     }
                     __syncthreads();
                 }
-                // tie-break among the farthest points, then the winner
+                // the tile's survivor totals (packed), kept in wave 0's slot
+                uint32_t c = row_count(stbits, 0);
 #pragma unroll
-                for (int i = 0; i < kItems; ++i) {
-                    const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-                    const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
-                    const uint32_t st = (stbits >> (2 * i)) & 3u;
-                    if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
-                    const int ls = sl - w0;
-                    if (sm->Dl[v - lo] != sm->k1[st][ls]) continue;
-                    const int ex = st == 0 ? sm->lgeo[ls][2] - sm->lgeo[ls][0] : sm->lgeo[ls][4] - sm->lgeo[ls][2];
-                    const int ey = st == 0 ? sm->lgeo[ls][3] - sm->lgeo[ls][1] : sm->lgeo[ls][5] - sm->lgeo[ls][3];
-                    atomicMin(&sm->k2[st][ls], tie_key(X[i], Y[i], I[i], ex, ey));
-                }
-                __syncthreads();
+                for (int qq = 1; qq < kQ; ++qq) c += row_count(stbits, qq);
+                c = wave_sum(c);
+                if (lane == 0) sm->wcnt[it][wv] = c;
+                if (tid == 0) sm->tgen[it] = 1;
+            }
+            sm->stc[it][tid] = stbits;
+        }
+        __syncthreads();
+
+        // ---------------- chunk bookkeeping: tile records, offsets, look-back
+        if (tid < 2 * tcount) {
+            // merge the wave records of every one-segment tile
+            const int it = tid >> 1, c = tid & 1;
+            if (!sm->tgen[it]) {
+                const int lt = t_first + it;
+                const int tile = (R ? nt0 : 0) + lt;
+                const int lo = lt * kTile;
+                const int hi = min(lo + kTile, NR);
+                const TileInfo ti = ws.tinfo(p, R)[lt];
+                Best b = sm->wrec[it][0][c];
 #pragma unroll
-                for (int i = 0; i < kItems; ++i) {
-                    const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-                    const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
-                    const uint32_t st = (stbits >> (2 * i)) & 3u;
-                    if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
-                    const int ls = sl - w0;
-                    if (sm->Dl[v - lo] != sm->k1[st][ls]) continue;
-                    const int ex = st == 0 ? sm->lgeo[ls][2] - sm->lgeo[ls][0] : sm->lgeo[ls][4] - sm->lgeo[ls][2];
-                    const int ey = st == 0 ? sm->lgeo[ls][3] - sm->lgeo[ls][1] : sm->lgeo[ls][5] - sm->lgeo[ls][3];
-                    if (tie_key(X[i], Y[i], I[i], ex, ey) == sm->k2[st][ls]) {
-                        sm->res[st][ls][0] = X[i]; sm->res[st][ls][1] = Y[i]; sm->res[st][ls][2] = I[i];
-                    }
-                }
-                __syncthreads();
-                // whole segments directly, the tile's first and last as partials
-                for (int j = tid; j < wn; j += kBlock) {
-                    const int sl = w0 + j;
-                    const int g = gbase + s0 + sl;
-                    const bool inside = sm->sstart[sl] >= lo && sm->sstart[sl + 1] <= hi;
-                    for (int c = 0; c < 2; ++c) {
-                        Best b;
-                        b.key1 = sm->k1[c][j];
-                        b.key2 = sm->k2[c][j];
-                        b.x = b.key1 ? sm->res[c][j][0] : 0;
-                        b.y = b.key1 ? sm->res[c][j][1] : 0;
-                        b.idx = b.key1 ? sm->res[c][j][2] : 0;
-                        b.pad = 0;
-                        if (inside) ws.adir[g * 2 + c] = b;
-                        if (sl == 0) ws.recF[tile * 2 + c] = b;
-                        if (sl == m - 1) ws.recL[tile * 2 + c] = b;
-                    }
-                }
-                __syncthreads();
+                for (int w = 1; w < kNW; ++w) rec_merge(b, sm->wrec[it][w][c]);
+                if (ti.start >= lo && ti.end <= hi) ws.adir[(gbase + ti.seg) * 2 + c] = b;
+                ws.recF[tile * 2 + c] = b;
+                ws.recL[tile * 2 + c] = b;
             }
         }
-
-        // 3. ranks of the survivors inside the tile (point order), per child
-        uint32_t cnt[kQ], tot[kQ];
-#pragma unroll
-        for (int qq = 0; qq < kQ; ++qq) {
-            uint32_t c = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t st = (stbits >> (2 * (qq * 4 + j))) & 3u;
-                c += st == 0 ? 1u : (st == 1 ? 0x10000u : 0u);
+        if (tid == 0) {
+            // chunk-local offsets of every (tile, wave) part, in chunk order
+            uint32_t acc = 0;
+            for (int it = 0; it < tcount; ++it) {
+                for (int w = 0; w < kNW; ++w) {
+                    sm->woff[it][w] = acc;
+                    acc += sm->wcnt[it][w];
+                }
             }
-            cnt[qq] = c;
+            sm->s_tot = acc;
         }
-        block_excl_scan<kBlock, kQ>(cnt, tot, sm->scan);
-        uint32_t rowbase[kQ];
-        uint32_t acc = 0;
-#pragma unroll
-        for (int qq = 0; qq < kQ; ++qq) { rowbase[qq] = acc; acc += tot[qq]; }
-        const uint32_t c0 = acc & 0xffffu, c1 = acc >> 16;
-
-        // 4. decoupled look-back: global offsets of this tile's survivors
+        __syncthreads();
+        const uint32_t run = sm->s_tot;
+        const uint32_t c0 = run & 0xffffu, c1 = run >> 16;
         if (wv == 0) {
-            const uint64_t ex = lookback_excl(ws.st2(p), tile, pack2(c0, c1), &ctl->error);
+            const uint64_t ex = lookback_excl(ws.st2(p), ch, pack2(c0, c1), &ctl->error);
             if (lane == 0) sm->s_ex = ex;
         }
         __syncthreads();
         const uint32_t E0 = unpackA(sm->s_ex), E1 = unpackB(sm->s_ex);
 
-        // 5. scatter the survivors into the two child regions; segment
-        // boundaries record their global offsets
+        // ---------------- pass 2: scatter the survivors of every tile
         int32_t *ox0 = ws.px(q, 0), *oy0 = ws.py(q, 0), *oi0 = ws.pi(q, 0);
         int32_t *ox1 = ws.px(q, 1), *oy1 = ws.py(q, 1), *oi1 = ws.pi(q, 1);
         const uint32_t cap = (uint32_t)ws.cap_pts;
         bool oob = false;
+        for (int it = 0; it < tcount; ++it) {
+            const int lt = t_first + it;
+            const int lo = lt * kTile;
+            const int hi = min(lo + kTile, NR);
+            int32_t X[kItems], Y[kItems], I[kItems];
+            load_tile(ws, a, INIT, p, R, lo, hi, X, Y, I);
+            const uint32_t stbits = sm->stc[it][tid];
+            uint32_t rr[kQ];
+            if (!sm->tgen[it]) {
+                // one segment: any order inside the tile keeps the children
+                // contiguous; wave order (wave, row, lane, item)
+                uint32_t base = sm->woff[it][wv];
 #pragma unroll
-        for (int qq = 0; qq < kQ; ++qq) {
-            uint32_t run = rowbase[qq] + cnt[qq];
+                for (int qq = 0; qq < kQ; ++qq) {
+                    const uint32_t c = row_count(stbits, qq);
+                    const uint32_t inc = wave_incl_sum(c);
+                    rr[qq] = base + inc - c;
+                    base += wave_read(inc, kWave - 1);
+                }
+            } else {
+                // several segments: point order
+                uint32_t cnt[kQ], rowbase[kQ];
+                (void)tile_ranks(stbits, cnt, rowbase, sm->scan);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int i = qq * 4 + j;
-                const int v = lo + qq * kBlock * 4 + tid * 4 + j;
-                const uint32_t st = (stbits >> (2 * i)) & 3u;
-                const uint32_t e0 = E0 + (run & 0xffffu);
-                const uint32_t e1 = E1 + (run >> 16);
-                if (v < hi) {
-                    const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
-                    const int g = gbase + s0 + sl;
-                    if (v == sm->sstart[sl]) ws.pst[g] = make_int2((int)e0, (int)e1);
+                for (int qq = 0; qq < kQ; ++qq) rr[qq] = sm->woff[it][0] + rowbase[qq] + cnt[qq];
+            }
+#pragma unroll
+            for (int qq = 0; qq < kQ; ++qq) {
+                uint32_t q_ = rr[qq];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = qq * 4 + j;
+                    const uint32_t st = (stbits >> (2 * i)) & 3u;
+                    const uint32_t e0 = E0 + (q_ & 0xffffu);
+                    const uint32_t e1 = E1 + (q_ >> 16);
                     if (st == 0) {
                         if (e0 < cap) { ox0[e0] = X[i]; oy0[e0] = Y[i]; oi0[e0] = I[i]; } else oob = true;
+                        q_ += 1u;
                     } else if (st == 1) {
                         if (e1 < cap) { ox1[e1] = X[i]; oy1[e1] = Y[i]; oi1[e1] = I[i]; } else oob = true;
+                        q_ += 0x10000u;
                     }
-                    const uint32_t run2 = run + (st == 0 ? 1u : (st == 1 ? 0x10000u : 0u));
-                    if (v == sm->sstart[sl + 1] - 1)
-                        ws.pen[g] = make_int2((int)(E0 + (run2 & 0xffffu)), (int)(E1 + (run2 >> 16)));
-                    run = run2;
                 }
             }
         }
         if (oob) atomicOr(&ctl->error, kErrInternal);
-        if (tile == ntiles - 1 && tid == 0) {
+        if (ch == nchunks - 1 && tid == 0) {
             rn->n[0] = (int32_t)(E0 + c0);
             rn->n[1] = (int32_t)(E1 + c1);
             if (INIT) {
@@ -955,8 +1079,6 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
             ctl->rounds_with_work += 1ull;
         }
         __syncthreads();
-        tile = sm->s_next[it & 1];
-        ++it;
     }
     if (MODE != 0) {
         if (tid == 0) { sm->stat[0] = 0; sm->stat[1] = 0; sm->stat[2] = 0; }
@@ -994,8 +1116,10 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
 
     if (blockIdx.x == 0 && tid == 0) rn->seg_ctr = 0;
-    for (int i = blockIdx.x * kSegBlock + tid; i < 2 * nsegt + 4 && i < ws.s4cap; i += gridDim.x * kSegBlock)
+    for (int i = blockIdx.x * kSegBlock + tid; i < 2 * nsegt + 4 && i < ws.s4cap; i += gridDim.x * kSegBlock) {
         ws.st4(q)[i] = 0;
+        ws.st4b(q)[i] = 0;
+    }
     if (Stot == 0 || ctl->error) {
         if (blockIdx.x == 0 && tid == 0) {
             rn->s[0] = 0; rn->s[1] = 0; rn->hbase = hbase;
@@ -1010,7 +1134,7 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             sm->qn_map = 0;
         }
         __syncthreads();
-        const int tile = sm->s_tile;
+        const int tile = __builtin_amdgcn_readfirstlane(sm->s_tile);
         if (tile >= nsegt) break;
         const int g = tile * kSegBlock + tid;
         const bool valid = g < Stot;
@@ -1018,48 +1142,16 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
         const int s = g - (R ? S0 : 0);
         SegGeo G = {};
         SegTop Tp = {};
-        int2 ps = make_int2(0, 0), pe = make_int2(0, 0);
-        int c0 = 0, c1 = 0, fc = 0;
         if (valid) {
             G = ws.geo(p, R)[s];
             Tp = ws.top(p, R)[s];
-            ps = ws.pst[g];
-            pe = ws.pen[g];
-            c0 = pe.x - ps.x;
-            c1 = pe.y - ps.y;
-            // the apex f of this segment joins the hull between u and v
-            const bool same = (G.fx == G.ux) && (G.fy == G.uy);
-            fc = same ? Tp.uc : hbase + g;
-            if (!same) {
-                if (fc < ws.hcap) {
-                    ws.V[fc] = Tp.fidx;
-                    ws.hinst[fc] = Tp.inst;
-                    ws.nxt[fc] = Tp.vc;
-                } else {
-                    atomicOr(&ctl->error, kErrHullCap);
-                }
-            }
-            ws.nxt[Tp.uc] = fc;
         }
-        const bool has0 = valid && c0 > 0, has1 = valid && c1 > 0;
-        uint32_t v[2] = {has0 ? 1u : 0u, has1 ? 1u : 0u}, tot[2];
-        block_excl_scan<kSegBlock, 2>(v, tot, sm->scan);
-        if (wv == 0) {
-            const uint64_t ex = lookback_excl(ws.st4(p), tile, pack2(tot[0], tot[1]), &ctl->error);
-            if (lane == 0) sm->s_ex = ex;
-        }
-        __syncthreads();
-        const int id0 = (int)(unpackA(sm->s_ex) + v[0]);
-        const int id1 = (int)(unpackB(sm->s_ex) + v[1]);
-        const bool ok0 = has0 && id0 < ws.scap, ok1 = has1 && id1 < ws.scap;
-        if ((has0 && !ok0) || (has1 && !ok1)) atomicOr(&ctl->error, kErrSegCap);
 
-        // apexes of the two children
+        // the children's argmax and counts: merged over the tiles the segment spans
         Best b0 = best_none(), b1 = best_none();
         const int t0 = (R ? nt0 : 0) + G.start / kTile;
         const int t1 = (R ? nt0 : 0) + (G.start + G.len - 1) / kTile;
-        const bool want = valid && (has0 || has1);
-        if (want) {
+        if (valid) {
             if (t0 == t1) {
                 b0 = ws.adir[g * 2 + 0];
                 b1 = ws.adir[g * 2 + 1];
@@ -1067,8 +1159,8 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
                 b0 = ws.recL[t0 * 2 + 0];
                 b1 = ws.recL[t0 * 2 + 1];
                 for (int t = t0 + 1; t <= t1; ++t) {
-                    best_merge(b0, ws.recF[t * 2 + 0]);
-                    best_merge(b1, ws.recF[t * 2 + 1]);
+                    rec_merge(b0, ws.recF[t * 2 + 0]);
+                    rec_merge(b1, ws.recF[t * 2 + 1]);
                 }
             } else {
                 const int qi = atomicAdd(&sm->qn_apex, 1);
@@ -1086,11 +1178,52 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             const Best r1 = block_merge_tiles(ws.recF, ws.recL, a0, a1, 1, sm->red);
             if (tid == own) { b0 = r0; b1 = r1; }
         }
+        const int c0 = valid ? b0.cnt : 0, c1 = valid ? b1.cnt : 0;
+
+        // the apex f of this segment joins the hull between u and v
+        int fc = 0;
+        if (valid) {
+            const bool same = (G.fx == G.ux) && (G.fy == G.uy);
+            fc = same ? Tp.uc : hbase + g;
+            if (!same) {
+                if (fc < ws.hcap) {
+                    ws.V[fc] = Tp.fidx;
+                    ws.hinst[fc] = Tp.inst;
+                    ws.nxt[fc] = Tp.vc;
+                } else {
+                    atomicOr(&ctl->error, kErrHullCap);
+                }
+            }
+            ws.nxt[Tp.uc] = fc;
+        }
+
+        // ids of the non-empty children, and their start offsets (children of
+        // earlier segments come first, in both regions of the next round)
+        const bool has0 = valid && c0 > 0, has1 = valid && c1 > 0;
+        uint32_t v[2] = {has0 ? 1u : 0u, has1 ? 1u : 0u}, tot[2];
+        block_excl_scan<kSegBlock, 2>(v, tot, sm->scan);
+        if (wv == 0) {
+            const uint64_t ex = lookback_excl(ws.st4(p), tile, pack2(tot[0], tot[1]), &ctl->error);
+            if (lane == 0) sm->s_ex = ex;
+        }
+        uint32_t w[2] = {(uint32_t)c0, (uint32_t)c1}, wt[2];
+        block_excl_scan<kSegBlock, 2>(w, wt, sm->scan2);
+        if (wv == 0) {
+            const uint64_t ex = lookback_excl(ws.st4b(p), tile, pack2(wt[0], wt[1]), &ctl->error);
+            if (lane == 0) sm->s_ex2 = ex;
+        }
+        __syncthreads();
+        const int id0 = (int)(unpackA(sm->s_ex) + v[0]);
+        const int id1 = (int)(unpackB(sm->s_ex) + v[1]);
+        const int st0 = (int)(unpackA(sm->s_ex2) + w[0]);
+        const int st1 = (int)(unpackB(sm->s_ex2) + w[1]);
+        const bool ok0 = has0 && id0 < ws.scap, ok1 = has1 && id1 < ws.scap;
+        if ((has0 && !ok0) || (has1 && !ok1)) atomicOr(&ctl->error, kErrSegCap);
 
         // child segments of the next round
         if (ok0) {
             SegGeo cg;
-            cg.start = ps.x; cg.len = c0;
+            cg.start = st0; cg.len = c0;
             cg.ux = G.ux; cg.uy = G.uy;
             cg.fx = b0.x; cg.fy = b0.y;
             cg.vx = G.fx; cg.vy = G.fy;
@@ -1101,7 +1234,7 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
         }
         if (ok1) {
             SegGeo cg;
-            cg.start = ps.y; cg.len = c1;
+            cg.start = st1; cg.len = c1;
             cg.ux = G.fx; cg.uy = G.fy;
             cg.fx = b1.x; cg.fy = b1.y;
             cg.vx = G.vx; cg.vy = G.vy;
@@ -1116,7 +1249,7 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             const bool ok = c == 0 ? ok0 : ok1;
             if (!ok) continue;
             const int id = c == 0 ? id0 : id1;
-            const int st = c == 0 ? ps.x : ps.y;
+            const int st = c == 0 ? st0 : st1;
             const int ln = c == 0 ? c0 : c1;
             const int ka = (st + kTile - 1) / kTile;
             const int kb = (st + ln + kTile - 1) / kTile;

@@ -73,13 +73,12 @@ size_t carve(qh_ctx *c, char *base) {
     w.geo_ = cv.take<SegGeo>((size_t)4 * c->scap);
     w.top_ = cv.take<SegTop>((size_t)4 * c->scap);
     w.tinfo_ = cv.take<TileInfo>((size_t)4 * c->tcap);
-    w.pst = cv.take<int2>(2 * (size_t)c->scap);
-    w.pen = cv.take<int2>(2 * (size_t)c->scap);
     w.adir = cv.take<Best>(4 * (size_t)c->scap);
     w.recF = cv.take<Best>(2 * (size_t)c->tcap);
     w.recL = cv.take<Best>(2 * (size_t)c->tcap);
     w.st2_ = cv.take<uint64_t>((size_t)2 * (c->tcap + 4));
     w.st4_ = cv.take<uint64_t>((size_t)2 * c->s4cap);
+    w.st4b_ = cv.take<uint64_t>((size_t)2 * c->s4cap);
     w.recF0 = cv.take<Best>(2 * (size_t)c->tcap);
     w.recL0 = cv.take<Best>(2 * (size_t)c->tcap);
     w.dir0 = cv.take<Best>(2 * (size_t)c->kcap);

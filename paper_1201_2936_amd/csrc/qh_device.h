@@ -166,11 +166,12 @@ struct SegTop {
 
 // Best point of a child segment seen by one tile (or the reduction of several
 // tiles).  key1 is the exact distance (0 = no point), key2 the tie-break
-// (lower is better), then the point itself.
+// (lower is better), then the point itself and the number of the child's
+// points the record covers.
 struct Best {
     uint64_t key1;
     uint64_t key2;
-    int32_t x, y, idx, pad;
+    int32_t x, y, idx, cnt;
 };
 
 __device__ __forceinline__ bool best_better(const Best &a, const Best &b) {
@@ -184,7 +185,7 @@ struct RoundState {
     int32_t hbase;      // first compact hull id of this round's apexes
     uint32_t tile_ctr;  // dynamic tile counter of the round kernel
     uint32_t seg_ctr;   // dynamic tile counter of the segment kernel
-    int32_t pad;
+    int32_t chunk;      // tiles per chunk used by the round kernel
 };
 
 enum : int32_t {
