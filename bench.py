@@ -32,12 +32,18 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = "square_16m"
 METRIC = "Mpoints/s per hull + HBM GB/s; FP32-filtered/batched vs exact-int64, bit-exact"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_round_square_16m.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1201_2936_amd", "csrc", "qh2d_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1201_2936_amd", "csrc")
 
 
 def kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of every kernel source: a traffic figure taken from other sources
+    is stale."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic():
