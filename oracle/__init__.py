@@ -9,6 +9,9 @@ method's arithmetic.
 
 * ``hull2d`` / ``hull2d_batched``: the C oracle in ``qh_oracle.c`` (Algorithm
   1 in 2D, first split of Algorithm 4), exact 128-bit predicates.
+* ``hull3d``: the C oracle in ``qh_oracle3d.c`` (Algorithm 1 in 3D with
+  outside sets, visible facets and horizons), exact 128-bit predicates,
+  canonical triangulation of every face.
 * ``segmented``: ``flagPermute`` and ``compact`` (Algorithms 2 and 3).
 """
 from __future__ import annotations
@@ -51,7 +54,7 @@ def _load():
     lib.qho_hull2d_batched.restype = ctypes.c_int64
     lib.qho_hull2d_batched.argtypes = [i32p, i32p, i64p, ctypes.c_int64, i32p, i64p]
     if hasattr(lib, "qho_hull3d"):
-        lib.qho_hull3d.restype = ctypes.c_int64
+        lib.qho_hull3d.restype = ctypes.c_int
         lib.qho_hull3d.argtypes = [i32p, i32p, i32p, ctypes.c_int64, i32p, i64p,
                                    i32p, i64p]
     _lib = lib
@@ -96,3 +99,33 @@ def hull2d_batched(pts, offsets):
     if h < 0:
         raise MemoryError("oracle ran out of memory")
     return out[:h].copy(), out_off
+
+
+class Degenerate(ValueError):
+    """Fewer than four affinely independent points (no 3D hull)."""
+
+
+def hull3d(pts):
+    """3D hull of int32[3, n] points: (facets int32[F, 3], vertices int32[V]).
+
+    Facets are the canonical triangulation (every face fanned from its
+    lowest-index vertex, counter-clockwise seen from outside), triples sorted;
+    vertices ascending.  Raises Degenerate when the points span less than 3D.
+    """
+    lib = _load()
+    pts = np.ascontiguousarray(pts, dtype=np.int32)
+    n = pts.shape[1]
+    x = np.ascontiguousarray(pts[0])
+    y = np.ascontiguousarray(pts[1])
+    z = np.ascontiguousarray(pts[2])
+    fac = np.empty(3 * max(2 * n - 4, 4), np.int32)
+    ver = np.empty(max(n, 1), np.int32)
+    nf = ctypes.c_int64(0)
+    nv = ctypes.c_int64(0)
+    rc = lib.qho_hull3d(_p32(x), _p32(y), _p32(z), n, _p32(fac), ctypes.byref(nf),
+                        _p32(ver), ctypes.byref(nv))
+    if rc == -4:
+        raise Degenerate("fewer than four affinely independent points")
+    if rc != 0:
+        raise MemoryError("oracle ran out of memory")
+    return fac[: 3 * nf.value].reshape(-1, 3).copy(), ver[: nv.value].copy()
