@@ -14,7 +14,9 @@ B per survivor written; later rounds 12 B per point read and 12 B per survivor
 written) over its average launch duration, timed with HIP events around each
 launch on the stream it runs on.
 ``cpu_baseline`` is the oracle (plain single-threaded C Quickhull) on the
-same points.
+same points.  ``batched`` is the batched form on 4,096 disks (about 5.1e8
+points) in one qh_hull2d_batched call, beside 4,096 sequential qh_hull2d
+calls; its round-kernel figures are timed the same way.
 """
 from __future__ import annotations
 
@@ -89,12 +91,103 @@ def cpu_baseline(pts, budget_s: float = 12.0):
             "sample": f"{WORKLOAD} full ({n} points), {runs} runs in {el:.1f} s, single thread"}
 
 
+def batched_leg(steps: int):
+    """The batched form on 4,096 disks (sizes log-uniform in [256, 2^20],
+    about 5.1e8 points) in one qh_hull2d_batched call, beside 4,096
+    sequential qh_hull2d calls on the same device-resident instances."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1201_2936_amd import qh
+
+    t0 = time.perf_counter()
+    pts_np, off_np = workloads.batched_disks()
+    gen_s = time.perf_counter() - t0
+    k = len(off_np) - 1
+    N = int(off_np[-1])
+    pts = torch.from_numpy(pts_np).cuda()
+    off = torch.from_numpy(off_np).cuda()
+    ctx = qh.Context()
+
+    def run(mode):
+        return qh.qh_hull2d_batched(pts, off, mode=mode, ctx=ctx)
+
+    sec_f, (idx_f, hoff_f, st_f) = time_steps(lambda: run(qh.QH_FP32_FILTER), steps, 1)
+    sec_x, (idx_x, hoff_x, _) = time_steps(lambda: run(qh.QH_EXACT_INT64), max(2, steps // 2), 1)
+    same = bool(torch.equal(idx_f, idx_x) and torch.equal(hoff_f, hoff_x))
+
+    # per-launch kernel timing of the round kernel (separate pass)
+    agg = {"round_kernel_bytes": 0.0, "round_kernel_ms": 0.0, "round_launches": 0.0,
+           "kernel_ms": 0.0, "split_ms": 0.0, "extremes_ms": 0.0, "segment_ms": 0.0}
+    tsteps = max(1, steps // 2)
+    for _ in range(tsteps):
+        _, _, s = qh.qh_hull2d_batched(pts, off, mode=qh.QH_FP32_FILTER, ctx=ctx, timing=True)
+        for key in agg:
+            agg[key] += s[key]
+    launches = max(agg["round_launches"], 1)
+    avg_ms = agg["round_kernel_ms"] / launches
+    bpl = agg["round_kernel_bytes"] / launches
+
+    # 4,096 sequential single-hull calls on contiguous per-instance copies
+    singles = [torch.stack([pts[0, off_np[i]:off_np[i + 1]], pts[1, off_np[i]:off_np[i + 1]]]).contiguous()
+               for i in range(k)]
+    sctx = qh.Context()
+    for i in range(min(k, 64)):
+        qh.qh_hull2d(singles[i], mode=qh.QH_FP32_FILTER, ctx=sctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_ok = True
+    hoff_host = hoff_f.cpu().numpy()
+    idx_host = idx_f.cpu().numpy()
+    for i in range(k):
+        one, _ = qh.qh_hull2d(singles[i], mode=qh.QH_FP32_FILTER, ctx=sctx)
+        if i % 64 == 0:
+            seq_ok &= np.array_equal(one.cpu().numpy(), idx_host[hoff_host[i]:hoff_host[i + 1]])
+    torch.cuda.synchronize()
+    sec_seq = time.perf_counter() - t0
+
+    # oracle parity on a sample of instances
+    import oracle  # checker only
+    sample = list(range(0, k, 97))
+    par = all(np.array_equal(oracle.hull2d(pts_np[:, off_np[i]:off_np[i + 1]]),
+                             idx_host[hoff_host[i]:hoff_host[i + 1]]) for i in sample)
+    sctx.close()
+    ctx.close()
+    del singles, pts, off
+    torch.cuda.empty_cache()
+    ach = bpl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return {
+        "workload": "batched_disks: 4,096 disks of radius 2^20, sizes log-uniform in [256, 2^20]",
+        "n_total": N, "k": k, "generate_s": round(gen_s, 1),
+        "fp32_filter": {"value": round(N / sec_f / 1e6, 3), "unit": "Mpoints/s",
+                        "ms_per_step": round(sec_f * 1e3, 3), "steps": steps},
+        "exact_int64": {"value": round(N / sec_x / 1e6, 3), "unit": "Mpoints/s",
+                        "ms_per_step": round(sec_x * 1e3, 3)},
+        "sequential_single_calls": {"value": round(N / sec_seq / 1e6, 3), "unit": "Mpoints/s",
+                                    "ms": round(sec_seq * 1e3, 1), "calls": k,
+                                    "match_batched": bool(seq_ok)},
+        "modes_identical": same,
+        "parity_vs_oracle_sample": {"instances": len(sample), "ok": bool(par)},
+        "rounds": int(st_f["rounds"]),
+        "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"]) if st_f["filter_tests"] else 0.0,
+        "round_kernel": {"launches_per_step": launches / tsteps, "avg_launch_us": round(avg_ms * 1e3, 2),
+                         "bytes_per_launch": round(bpl), "achieved_GBs": round(ach, 1),
+                         "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)},
+        "device_time_us": {"all_kernels": round(agg["kernel_ms"] / tsteps * 1e3, 1),
+                           "extremes": round(agg["extremes_ms"] / tsteps * 1e3, 1),
+                           "segments": round(agg["segment_ms"] / tsteps * 1e3, 1)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched 4,096-instance leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the hull of one point set "
@@ -195,6 +288,10 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pts_np)
     ctx.close()
+    del pts
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        line["batched"] = batched_leg(max(2, min(args.steps, 5)))
     print(json.dumps(line), flush=True)
 
 

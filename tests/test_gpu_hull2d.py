@@ -188,3 +188,120 @@ def test_circle_mix_4m(qhm, ctx, mode):
     if mode == 1:
         # the exactly collinear support lines force undecided FP32 signs
         assert stats["filter_fallbacks"] > 0
+
+
+# ---------------------------------------------------------------------------
+# batched form: k instances in one call
+# ---------------------------------------------------------------------------
+def _gpu_batched(qhm, ctx, pts, offsets, mode):
+    t = torch.from_numpy(np.ascontiguousarray(pts)).to("cuda")
+    o = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int64)).to("cuda")
+    idx, hoff, stats = qhm.qh_hull2d_batched(t, o, mode=mode, ctx=ctx)
+    return idx.cpu().numpy(), hoff.cpu().numpy(), stats
+
+
+def _small_instance(rng, kind):
+    if kind == 0:
+        return np.zeros((2, 0), np.int32)
+    if kind == 1:
+        n = int(rng.integers(1, 4))
+        return workloads.small_random(int(rng.integers(1 << 30)), n, 50)
+    if kind == 2:
+        return workloads.small_collinear(int(rng.integers(1 << 30)), int(rng.integers(2, 300)))
+    if kind == 3:
+        return workloads.small_grid(int(rng.integers(1 << 30)), int(rng.integers(1, 3000)), 7)
+    if kind == 4:
+        return np.full((2, int(rng.integers(1, 500))), int(rng.integers(-9, 9)), np.int32)
+    n = int(rng.integers(1, 9000))
+    return workloads.small_random(int(rng.integers(1 << 30)), n, int(rng.choice([30, 1 << 20, (1 << 30) - 1])))
+
+
+def _concat(insts):
+    sizes = np.array([p.shape[1] for p in insts], np.int64)
+    offsets = np.zeros(len(insts) + 1, np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    pts = np.concatenate(insts, axis=1) if offsets[-1] else np.zeros((2, 0), np.int32)
+    return np.ascontiguousarray(pts.astype(np.int32)), offsets
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("seed", range(6))
+def test_batched_small_mixed(qhm, ctx, mode, seed):
+    rng = np.random.default_rng(1000 + seed)
+    k = int(rng.integers(1, 80))
+    insts = [_small_instance(rng, int(rng.integers(0, 6))) for _ in range(k)]
+    pts, offsets = _concat(insts)
+    _say(f"batched seed={seed} k={k} N={offsets[-1]} mode={mode}")
+    want, want_off = oracle.hull2d_batched(pts, offsets)
+    got, got_off, _ = _gpu_batched(qhm, ctx, pts, offsets, mode)
+    assert got_off.tolist() == want_off.tolist()
+    assert got.tolist() == want.tolist()
+    # and each instance alone
+    for i, p in enumerate(insts):
+        assert got[got_off[i]:got_off[i + 1]].tolist() == oracle.hull2d(p).tolist()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batched_many_tiny_instances(qhm, ctx, mode):
+    rng = np.random.default_rng(77)
+    insts = []
+    for _ in range(5000):
+        n = int(rng.integers(0, 40))
+        insts.append(workloads.small_random(int(rng.integers(1 << 30)), n, 1000) if n else
+                     np.zeros((2, 0), np.int32))
+    pts, offsets = _concat(insts)
+    _say(f"batched tiny k=5000 N={offsets[-1]} mode={mode}")
+    want, want_off = oracle.hull2d_batched(pts, offsets)
+    got, got_off, _ = _gpu_batched(qhm, ctx, pts, offsets, mode)
+    assert got_off.tolist() == want_off.tolist()
+    assert got.tolist() == want.tolist()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batched_equals_single_calls(qhm, ctx, mode):
+    sizes = np.array([256, 300, 5000, 70000, 2048, 2049, 1 << 17, 999], np.int64)
+    pts, offsets = workloads.batched_disks(len(sizes), sizes)
+    _say(f"batched vs single N={offsets[-1]} mode={mode}")
+    got, got_off, _ = _gpu_batched(qhm, ctx, pts, offsets, mode)
+    for i in range(len(sizes)):
+        single, _ = _gpu_hull(qhm, ctx, pts[:, offsets[i]:offsets[i + 1]], mode)
+        assert got[got_off[i]:got_off[i + 1]].tolist() == single.tolist()
+    want, want_off = oracle.hull2d_batched(pts, offsets)
+    assert got.tolist() == want.tolist()
+
+
+def test_batched_bad_offsets(qhm, ctx):
+    pts = torch.zeros((2, 10), dtype=torch.int32, device="cuda")
+    for off in ([0, 5, 3, 10], [0, 5, 11], [1, 5, 10], [0, 4, 9]):
+        o = torch.tensor(off, dtype=torch.int64, device="cuda")
+        with pytest.raises(qhm.QhError) as ei:
+            qhm.qh_hull2d_batched(pts, o, ctx=ctx)
+        assert ei.value.status == qhm.QH_EINVAL
+    # still usable afterwards
+    o = torch.tensor([0, 4, 10], dtype=torch.int64, device="cuda")
+    idx, hoff, _ = qhm.qh_hull2d_batched(pts, o, ctx=ctx)
+    assert hoff.cpu().tolist() == [0, 1, 2] and idx.cpu().tolist() == [0, 0]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batched_disks_4096(qhm, ctx, mode, batched_full):
+    """The full batched workload: 4,096 disks, about 5.1e8 points."""
+    pts_t, off_t, want, want_off = batched_full
+    _say(f"batched_disks full N={int(off_t[-1])} mode={mode}")
+    idx, hoff, st = qhm.qh_hull2d_batched(pts_t, off_t, mode=mode, ctx=ctx)
+    assert hoff.cpu().numpy().tolist() == want_off.tolist()
+    assert np.array_equal(idx.cpu().numpy(), want)
+
+
+@pytest.fixture(scope="module")
+def batched_full(qhm):
+    _say("generating the 4,096-disk batch")
+    pts, offsets = workloads.batched_disks()
+    _say("oracle on the 4,096-disk batch")
+    want, want_off = oracle.hull2d_batched(pts, offsets)
+    pts_t = torch.from_numpy(pts).to("cuda")
+    off_t = torch.from_numpy(offsets).to("cuda")
+    del pts
+    yield pts_t, off_t, want, want_off
+    del pts_t, off_t
+    torch.cuda.empty_cache()
