@@ -94,6 +94,8 @@ typedef struct qh_stats {
     int64_t max_segments;       /* most segments alive in one round */
     int64_t grid_blocks;        /* blocks of a round-kernel launch */
     int64_t host_syncs;         /* device-to-host waits of the call */
+    double host_ms;             /* host time of the 3D topology step and output
+                                   (qh_hull3d only) */
 } qh_stats;
 
 typedef struct qh_opts {
@@ -149,6 +151,34 @@ qh_status qh_hull2d(const int32_t *pts, int64_t n, int32_t *hull_idx, int64_t *h
 qh_status qh_hull2d_batched(const int32_t *pts, int64_t n_total, const int64_t *offsets,
                             int32_t k, int32_t *hull_idx, int64_t *hull_offsets,
                             int64_t *h_total, const qh_opts *opts);
+
+/*
+ * 3D convex hull (Algorithm 1 with d = 3; Section 4.3 on three dimensions).
+ * Every facet with points outside it finds its farthest point (its apex);
+ * apexes whose visible regions do not touch replace their regions by cones
+ * in the same round; the points of a removed facet go to the first new facet
+ * of its cone they lie strictly above, or are dropped.
+ *
+ *   pts      device int32[3*n]: x[0..n), y[0..n), z[0..n); |coordinate| <= 2^19
+ *            (so every plane test is exact in int64), else QH_ERANGE
+ *   n        number of points, 4 <= n <= 2^30 - 2^12
+ *   facets   device int32[3 * (2n - 4)]: triangles as index triples,
+ *            counter-clockwise seen from outside.  Every face of the hull (a
+ *            maximal planar region) is a fan from its lowest-index vertex over
+ *            its vertices, and the triples are sorted, so the list is a
+ *            function of the point set alone
+ *   nfacets  host: triangles written (2 * nverts - 4)
+ *   verts    device int32[n]: hull vertex indices (extreme points, the lowest
+ *            index among duplicates), ascending
+ *   nverts   host: vertices written
+ *
+ * Fewer than four affinely independent points give QH_EDEGENERATE.  In
+ * QH_FP32_FILTER mode the plane tests of the classification are made in FP32
+ * with an error bound and redone in int64 when undecided; the output is the
+ * same.  The topology step runs on the host, inside the call.
+ */
+qh_status qh_hull3d(const int32_t *pts, int64_t n, int32_t *facets, int64_t *nfacets,
+                    int32_t *verts, int64_t *nverts, const qh_opts *opts);
 
 #ifdef __cplusplus
 }

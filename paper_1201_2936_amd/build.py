@@ -8,8 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqh.so")
-SOURCES = ["qh2d_kernels.hip", "qh_api.hip"]
-HEADERS = ["qh_device.h", "qh2d.h"]
+SOURCES = ["qh2d_kernels.hip", "qh_api.hip", "qh3d_kernels.hip", "qh3d_host.hip"]
+HEADERS = ["qh_device.h", "qh2d.h", "qh_ctx.h", "qh3d.h"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

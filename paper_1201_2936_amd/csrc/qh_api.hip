@@ -22,31 +22,13 @@
 
 #include "../../include/qh.h"
 #include "qh2d.h"
+#include "qh_ctx.h"
 
 using namespace qh;
 
 namespace qh {
 hipError_t fill_single_offsets(int64_t *off, int64_t n, hipStream_t st);
 }
-
-struct qh_ctx {
-    int device = 0;
-    int cus = 256;
-    // capacities of the current allocation
-    int64_t cap_pts = 0;
-    int32_t scap = 0, hcap = 0, tcap = 0, s4cap = 0, kcap = 0;
-    // pending growth requests after a capacity overflow
-    int32_t want_scap = 0, want_hcap = 0;
-    void *dmem = nullptr;
-    size_t dbytes = 0;
-    Ws2 ws = {};
-    Control *ctl_host = nullptr;   // pinned copy of the control block
-    int64_t *h_host = nullptr;     // pinned: hull count of a single call
-    int64_t *single_off = nullptr; // device int64[2]
-    int64_t *single_hoff = nullptr;// device int64[2]
-    std::vector<hipEvent_t> ev;    // timing events (pairs)
-    int grid[2] = {0, 0};          // resident blocks of the round kernel, per mode
-};
 
 namespace {
 
@@ -134,6 +116,10 @@ qh_status ensure(qh_ctx *c, int64_t n, int32_t k) {
     return QH_OK;
 }
 
+}  // namespace
+
+namespace qhi {
+
 qh_status ctx_init(qh_ctx *c) {
     if (hipGetDevice(&c->device) != hipSuccess) return QH_EDEVICE;
     int cus = 0;
@@ -161,8 +147,16 @@ void ctx_free(qh_ctx *c) {
 
     if (c->ctl_host) (void)hipHostFree(c->ctl_host);
     if (c->h_host) (void)hipHostFree(c->h_host);
+    ctx3_free(c->c3);
     delete c;
 }
+
+}  // namespace qhi
+
+namespace {
+
+using qhi::ctx_free;
+using qhi::ctx_init;
 
 #define QH_TRY(expr)                                  \
     do {                                              \
@@ -316,13 +310,9 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
     return QH_OK;
 }
 
-struct TempCtx {
-    qh_ctx *c = nullptr;
-    bool owned = false;
-    ~TempCtx() {
-        if (owned) ctx_free(c);
-    }
-};
+}  // namespace
+
+namespace qhi {
 
 qh_status get_ctx(const qh_opts *o, TempCtx &t) {
     if (o && o->ctx) {
@@ -336,7 +326,10 @@ qh_status get_ctx(const qh_opts *o, TempCtx &t) {
     return ctx_init(c);
 }
 
-}  // namespace
+}  // namespace qhi
+
+using qhi::TempCtx;
+using qhi::get_ctx;
 
 extern "C" {
 

@@ -1,0 +1,53 @@
+// qh_ctx.h -- the workspace context behind the opaque qh_ctx handle (library
+// internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/qh.h"
+#include "qh2d.h"
+
+namespace qh3 {
+struct Ctx3;
+}
+
+struct qh_ctx {
+    int device = 0;
+    int cus = 256;
+    // capacities of the current allocation
+    int64_t cap_pts = 0;
+    int32_t scap = 0, hcap = 0, tcap = 0, s4cap = 0, kcap = 0;
+    // pending growth requests after a capacity overflow
+    int32_t want_scap = 0, want_hcap = 0;
+    void *dmem = nullptr;
+    size_t dbytes = 0;
+    qh::Ws2 ws = {};
+    qh::Control *ctl_host = nullptr;  // pinned copy of the control block
+    int64_t *h_host = nullptr;        // pinned: hull count of a single call
+    int64_t *single_off = nullptr;    // device int64[2]
+    int64_t *single_hoff = nullptr;   // device int64[2]
+    std::vector<hipEvent_t> ev;       // timing events (pairs)
+    int grid[2] = {0, 0};             // resident blocks of the round kernel, per mode
+    qh3::Ctx3 *c3 = nullptr;          // 3D workspace, made on the first 3D call
+};
+
+namespace qhi {
+
+qh_status ctx_init(qh_ctx *c);
+void ctx_free(qh_ctx *c);
+void ctx3_free(qh3::Ctx3 *c3);
+
+// A caller's context, or a temporary one freed at scope exit.
+struct TempCtx {
+    qh_ctx *c = nullptr;
+    bool owned = false;
+    ~TempCtx() {
+        if (owned) ctx_free(c);
+    }
+};
+
+qh_status get_ctx(const qh_opts *o, TempCtx &t);
+
+}  // namespace qhi

@@ -25,7 +25,7 @@ QH_FP32_FILTER = 1
 QH_FLAG_TIMING = 1
 
 EXPORTED = ["qh_ctx_create", "qh_ctx_destroy", "qh_status_str", "qh_version",
-            "qh_hull2d", "qh_hull2d_batched"]
+            "qh_hull2d", "qh_hull2d_batched", "qh_hull3d"]
 
 
 class QhStats(ctypes.Structure):
@@ -48,6 +48,7 @@ class QhStats(ctypes.Structure):
         ("max_segments", ctypes.c_int64),
         ("grid_blocks", ctypes.c_int64),
         ("host_syncs", ctypes.c_int64),
+        ("host_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -96,6 +97,9 @@ def load(path: str = LIB_PATH):
     lib.qh_hull2d_batched.restype = ctypes.c_int
     lib.qh_hull2d_batched.argtypes = [vp, i64, vp, ctypes.c_int32, vp, vp,
                                       ctypes.POINTER(i64), ctypes.POINTER(QhOpts)]
+    lib.qh_hull3d.restype = ctypes.c_int
+    lib.qh_hull3d.argtypes = [vp, i64, vp, ctypes.POINTER(i64), vp, ctypes.POINTER(i64),
+                              ctypes.POINTER(QhOpts)]
     _lib = lib
     return lib
 
@@ -191,3 +195,24 @@ def qh_hull2d_batched(pts, offsets, mode: int = QH_EXACT_INT64, ctx: Context | N
     if st != QH_OK:
         raise QhError(st, "qh_hull2d_batched")
     return out[: ht.value], hoff, stats.as_dict()
+
+
+def qh_hull3d(pts, mode: int = QH_EXACT_INT64, ctx: Context | None = None,
+              timing: bool = False, stream=None):
+    """3D hull of int32[3, n] device points: (facets int32[F, 3] on the device,
+    vertices int32[V] on the device, stats dict)."""
+    import torch
+    lib = load()
+    pts = _check_points(pts, 3)
+    n = pts.shape[1]
+    fac = torch.empty(3 * max(2 * n - 4, 4), dtype=torch.int32, device=pts.device)
+    ver = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
+    nf = ctypes.c_int64(0)
+    nv = ctypes.c_int64(0)
+    o, stats = _opts(ctx, mode, timing, stream)
+    st = lib.qh_hull3d(ctypes.c_void_p(pts.data_ptr()), n, ctypes.c_void_p(fac.data_ptr()),
+                       ctypes.byref(nf), ctypes.c_void_p(ver.data_ptr()), ctypes.byref(nv),
+                       ctypes.byref(o))
+    if st != QH_OK:
+        raise QhError(st, "qh_hull3d")
+    return fac[: 3 * nf.value].view(-1, 3), ver[: nv.value], stats.as_dict()
