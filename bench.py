@@ -16,7 +16,8 @@ launch on the stream it runs on.
 ``cpu_baseline`` is the oracle (plain single-threaded C Quickhull) on the
 same points.  ``batched`` is the batched form on 4,096 disks (about 5.1e8
 points) in one qh_hull2d_batched call, beside 4,096 sequential qh_hull2d
-calls; its round-kernel figures are timed the same way.
+calls; its round-kernel figures are timed the same way.  ``hull3d`` is the
+3D form (qh_hull3d) on 5,242,880 ball and sphere points.
 """
 from __future__ import annotations
 
@@ -180,6 +181,53 @@ def batched_leg(steps: int):
     }
 
 
+def hull3d_leg(steps: int):
+    """The 3D form on 4,194,304 points in the ball of radius 2^16 plus
+    1,048,576 snapped to its sphere (5,242,880 in total), exact int64 and FP32
+    filter, through qh_hull3d."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1201_2936_amd import qh
+
+    pts_np = workloads.ball_sphere_5m()
+    n = pts_np.shape[1]
+    pts = torch.from_numpy(pts_np).cuda()
+    ctx = qh.Context()
+    sec_x, (f_x, v_x, st_x) = time_steps(lambda: qh.qh_hull3d(pts, mode=qh.QH_EXACT_INT64, ctx=ctx),
+                                         steps, 1)
+    sec_f, (f_f, v_f, st_f) = time_steps(lambda: qh.qh_hull3d(pts, mode=qh.QH_FP32_FILTER, ctx=ctx),
+                                         steps, 1)
+    same = bool(torch.equal(f_x, f_f) and torch.equal(v_x, v_f))
+    _, _, tt = qh.qh_hull3d(pts, mode=qh.QH_EXACT_INT64, ctx=ctx, timing=True)
+    import oracle  # checker only
+    t0 = time.perf_counter()
+    want_f, want_v = oracle.hull3d(pts_np)
+    oracle_s = time.perf_counter() - t0
+    par = bool(np.array_equal(v_x.cpu().numpy(), want_v) and np.array_equal(f_x.cpu().numpy(), want_f))
+    ctx.close()
+    return {
+        "workload": "ball_sphere_5m: 4,194,304 in the ball of radius 2^16 + 1,048,576 on its sphere",
+        "n": n, "vertices": int(v_x.numel()), "facets": int(f_x.shape[0]),
+        "exact_int64": {"value": round(n / sec_x / 1e6, 3), "unit": "Mpoints/s",
+                        "ms_per_step": round(sec_x * 1e3, 2)},
+        "fp32_filter": {"value": round(n / sec_f / 1e6, 3), "unit": "Mpoints/s",
+                        "ms_per_step": round(sec_f * 1e3, 2),
+                        "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"])
+                        if st_f["filter_tests"] else 0.0},
+        "modes_identical": same, "parity_vs_oracle": par,
+        "rounds": int(st_x["rounds"]), "host_syncs": int(st_x["host_syncs"]),
+        "max_active_facets": int(st_x["max_segments"]),
+        "host_topology_ms": round(tt["host_ms"], 2),
+        "device_ms": {"classify": round(tt["round_kernel_ms"], 3), "apex": round(tt["segment_ms"], 3),
+                      "init": round(tt["extremes_ms"], 3), "all": round(tt["kernel_ms"], 3)},
+        "classify_apex_GBs": round(tt["round_kernel_bytes"] / ((tt["round_kernel_ms"] + tt["segment_ms"]) * 1e-3) / 1e9, 1)
+        if tt["round_kernel_ms"] > 0 else None,
+        "oracle_s": round(oracle_s, 2),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +236,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched 4,096-instance leg")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the hull of one point set "
@@ -292,6 +341,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         line["batched"] = batched_leg(max(2, min(args.steps, 5)))
+    if not args.no_3d:
+        line["hull3d"] = hull3d_leg(max(2, min(args.steps, 3)))
     print(json.dumps(line), flush=True)
 
 

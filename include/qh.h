@@ -96,6 +96,8 @@ typedef struct qh_stats {
     int64_t host_syncs;         /* device-to-host waits of the call */
     double host_ms;             /* host time of the 3D topology step and output
                                    (qh_hull3d only) */
+    double host_output_ms;      /* ... of which the output (vertex test and
+                                   canonical triangulation) */
 } qh_stats;
 
 typedef struct qh_opts {
@@ -179,6 +181,29 @@ qh_status qh_hull2d_batched(const int32_t *pts, int64_t n_total, const int64_t *
  */
 qh_status qh_hull3d(const int32_t *pts, int64_t n, int32_t *facets, int64_t *nfacets,
                     int32_t *verts, int64_t *nverts, const qh_opts *opts);
+
+/*
+ * The k-state segmented stable partition on its own (flagPermute, Section
+ * 4.1 and Figure 1; the rounds above fuse it into their scatter).  Segments
+ * are runs of the array started by a head flag (element 0 always starts
+ * one).  Element i of state f[i] in segment [h, e) moves to
+ *   p[i] = h + #{j in [h, e): f[j] < f[i]} + #{j in [h, i): f[j] = f[i]},
+ * and s_new flags the first slot of every non-empty state group of every
+ * segment.  For tests and for callers of the primitive; not on the hull path.
+ *
+ *   f       device int32[n]: states, each in [0, k), else QH_EINVAL
+ *   s       device uint8[n]: head flags (non-zero = a segment starts here)
+ *   n       elements, 0 <= n <= 2^30
+ *   k       states, 1 <= k <= 16
+ *   p       device int32[n]: new positions (a permutation of 0..n-1)
+ *   s_new   device uint8[n]: head flags after the permutation
+ *   stream  hipStream_t or NULL; the call returns when the outputs are written
+ *
+ * Scratch device memory of about 4 (k + 2) n bytes is allocated and freed
+ * inside the call.
+ */
+qh_status qh_test_flag_permute(const int32_t *f, const uint8_t *s, int64_t n, int32_t k,
+                               int32_t *p, uint8_t *s_new, void *stream);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqh.so")
-SOURCES = ["qh2d_kernels.hip", "qh_api.hip", "qh3d_kernels.hip", "qh3d_host.hip"]
+SOURCES = ["qh2d_kernels.hip", "qh_api.hip", "qh3d_kernels.hip", "qh3d_host.hip",
+           "qh_flag_permute.hip"]
 HEADERS = ["qh_device.h", "qh2d.h", "qh_ctx.h", "qh3d.h"]
 
 HIPCC_FLAGS = [

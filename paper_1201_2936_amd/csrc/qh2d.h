@@ -9,7 +9,7 @@ constexpr int kBlock = 256;              // threads per block
 constexpr int kItems = 8;                // points per thread
 constexpr int kTile = kBlock * kItems;   // points per tile
 constexpr int kSlots = 128;              // segments per LDS window (multi-segment tiles)
-constexpr int kChunk = 8;                // tiles per chunk of the round (one look-back each)
+constexpr int kPieceItems = 8;           // tile counts per thread of the piece scan
 constexpr int kSegBlock = 256;           // segments per tile of the segment phase
 constexpr int kRankSmallCap = 4096;      // hull ids ranked inside one block's LDS
 constexpr int32_t kCoordMax2D = (1 << 30) - 1;
@@ -36,7 +36,12 @@ struct Ws2 {
     SegGeo *geo_;       // segment tables: [parity][region][scap]
     SegTop *top_;       // [parity][region][scap]
     TileInfo *tinfo_;   // tile records: [parity][region][tcap]
-    uint64_t *st2_;     // look-back words of the round phase: [parity][tcap + 4]
+    uint32_t *tcnt_;    // survivors per tile of a round (child 0 | child 1 << 16): [parity][tcap]
+    int32_t *pv_;       // pieces of a round's input: virtual start [parity][region][tcap + 2]
+    int32_t *pp_;       // ... physical start [parity][region][tcap + 2]
+    int32_t *kf_;       // first piece of every tile [parity][region][tcap + 2]
+    uint64_t *st5_;     // look-back words of the piece scan (counts): [parity][s5cap]
+    uint64_t *st5b_;    // ... (non-empty pieces): [parity][s5cap]
     uint64_t *st4_;     // look-back words of the segment phase: [parity][s4cap]
     uint64_t *st4b_;    // ... of its second scan (child offsets): [parity][s4cap]
     int32_t *succ_;     // list ranking: [2][hcap]
@@ -58,6 +63,7 @@ struct Ws2 {
     int32_t hcap;     // compact hull ids
     int32_t tcap;     // tiles per round
     int32_t s4cap;    // look-back words of the segment phase
+    int32_t s5cap;    // look-back words of the piece scan
 
     __host__ __device__ int32_t *px(int p, int r) const { return pts_ + (size_t)((p * 2 + r) * 3 + 0) * cap_pts; }
     __host__ __device__ int32_t *py(int p, int r) const { return pts_ + (size_t)((p * 2 + r) * 3 + 1) * cap_pts; }
@@ -65,7 +71,12 @@ struct Ws2 {
     __host__ __device__ SegGeo *geo(int p, int r) const { return geo_ + (size_t)(p * 2 + r) * scap; }
     __host__ __device__ SegTop *top(int p, int r) const { return top_ + (size_t)(p * 2 + r) * scap; }
     __host__ __device__ TileInfo *tinfo(int p, int r) const { return tinfo_ + (size_t)(p * 2 + r) * tcap; }
-    __host__ __device__ uint64_t *st2(int p) const { return st2_ + (size_t)p * (tcap + 4); }
+    __host__ __device__ uint32_t *tcnt(int p) const { return tcnt_ + (size_t)p * tcap; }
+    __host__ __device__ int32_t *pv(int p, int r) const { return pv_ + (size_t)(p * 2 + r) * (tcap + 2); }
+    __host__ __device__ int32_t *pp(int p, int r) const { return pp_ + (size_t)(p * 2 + r) * (tcap + 2); }
+    __host__ __device__ int32_t *kf(int p, int r) const { return kf_ + (size_t)(p * 2 + r) * (tcap + 2); }
+    __host__ __device__ uint64_t *st5(int p) const { return st5_ + (size_t)p * s5cap; }
+    __host__ __device__ uint64_t *st5b(int p) const { return st5b_ + (size_t)p * s5cap; }
     __host__ __device__ uint64_t *st4(int p) const { return st4_ + (size_t)p * s4cap; }
     __host__ __device__ uint64_t *st4b(int p) const { return st4b_ + (size_t)p * s4cap; }
     __host__ __device__ int32_t *succ(int p) const { return succ_ + (size_t)p * hcap; }

@@ -182,23 +182,22 @@ __device__ __forceinline__ void best_offer(Best &b, uint64_t d, int32_t x, int32
 // LDS layouts of the phases (they share one buffer)
 // ---------------------------------------------------------------------------
 struct RoundSmem {
-    int32_t s_tile, s_m;
+    int32_t s_m;
     uint32_t s_tot;
-    uint64_t s_ex;
     uint32_t stat[4];
     uint32_t scan[kQ * kNW];
-    int32_t sstart[kTile + 4];
+    int32_t sstart[kTile + 4];      // segment starts of a multi-segment tile
+    int32_t pvs[kTile + 4];         // virtual starts of the tile's input pieces
+    int32_t pps[kTile + 4];         // ... their physical starts
     int32_t lgeo[kSlots][6];
     uint64_t k1[2][kSlots];
     uint64_t k2[2][kSlots];
     uint32_t lm[2][kSlots];
     uint32_t scnt[2][kSlots];
     int32_t res[2][kSlots][3];
-    Best wrec[kChunk][kNW][2];      // per-wave argmax records of one-segment tiles
-    uint32_t wcnt[kChunk][kNW];     // per-wave survivor counts (child 0 | child 1 << 16)
-    uint32_t woff[kChunk][kNW];     // their chunk-local offsets
-    int32_t tgen[kChunk];           // tile has several segments
-    uint32_t stc[kChunk][kBlock];   // 2-bit states of the chunk's tiles, pass 1 -> pass 2
+    Best wrec[kNW][2];              // per-wave argmax records of a one-segment tile
+    uint32_t wcnt[kNW];             // per-wave survivor counts (child 0 | child 1 << 16)
+    uint32_t woff[kNW];             // their tile-local offsets
 };
 
 struct ExtSmem {
@@ -210,6 +209,7 @@ struct ExtSmem {
 };
 
 struct SegSmem {
+    uint32_t pscan[4 * (kSegBlock / kWave)];
     uint32_t scan[2 * (kSegBlock / kWave)];
     uint32_t scan2[2 * (kSegBlock / kWave)];
     int32_t s_tile, qn_apex, qn_map, pad;
@@ -305,6 +305,8 @@ __device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a
         ctl->rounds_with_work = 0;
         ctl->H = 0;
         ctl->h_total = 0;
+        ctl->nacc[0][0] = ctl->nacc[0][1] = 0;
+        ctl->nacc[1][0] = ctl->nacc[1][1] = 0;
     }
 }
 
@@ -312,9 +314,11 @@ __device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a
 __device__ __forceinline__ void phase_setup(const Ws2 &ws, const HullArgs &a) {
     const int stride = gridDim.x * blockDim.x;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int i = tid; i < ws.tcap + 4; i += stride) {
-        ws.st2(0)[i] = 0;
-        ws.st2(1)[i] = 0;
+    for (int i = tid; i < ws.s5cap; i += stride) {
+        ws.st5(0)[i] = 0;
+        ws.st5(1)[i] = 0;
+        ws.st5b(0)[i] = 0;
+        ws.st5b(1)[i] = 0;
     }
     for (int i = tid; i < ws.s4cap; i += stride) {
         ws.st4(0)[i] = 0;
@@ -577,47 +581,84 @@ __device__ __forceinline__ void phase_extremes_final(const Ws2 &ws, const HullAr
 // ---------------------------------------------------------------------------
 // one round over the survivors
 // ---------------------------------------------------------------------------
-// The tiles of a round are grouped into chunks of up to kChunk tiles, claimed
-// in order from an atomic counter.  Pass 1 classifies every tile of the chunk
-// and produces its argmax records (with the child counts); one look-back gives
-// the chunk its global offsets; pass 2 reads the chunk's points again (from L2
-// / Infinity Cache) and scatters the survivors.  A tile covered by one segment
-// (the common case) is processed by each wave on its own quarter, without
-// block barriers; a tile with several segments is processed by the whole
-// block in point order.
+// Every tile of a round is classified, reduced and scattered by one block in
+// one pass: the survivors of child c of tile t go to region c at t * kTile
+// (a "piece"), so no tile waits for another.  The next round reads its input
+// in compacted order through the piece table that the segment kernel builds
+// from the tiles' survivor counts (an exclusive scan), which is the order the
+// child segments are laid out in.  Tiles are dealt to the resident blocks in
+// a fixed stride, with no atomics.  A tile covered by one segment (the common
+// case) is processed by each wave on its own quarter; a tile with several
+// segments is processed by the whole block in point order.
 
-__device__ __forceinline__ void load_tile(const Ws2 &ws, const HullArgs &a, bool init, int p, int R,
-                                          int lo, int hi, int32_t (&X)[kItems], int32_t (&Y)[kItems],
-                                          int32_t (&I)[kItems]) {
+// items of a thread: v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3)
+__device__ __forceinline__ int item_pos(int lo, int i) {
+    return lo + (i >> 2) * kBlock * 4 + (int)threadIdx.x * 4 + (i & 3);
+}
+
+// the first split reads the caller's array (index = position)
+__device__ __forceinline__ void load_input(const HullArgs &a, int lo, int hi, int32_t (&X)[kItems],
+                                           int32_t (&Y)[kItems], int32_t (&I)[kItems]) {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int qq = 0; qq < kQ; ++qq) {
         const int v0 = lo + qq * kBlock * 4 + tid * 4;
-        if (init) {
-            if (a.vec_ok && v0 + 3 < hi) {
-                const int4 pa = *reinterpret_cast<const int4 *>(a.x + v0);
-                const int4 pb = *reinterpret_cast<const int4 *>(a.y + v0);
-                X[qq * 4 + 0] = pa.x; X[qq * 4 + 1] = pa.y; X[qq * 4 + 2] = pa.z; X[qq * 4 + 3] = pa.w;
-                Y[qq * 4 + 0] = pb.x; Y[qq * 4 + 1] = pb.y; Y[qq * 4 + 2] = pb.z; Y[qq * 4 + 3] = pb.w;
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int v = v0 + j;
-                    X[qq * 4 + j] = v < hi ? a.x[v] : 0;
-                    Y[qq * 4 + j] = v < hi ? a.y[v] : 0;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) I[qq * 4 + j] = v0 + j;
-        } else {
-            const int4 pa = *reinterpret_cast<const int4 *>(ws.px(p, R) + v0);
-            const int4 pb = *reinterpret_cast<const int4 *>(ws.py(p, R) + v0);
-            const int4 pc = *reinterpret_cast<const int4 *>(ws.pi(p, R) + v0);
+        if (a.vec_ok && v0 + 3 < hi) {
+            const int4 pa = *reinterpret_cast<const int4 *>(a.x + v0);
+            const int4 pb = *reinterpret_cast<const int4 *>(a.y + v0);
             X[qq * 4 + 0] = pa.x; X[qq * 4 + 1] = pa.y; X[qq * 4 + 2] = pa.z; X[qq * 4 + 3] = pa.w;
             Y[qq * 4 + 0] = pb.x; Y[qq * 4 + 1] = pb.y; Y[qq * 4 + 2] = pb.z; Y[qq * 4 + 3] = pb.w;
-            I[qq * 4 + 0] = pc.x; I[qq * 4 + 1] = pc.y; I[qq * 4 + 2] = pc.z; I[qq * 4 + 3] = pc.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int v = v0 + j;
+                X[qq * 4 + j] = v < hi ? a.x[v] : 0;
+                Y[qq * 4 + j] = v < hi ? a.y[v] : 0;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) I[qq * 4 + j] = v0 + j;
+    }
+}
+
+// later rounds: the tile's virtual range [lo, hi) of region R, gathered from
+// the pieces kA .. kB the previous round wrote.  Returns false (and raises
+// an internal error) if the piece table does not fit the tile.
+__device__ __forceinline__ bool load_pieces(const Ws2 &ws, int p, int R, int lt, int ntR, int npc,
+                                            int lo, int hi, RoundSmem *sm, int32_t (&X)[kItems],
+                                            int32_t (&Y)[kItems], int32_t (&I)[kItems]) {
+    const int tid = threadIdx.x;
+    const int32_t *kf = ws.kf(p, R);
+    const int kA = kf[lt];
+    const int kB = (lt + 1 < ntR) ? kf[lt + 1] : npc - 1;
+    const int K = kB - kA + 1;
+    const bool ok = kA >= 0 && K >= 1 && K <= kTile + 2 && kB < npc;
+    if (ok) {
+        const int32_t *pv = ws.pv(p, R) + kA;
+        const int32_t *pp = ws.pp(p, R) + kA;
+        for (int j = tid; j < K; j += kBlock) {
+            sm->pvs[j] = pv[j];
+            sm->pps[j] = pp[j];
         }
     }
+    __syncthreads();
+    const int32_t *sx = ws.px(p, R), *sy = ws.py(p, R), *si = ws.pi(p, R);
+    const int64_t cap = ws.cap_pts;
+    bool bad = !ok;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        const int v = item_pos(lo, i);
+        X[i] = Y[i] = I[i] = 0;
+        if (!ok || v >= hi) continue;
+        const int j = slot_of(sm->pvs, K, v);
+        const int64_t ph = (int64_t)sm->pps[j] + (v - sm->pvs[j]);
+        if (ph < 0 || ph >= cap) { bad = true; continue; }
+        X[i] = sx[ph];
+        Y[i] = sy[ph];
+        I[i] = si[ph];
+    }
+    if (bad) atomicOr(&ws.ctl->error, kErrInternal);
+    return ok;
 }
 
 __device__ __forceinline__ uint32_t row_count(uint32_t stbits, int qq) {
@@ -660,93 +701,224 @@ __device__ __forceinline__ bool filter_cand(int32_t x, int32_t y, uint32_t st, c
     return fkey(__fadd_rn(e, 2.f * B)) >= lmk;
 }
 
-
-
 template <int MODE>
 __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, int r, char *smem) {
     const bool INIT = r == 0;  // the first split reads the input (index = position)
     Control *ctl = ws.ctl;
     RoundSmem *sm = reinterpret_cast<RoundSmem *>(smem);
     const int p = r & 1, q = p ^ 1;
-    RoundState *rs = &ctl->rs[p];
-    RoundState *rn = &ctl->rs[q];
+    const RoundState *rs = &ctl->rs[p];
     const int n0 = rs->n[0], n1 = rs->n[1];
     const int S0 = rs->s[0], S1 = rs->s[1];
     const int nt0 = (n0 + kTile - 1) / kTile, nt1 = (n1 + kTile - 1) / kTile;
     const int ntiles = nt0 + nt1;
-    const int C = max(1, min(kChunk, ntiles / (2 * (int)gridDim.x)));
-    const int nc0 = (nt0 + C - 1) / C, nc1 = (nt1 + C - 1) / C;
-    const int nchunks = nc0 + nc1;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
-
-    // house-keeping for the next round
-    if (blockIdx.x == 0 && tid == 0) rn->tile_ctr = 0;
-    for (int i = blockIdx.x * kBlock + tid; i < ntiles + 2 && i < ws.tcap + 4; i += gridDim.x * kBlock)
-        ws.st2(q)[i] = 0;
-    if (ntiles == 0) {
-        if (blockIdx.x == 0 && tid == 0) { rn->n[0] = 0; rn->n[1] = 0; }
-        return;
-    }
+    int32_t *ox0 = ws.px(q, 0), *oy0 = ws.py(q, 0), *oi0 = ws.pi(q, 0);
+    int32_t *ox1 = ws.px(q, 1), *oy1 = ws.py(q, 1), *oi1 = ws.pi(q, 1);
+    const int64_t cap = ws.cap_pts;
 
     uint32_t ntests = 0, nfall = 0, ncand = 0;
-    while (true) {
-        if (tid == 0) sm->s_tile = (int32_t)atomicAdd(&rs->tile_ctr, 1u);
-        __syncthreads();
-        const int ch = __builtin_amdgcn_readfirstlane(sm->s_tile);  // uniform: scalar registers
-        if (ch >= nchunks) break;
-        const int R = ch < nc0 ? 0 : 1;
-        const int lc = ch - (R ? nc0 : 0);
+    uint32_t acc0 = 0, acc1 = 0;  // survivors written by this block (thread 0)
+    bool oob = false;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int R = tile < nt0 ? 0 : 1;
+        const int lt = tile - (R ? nt0 : 0);
         const int NR = R ? n1 : n0;
         const int SR = R ? S1 : S0;
-        const int ntR = R ? nt1 : nt0;
         const int gbase = R ? S0 : 0;
-        const int t_first = lc * C;
-        const int tcount = min(C, ntR - t_first);
+        const int lo = lt * kTile;
+        const int hi = min(lo + kTile, NR);
+        int32_t X[kItems], Y[kItems], I[kItems];
+        if (INIT) {
+            load_input(a, lo, hi, X, Y, I);
+        } else if (!load_pieces(ws, p, R, lt, R ? nt1 : nt0, rs->npc[R], lo, hi, sm, X, Y, I)) {
+            __syncthreads();
+            continue;
+        }
+        const TileInfo ti = ws.tinfo(p, R)[lt];
+        const int s0 = ti.seg;
+        uint32_t stbits = 0xaaaaaaaau;  // 2 bits per point: 0, 1 = child, 2 = dropped
+        uint32_t rr[kQ];                // packed in-tile ranks of each row's first survivor
+        uint32_t total;                 // the tile's survivors (packed)
 
-        // ---------------- pass 1: classify every tile of the chunk
-        for (int it = 0; it < tcount; ++it) {
-            const int lt = t_first + it;
-            const int tile = (R ? nt0 : 0) + lt;
-            const int lo = lt * kTile;
-            const int hi = min(lo + kTile, NR);
-            int32_t X[kItems], Y[kItems], I[kItems];
-            load_tile(ws, a, INIT, p, R, lo, hi, X, Y, I);
-            const TileInfo ti = ws.tinfo(p, R)[lt];
-            const int s0 = ti.seg;
-            uint32_t stbits = 0xaaaaaaaau;  // 2 bits per point: 0, 1 = child, 2 = dropped
-
-            if (ti.single) {
-                // one segment covers the tile: uniform geometry, every wave on its own
-                const int ux = ti.ux, uy = ti.uy, fx = ti.fx, fy = ti.fy, vx = ti.vx, vy = ti.vy;
-                const int e0x = fx - ux, e0y = fy - uy, e1x = vx - fx, e1y = vy - fy;
-                Best b0 = best_none(), b1 = best_none();
-                if (MODE == 0) {
+        if (ti.single) {
+            // one segment covers the tile: uniform geometry, every wave on its own
+            const int ux = ti.ux, uy = ti.uy, fx = ti.fx, fy = ti.fy, vx = ti.vx, vy = ti.vy;
+            const int e0x = fx - ux, e0y = fy - uy, e1x = vx - fx, e1y = vy - fy;
+            Best b0 = best_none(), b1 = best_none();
+            if (MODE == 0) {
 #pragma unroll
-                    for (int i = 0; i < kItems; ++i) {
-                        const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-                        if (v >= hi) continue;
+                for (int i = 0; i < kItems; ++i) {
+                    if (item_pos(lo, i) >= hi) continue;
+                    const int64_t d0 = cross_i64(X[i], Y[i], ux, uy, fx, fy);
+                    uint32_t st = 2;
+                    if (d0 > 0) {
+                        st = 0;
+                        b0.cnt++;
+                        best_offer(b0, (uint64_t)d0, X[i], Y[i], I[i], e0x, e0y);
+                    } else {
+                        const int64_t d1 = cross_i64(X[i], Y[i], fx, fy, vx, vy);
+                        if (d1 > 0) {
+                            st = 1;
+                            b1.cnt++;
+                            best_offer(b1, (uint64_t)d1, X[i], Y[i], I[i], e1x, e1y);
+                        }
+                    }
+                    stbits ^= (st ^ 2u) << (2 * i);
+                }
+            } else {
+                float l0 = -INFINITY, l1 = -INFINITY;
+#pragma unroll
+                for (int i = 0; i < kItems; ++i) {
+                    if (item_pos(lo, i) >= hi) continue;
+                    float B0;
+                    const float e0 = cross_f32(X[i], Y[i], ux, uy, fx, fy, B0);
+                    ntests++;
+                    bool out0;
+                    if (e0 > B0) out0 = true;
+                    else if (e0 < -B0) out0 = false;
+                    else { nfall++; out0 = cross_i64(X[i], Y[i], ux, uy, fx, fy) > 0; }
+                    uint32_t st = 2;
+                    if (out0) {
+                        st = 0;
+                        b0.cnt++;
+                        l0 = fmaxf(l0, __fsub_rn(e0, 2.f * B0));
+                    } else {
+                        float B1;
+                        const float e1 = cross_f32(X[i], Y[i], fx, fy, vx, vy, B1);
+                        ntests++;
+                        bool out1;
+                        if (e1 > B1) out1 = true;
+                        else if (e1 < -B1) out1 = false;
+                        else { nfall++; out1 = cross_i64(X[i], Y[i], fx, fy, vx, vy) > 0; }
+                        if (out1) {
+                            st = 1;
+                            b1.cnt++;
+                            l1 = fmaxf(l1, __fsub_rn(e1, 2.f * B1));
+                        }
+                    }
+                    stbits ^= (st ^ 2u) << (2 * i);
+                }
+                // the wave's best lower bound per child; only points whose
+                // upper bound reaches it can be the argmax
+                const float M0 = wave_max_f(l0), M1 = wave_max_f(l1);
+#pragma unroll
+                for (int i = 0; i < kItems; ++i) {
+                    const uint32_t st = (stbits >> (2 * i)) & 3u;
+                    if (st > 1) continue;
+                    float B;
+                    const float e = st == 0 ? cross_f32(X[i], Y[i], ux, uy, fx, fy, B)
+                                            : cross_f32(X[i], Y[i], fx, fy, vx, vy, B);
+                    const float U = __fadd_rn(e, 2.f * B);
+                    if (U < (st == 0 ? M0 : M1)) continue;
+                    ncand++;
+                    if (st == 0)
+                        best_offer(b0, (uint64_t)cross_i64(X[i], Y[i], ux, uy, fx, fy), X[i], Y[i], I[i], e0x, e0y);
+                    else
+                        best_offer(b1, (uint64_t)cross_i64(X[i], Y[i], fx, fy, vx, vy), X[i], Y[i], I[i], e1x, e1y);
+                }
+            }
+            wave_rec(b0);
+            wave_rec(b1);
+            if (lane == 0) {
+                sm->wrec[wv][0] = b0;
+                sm->wrec[wv][1] = b1;
+                sm->wcnt[wv] = (uint32_t)b0.cnt | ((uint32_t)b1.cnt << 16);
+            }
+            __syncthreads();
+            if (tid < 2) {
+                // the tile's record of child tid
+                Best b = sm->wrec[0][tid];
+#pragma unroll
+                for (int w = 1; w < kNW; ++w) rec_merge(b, sm->wrec[w][tid]);
+                if (ti.start >= lo && ti.end <= hi) ws.adir[(gbase + ti.seg) * 2 + tid] = b;
+                ws.recF[tile * 2 + tid] = b;
+                ws.recL[tile * 2 + tid] = b;
+            }
+            // any order inside the tile keeps the children contiguous: wave
+            // order (wave, row, lane, item)
+            uint32_t base = 0;
+            total = 0;
+#pragma unroll
+            for (int w = 0; w < kNW; ++w) {
+                const uint32_t c = sm->wcnt[w];
+                base += (w < wv) ? c : 0u;
+                total += c;
+            }
+#pragma unroll
+            for (int qq = 0; qq < kQ; ++qq) {
+                const uint32_t c = row_count(stbits, qq);
+                const uint32_t inc = wave_incl_sum(c);
+                rr[qq] = base + inc - c;
+                base += wave_read(inc, kWave - 1);
+            }
+        } else {
+            // several segments: starts into LDS, per-slot reductions (point order)
+            const SegGeo *geo = ws.geo(p, R);
+            if (tid == 0) sm->s_m = 0;
+            __syncthreads();
+            for (int b = 0; b <= kTile; b += kBlock) {
+                const int j = b + tid;
+                bool in = false;
+                if (j <= kTile) {
+                    const int si = s0 + j;
+                    const int st = si < SR ? geo[si].start : NR;
+                    sm->sstart[j] = st;
+                    in = st < hi;
+                }
+                const int cnt = __syncthreads_count(in);
+                if (tid == 0) sm->s_m += cnt;
+                if (cnt < kBlock) break;
+            }
+            __syncthreads();
+            const int m = sm->s_m;
+            uint32_t slotpk[kItems / 2];
+#pragma unroll
+            for (int i = 0; i < kItems; i += 2) {
+                const int va = item_pos(lo, i);
+                const int sa = (va >= hi) ? 0 : slot_of(sm->sstart, m, va);
+                const int sb = (va + 1 >= hi) ? 0 : slot_of(sm->sstart, m, va + 1);
+                slotpk[i >> 1] = (uint32_t)sa | ((uint32_t)sb << 16);
+            }
+            for (int w0 = 0; w0 < m; w0 += kSlots) {
+                const int wn = min(kSlots, m - w0);
+                for (int j = tid; j < wn; j += kBlock) {
+                    const SegGeo g = geo[s0 + w0 + j];
+                    sm->lgeo[j][0] = g.ux; sm->lgeo[j][1] = g.uy;
+                    sm->lgeo[j][2] = g.fx; sm->lgeo[j][3] = g.fy;
+                    sm->lgeo[j][4] = g.vx; sm->lgeo[j][5] = g.vy;
+                }
+                for (int j = tid; j < 2 * kSlots; j += kBlock) {
+                    (&sm->k1[0][0])[j] = 0;
+                    (&sm->k2[0][0])[j] = ~0ull;
+                    (&sm->lm[0][0])[j] = 0;
+                    (&sm->scnt[0][0])[j] = 0;
+                }
+                __syncthreads();
+                // classify; the best distance (exact) or lower bound (filter) per slot
+#pragma unroll
+                for (int i = 0; i < kItems; ++i) {
+                    const int v = item_pos(lo, i);
+                    const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
+                    if (v >= hi || sl < w0 || sl >= w0 + wn) continue;
+                    const int ls = sl - w0;
+                    const int ux = sm->lgeo[ls][0], uy = sm->lgeo[ls][1];
+                    const int fx = sm->lgeo[ls][2], fy = sm->lgeo[ls][3];
+                    const int vx = sm->lgeo[ls][4], vy = sm->lgeo[ls][5];
+                    uint32_t st = 2;
+                    if (MODE == 0) {
                         const int64_t d0 = cross_i64(X[i], Y[i], ux, uy, fx, fy);
-                        uint32_t st = 2;
                         if (d0 > 0) {
                             st = 0;
-                            b0.cnt++;
-                            best_offer(b0, (uint64_t)d0, X[i], Y[i], I[i], e0x, e0y);
+                            atomicMax(&sm->k1[0][ls], (uint64_t)d0);
                         } else {
                             const int64_t d1 = cross_i64(X[i], Y[i], fx, fy, vx, vy);
                             if (d1 > 0) {
                                 st = 1;
-                                b1.cnt++;
-                                best_offer(b1, (uint64_t)d1, X[i], Y[i], I[i], e1x, e1y);
+                                atomicMax(&sm->k1[1][ls], (uint64_t)d1);
                             }
                         }
-                        stbits ^= (st ^ 2u) << (2 * i);
-                    }
-                } else {
-                    float l0 = -INFINITY, l1 = -INFINITY;
-#pragma unroll
-                    for (int i = 0; i < kItems; ++i) {
-                        const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-                        if (v >= hi) continue;
+                    } else {
                         float B0;
                         const float e0 = cross_f32(X[i], Y[i], ux, uy, fx, fy, B0);
                         ntests++;
@@ -754,11 +926,9 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
                         if (e0 > B0) out0 = true;
                         else if (e0 < -B0) out0 = false;
                         else { nfall++; out0 = cross_i64(X[i], Y[i], ux, uy, fx, fy) > 0; }
-                        uint32_t st = 2;
                         if (out0) {
                             st = 0;
-                            b0.cnt++;
-                            l0 = fmaxf(l0, __fsub_rn(e0, 2.f * B0));
+                            atomicMax(&sm->lm[0][ls], fkey(__fsub_rn(e0, 2.f * B0)));
                         } else {
                             float B1;
                             const float e1 = cross_f32(X[i], Y[i], fx, fy, vx, vy, B1);
@@ -769,316 +939,119 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
                             else { nfall++; out1 = cross_i64(X[i], Y[i], fx, fy, vx, vy) > 0; }
                             if (out1) {
                                 st = 1;
-                                b1.cnt++;
-                                l1 = fmaxf(l1, __fsub_rn(e1, 2.f * B1));
+                                atomicMax(&sm->lm[1][ls], fkey(__fsub_rn(e1, 2.f * B1)));
                             }
                         }
-                        stbits ^= (st ^ 2u) << (2 * i);
                     }
-                    // the wave's best lower bound per child; only points whose
-                    // upper bound reaches it can be the argmax
-                    const float M0 = wave_max_f(l0), M1 = wave_max_f(l1);
+                    if (st < 2) atomicAdd(&sm->scnt[st][ls], 1u);
+                    stbits ^= (st ^ 2u) << (2 * i);
+                }
+                __syncthreads();
+                if (MODE != 0) {
+                    // candidates of the argmax get exact distances
 #pragma unroll
                     for (int i = 0; i < kItems; ++i) {
+                        const int v = item_pos(lo, i);
+                        const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
                         const uint32_t st = (stbits >> (2 * i)) & 3u;
-                        if (st > 1) continue;
-                        float B;
-                        const float e = st == 0 ? cross_f32(X[i], Y[i], ux, uy, fx, fy, B)
-                                                : cross_f32(X[i], Y[i], fx, fy, vx, vy, B);
-                        const float U = __fadd_rn(e, 2.f * B);
-                        if (U < (st == 0 ? M0 : M1)) continue;
+                        if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
+                        const int ls = sl - w0;
+                        if (!filter_cand(X[i], Y[i], st, sm->lgeo[ls], sm->lm[st][ls])) continue;
                         ncand++;
-                        if (st == 0)
-                            best_offer(b0, (uint64_t)cross_i64(X[i], Y[i], ux, uy, fx, fy), X[i], Y[i], I[i], e0x, e0y);
-                        else
-                            best_offer(b1, (uint64_t)cross_i64(X[i], Y[i], fx, fy, vx, vy), X[i], Y[i], I[i], e1x, e1y);
+                        atomicMax(&sm->k1[st][ls], (uint64_t)child_d(X[i], Y[i], st, sm->lgeo[ls]));
                     }
+                    __syncthreads();
                 }
-                wave_rec(b0);
-                wave_rec(b1);
-                if (lane == 0) {
-                    sm->wrec[it][wv][0] = b0;
-                    sm->wrec[it][wv][1] = b1;
-                    sm->wcnt[it][wv] = (uint32_t)b0.cnt | ((uint32_t)b1.cnt << 16);
-                }
-                if (tid == 0) sm->tgen[it] = 0;
-            } else {
-                // several segments: starts into LDS, per-slot reductions (point order)
-                const SegGeo *geo = ws.geo(p, R);
-                if (tid == 0) sm->s_m = 0;
-                __syncthreads();
-                for (int b = 0; b <= kTile; b += kBlock) {
-                    const int j = b + tid;
-                    bool in = false;
-                    if (j <= kTile) {
-                        const int si = s0 + j;
-                        const int st = si < SR ? geo[si].start : NR;
-                        sm->sstart[j] = st;
-                        in = st < hi;
-                    }
-                    const int cnt = __syncthreads_count(in);
-                    if (tid == 0) sm->s_m += cnt;
-                    if (cnt < kBlock) break;
+                // tie-break among the farthest points, then the winner (the
+                // exact distances are recomputed rather than kept)
+#pragma unroll
+                for (int i = 0; i < kItems; ++i) {
+                    const int v = item_pos(lo, i);
+                    const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
+                    const uint32_t st = (stbits >> (2 * i)) & 3u;
+                    if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
+                    const int ls = sl - w0;
+                    if (MODE != 0 && !filter_cand(X[i], Y[i], st, sm->lgeo[ls], sm->lm[st][ls])) continue;
+                    if ((uint64_t)child_d(X[i], Y[i], st, sm->lgeo[ls]) != sm->k1[st][ls]) continue;
+                    const int ex = st == 0 ? sm->lgeo[ls][2] - sm->lgeo[ls][0] : sm->lgeo[ls][4] - sm->lgeo[ls][2];
+                    const int ey = st == 0 ? sm->lgeo[ls][3] - sm->lgeo[ls][1] : sm->lgeo[ls][5] - sm->lgeo[ls][3];
+                    atomicMin(&sm->k2[st][ls], tie_key(X[i], Y[i], I[i], ex, ey));
                 }
                 __syncthreads();
-                const int m = sm->s_m;
-                uint32_t slotpk[kItems / 2];
 #pragma unroll
-                for (int i = 0; i < kItems; i += 2) {
-                    const int va = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-                    const int sa = (va >= hi) ? 0 : slot_of(sm->sstart, m, va);
-                    const int sb = (va + 1 >= hi) ? 0 : slot_of(sm->sstart, m, va + 1);
-                    slotpk[i >> 1] = (uint32_t)sa | ((uint32_t)sb << 16);
+                for (int i = 0; i < kItems; ++i) {
+                    const int v = item_pos(lo, i);
+                    const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
+                    const uint32_t st = (stbits >> (2 * i)) & 3u;
+                    if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
+                    const int ls = sl - w0;
+                    if (MODE != 0 && !filter_cand(X[i], Y[i], st, sm->lgeo[ls], sm->lm[st][ls])) continue;
+                    if ((uint64_t)child_d(X[i], Y[i], st, sm->lgeo[ls]) != sm->k1[st][ls]) continue;
+                    const int ex = st == 0 ? sm->lgeo[ls][2] - sm->lgeo[ls][0] : sm->lgeo[ls][4] - sm->lgeo[ls][2];
+                    const int ey = st == 0 ? sm->lgeo[ls][3] - sm->lgeo[ls][1] : sm->lgeo[ls][5] - sm->lgeo[ls][3];
+                    if (tie_key(X[i], Y[i], I[i], ex, ey) == sm->k2[st][ls]) {
+                        sm->res[st][ls][0] = X[i]; sm->res[st][ls][1] = Y[i]; sm->res[st][ls][2] = I[i];
+                    }
                 }
-                for (int w0 = 0; w0 < m; w0 += kSlots) {
-                    const int wn = min(kSlots, m - w0);
-                    for (int j = tid; j < wn; j += kBlock) {
-                        const SegGeo g = geo[s0 + w0 + j];
-                        sm->lgeo[j][0] = g.ux; sm->lgeo[j][1] = g.uy;
-                        sm->lgeo[j][2] = g.fx; sm->lgeo[j][3] = g.fy;
-                        sm->lgeo[j][4] = g.vx; sm->lgeo[j][5] = g.vy;
+                __syncthreads();
+                // whole segments directly, the tile's first and last as partials
+                for (int j = tid; j < wn; j += kBlock) {
+                    const int sl = w0 + j;
+                    const int g = gbase + s0 + sl;
+                    const bool inside = sm->sstart[sl] >= lo && sm->sstart[sl + 1] <= hi;
+                    for (int c = 0; c < 2; ++c) {
+                        Best b;
+                        b.key1 = sm->k1[c][j];
+                        b.key2 = sm->k2[c][j];
+                        b.x = b.key1 ? sm->res[c][j][0] : 0;
+                        b.y = b.key1 ? sm->res[c][j][1] : 0;
+                        b.idx = b.key1 ? sm->res[c][j][2] : 0;
+                        b.cnt = (int32_t)sm->scnt[c][j];
+                        if (inside) ws.adir[g * 2 + c] = b;
+                        if (sl == 0) ws.recF[tile * 2 + c] = b;
+                        if (sl == m - 1) ws.recL[tile * 2 + c] = b;
                     }
-                    for (int j = tid; j < 2 * kSlots; j += kBlock) {
-                        (&sm->k1[0][0])[j] = 0;
-                        (&sm->k2[0][0])[j] = ~0ull;
-                        (&sm->lm[0][0])[j] = 0;
-                        (&sm->scnt[0][0])[j] = 0;
-                    }
-                    __syncthreads();
-                    // classify; the best distance (exact) or lower bound (filter) per slot
-#pragma unroll
-                    for (int i = 0; i < kItems; ++i) {
-                        const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-                        const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
-                        if (v >= hi || sl < w0 || sl >= w0 + wn) continue;
-                        const int ls = sl - w0;
-                        const int ux = sm->lgeo[ls][0], uy = sm->lgeo[ls][1];
-                        const int fx = sm->lgeo[ls][2], fy = sm->lgeo[ls][3];
-                        const int vx = sm->lgeo[ls][4], vy = sm->lgeo[ls][5];
-                        uint32_t st = 2;
-                        if (MODE == 0) {
-                            const int64_t d0 = cross_i64(X[i], Y[i], ux, uy, fx, fy);
-                            if (d0 > 0) {
-                                st = 0;
-                                atomicMax(&sm->k1[0][ls], (uint64_t)d0);
-                            } else {
-                                const int64_t d1 = cross_i64(X[i], Y[i], fx, fy, vx, vy);
-                                if (d1 > 0) {
-                                    st = 1;
-                                    atomicMax(&sm->k1[1][ls], (uint64_t)d1);
-                                }
-                            }
-                        } else {
-                            float B0;
-                            const float e0 = cross_f32(X[i], Y[i], ux, uy, fx, fy, B0);
-                            ntests++;
-                            bool out0;
-                            if (e0 > B0) out0 = true;
-                            else if (e0 < -B0) out0 = false;
-                            else { nfall++; out0 = cross_i64(X[i], Y[i], ux, uy, fx, fy) > 0; }
-                            if (out0) {
-                                st = 0;
-                                atomicMax(&sm->lm[0][ls], fkey(__fsub_rn(e0, 2.f * B0)));
-                            } else {
-                                float B1;
-                                const float e1 = cross_f32(X[i], Y[i], fx, fy, vx, vy, B1);
-                                ntests++;
-                                bool out1;
-                                if (e1 > B1) out1 = true;
-                                else if (e1 < -B1) out1 = false;
-                                else { nfall++; out1 = cross_i64(X[i], Y[i], fx, fy, vx, vy) > 0; }
-                                if (out1) {
-                                    st = 1;
-                                    atomicMax(&sm->lm[1][ls], fkey(__fsub_rn(e1, 2.f * B1)));
-                                }
-                            }
-                        }
-                        if (st < 2) atomicAdd(&sm->scnt[st][ls], 1u);
-                        stbits ^= (st ^ 2u) << (2 * i);
-                    }
-                    __syncthreads();
-                    if (MODE != 0) {
-                        // candidates of the argmax get exact distances
-#pragma unroll
-                        for (int i = 0; i < kItems; ++i) {
-                            const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-                            const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
-                            const uint32_t st = (stbits >> (2 * i)) & 3u;
-                            if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
-                            const int ls = sl - w0;
-                            if (!filter_cand(X[i], Y[i], st, sm->lgeo[ls], sm->lm[st][ls])) continue;
-                            ncand++;
-                            atomicMax(&sm->k1[st][ls], (uint64_t)child_d(X[i], Y[i], st, sm->lgeo[ls]));
-                        }
-                        __syncthreads();
-                    }
-                    // tie-break among the farthest points, then the winner (the
-                    // exact distances are recomputed rather than kept)
-#pragma unroll
-                    for (int i = 0; i < kItems; ++i) {
-                        const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-                        const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
-                        const uint32_t st = (stbits >> (2 * i)) & 3u;
-                        if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
-                        const int ls = sl - w0;
-                        if (MODE != 0 && !filter_cand(X[i], Y[i], st, sm->lgeo[ls], sm->lm[st][ls])) continue;
-                        if ((uint64_t)child_d(X[i], Y[i], st, sm->lgeo[ls]) != sm->k1[st][ls]) continue;
-                        const int ex = st == 0 ? sm->lgeo[ls][2] - sm->lgeo[ls][0] : sm->lgeo[ls][4] - sm->lgeo[ls][2];
-                        const int ey = st == 0 ? sm->lgeo[ls][3] - sm->lgeo[ls][1] : sm->lgeo[ls][5] - sm->lgeo[ls][3];
-                        atomicMin(&sm->k2[st][ls], tie_key(X[i], Y[i], I[i], ex, ey));
-                    }
-                    __syncthreads();
-#pragma unroll
-                    for (int i = 0; i < kItems; ++i) {
-                        const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-                        const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
-                        const uint32_t st = (stbits >> (2 * i)) & 3u;
-                        if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
-                        const int ls = sl - w0;
-                        if (MODE != 0 && !filter_cand(X[i], Y[i], st, sm->lgeo[ls], sm->lm[st][ls])) continue;
-                        if ((uint64_t)child_d(X[i], Y[i], st, sm->lgeo[ls]) != sm->k1[st][ls]) continue;
-                        const int ex = st == 0 ? sm->lgeo[ls][2] - sm->lgeo[ls][0] : sm->lgeo[ls][4] - sm->lgeo[ls][2];
-                        const int ey = st == 0 ? sm->lgeo[ls][3] - sm->lgeo[ls][1] : sm->lgeo[ls][5] - sm->lgeo[ls][3];
-                        if (tie_key(X[i], Y[i], I[i], ex, ey) == sm->k2[st][ls]) {
-                            sm->res[st][ls][0] = X[i]; sm->res[st][ls][1] = Y[i]; sm->res[st][ls][2] = I[i];
-                        }
-                    }
-                    __syncthreads();
-                    // whole segments directly, the tile's first and last as partials
-                    for (int j = tid; j < wn; j += kBlock) {
-                        const int sl = w0 + j;
-                        const int g = gbase + s0 + sl;
-                        const bool inside = sm->sstart[sl] >= lo && sm->sstart[sl + 1] <= hi;
-                        for (int c = 0; c < 2; ++c) {
-                            Best b;
-                            b.key1 = sm->k1[c][j];
-                            b.key2 = sm->k2[c][j];
-                            b.x = b.key1 ? sm->res[c][j][0] : 0;
-                            b.y = b.key1 ? sm->res[c][j][1] : 0;
-                            b.idx = b.key1 ? sm->res[c][j][2] : 0;
-                            b.cnt = (int32_t)sm->scnt[c][j];
-                            if (inside) ws.adir[g * 2 + c] = b;
-                            if (sl == 0) ws.recF[tile * 2 + c] = b;
-                            if (sl == m - 1) ws.recL[tile * 2 + c] = b;
-                        }
-                    }
-                    __syncthreads();
                 }
-                // the tile's survivor totals (packed), kept in wave 0's slot
-                uint32_t c = row_count(stbits, 0);
-#pragma unroll
-                for (int qq = 1; qq < kQ; ++qq) c += row_count(stbits, qq);
-                c = wave_sum(c);
-                if (lane == 0) sm->wcnt[it][wv] = c;
-                if (tid == 0) sm->tgen[it] = 1;
+                __syncthreads();
             }
-            sm->stc[it][tid] = stbits;
-        }
-        __syncthreads();
-
-        // ---------------- chunk bookkeeping: tile records, offsets, look-back
-        if (tid < 2 * tcount) {
-            // merge the wave records of every one-segment tile
-            const int it = tid >> 1, c = tid & 1;
-            if (!sm->tgen[it]) {
-                const int lt = t_first + it;
-                const int tile = (R ? nt0 : 0) + lt;
-                const int lo = lt * kTile;
-                const int hi = min(lo + kTile, NR);
-                const TileInfo ti = ws.tinfo(p, R)[lt];
-                Best b = sm->wrec[it][0][c];
+            // point order keeps every segment's children contiguous
+            uint32_t cnt[kQ], rowbase[kQ];
+            total = tile_ranks(stbits, cnt, rowbase, sm->scan);
 #pragma unroll
-                for (int w = 1; w < kNW; ++w) rec_merge(b, sm->wrec[it][w][c]);
-                if (ti.start >= lo && ti.end <= hi) ws.adir[(gbase + ti.seg) * 2 + c] = b;
-                ws.recF[tile * 2 + c] = b;
-                ws.recL[tile * 2 + c] = b;
+            for (int qq = 0; qq < kQ; ++qq) rr[qq] = rowbase[qq] + cnt[qq];
+        }
+
+        // scatter: child c of this tile goes to region c at tile * kTile
+        const int64_t pbase = (int64_t)tile * kTile;
+#pragma unroll
+        for (int qq = 0; qq < kQ; ++qq) {
+            uint32_t q_ = rr[qq];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = qq * 4 + j;
+                const uint32_t st = (stbits >> (2 * i)) & 3u;
+                if (st == 0) {
+                    const int64_t e = pbase + (q_ & 0xffffu);
+                    if (e < cap) { ox0[e] = X[i]; oy0[e] = Y[i]; oi0[e] = I[i]; } else oob = true;
+                    q_ += 1u;
+                } else if (st == 1) {
+                    const int64_t e = pbase + (q_ >> 16);
+                    if (e < cap) { ox1[e] = X[i]; oy1[e] = Y[i]; oi1[e] = I[i]; } else oob = true;
+                    q_ += 0x10000u;
+                }
             }
         }
         if (tid == 0) {
-            // chunk-local offsets of every (tile, wave) part, in chunk order
-            uint32_t acc = 0;
-            for (int it = 0; it < tcount; ++it) {
-                for (int w = 0; w < kNW; ++w) {
-                    sm->woff[it][w] = acc;
-                    acc += sm->wcnt[it][w];
-                }
-            }
-            sm->s_tot = acc;
+            ws.tcnt(p)[tile] = total;
+            acc0 += total & 0xffffu;
+            acc1 += total >> 16;
         }
-        __syncthreads();
-        const uint32_t run = sm->s_tot;
-        const uint32_t c0 = run & 0xffffu, c1 = run >> 16;
-        if (wv == 0) {
-            const uint64_t ex = lookback_excl(ws.st2(p), ch, pack2(c0, c1), &ctl->error);
-            if (lane == 0) sm->s_ex = ex;
-        }
-        __syncthreads();
-        const uint32_t E0 = unpackA(sm->s_ex), E1 = unpackB(sm->s_ex);
-
-        // ---------------- pass 2: scatter the survivors of every tile
-        int32_t *ox0 = ws.px(q, 0), *oy0 = ws.py(q, 0), *oi0 = ws.pi(q, 0);
-        int32_t *ox1 = ws.px(q, 1), *oy1 = ws.py(q, 1), *oi1 = ws.pi(q, 1);
-        const uint32_t cap = (uint32_t)ws.cap_pts;
-        bool oob = false;
-        for (int it = 0; it < tcount; ++it) {
-            const int lt = t_first + it;
-            const int lo = lt * kTile;
-            const int hi = min(lo + kTile, NR);
-            int32_t X[kItems], Y[kItems], I[kItems];
-            load_tile(ws, a, INIT, p, R, lo, hi, X, Y, I);
-            const uint32_t stbits = sm->stc[it][tid];
-            uint32_t rr[kQ];
-            if (!sm->tgen[it]) {
-                // one segment: any order inside the tile keeps the children
-                // contiguous; wave order (wave, row, lane, item)
-                uint32_t base = sm->woff[it][wv];
-#pragma unroll
-                for (int qq = 0; qq < kQ; ++qq) {
-                    const uint32_t c = row_count(stbits, qq);
-                    const uint32_t inc = wave_incl_sum(c);
-                    rr[qq] = base + inc - c;
-                    base += wave_read(inc, kWave - 1);
-                }
-            } else {
-                // several segments: point order
-                uint32_t cnt[kQ], rowbase[kQ];
-                (void)tile_ranks(stbits, cnt, rowbase, sm->scan);
-#pragma unroll
-                for (int qq = 0; qq < kQ; ++qq) rr[qq] = sm->woff[it][0] + rowbase[qq] + cnt[qq];
-            }
-#pragma unroll
-            for (int qq = 0; qq < kQ; ++qq) {
-                uint32_t q_ = rr[qq];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int i = qq * 4 + j;
-                    const uint32_t st = (stbits >> (2 * i)) & 3u;
-                    const uint32_t e0 = E0 + (q_ & 0xffffu);
-                    const uint32_t e1 = E1 + (q_ >> 16);
-                    if (st == 0) {
-                        if (e0 < cap) { ox0[e0] = X[i]; oy0[e0] = Y[i]; oi0[e0] = I[i]; } else oob = true;
-                        q_ += 1u;
-                    } else if (st == 1) {
-                        if (e1 < cap) { ox1[e1] = X[i]; oy1[e1] = Y[i]; oi1[e1] = I[i]; } else oob = true;
-                        q_ += 0x10000u;
-                    }
-                }
-            }
-        }
-        if (oob) atomicOr(&ctl->error, kErrInternal);
-        if (ch == nchunks - 1 && tid == 0) {
-            rn->n[0] = (int32_t)(E0 + c0);
-            rn->n[1] = (int32_t)(E1 + c1);
-            if (INIT) {
-                ctl->first_in += (unsigned long long)(n0 + n1);
-                ctl->first_out += (unsigned long long)(E0 + c0 + E1 + c1);
-            } else {
-                ctl->points_in += (unsigned long long)(n0 + n1);
-                ctl->points_out += (unsigned long long)(E0 + c0 + E1 + c1);
-            }
-            ctl->rounds_with_work += 1ull;
-        }
-        __syncthreads();
+        __syncthreads();  // LDS is reused by the next tile
+    }
+    if (oob) atomicOr(&ctl->error, kErrInternal);
+    if (tid == 0 && (acc0 | acc1)) {
+        atomicAdd(&ctl->nacc[p][0], acc0);
+        atomicAdd(&ctl->nacc[p][1], acc1);
     }
     if (MODE != 0) {
         if (tid == 0) { sm->stat[0] = 0; sm->stat[1] = 0; sm->stat[2] = 0; }
@@ -1111,18 +1084,43 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
     const int Stot = S0 + S1;
     const int hbase = rs->hbase;
     const int nt0 = (rs->n[0] + kTile - 1) / kTile;
-    const int Nn0 = rn->n[0], Nn1 = rn->n[1];
+    const int nt1 = (rs->n[1] + kTile - 1) / kTile;
+    // survivors of this round per region (summed by the round kernel's blocks)
+    const int Nn0 = (int)ctl->nacc[p][0], Nn1 = (int)ctl->nacc[p][1];
     const int nsegt = (Stot + kSegBlock - 1) / kSegBlock;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
 
-    if (blockIdx.x == 0 && tid == 0) rn->seg_ctr = 0;
+    if (blockIdx.x == 0 && tid == 0) {
+        rn->seg_ctr = 0;
+        rn->piece_ctr = 0;
+        rn->n[0] = Nn0;
+        rn->n[1] = Nn1;
+        ctl->nacc[q][0] = 0;
+        ctl->nacc[q][1] = 0;
+        const unsigned long long nin = (unsigned long long)(rs->n[0] + rs->n[1]);
+        if (nin) {
+            if (r == 0) {
+                ctl->first_in += nin;
+                ctl->first_out += (unsigned long long)(Nn0 + Nn1);
+            } else {
+                ctl->points_in += nin;
+                ctl->points_out += (unsigned long long)(Nn0 + Nn1);
+            }
+            ctl->rounds_with_work += 1ull;
+        }
+    }
     for (int i = blockIdx.x * kSegBlock + tid; i < 2 * nsegt + 4 && i < ws.s4cap; i += gridDim.x * kSegBlock) {
         ws.st4(q)[i] = 0;
         ws.st4b(q)[i] = 0;
     }
+    for (int i = blockIdx.x * kSegBlock + tid; i < ws.s5cap; i += gridDim.x * kSegBlock) {
+        ws.st5(q)[i] = 0;
+        ws.st5b(q)[i] = 0;
+    }
     if (Stot == 0 || ctl->error) {
         if (blockIdx.x == 0 && tid == 0) {
             rn->s[0] = 0; rn->s[1] = 0; rn->hbase = hbase;
+            rn->npc[0] = 0; rn->npc[1] = 0;
         }
         return;
     }
@@ -1303,6 +1301,84 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             rn->hbase = hbase + Stot;
             atomicMax(&ctl->max_segments, n0n + n1n);
             ctl->rounds_done += 1;
+        }
+        __syncthreads();
+    }
+
+    // The next round's piece table: the survivors tile t of this round wrote
+    // to region c (at t * kTile) are the next input's virtual range that
+    // starts at the exclusive sum of the earlier tiles' counts.  Non-empty
+    // pieces are listed in order with their virtual and physical starts, and
+    // every next-round tile gets the piece holding its first point.
+    __syncthreads();  // every thread has read the last segment-tile claim
+    const int NT = nt0 + nt1;
+    constexpr int kPer = kSegBlock * kPieceItems;
+    const int npt = (NT + kPer - 1) / kPer;
+    while (true) {
+        if (tid == 0) sm->s_tile = (int32_t)atomicAdd(&rs->piece_ctr, 1u);
+        __syncthreads();
+        const int pt = __builtin_amdgcn_readfirstlane(sm->s_tile);
+        if (pt >= npt) break;
+        const int t0 = pt * kPer + tid * kPieceItems;
+        uint32_t cp[kPieceItems];
+        uint32_t v[4] = {0u, 0u, 0u, 0u}, tot[4];
+#pragma unroll
+        for (int i = 0; i < kPieceItems; ++i) {
+            const int t = t0 + i;
+            cp[i] = t < NT ? ws.tcnt(p)[t] : 0u;
+            const uint32_t a0 = cp[i] & 0xffffu, a1 = cp[i] >> 16;
+            v[0] += a0;
+            v[1] += a1;
+            v[2] += a0 ? 1u : 0u;
+            v[3] += a1 ? 1u : 0u;
+        }
+        block_excl_scan<kSegBlock, 4>(v, tot, sm->pscan);
+        if (wv == 0) {
+            const uint64_t ex = lookback_excl(ws.st5(p), pt, pack2(tot[0], tot[1]), &ctl->error);
+            if (lane == 0) sm->s_ex = ex;
+        } else if (wv == 1) {
+            const uint64_t ex = lookback_excl(ws.st5b(p), pt, pack2(tot[2], tot[3]), &ctl->error);
+            if (lane == 0) sm->s_ex2 = ex;
+        }
+        __syncthreads();
+        int32_t V[2] = {(int32_t)(unpackA(sm->s_ex) + v[0]), (int32_t)(unpackB(sm->s_ex) + v[1])};
+        int32_t K[2] = {(int32_t)(unpackA(sm->s_ex2) + v[2]), (int32_t)(unpackB(sm->s_ex2) + v[3])};
+        const int Nn[2] = {Nn0, Nn1};
+        bool bad = false;
+#pragma unroll
+        for (int i = 0; i < kPieceItems; ++i) {
+            const int t = t0 + i;
+            if (t >= NT) break;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int32_t cnt = (int32_t)(c == 0 ? (cp[i] & 0xffffu) : (cp[i] >> 16));
+                if (cnt == 0) continue;
+                if (K[c] >= ws.tcap || V[c] + cnt > Nn[c]) {
+                    bad = true;
+                    continue;
+                }
+                ws.pv(q, c)[K[c]] = V[c];
+                ws.pp(q, c)[K[c]] = t * kTile;
+                // next-round tiles whose first point lies in this piece
+                for (int tt = (V[c] + kTile - 1) / kTile; tt * kTile < V[c] + cnt && tt < ws.tcap; ++tt)
+                    ws.kf(q, c)[tt] = K[c];
+                K[c] += 1;
+                V[c] += cnt;
+            }
+        }
+        if (bad) atomicOr(&ctl->error, kErrInternal);
+        if (pt == npt - 1 && tid == kSegBlock - 1) {
+            // the last thread of the last block: totals, sentinels
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (V[c] != Nn[c] || K[c] > ws.tcap) {
+                    atomicOr(&ctl->error, kErrInternal);
+                    continue;
+                }
+                ws.pv(q, c)[K[c]] = V[c];
+                ws.pp(q, c)[K[c]] = 0;
+                rn->npc[c] = K[c];
+            }
         }
         __syncthreads();
     }

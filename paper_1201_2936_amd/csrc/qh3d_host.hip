@@ -240,12 +240,13 @@ struct Run {
     std::vector<HFacet> F;
     std::vector<int32_t> active;   // facets with outside points, ascending id
     int64_t walks = 0;             // visibility walks made (stamps)
+    std::vector<int32_t> from;     // per point: the cone facet whose horizon edge starts there
     int cur = 0;                   // pool holding the live ranges
     int64_t top = 0;               // first free pool position
     // statistics
     int64_t rounds = 0, launches = 0, syncs = 0, pts_in = 0, pts_out = 0, apex_pts = 0;
     int64_t max_active = 0;
-    double host_ms = 0, classify_ms = 0, apex_ms = 0, init_ms = 0, gather_ms = 0;
+    double host_ms = 0, output_ms = 0;
     std::vector<std::pair<int, int>> evk;  // (kind, event pair index)
 
     Pool pool(int i) const {
@@ -466,7 +467,7 @@ qh_status Run::topology(std::vector<SrcRec> &srcs, std::vector<int32_t> &newf) {
         int32_t u, w, g;
     };
     std::vector<Edge> horizon;
-    std::unordered_map<int32_t, int32_t> from;  // horizon vertex -> cone facet starting there
+    if (from.size() < (size_t)n) from.assign((size_t)n, -1);  // horizon vertex -> cone facet starting there
     for (int32_t cand : active) {
         if (!F[cand].alive || F[cand].len == 0) continue;
         if (F[cand].lock == stamp) continue;
@@ -512,7 +513,6 @@ qh_status Run::topology(std::vector<SrcRec> &srcs, std::vector<int32_t> &newf) {
                 horizon.push_back({F[f].v[i], F[f].v[(i + 1) % 3], g});
             }
         // the cone
-        from.clear();
         const int32_t gfirst = (int32_t)newf.size();
         const int32_t first_id = (int32_t)F.size();
         for (const Edge &e : horizon) {
@@ -535,12 +535,13 @@ qh_status Run::topology(std::vector<SrcRec> &srcs, std::vector<int32_t> &newf) {
             newf.push_back(id);
         }
         for (int32_t id = first_id; id < (int32_t)F.size(); ++id) {
-            auto it = from.find(F[id].v[1]);
-            if (it == from.end()) return QH_EDEVICE;
-            F[id].nb[1] = it->second;      // edge w -> p
-            F[it->second].nb[2] = id;       // its edge p -> w
+            const int32_t nxt = from[F[id].v[1]];
+            if (nxt < 0) return QH_EDEVICE;
+            F[id].nb[1] = nxt;        // edge w -> p
+            F[nxt].nb[2] = id;        // its edge p -> w
             F[id].lock = stamp;
         }
+        for (int32_t id = first_id; id < (int32_t)F.size(); ++id) from[F[id].v[0]] = -1;
         const int32_t gcount = (int32_t)F.size() - first_id;
         // the region dies; its points go to the cone
         for (int32_t f : region) {
@@ -566,33 +567,47 @@ qh_status Run::topology(std::vector<SrcRec> &srcs, std::vector<int32_t> &newf) {
     return QH_OK;
 }
 
-// Hull vertices and the canonical triangulation.
+// Hull vertices and the canonical triangulation.  Everything is indexed by
+// point or facet id in flat arrays (no hashing): corners -> incident facets
+// by counting, faces by union-find over coplanar neighbours, each face's
+// boundary walked through a next-vertex array.
 qh_status Run::output(int32_t *facets, int64_t *nfacets, int32_t *verts, int64_t *nverts) {
+    const int32_t nf = (int32_t)F.size();
     std::vector<int32_t> alive;
-    for (int32_t i = 0; i < (int32_t)F.size(); ++i)
+    alive.reserve(nf / 2 + 16);
+    for (int32_t i = 0; i < nf; ++i)
         if (F[i].alive) alive.push_back(i);
-    // incident facets per corner
-    std::unordered_map<int32_t, std::vector<int32_t>> inc;
+    // incident facets per corner (CSR over point ids)
+    std::vector<int32_t> deg((size_t)n + 1, 0);
     for (int32_t f : alive)
-        for (int k = 0; k < 3; ++k) inc[F[f].v[k]].push_back(f);
-    std::unordered_map<int32_t, char> is_vertex;
+        for (int k = 0; k < 3; ++k) deg[F[f].v[k] + 1]++;
+    for (int32_t i = 0; i < n; ++i) deg[i + 1] += deg[i];
+    std::vector<int32_t> inc(deg[n]);
+    {
+        std::vector<int32_t> fill(deg.begin(), deg.end() - 1);
+        for (int32_t f : alive)
+            for (int k = 0; k < 3; ++k) inc[fill[F[f].v[k]]++] = f;
+    }
+    std::vector<char> isv((size_t)n, 0);
     std::vector<int32_t> vlist;
-    for (auto &kv : inc) {
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t lo = deg[v], hi = deg[v + 1];
+        if (lo == hi) continue;
         int32_t planes[3];
         int np = 0;
-        for (int32_t f : kv.second) {
+        for (int32_t q = lo; q < hi && np < 3; ++q) {
+            const int32_t f = inc[q];
             bool dup = false;
-            for (int q = 0; q < np && !dup; ++q) dup = coplanar_dir(F[f].n, F[planes[q]].n);
+            for (int r = 0; r < np && !dup; ++r) dup = coplanar_dir(F[f].n, F[planes[r]].n);
             if (!dup) planes[np++] = f;
-            if (np == 3) break;
         }
-        const bool v = np >= 3;
-        is_vertex[kv.first] = v;
-        if (v) vlist.push_back(kv.first);
+        if (np >= 3) {
+            isv[v] = 1;
+            vlist.push_back(v);
+        }
     }
-    std::sort(vlist.begin(), vlist.end());
-    // faces: union of facets across edges between coplanar facets
-    std::unordered_map<int32_t, int32_t> parent;
+    // faces: union-find over facets joined across coplanar edges
+    std::vector<int32_t> parent((size_t)nf);
     for (int32_t f : alive) parent[f] = f;
     auto root = [&](int32_t f) {
         while (parent[f] != f) {
@@ -604,60 +619,69 @@ qh_status Run::output(int32_t *facets, int64_t *nfacets, int32_t *verts, int64_t
     for (int32_t f : alive)
         for (int k = 0; k < 3; ++k) {
             const int32_t g = F[f].nb[k];
-            if (coplanar_dir(F[f].n, F[g].n)) {
+            if (g > f && coplanar_dir(F[f].n, F[g].n)) {
                 const int32_t a = root(f), b = root(g);
                 if (a != b) parent[std::max(a, b)] = std::min(a, b);
             }
         }
-    std::unordered_map<int32_t, std::vector<int32_t>> faces;
-    for (int32_t f : alive) faces[root(f)].push_back(f);
-    std::vector<int32_t> tri;
-    tri.reserve(3 * (2 * vlist.size()));
-    std::unordered_map<int32_t, int32_t> next;
-    std::vector<int32_t> poly;
-    for (auto &kv : faces) {
-        const int32_t r = kv.first;
-        next.clear();
+    for (int32_t f : alive) parent[f] = root(f);
+    // facets grouped by face (counting sort on the root id)
+    std::vector<int32_t> fstart((size_t)nf + 1, 0);
+    for (int32_t f : alive) fstart[root(f) + 1]++;
+    for (int32_t i = 0; i < nf; ++i) fstart[i + 1] += fstart[i];
+    std::vector<int32_t> byface(alive.size());
+    {
+        std::vector<int32_t> fill(fstart.begin(), fstart.end() - 1);
+        for (int32_t f : alive) byface[fill[parent[f]]++] = f;
+    }
+    struct Tri {
+        int32_t a, b, c;
+    };
+    std::vector<Tri> tri;
+    tri.reserve(2 * vlist.size());
+    std::vector<int32_t> next((size_t)n, -1);
+    std::vector<int32_t> poly, touched;
+    for (int32_t r = 0; r < nf; ++r) {
+        const int32_t lo = fstart[r], hi = fstart[r + 1];
+        if (lo == hi) continue;
+        touched.clear();
         int32_t start = -1;
-        for (int32_t f : kv.second)
+        for (int32_t q = lo; q < hi; ++q) {
+            const HFacet &f = F[byface[q]];
             for (int k = 0; k < 3; ++k) {
-                if (root(F[f].nb[k]) == r) continue;
-                const int32_t u = F[f].v[k], w = F[f].v[(k + 1) % 3];
-                next[u] = w;
+                if (parent[f.nb[k]] == r) continue;
+                const int32_t u = f.v[k], w2 = f.v[(k + 1) % 3];
+                next[u] = w2;
+                touched.push_back(u);
                 if (start < 0 || u < start) start = u;
             }
+        }
         if (start < 0) return QH_EDEVICE;
         poly.clear();
         int32_t u = start;
-        for (size_t guard = 0; guard <= next.size(); ++guard) {
-            if (is_vertex[u]) poly.push_back(u);
-            auto it = next.find(u);
-            if (it == next.end()) return QH_EDEVICE;
-            u = it->second;
-            if (u == start) break;
-        }
-        if (u != start || poly.size() < 3) return QH_EDEVICE;
-        const size_t lo = std::min_element(poly.begin(), poly.end()) - poly.begin();
+        size_t steps = 0;
+        do {
+            if (isv[u]) poly.push_back(u);
+            u = next[u];
+            if (u < 0 || ++steps > touched.size()) return QH_EDEVICE;
+        } while (u != start);
+        for (int32_t t : touched) next[t] = -1;
         const size_t m = poly.size();
-        for (size_t i = 1; i + 1 < m; ++i) {
-            tri.push_back(poly[lo]);
-            tri.push_back(poly[(lo + i) % m]);
-            tri.push_back(poly[(lo + i + 1) % m]);
-        }
+        if (m < 3) return QH_EDEVICE;
+        const size_t l0 = std::min_element(poly.begin(), poly.end()) - poly.begin();
+        for (size_t i = 1; i + 1 < m; ++i)
+            tri.push_back({poly[l0], poly[(l0 + i) % m], poly[(l0 + i + 1) % m]});
     }
-    const size_t nt = tri.size() / 3;
-    std::vector<size_t> order(nt);
-    for (size_t i = 0; i < nt; ++i) order[i] = i;
-    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-        for (int k = 0; k < 3; ++k)
-            if (tri[3 * a + k] != tri[3 * b + k]) return tri[3 * a + k] < tri[3 * b + k];
-        return false;
+    std::sort(tri.begin(), tri.end(), [](const Tri &p, const Tri &q) {
+        if (p.a != q.a) return p.a < q.a;
+        if (p.b != q.b) return p.b < q.b;
+        return p.c < q.c;
     });
+    const size_t nt = tri.size();
     if (nt != 2 * vlist.size() - 4) return QH_EDEVICE;
     QH3_TRY(w->up.want(sizeof(int32_t) * (3 * nt + vlist.size()) + 512));
     int32_t *ht = w->up.as<int32_t>();
-    for (size_t i = 0; i < nt; ++i)
-        for (int k = 0; k < 3; ++k) ht[3 * i + k] = tri[3 * order[i] + k];
+    memcpy(ht, tri.data(), sizeof(int32_t) * 3 * nt);
     int32_t *hv = ht + 3 * nt;
     std::copy(vlist.begin(), vlist.end(), hv);
     QH3_TRY(hipMemcpyAsync(facets, ht, sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, st));
@@ -762,7 +786,8 @@ qh_status run3d(qh_ctx *c, const int32_t *pts, int64_t n, int32_t *facets, int64
     }
     const auto t0 = clk::now();
     qh_status s = R.output(facets, nfacets, verts, nverts);
-    R.host_ms += std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    R.output_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    R.host_ms += R.output_ms;
     if (s != QH_OK) return s;
 
     if (o && o->stats) {
@@ -783,6 +808,7 @@ qh_status run3d(qh_ctx *c, const int32_t *pts, int64_t n, int32_t *facets, int64
         S->max_segments = R.max_active;
         S->host_syncs = R.syncs;
         S->host_ms = R.host_ms;
+        S->host_output_ms = R.output_ms;
         if (R.timing) {
             double ms[4] = {0, 0, 0, 0};
             for (size_t j = 0; j < R.evk.size(); ++j) {

@@ -58,7 +58,12 @@ size_t carve(qh_ctx *c, char *base) {
     w.adir = cv.take<Best>(4 * (size_t)c->scap);
     w.recF = cv.take<Best>(2 * (size_t)c->tcap);
     w.recL = cv.take<Best>(2 * (size_t)c->tcap);
-    w.st2_ = cv.take<uint64_t>((size_t)2 * (c->tcap + 4));
+    w.tcnt_ = cv.take<uint32_t>((size_t)2 * c->tcap);
+    w.pv_ = cv.take<int32_t>((size_t)4 * (c->tcap + 2));
+    w.pp_ = cv.take<int32_t>((size_t)4 * (c->tcap + 2));
+    w.kf_ = cv.take<int32_t>((size_t)4 * (c->tcap + 2));
+    w.st5_ = cv.take<uint64_t>((size_t)2 * c->s5cap);
+    w.st5b_ = cv.take<uint64_t>((size_t)2 * c->s5cap);
     w.st4_ = cv.take<uint64_t>((size_t)2 * c->s4cap);
     w.st4b_ = cv.take<uint64_t>((size_t)2 * c->s4cap);
     w.recF0 = cv.take<Best>(2 * (size_t)c->tcap);
@@ -75,12 +80,16 @@ size_t carve(qh_ctx *c, char *base) {
     w.hcap = c->hcap;
     w.tcap = c->tcap;
     w.s4cap = c->s4cap;
+    w.s5cap = c->s5cap;
     return align_up(cv.off, 256);
 }
 
 qh_status ensure(qh_ctx *c, int64_t n, int32_t k) {
-    const int64_t cap_pts = std::max<int64_t>(1, (n + kTile - 1) / kTile) * kTile;
+    // a round writes the survivors of tile t at t * kTile of each region, and a
+    // round has at most n / kTile + 2 tiles (two regions with a ragged tail)
+    const int64_t cap_pts = (std::max<int64_t>(1, (n + kTile - 1) / kTile) + 2) * kTile;
     const int32_t tcap = (int32_t)(cap_pts / kTile + 2);
+    const int32_t s5cap = (int32_t)(tcap / (kSegBlock * kPieceItems) + 8);
     const int64_t smax = n + k + 16;
     int64_t scap = std::max<int64_t>({4096, n / 16 + 2 * (int64_t)k + 1024, c->want_scap});
     scap = std::min(scap, std::max<int64_t>(smax, 4096));
@@ -90,7 +99,7 @@ qh_status ensure(qh_ctx *c, int64_t n, int32_t k) {
     const int32_t kcap = std::max(k, 1);
     const int32_t s4cap = (int32_t)(2 * ((2 * scap + kSegBlock - 1) / kSegBlock) + 8);
     if (c->dmem && cap_pts <= c->cap_pts && scap <= c->scap && hcap <= c->hcap && tcap <= c->tcap &&
-        kcap <= c->kcap)
+        kcap <= c->kcap && s5cap <= c->s5cap)
         return QH_OK;
     if (c->dmem) {
         (void)hipFree(c->dmem);
@@ -102,12 +111,13 @@ qh_status ensure(qh_ctx *c, int64_t n, int32_t k) {
     c->hcap = std::max((int32_t)hcap, c->hcap);
     c->kcap = std::max(kcap, c->kcap);
     c->s4cap = std::max(s4cap, c->s4cap);
+    c->s5cap = std::max(s5cap, c->s5cap);
     const size_t bytes = carve(c, nullptr);
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         c->cap_pts = 0;
-        c->scap = c->hcap = c->tcap = c->kcap = c->s4cap = 0;
+        c->scap = c->hcap = c->tcap = c->kcap = c->s4cap = c->s5cap = 0;
         return QH_ENOMEM;
     }
     c->dmem = p;

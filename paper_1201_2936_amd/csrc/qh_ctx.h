@@ -18,7 +18,7 @@ struct qh_ctx {
     int cus = 256;
     // capacities of the current allocation
     int64_t cap_pts = 0;
-    int32_t scap = 0, hcap = 0, tcap = 0, s4cap = 0, kcap = 0;
+    int32_t scap = 0, hcap = 0, tcap = 0, s4cap = 0, s5cap = 0, kcap = 0;
     // pending growth requests after a capacity overflow
     int32_t want_scap = 0, want_hcap = 0;
     void *dmem = nullptr;

@@ -183,9 +183,10 @@ struct RoundState {
     int32_t n[2];       // points in region 0 / 1
     int32_t s[2];       // segments in table 0 / 1
     int32_t hbase;      // first compact hull id of this round's apexes
-    uint32_t tile_ctr;  // dynamic tile counter of the round kernel
+    int32_t npc[2];     // non-empty pieces of region 0 / 1 (rounds after the first split)
     uint32_t seg_ctr;   // dynamic tile counter of the segment kernel
-    int32_t chunk;      // tiles per chunk used by the round kernel
+    uint32_t piece_ctr; // dynamic tile counter of the piece scan
+    int32_t pad;
 };
 
 enum : int32_t {
@@ -211,7 +212,7 @@ struct Control {
     unsigned long long filter_fallbacks;
     unsigned long long candidates;
     unsigned long long rounds_with_work;
-    unsigned int bar;                 // grid barrier arrivals (reset before each launch)
+    unsigned int nacc[2][2];          // survivors per region written by the round kernel, by parity
     int32_t H;                        // compact hull ids used
     long long h_total;                // hull vertices of all instances
     int32_t nstamps;

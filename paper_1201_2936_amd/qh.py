@@ -25,7 +25,7 @@ QH_FP32_FILTER = 1
 QH_FLAG_TIMING = 1
 
 EXPORTED = ["qh_ctx_create", "qh_ctx_destroy", "qh_status_str", "qh_version",
-            "qh_hull2d", "qh_hull2d_batched", "qh_hull3d"]
+            "qh_hull2d", "qh_hull2d_batched", "qh_hull3d", "qh_test_flag_permute"]
 
 
 class QhStats(ctypes.Structure):
@@ -49,6 +49,7 @@ class QhStats(ctypes.Structure):
         ("grid_blocks", ctypes.c_int64),
         ("host_syncs", ctypes.c_int64),
         ("host_ms", ctypes.c_double),
+        ("host_output_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -97,6 +98,8 @@ def load(path: str = LIB_PATH):
     lib.qh_hull2d_batched.restype = ctypes.c_int
     lib.qh_hull2d_batched.argtypes = [vp, i64, vp, ctypes.c_int32, vp, vp,
                                       ctypes.POINTER(i64), ctypes.POINTER(QhOpts)]
+    lib.qh_test_flag_permute.restype = ctypes.c_int
+    lib.qh_test_flag_permute.argtypes = [vp, vp, i64, ctypes.c_int32, vp, vp, vp]
     lib.qh_hull3d.restype = ctypes.c_int
     lib.qh_hull3d.argtypes = [vp, i64, vp, ctypes.POINTER(i64), vp, ctypes.POINTER(i64),
                               ctypes.POINTER(QhOpts)]
@@ -216,3 +219,26 @@ def qh_hull3d(pts, mode: int = QH_EXACT_INT64, ctx: Context | None = None,
     if st != QH_OK:
         raise QhError(st, "qh_hull3d")
     return fac[: 3 * nf.value].view(-1, 3), ver[: nv.value], stats.as_dict()
+
+
+def qh_test_flag_permute(f, s, k: int, stream=None):
+    """k-state segmented stable partition of device int32 states f and uint8
+    head flags s: returns (p int32, s_new uint8) device tensors."""
+    import torch
+    lib = load()
+    if (not isinstance(f, torch.Tensor) or not f.is_cuda or f.dtype != torch.int32 or f.dim() != 1
+            or not isinstance(s, torch.Tensor) or not s.is_cuda or s.dtype != torch.uint8
+            or s.shape != f.shape):
+        raise TypeError("f must be int32 and s uint8 CUDA tensors of one shape (n,)")
+    f = f.contiguous()
+    s = s.contiguous()
+    n = f.shape[0]
+    p = torch.empty(max(n, 1), dtype=torch.int32, device=f.device)
+    s_new = torch.empty(max(n, 1), dtype=torch.uint8, device=f.device)
+    st = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    rc = lib.qh_test_flag_permute(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(s.data_ptr()), n,
+                                  int(k), ctypes.c_void_p(p.data_ptr()),
+                                  ctypes.c_void_p(s_new.data_ptr()), ctypes.c_void_p(st))
+    if rc != QH_OK:
+        raise QhError(rc, "qh_test_flag_permute")
+    return p[:n], s_new[:n]
