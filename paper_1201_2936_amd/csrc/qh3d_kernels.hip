@@ -289,13 +289,15 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return l ? (~0ull >> (64 - l)) : 0ull;
 }
 
-// FP32 filter of the plane test.  With |coordinate| <= 2^19 every input of
-// the products is an exact float except the normal components (|n_i| < 2^41,
-// rounded once).  Each of the three products has relative error <= 2 eps
-// (+ eps^2) against the exact n_i p_i, the two sums and the subtraction of
-// the offset (rounded once when stored) add at most 3 eps of the running
-// magnitudes, so |fl(d) - d| <= 6 eps (|n.p| terms + |off|) (1 + O(eps)).
-// 8 eps covers the higher-order terms and the rounding of the bound itself.
+// FP32 filter of the plane test d = n.p - off.  With |coordinate| <= 2^19
+// the coordinates are exact floats; the normal components and the offset
+// are rounded once when converted.  Each of the four terms then passes
+// through at most five roundings (conversion, product, two sums, the final
+// difference), so |fl(d) - d| <= gamma_5 (|n_x p_x| + |n_y p_y| + |n_z p_z| +
+// |off|) with gamma_5 = 5 eps / (1 - 5 eps), eps = 2^-24.  In terms of the
+// computed magnitudes (each within a factor (1 - eps)^2 of the exact ones)
+// the bound is below 5.0001 eps times their sum; 8 eps also covers the
+// rounding of the sum and of the product that form the bound.
 constexpr float kErr3 = 8.0f / 16777216.0f;
 
 __device__ __forceinline__ int classify_point(const FacetRec *fac, int32_t gfirst, int32_t gcount,
