@@ -7,12 +7,13 @@ in device memory, through the C ABI (qh_hull2d).  The headline form is the
 FP32 filter with exact int64 fallback (bit-exact); the plain exact-int64 form
 is timed beside it on the same data.
 
-Prints ONE JSON line.  ``roofline`` describes the round kernel (k_round: the
-first split and one launch per later round), the kernel that moves nearly all
-the bytes: algorithmic bytes per launch (first split 8 B per point read and 12
-B per survivor written; later rounds 12 B per point read and 12 B per survivor
-written) over its average launch duration, timed with HIP events around each
-launch on the stream it runs on.
+Prints ONE JSON line.  ``roofline`` describes the round (k_round for the tiles
+covered by one segment and k_round_multi for the others, launched together
+for the first split and once per later round), which moves nearly all the
+bytes: algorithmic bytes per round (first split 8 B per point read and 12 B
+per survivor written; later rounds 12 B per point read and 12 B per survivor
+written) over the round's average duration, timed with HIP events around the
+pair of launches on the stream they run on.
 ``cpu_baseline`` is the oracle (plain single-threaded C Quickhull) on the
 same points.  ``batched`` is the batched form on 4,096 disks (about 5.1e8
 points) in one qh_hull2d_batched call, beside 4,096 sequential qh_hull2d
@@ -317,7 +318,7 @@ def main():
         "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"]
                           if st_f["filter_tests"] else 0.0),
         "argmax_candidates": int(st_f["argmax_candidates"]),
-        "round_kernel": {"name": "k_round (first split and every later round)",
+        "round_kernel": {"name": "k_round + k_round_multi (first split and every later round)",
                          "launches_per_step": launches / args.steps,
                          "avg_launch_us": round(avg_launch_ms * 1e3, 3),
                          "bytes_per_launch": round(bytes_per_launch),

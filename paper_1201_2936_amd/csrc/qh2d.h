@@ -40,6 +40,7 @@ struct Ws2 {
     int32_t *pv_;       // pieces of a round's input: virtual start [parity][region][tcap + 2]
     int32_t *pp_;       // ... physical start [parity][region][tcap + 2]
     int32_t *kf_;       // first piece of every tile [parity][region][tcap + 2]
+    int32_t *ml_;       // tiles of a round that hold several segments: [parity][tcap]
     uint64_t *st5_;     // look-back words of the piece scan (counts): [parity][s5cap]
     uint64_t *st5b_;    // ... (non-empty pieces): [parity][s5cap]
     uint64_t *st4_;     // look-back words of the segment phase: [parity][s4cap]
@@ -75,6 +76,7 @@ struct Ws2 {
     __host__ __device__ int32_t *pv(int p, int r) const { return pv_ + (size_t)(p * 2 + r) * (tcap + 2); }
     __host__ __device__ int32_t *pp(int p, int r) const { return pp_ + (size_t)(p * 2 + r) * (tcap + 2); }
     __host__ __device__ int32_t *kf(int p, int r) const { return kf_ + (size_t)(p * 2 + r) * (tcap + 2); }
+    __host__ __device__ int32_t *ml(int p) const { return ml_ + (size_t)p * tcap; }
     __host__ __device__ uint64_t *st5(int p) const { return st5_ + (size_t)p * s5cap; }
     __host__ __device__ uint64_t *st5b(int p) const { return st5b_ + (size_t)p * s5cap; }
     __host__ __device__ uint64_t *st4(int p) const { return st4_ + (size_t)p * s4cap; }
@@ -100,7 +102,7 @@ struct HullArgs {
 hipError_t launch_setup(const Ws2 &ws, const HullArgs &a, int grid, hipStream_t st);
 hipError_t launch_extremes(const Ws2 &ws, const HullArgs &a, int grid, hipStream_t st);
 hipError_t launch_round(const Ws2 &ws, const HullArgs &a, int mode, int32_t r, int grid,
-                        hipStream_t st);
+                        int grid_multi, hipStream_t st);
 hipError_t launch_segments(const Ws2 &ws, const HullArgs &a, int32_t r, int grid, hipStream_t st);
 hipError_t launch_output(const Ws2 &ws, const HullArgs &a, int32_t H, hipStream_t st);
 // resident blocks of the round kernel on the whole device

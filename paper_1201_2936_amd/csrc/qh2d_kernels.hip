@@ -161,6 +161,113 @@ __device__ __forceinline__ float wave_max_f(float v) {
     return v;
 }
 
+// DPP reductions (row shifts and row broadcasts, no LDS): the result is
+// complete in lane 63 only.  A lane whose source is outside its row, or
+// whose row is masked off, receives the operation's identity.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ uint32_t dpp_or0(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, RowMask, 0xf, true);
+}
+
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ void rec_step(Best &b) {
+    Best o;
+    o.key1 = ((uint64_t)dpp_or0<Ctrl, RowMask>((uint32_t)(b.key1 >> 32)) << 32) |
+             (uint64_t)dpp_or0<Ctrl, RowMask>((uint32_t)b.key1);
+    o.key2 = ((uint64_t)dpp_or0<Ctrl, RowMask>((uint32_t)(b.key2 >> 32)) << 32) |
+             (uint64_t)dpp_or0<Ctrl, RowMask>((uint32_t)b.key2);
+    o.x = (int32_t)dpp_or0<Ctrl, RowMask>((uint32_t)b.x);
+    o.y = (int32_t)dpp_or0<Ctrl, RowMask>((uint32_t)b.y);
+    o.idx = (int32_t)dpp_or0<Ctrl, RowMask>((uint32_t)b.idx);
+    o.cnt = (int32_t)dpp_or0<Ctrl, RowMask>((uint32_t)b.cnt);
+    rec_merge(b, o);  // a zero record (key1 = 0) never wins; it adds no count
+}
+
+// argmax record with summed counts over the wave, complete in lane 63
+__device__ __forceinline__ void wave_rec63(Best &b) {
+    rec_step<0x111, 0xf>(b);   // row_shr:1
+    rec_step<0x112, 0xf>(b);   // row_shr:2
+    rec_step<0x114, 0xf>(b);   // row_shr:4
+    rec_step<0x118, 0xf>(b);   // row_shr:8
+    rec_step<0x142, 0xa>(b);   // row_bcast:15 -> rows 1 and 3
+    rec_step<0x143, 0xc>(b);   // row_bcast:31 -> rows 2 and 3
+}
+
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ float dpp_fmax_step(float v) {
+    const uint32_t ninf = 0xff800000u;  // -inf: the identity of max
+    const float o = __uint_as_float((uint32_t)__builtin_amdgcn_update_dpp(
+        (int)ninf, (int)__float_as_uint(v), Ctrl, RowMask, 0xf, false));
+    return fmaxf(v, o);
+}
+
+// A lighter running argmax for the one-segment path: the exact distance, the
+// tie key (its low 32 bits are the point's index) and the count; the
+// point's coordinates are read back from the input when the record is made.
+struct RunBest {
+    uint64_t k1, k2;
+    int32_t cnt;
+};
+
+__device__ __forceinline__ RunBest rb_none() {
+    RunBest b;
+    b.k1 = 0;
+    b.k2 = ~0ull;
+    b.cnt = 0;
+    return b;
+}
+
+__device__ __forceinline__ void rb_offer(RunBest &b, uint64_t d, int32_t x, int32_t y, int32_t idx,
+                                         int32_t ex, int32_t ey) {
+    if (d < b.k1) return;
+    const uint64_t k2 = tie_key(x, y, idx, ex, ey);
+    if (d > b.k1 || k2 < b.k2) {
+        b.k1 = d;
+        b.k2 = k2;
+    }
+}
+
+__device__ __forceinline__ void rb_merge(RunBest &acc, const RunBest &o) {
+    const int32_t c = acc.cnt + o.cnt;
+    if (o.k1 > acc.k1 || (o.k1 == acc.k1 && o.k1 != 0 && o.k2 < acc.k2)) {
+        acc.k1 = o.k1;
+        acc.k2 = o.k2;
+    }
+    acc.cnt = c;
+}
+
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ void rb_step(RunBest &b) {
+    RunBest o;
+    o.k1 = ((uint64_t)dpp_or0<Ctrl, RowMask>((uint32_t)(b.k1 >> 32)) << 32) |
+           (uint64_t)dpp_or0<Ctrl, RowMask>((uint32_t)b.k1);
+    o.k2 = ((uint64_t)dpp_or0<Ctrl, RowMask>((uint32_t)(b.k2 >> 32)) << 32) |
+           (uint64_t)dpp_or0<Ctrl, RowMask>((uint32_t)b.k2);
+    o.cnt = (int32_t)dpp_or0<Ctrl, RowMask>((uint32_t)b.cnt);
+    rb_merge(b, o);  // a zero record (k1 = 0) never wins; it adds no count
+}
+
+// complete in lane 63
+__device__ __forceinline__ void wave_rb63(RunBest &b) {
+    rb_step<0x111, 0xf>(b);
+    rb_step<0x112, 0xf>(b);
+    rb_step<0x114, 0xf>(b);
+    rb_step<0x118, 0xf>(b);
+    rb_step<0x142, 0xa>(b);
+    rb_step<0x143, 0xc>(b);
+}
+
+// maximum over the wave, returned to every lane
+__device__ __forceinline__ float wave_max_f_dpp(float v) {
+    v = dpp_fmax_step<0x111, 0xf>(v);
+    v = dpp_fmax_step<0x112, 0xf>(v);
+    v = dpp_fmax_step<0x114, 0xf>(v);
+    v = dpp_fmax_step<0x118, 0xf>(v);
+    v = dpp_fmax_step<0x142, 0xa>(v);
+    v = dpp_fmax_step<0x143, 0xc>(v);
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), kWave - 1));
+}
+
 // candidate update of a running best with an exact distance d > 0
 __device__ __forceinline__ void best_offer(Best &b, uint64_t d, int32_t x, int32_t y, int32_t idx,
                                            int32_t ex, int32_t ey) {
@@ -200,6 +307,14 @@ struct RoundSmem {
     uint32_t woff[kNW];             // their tile-local offsets
 };
 
+struct FastSmem {
+    uint32_t stat[4];
+    int32_t pvs[kTile + 4];         // virtual starts of the tile's input pieces
+    int32_t pps[kTile + 4];         // ... their physical starts
+    RunBest wrb[kNW][2];            // per-wave argmax of a run
+    uint32_t wcnt[kNW];             // per-wave survivor counts (child 0 | child 1 << 16)
+};
+
 struct ExtSmem {
     int32_t s_m, pad;
     Best red[kNW][2];
@@ -237,6 +352,25 @@ constexpr size_t cmax(A a, B b) { return a > b ? a : b; }
 constexpr size_t kSmemBytes =
     cmax(cmax(cmax(sizeof(RoundSmem), sizeof(ExtSmem)), cmax(sizeof(SegSmem), sizeof(RankSmem))),
          sizeof(ScanSmem));
+
+
+// Append tile t to the list of multi-segment tiles (wave-aggregated atomic).
+// Called by every lane of a wave; lanes with want == false add nothing.
+__device__ __forceinline__ void ml_append(const Ws2 &ws, int p, RoundState *rsp, bool want, int t) {
+    const uint64_t m = __ballot(want);
+    if (m == 0) return;
+    const int leader = __builtin_ctzll(m);
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(&rsp->nmulti, (int)__popcll(m));
+    base = __builtin_amdgcn_readlane(base, leader);
+    if (want) {
+        const int l = lane_id();
+        const uint64_t below = l ? (m & (~0ull >> (64 - l))) : 0ull;
+        const int slot = base + (int)__popcll(below);
+        if (slot < ws.tcap) ws.ml(p)[slot] = t;
+        else atomicOr(&ws.ctl->error, kErrInternal);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // set-up
@@ -328,7 +462,13 @@ __device__ __forceinline__ void phase_setup(const Ws2 &ws, const HullArgs &a) {
     }
     if (ws.ctl->error) return;
     const int ntiles = (a.n + kTile - 1) / kTile;
-    for (int t = tid; t < ntiles; t += stride) {
+    // every wave iterates in lock step (ml_append is wave-collective)
+    for (int t0 = tid - lane_id(); t0 < ntiles; t0 += stride) {
+        const int t = t0 + lane_id();
+        if (t >= ntiles) {
+            ml_append(ws, 0, &ws.ctl->rs[0], false, 0);
+            continue;
+        }
         const int64_t v = (int64_t)t * kTile;
         // largest i with offsets[i] <= v: that instance holds v and is non-empty
         int lo = 0, hi = a.k;
@@ -343,6 +483,7 @@ __device__ __forceinline__ void phase_setup(const Ws2 &ws, const HullArgs &a) {
         ti.end = (int32_t)en;
         ti.single = en >= min(v + kTile, (int64_t)a.n) ? 1 : 0;
         ws.tinfo(0, 0)[t] = ti;
+        ml_append(ws, 0, &ws.ctl->rs[0], !ti.single, t);
     }
 }
 
@@ -358,7 +499,38 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
     const int ntiles = (n + kTile - 1) / kTile;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
     bool bad = false;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // Every block takes a contiguous range of tiles.  Consecutive tiles of
+    // one instance form a run whose minimum and maximum stay in registers;
+    // the block reduces once per run and writes the run's record at its first
+    // tile (the other tiles of the run get empty records).  Tiles that hold
+    // several instances are reduced per instance in LDS.
+    const int T = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int tb = blockIdx.x * T, te = min(tb + T, ntiles);
+    Best rmn = best_none(), rmx = best_none();
+    int cur = -1, run0 = 0, cst = 0, cen = 0;
+    auto flush = [&](int tend) {
+        wave_rec63(rmn);
+        wave_rec63(rmx);
+        if (lane == kWave - 1) { sm->red[wv][0] = rmn; sm->red[wv][1] = rmx; }
+        __syncthreads();
+        if (tid == 0) {
+            Best m0 = sm->red[0][0], m1 = sm->red[0][1];
+            for (int w = 1; w < kNW; ++w) {
+                best_merge(m0, sm->red[w][0]);
+                best_merge(m1, sm->red[w][1]);
+            }
+            ws.recF0[run0 * 2 + 0] = m0; ws.recF0[run0 * 2 + 1] = m1;
+            ws.recL0[run0 * 2 + 0] = m0; ws.recL0[run0 * 2 + 1] = m1;
+            if (cst >= run0 * kTile && cen <= min(tend * kTile, n)) {
+                ws.dir0[cur * 2 + 0] = m0;
+                ws.dir0[cur * 2 + 1] = m1;
+            }
+        }
+        __syncthreads();
+        rmn = best_none();
+        rmx = best_none();
+    };
+    for (int tile = tb; tile < te; ++tile) {
         const int lo = tile * kTile;
         const int hi = min(lo + kTile, n);
         int32_t X[kItems], Y[kItems];
@@ -388,8 +560,18 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
                        (Y[i] < -kCoordMax2D);
         }
         if (ti.single) {
-            // one instance covers the tile: running min / max in registers
-            Best mn = best_none(), mx = best_none();
+            if (ti.seg != cur) {
+                if (cur >= 0) flush(tile);
+                cur = ti.seg;
+                run0 = tile;
+                cst = ti.start;
+                cen = ti.end;
+            } else if (tid < 4) {
+                // inside a run: an empty record (the run's record is at run0)
+                const Best e = best_none();
+                if (tid < 2) ws.recF0[tile * 2 + tid] = e;
+                else ws.recL0[tile * 2 + tid - 2] = e;
+            }
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
                 const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
@@ -397,26 +579,15 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
                 const uint64_t ck = coord_key(X[i], Y[i]);
                 Best c;
                 c.key1 = ~ck; c.key2 = (uint32_t)v; c.x = X[i]; c.y = Y[i]; c.idx = v; c.cnt = 0;
-                best_merge(mn, c);
+                best_merge(rmn, c);
                 c.key1 = ck;
-                best_merge(mx, c);
+                best_merge(rmx, c);
             }
-            wave_best(mn);
-            wave_best(mx);
-            if (lane == 0) { sm->red[wv][0] = mn; sm->red[wv][1] = mx; }
-            __syncthreads();
-            if (tid == 0) {
-                for (int w = 1; w < kNW; ++w) {
-                    best_merge(mn, sm->red[w][0]);
-                    best_merge(mx, sm->red[w][1]);
-                }
-                const bool inside = ti.start >= lo && ti.end <= hi;
-                if (inside) { ws.dir0[ti.seg * 2 + 0] = mn; ws.dir0[ti.seg * 2 + 1] = mx; }
-                ws.recF0[tile * 2 + 0] = mn; ws.recF0[tile * 2 + 1] = mx;
-                ws.recL0[tile * 2 + 0] = mn; ws.recL0[tile * 2 + 1] = mx;
-            }
-            __syncthreads();
             continue;
+        }
+        if (cur >= 0) {
+            flush(tile);
+            cur = -1;
         }
         // several instances in the tile: per-slot LDS reduction
         const int s0 = ti.seg;
@@ -497,6 +668,7 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
             __syncthreads();
         }
     }
+    if (cur >= 0) flush(te);
     if (__syncthreads_or(bad) && threadIdx.x == 0) {
         atomicOr(&ctl->error, kErrRange);
         atomicOr(&ctl->setup_error, kErrRange);
@@ -625,8 +797,9 @@ __device__ __forceinline__ void load_input(const HullArgs &a, int lo, int hi, in
 // the pieces kA .. kB the previous round wrote.  Returns false (and raises
 // an internal error) if the piece table does not fit the tile.
 __device__ __forceinline__ bool load_pieces(const Ws2 &ws, int p, int R, int lt, int ntR, int npc,
-                                            int lo, int hi, RoundSmem *sm, int32_t (&X)[kItems],
-                                            int32_t (&Y)[kItems], int32_t (&I)[kItems]) {
+                                            int lo, int hi, int32_t *pvs, int32_t *pps,
+                                            int32_t (&X)[kItems], int32_t (&Y)[kItems],
+                                            int32_t (&I)[kItems]) {
     const int tid = threadIdx.x;
     const int32_t *kf = ws.kf(p, R);
     const int kA = kf[lt];
@@ -637,8 +810,8 @@ __device__ __forceinline__ bool load_pieces(const Ws2 &ws, int p, int R, int lt,
         const int32_t *pv = ws.pv(p, R) + kA;
         const int32_t *pp = ws.pp(p, R) + kA;
         for (int j = tid; j < K; j += kBlock) {
-            sm->pvs[j] = pv[j];
-            sm->pps[j] = pp[j];
+            pvs[j] = pv[j];
+            pps[j] = pp[j];
         }
     }
     __syncthreads();
@@ -650,8 +823,8 @@ __device__ __forceinline__ bool load_pieces(const Ws2 &ws, int p, int R, int lt,
         const int v = item_pos(lo, i);
         X[i] = Y[i] = I[i] = 0;
         if (!ok || v >= hi) continue;
-        const int j = slot_of(sm->pvs, K, v);
-        const int64_t ph = (int64_t)sm->pps[j] + (v - sm->pvs[j]);
+        const int j = slot_of(pvs, K, v);
+        const int64_t ph = (int64_t)pps[j] + (v - pvs[j]);
         if (ph < 0 || ph >= cap) { bad = true; continue; }
         X[i] = sx[ph];
         Y[i] = sy[ph];
@@ -701,11 +874,104 @@ __device__ __forceinline__ bool filter_cand(int32_t x, int32_t y, uint32_t st, c
     return fkey(__fadd_rn(e, 2.f * B)) >= lmk;
 }
 
+// The one-segment tiles may emit their survivors in any order, so their
+// waves work on contiguous quarters of the tile with 64-lane runs: lane l of
+// wave w holds items v = lo + 512 w + 64 i + l (gathered loads and the
+// per-item scatter are dense per instruction); the first split reads the
+// caller's array as 4-point vectors, v = lo + 512 w + 256 (i / 4) + 4 l + i % 4.
+__device__ __forceinline__ int fast_pos(int lo, int i) {
+    return lo + (int)(threadIdx.x / kWave) * 512 + i * kWave + lane_id();
+}
+__device__ __forceinline__ int fast_pos_init(int lo, int i) {
+    return lo + (int)(threadIdx.x / kWave) * 512 + (i >> 2) * 256 + lane_id() * 4 + (i & 3);
+}
+
+__device__ __forceinline__ uint32_t load_input_wave(const HullArgs &a, int lo, int hi,
+                                                    int32_t (&X)[kItems], int32_t (&Y)[kItems],
+                                                    int32_t (&I)[kItems]) {
+    uint32_t vm = 0;
+#pragma unroll
+    for (int qq = 0; qq < kQ; ++qq) {
+        const int v0 = fast_pos_init(lo, qq * 4);
+        if (a.vec_ok && v0 + 3 < hi) {
+            const int4 pa = *reinterpret_cast<const int4 *>(a.x + v0);
+            const int4 pb = *reinterpret_cast<const int4 *>(a.y + v0);
+            X[qq * 4 + 0] = pa.x; X[qq * 4 + 1] = pa.y; X[qq * 4 + 2] = pa.z; X[qq * 4 + 3] = pa.w;
+            Y[qq * 4 + 0] = pb.x; Y[qq * 4 + 1] = pb.y; Y[qq * 4 + 2] = pb.z; Y[qq * 4 + 3] = pb.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int v = v0 + j;
+                X[qq * 4 + j] = v < hi ? a.x[v] : 0;
+                Y[qq * 4 + j] = v < hi ? a.y[v] : 0;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            I[qq * 4 + j] = v0 + j;
+            vm |= (v0 + j < hi ? 1u : 0u) << (qq * 4 + j);
+        }
+    }
+    return vm;
+}
+
+// later rounds: gather the tile's virtual range from the pieces kA .. kB of
+// the previous round (see load_pieces); returns the valid-item mask, or
+// 0xffffffff if the piece table does not fit the tile
+__device__ __forceinline__ uint32_t load_pieces_wave(const Ws2 &ws, int p, int R, int lt, int ntR,
+                                                     int npc, int lo, int hi, int32_t *pvs,
+                                                     int32_t *pps, int32_t (&X)[kItems],
+                                                     int32_t (&Y)[kItems], int32_t (&I)[kItems]) {
+    const int tid = threadIdx.x;
+    const int32_t *kf = ws.kf(p, R);
+    const int kA = kf[lt];
+    const int kB = (lt + 1 < ntR) ? kf[lt + 1] : npc - 1;
+    const int K = kB - kA + 1;
+    const bool ok = kA >= 0 && K >= 1 && K <= kTile + 2 && kB < npc;
+    if (ok) {
+        const int32_t *pv = ws.pv(p, R) + kA;
+        const int32_t *pp = ws.pp(p, R) + kA;
+        for (int j = tid; j < K; j += kBlock) {
+            pvs[j] = pv[j];
+            pps[j] = pp[j];
+        }
+    }
+    __syncthreads();
+    if (!ok) {
+        atomicOr(&ws.ctl->error, kErrInternal);
+        return 0xffffffffu;
+    }
+    const int32_t *sx = ws.px(p, R), *sy = ws.py(p, R), *si = ws.pi(p, R);
+    const int64_t cap = ws.cap_pts;
+    uint32_t vm = 0;
+    bool bad = false;
+    // the piece of the wave's first item, then a short forward walk per item
+    int j = 0;
+    const int w0 = fast_pos(lo, 0);
+    if (K > 1) j = slot_of(pvs, K, min(w0, hi - 1));
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        const int v = fast_pos(lo, i);
+        X[i] = Y[i] = I[i] = 0;
+        if (v >= hi) continue;
+        while (j + 1 < K && pvs[j + 1] <= v) ++j;
+        const int64_t ph = (int64_t)pps[j] + (v - pvs[j]);
+        if (ph < 0 || ph >= cap) { bad = true; continue; }
+        X[i] = sx[ph];
+        Y[i] = sy[ph];
+        I[i] = si[ph];
+        vm |= 1u << i;
+    }
+    if (bad) atomicOr(&ws.ctl->error, kErrInternal);
+    return vm;
+}
+
 template <int MODE>
-__device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, int r, char *smem) {
+__device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &a, int r, char *smem) {
+    FastSmem *sm = reinterpret_cast<FastSmem *>(smem);
+    uint32_t *stat = sm->stat;
     const bool INIT = r == 0;  // the first split reads the input (index = position)
     Control *ctl = ws.ctl;
-    RoundSmem *sm = reinterpret_cast<RoundSmem *>(smem);
     const int p = r & 1, q = p ^ 1;
     const RoundState *rs = &ctl->rs[p];
     const int n0 = rs->n[0], n1 = rs->n[1];
@@ -716,11 +982,30 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
     int32_t *ox0 = ws.px(q, 0), *oy0 = ws.py(q, 0), *oi0 = ws.pi(q, 0);
     int32_t *ox1 = ws.px(q, 1), *oy1 = ws.py(q, 1), *oi1 = ws.pi(q, 1);
     const int64_t cap = ws.cap_pts;
+    (void)S0; (void)S1; (void)lane; (void)wv;
 
     uint32_t ntests = 0, nfall = 0, ncand = 0;
     uint32_t acc0 = 0, acc1 = 0;  // survivors written by this block (thread 0)
     bool oob = false;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // the multi-segment tiles of the next round are listed afresh by the
+    // segment kernel that follows
+    // every block takes a contiguous range of T tiles (the segment kernel
+    // finds the argmax records of a run at the first tile of the run in each
+    // range, so it needs T)
+    const int T = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+    if (blockIdx.x == 0 && tid == 0) {
+        ctl->rs[q].nmulti = 0;
+        ctl->tper[p] = T;
+    }
+    const int tb = blockIdx.x * T, te = min(tb + T, ntiles);
+    // A run: consecutive one-segment tiles of one segment in this block.  Its
+    // argmax of each child stays in the lanes' registers (r0, r1) and is
+    // reduced once, when the run ends.
+    RunBest r0 = rb_none(), r1 = rb_none();
+    int cur = -1, run0 = 0, run_lo = 0, run_hi = 0, seg_st = 0, seg_en = 0;
+    for (int tile = tb; tile <= te; ++tile) {
+        // tile == te only closes the last run
+        const bool past = tile == te;
         const int R = tile < nt0 ? 0 : 1;
         const int lt = tile - (R ? nt0 : 0);
         const int NR = R ? n1 : n0;
@@ -728,40 +1013,83 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
         const int gbase = R ? S0 : 0;
         const int lo = lt * kTile;
         const int hi = min(lo + kTile, NR);
+        (void)SR;
+        TileInfo ti;
+        if (!past) ti = ws.tinfo(p, R)[lt];
+        else ti.single = 0;
+        const int gseg = gbase + ti.seg;
+        if (cur >= 0 && (!ti.single || gseg != cur)) {
+            // the run ends: reduce it, record it at its first tile
+            wave_rb63(r0);
+            wave_rb63(r1);
+            if (lane == kWave - 1) {
+                sm->wrb[wv][0] = r0;
+                sm->wrb[wv][1] = r1;
+            }
+            __syncthreads();
+            if (tid < 2) {
+                RunBest m = sm->wrb[0][tid];
+#pragma unroll
+                for (int w = 1; w < kNW; ++w) rb_merge(m, sm->wrb[w][tid]);
+                Best b;
+                b.key1 = m.k1;
+                b.key2 = m.k2;
+                b.cnt = m.cnt;
+                b.idx = m.k1 ? (int32_t)(uint32_t)m.k2 : 0;
+                b.x = m.k1 ? a.x[b.idx] : 0;
+                b.y = m.k1 ? a.y[b.idx] : 0;
+                if (seg_st >= run_lo && seg_en <= run_hi) ws.adir[cur * 2 + tid] = b;
+                ws.recF[run0 * 2 + tid] = b;
+                ws.recL[run0 * 2 + tid] = b;
+            }
+            __syncthreads();
+            r0 = rb_none();
+            r1 = rb_none();
+            cur = -1;
+        }
+        if (!ti.single) continue;  // uniform: the multi-segment kernel takes it
+        if (cur < 0) {
+            cur = gseg;
+            run0 = tile;
+            run_lo = lo;
+            seg_st = ti.start;
+            seg_en = ti.end;
+        }
+        run_hi = hi;
         int32_t X[kItems], Y[kItems], I[kItems];
-        if (INIT) {
-            load_input(a, lo, hi, X, Y, I);
-        } else if (!load_pieces(ws, p, R, lt, R ? nt1 : nt0, rs->npc[R], lo, hi, sm, X, Y, I)) {
+        const uint32_t vm = INIT ? load_input_wave(a, lo, hi, X, Y, I)
+                                 : load_pieces_wave(ws, p, R, lt, R ? nt1 : nt0, rs->npc[R], lo, hi,
+                                                    sm->pvs, sm->pps, X, Y, I);
+        if (vm == 0xffffffffu) {
             __syncthreads();
             continue;
         }
-        const TileInfo ti = ws.tinfo(p, R)[lt];
-        const int s0 = ti.seg;
         uint32_t stbits = 0xaaaaaaaau;  // 2 bits per point: 0, 1 = child, 2 = dropped
-        uint32_t rr[kQ];                // packed in-tile ranks of each row's first survivor
+        uint32_t rk[kItems];            // packed in-tile rank of each item
         uint32_t total;                 // the tile's survivors (packed)
-
-        if (ti.single) {
+        {
             // one segment covers the tile: uniform geometry, every wave on its own
             const int ux = ti.ux, uy = ti.uy, fx = ti.fx, fy = ti.fy, vx = ti.vx, vy = ti.vy;
             const int e0x = fx - ux, e0y = fy - uy, e1x = vx - fx, e1y = vy - fy;
-            Best b0 = best_none(), b1 = best_none();
+            uint32_t tc = 0;  // this lane's survivors in the tile (child 0 | child 1 << 16)
             if (MODE == 0) {
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
-                    if (item_pos(lo, i) >= hi) continue;
+                    if (!((vm >> i) & 1u)) continue;
                     const int64_t d0 = cross_i64(X[i], Y[i], ux, uy, fx, fy);
                     uint32_t st = 2;
                     if (d0 > 0) {
                         st = 0;
-                        b0.cnt++;
-                        best_offer(b0, (uint64_t)d0, X[i], Y[i], I[i], e0x, e0y);
+                        r0.cnt++;
+                        tc += 1u;
+                        rb_offer(r0, (uint64_t)d0, X[i], Y[i], I[i], e0x, e0y);
                     } else {
                         const int64_t d1 = cross_i64(X[i], Y[i], fx, fy, vx, vy);
                         if (d1 > 0) {
                             st = 1;
-                            b1.cnt++;
-                            best_offer(b1, (uint64_t)d1, X[i], Y[i], I[i], e1x, e1y);
+                            r1.cnt++;
+                            tc += 0x10000u;
+                            rb_offer(r1, (uint64_t)d1, X[i], Y[i], I[i], e1x, e1y);
                         }
                     }
                     stbits ^= (st ^ 2u) << (2 * i);
@@ -770,7 +1098,7 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
                 float l0 = -INFINITY, l1 = -INFINITY;
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
-                    if (item_pos(lo, i) >= hi) continue;
+                    if (!((vm >> i) & 1u)) continue;
                     float B0;
                     const float e0 = cross_f32(X[i], Y[i], ux, uy, fx, fy, B0);
                     ntests++;
@@ -781,7 +1109,8 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
                     uint32_t st = 2;
                     if (out0) {
                         st = 0;
-                        b0.cnt++;
+                        r0.cnt++;
+                        tc += 1u;
                         l0 = fmaxf(l0, __fsub_rn(e0, 2.f * B0));
                     } else {
                         float B1;
@@ -793,7 +1122,8 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
                         else { nfall++; out1 = cross_i64(X[i], Y[i], fx, fy, vx, vy) > 0; }
                         if (out1) {
                             st = 1;
-                            b1.cnt++;
+                            r1.cnt++;
+                            tc += 0x10000u;
                             l1 = fmaxf(l1, __fsub_rn(e1, 2.f * B1));
                         }
                     }
@@ -801,7 +1131,7 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
                 }
                 // the wave's best lower bound per child; only points whose
                 // upper bound reaches it can be the argmax
-                const float M0 = wave_max_f(l0), M1 = wave_max_f(l1);
+                const float M0 = wave_max_f_dpp(l0), M1 = wave_max_f_dpp(l1);
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
                     const uint32_t st = (stbits >> (2 * i)) & 3u;
@@ -813,30 +1143,16 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
                     if (U < (st == 0 ? M0 : M1)) continue;
                     ncand++;
                     if (st == 0)
-                        best_offer(b0, (uint64_t)cross_i64(X[i], Y[i], ux, uy, fx, fy), X[i], Y[i], I[i], e0x, e0y);
+                        rb_offer(r0, (uint64_t)cross_i64(X[i], Y[i], ux, uy, fx, fy), X[i], Y[i], I[i], e0x, e0y);
                     else
-                        best_offer(b1, (uint64_t)cross_i64(X[i], Y[i], fx, fy, vx, vy), X[i], Y[i], I[i], e1x, e1y);
+                        rb_offer(r1, (uint64_t)cross_i64(X[i], Y[i], fx, fy, vx, vy), X[i], Y[i], I[i], e1x, e1y);
                 }
             }
-            wave_rec(b0);
-            wave_rec(b1);
-            if (lane == 0) {
-                sm->wrec[wv][0] = b0;
-                sm->wrec[wv][1] = b1;
-                sm->wcnt[wv] = (uint32_t)b0.cnt | ((uint32_t)b1.cnt << 16);
-            }
+            const uint32_t wt = wave_sum(tc);
+            if (lane == 0) sm->wcnt[wv] = wt;
             __syncthreads();
-            if (tid < 2) {
-                // the tile's record of child tid
-                Best b = sm->wrec[0][tid];
-#pragma unroll
-                for (int w = 1; w < kNW; ++w) rec_merge(b, sm->wrec[w][tid]);
-                if (ti.start >= lo && ti.end <= hi) ws.adir[(gbase + ti.seg) * 2 + tid] = b;
-                ws.recF[tile * 2 + tid] = b;
-                ws.recL[tile * 2 + tid] = b;
-            }
             // any order inside the tile keeps the children contiguous: wave
-            // order (wave, row, lane, item)
+            // order, then item, then lane (each store instruction is dense)
             uint32_t base = 0;
             total = 0;
 #pragma unroll
@@ -846,13 +1162,110 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
                 total += c;
             }
 #pragma unroll
-            for (int qq = 0; qq < kQ; ++qq) {
-                const uint32_t c = row_count(stbits, qq);
+            for (int i = 0; i < kItems; ++i) {
+                const uint32_t st = (stbits >> (2 * i)) & 3u;
+                const uint32_t c = st == 0 ? 1u : (st == 1 ? 0x10000u : 0u);
                 const uint32_t inc = wave_incl_sum(c);
-                rr[qq] = base + inc - c;
+                rk[i] = base + inc - c;
                 base += wave_read(inc, kWave - 1);
             }
-        } else {
+        }
+        // scatter: child c of this tile goes to region c at tile * kTile
+        const int64_t pbase = (int64_t)tile * kTile;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t st = (stbits >> (2 * i)) & 3u;
+            if (st == 0) {
+                const int64_t e = pbase + (rk[i] & 0xffffu);
+                if (e < cap) { ox0[e] = X[i]; oy0[e] = Y[i]; oi0[e] = I[i]; } else oob = true;
+            } else if (st == 1) {
+                const int64_t e = pbase + (rk[i] >> 16);
+                if (e < cap) { ox1[e] = X[i]; oy1[e] = Y[i]; oi1[e] = I[i]; } else oob = true;
+            }
+        }
+        if (tid == 0) {
+            ws.tcnt(p)[tile] = total;
+            acc0 += total & 0xffffu;
+            acc1 += total >> 16;
+        }
+        __syncthreads();  // LDS is reused by the next tile
+    }
+    if (oob) atomicOr(&ctl->error, kErrInternal);
+    if (tid == 0 && (acc0 | acc1)) {
+        atomicAdd(&ctl->nacc[p][0], acc0);
+        atomicAdd(&ctl->nacc[p][1], acc1);
+    }
+    if (MODE != 0) {
+        if (tid == 0) { stat[0] = 0; stat[1] = 0; stat[2] = 0; }
+        __syncthreads();
+        const uint32_t t = wave_sum(ntests), f = wave_sum(nfall), c = wave_sum(ncand);
+        if (lane == 0) {
+            atomicAdd(&stat[0], t);
+            atomicAdd(&stat[1], f);
+            atomicAdd(&stat[2], c);
+        }
+        __syncthreads();
+        if (tid == 0 && stat[0]) {
+            atomicAdd(&ctl->filter_tests, (unsigned long long)stat[0]);
+            atomicAdd(&ctl->filter_fallbacks, (unsigned long long)stat[1]);
+            atomicAdd(&ctl->candidates, (unsigned long long)stat[2]);
+        }
+    }
+}
+
+// Tiles that hold several segments (listed by the segment kernel): the whole
+// block in point order, per-segment reductions in LDS.
+template <int MODE>
+__device__ __forceinline__ void phase_round_multi(const Ws2 &ws, const HullArgs &a, int r, char *smem) {
+    RoundSmem *sm = reinterpret_cast<RoundSmem *>(smem);
+    uint32_t *stat = sm->stat;
+    const bool INIT = r == 0;  // the first split reads the input (index = position)
+    Control *ctl = ws.ctl;
+    const int p = r & 1, q = p ^ 1;
+    const RoundState *rs = &ctl->rs[p];
+    const int n0 = rs->n[0], n1 = rs->n[1];
+    const int S0 = rs->s[0], S1 = rs->s[1];
+    const int nt0 = (n0 + kTile - 1) / kTile, nt1 = (n1 + kTile - 1) / kTile;
+    const int ntiles = nt0 + nt1;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+    int32_t *ox0 = ws.px(q, 0), *oy0 = ws.py(q, 0), *oi0 = ws.pi(q, 0);
+    int32_t *ox1 = ws.px(q, 1), *oy1 = ws.py(q, 1), *oi1 = ws.pi(q, 1);
+    const int64_t cap = ws.cap_pts;
+    (void)S0; (void)S1; (void)lane; (void)wv;
+
+    uint32_t ntests = 0, nfall = 0, ncand = 0;
+    uint32_t acc0 = 0, acc1 = 0;  // survivors written by this block (thread 0)
+    bool oob = false;
+    const int nm = min(rs->nmulti, ws.tcap);
+    const int32_t *ml = ws.ml(p);
+    for (int j = blockIdx.x; j < nm; j += gridDim.x) {
+        const int tile = ml[j];
+        if (tile < 0 || tile >= ntiles) {
+            oob = true;
+            continue;
+        }
+        const int R = tile < nt0 ? 0 : 1;
+        const int lt = tile - (R ? nt0 : 0);
+        const int NR = R ? n1 : n0;
+        const int SR = R ? S1 : S0;
+        const int gbase = R ? S0 : 0;
+        const int lo = lt * kTile;
+        const int hi = min(lo + kTile, NR);
+        (void)SR;
+        const TileInfo ti = ws.tinfo(p, R)[lt];
+        const int s0 = ti.seg;
+        int32_t X[kItems], Y[kItems], I[kItems];
+        if (INIT) {
+            load_input(a, lo, hi, X, Y, I);
+        } else if (!load_pieces(ws, p, R, lt, R ? nt1 : nt0, rs->npc[R], lo, hi, sm->pvs, sm->pps,
+                                X, Y, I)) {
+            __syncthreads();
+            continue;
+        }
+        uint32_t stbits = 0xaaaaaaaau;  // 2 bits per point: 0, 1 = child, 2 = dropped
+        uint32_t rr[kQ];                // packed in-tile ranks of each row's first survivor
+        uint32_t total;                 // the tile's survivors (packed)
+        {
             // several segments: starts into LDS, per-slot reductions (point order)
             const SegGeo *geo = ws.geo(p, R);
             if (tid == 0) sm->s_m = 0;
@@ -1020,7 +1433,6 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
 #pragma unroll
             for (int qq = 0; qq < kQ; ++qq) rr[qq] = rowbase[qq] + cnt[qq];
         }
-
         // scatter: child c of this tile goes to region c at tile * kTile
         const int64_t pbase = (int64_t)tile * kTile;
 #pragma unroll
@@ -1054,23 +1466,75 @@ __device__ __forceinline__ void phase_round(const Ws2 &ws, const HullArgs &a, in
         atomicAdd(&ctl->nacc[p][1], acc1);
     }
     if (MODE != 0) {
-        if (tid == 0) { sm->stat[0] = 0; sm->stat[1] = 0; sm->stat[2] = 0; }
+        if (tid == 0) { stat[0] = 0; stat[1] = 0; stat[2] = 0; }
         __syncthreads();
         const uint32_t t = wave_sum(ntests), f = wave_sum(nfall), c = wave_sum(ncand);
         if (lane == 0) {
-            atomicAdd(&sm->stat[0], t);
-            atomicAdd(&sm->stat[1], f);
-            atomicAdd(&sm->stat[2], c);
+            atomicAdd(&stat[0], t);
+            atomicAdd(&stat[1], f);
+            atomicAdd(&stat[2], c);
         }
         __syncthreads();
-        if (tid == 0 && sm->stat[0]) {
-            atomicAdd(&ctl->filter_tests, (unsigned long long)sm->stat[0]);
-            atomicAdd(&ctl->filter_fallbacks, (unsigned long long)sm->stat[1]);
-            atomicAdd(&ctl->candidates, (unsigned long long)sm->stat[2]);
+        if (tid == 0 && stat[0]) {
+            atomicAdd(&ctl->filter_tests, (unsigned long long)stat[0]);
+            atomicAdd(&ctl->filter_fallbacks, (unsigned long long)stat[1]);
+            atomicAdd(&ctl->candidates, (unsigned long long)stat[2]);
         }
     }
 }
 
+
+// The argmax records of a segment of region R whose points span the tiles
+// t0 < t1 of round p (global tile indices): slot 0 is tile t0 (its last
+// segment's record if t0 holds several segments, else the record of the run
+// that starts there); slot 1 + j is the run head in the j-th range of T tiles
+// the segment meets (the round kernel keeps one record per run, at the run's
+// first tile); the last slot is tile t1 if it holds several segments.  A slot
+// without a record returns false.
+__device__ __forceinline__ bool seg_record(const Ws2 &ws, int p, int R, int nt0, int T, int t0,
+                                           int t1, int k, int c, Best &out) {
+    const TileInfo *ti = ws.tinfo(p, R);
+    const int off = R ? nt0 : 0;
+    const int nb = t1 / T - t0 / T + 1;
+    if (k == 0) {
+        out = ti[t0 - off].single ? ws.recF[t0 * 2 + c] : ws.recL[t0 * 2 + c];
+        return true;
+    }
+    if (k <= nb) {
+        const int b = t0 / T + (k - 1);
+        const int st = max(b * T, t0 + 1);
+        if (st > t1 || st >= (b + 1) * T || !ti[st - off].single) return false;
+        if (st != b * T && ti[t0 - off].single) return false;  // same run as t0
+        out = ws.recF[st * 2 + c];
+        return true;
+    }
+    if (k == nb + 1 && !ti[t1 - off].single) {
+        out = ws.recF[t1 * 2 + c];
+        return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ int seg_slots(int T, int t0, int t1) { return t1 / T - t0 / T + 3; }
+
+// Merge the record slots of one segment with the whole block (every thread
+// gets the result).
+__device__ __forceinline__ Best block_merge_seg(const Ws2 &ws, int p, int R, int nt0, int T, int t0,
+                                               int t1, int c, Best *red) {
+    Best acc = best_none();
+    const int ns = seg_slots(T, t0, t1);
+    for (int k = threadIdx.x; k < ns; k += kSegBlock) {
+        Best b;
+        if (seg_record(ws, p, R, nt0, T, t0, t1, k, c, b)) rec_merge(acc, b);
+    }
+    wave_rec(acc);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    Best r = red[0];
+    for (int w = 1; w < kSegBlock / kWave; ++w) rec_merge(r, red[w]);
+    __syncthreads();
+    return r;
+}
 // ---------------------------------------------------------------------------
 // segments: hull insertion, multi-tile argmax, next segment table
 // ---------------------------------------------------------------------------
@@ -1145,20 +1609,22 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             Tp = ws.top(p, R)[s];
         }
 
-        // the children's argmax and counts: merged over the tiles the segment spans
+        // the children's argmax and counts: merged over the records of the
+        // tiles the segment spans
         Best b0 = best_none(), b1 = best_none();
         const int t0 = (R ? nt0 : 0) + G.start / kTile;
         const int t1 = (R ? nt0 : 0) + (G.start + G.len - 1) / kTile;
+        const int T = max(1, ctl->tper[p]);
         if (valid) {
             if (t0 == t1) {
                 b0 = ws.adir[g * 2 + 0];
                 b1 = ws.adir[g * 2 + 1];
-            } else if (t1 - t0 <= 8) {
-                b0 = ws.recL[t0 * 2 + 0];
-                b1 = ws.recL[t0 * 2 + 1];
-                for (int t = t0 + 1; t <= t1; ++t) {
-                    rec_merge(b0, ws.recF[t * 2 + 0]);
-                    rec_merge(b1, ws.recF[t * 2 + 1]);
+            } else if (seg_slots(T, t0, t1) <= 12) {
+                const int ns = seg_slots(T, t0, t1);
+                for (int k = 0; k < ns; ++k) {
+                    Best r;
+                    if (seg_record(ws, p, R, nt0, T, t0, t1, k, 0, r)) rec_merge(b0, r);
+                    if (seg_record(ws, p, R, nt0, T, t0, t1, k, 1, r)) rec_merge(b1, r);
                 }
             } else {
                 const int qi = atomicAdd(&sm->qn_apex, 1);
@@ -1172,9 +1638,10 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
         for (int qi = 0; qi < nqa; ++qi) {
             const int own = sm->q_apex[qi];
             const int a0 = sm->o_t0[own], a1 = sm->o_t1[own];
-            const Best r0 = block_merge_tiles(ws.recF, ws.recL, a0, a1, 0, sm->red);
-            const Best r1 = block_merge_tiles(ws.recF, ws.recL, a0, a1, 1, sm->red);
-            if (tid == own) { b0 = r0; b1 = r1; }
+            const int Ro = own + tile * kSegBlock < S0 ? 0 : 1;
+            const Best m0 = block_merge_seg(ws, p, Ro, nt0, T, a0, a1, 0, sm->red);
+            const Best m1 = block_merge_seg(ws, p, Ro, nt0, T, a0, a1, 1, sm->red);
+            if (tid == own) { b0 = m0; b1 = m1; }
         }
         const int c0 = valid ? b0.cnt : 0, c1 = valid ? b1.cnt : 0;
 
@@ -1240,6 +1707,21 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             SegTop ct;
             ct.fidx = b1.idx; ct.uc = fc; ct.vc = Tp.vc; ct.inst = Tp.inst;
             ws.top(q, 1)[id1] = ct;
+        }
+        // the child's last tile holds further segments unless the child runs
+        // to the tile's end: list it for the multi-segment round kernel
+        {
+            const int ntn0 = (Nn0 + kTile - 1) / kTile;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const bool ok = c == 0 ? ok0 : ok1;
+                const int st = c == 0 ? st0 : st1;
+                const int ln = c == 0 ? c0 : c1;
+                const int ka = (st + kTile - 1) / kTile, kb = (st + ln + kTile - 1) / kTile;
+                const int Nc = c == 0 ? Nn0 : Nn1;
+                const bool multi = ok && kb > ka && (st + ln) < min(kb * kTile, Nc);
+                ml_append(ws, q, rn, multi, (c ? ntn0 : 0) + kb - 1);
+            }
         }
         // tile records of the next round: tiles whose first point lies in a
         // child; a child over many tiles is written by the whole block
@@ -1498,9 +1980,16 @@ __global__ __launch_bounds__(kBlock) void k_extremes_final(Ws2 ws, HullArgs a) {
 
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_round(Ws2 ws, HullArgs a, int32_t r) {
+    __shared__ FastSmem sm;
+    if (ws.ctl->setup_error) return;
+    phase_round_fast<MODE>(ws, a, r, reinterpret_cast<char *>(&sm));
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_round_multi(Ws2 ws, HullArgs a, int32_t r) {
     __shared__ RoundSmem sm;
     if (ws.ctl->setup_error) return;
-    phase_round<MODE>(ws, a, r, reinterpret_cast<char *>(&sm));
+    phase_round_multi<MODE>(ws, a, r, reinterpret_cast<char *>(&sm));
 }
 
 __global__ __launch_bounds__(kSegBlock) void k_segments(Ws2 ws, HullArgs a, int32_t r) {
@@ -1524,11 +2013,14 @@ hipError_t launch_extremes(const Ws2 &ws, const HullArgs &a, int grid, hipStream
 }
 
 hipError_t launch_round(const Ws2 &ws, const HullArgs &a, int mode, int32_t r, int grid,
-                        hipStream_t st) {
-    if (mode == 0)
+                        int grid_multi, hipStream_t st) {
+    if (mode == 0) {
         hipLaunchKernelGGL(k_round<0>, dim3(grid), dim3(kBlock), 0, st, ws, a, r);
-    else
+        hipLaunchKernelGGL(k_round_multi<0>, dim3(grid_multi), dim3(kBlock), 0, st, ws, a, r);
+    } else {
         hipLaunchKernelGGL(k_round<1>, dim3(grid), dim3(kBlock), 0, st, ws, a, r);
+        hipLaunchKernelGGL(k_round_multi<1>, dim3(grid_multi), dim3(kBlock), 0, st, ws, a, r);
+    }
     return hipGetLastError();
 }
 

@@ -33,7 +33,7 @@
 #include <algorithm>
 #include <chrono>
 #include <new>
-#include <unordered_map>
+#include <thread>
 #include <vector>
 
 #include "../../include/qh.h"
@@ -567,16 +567,45 @@ qh_status Run::topology(std::vector<SrcRec> &srcs, std::vector<int32_t> &newf) {
     return QH_OK;
 }
 
+// Run fn(lo, hi, t) over [0, n) on up to 16 host threads.
+template <typename Fn>
+void par_for(int64_t n, Fn fn) {
+    int T = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
+    if (n < 32768) T = 1;
+    std::vector<std::thread> th;
+    th.reserve(T);
+    for (int t = 1; t < T; ++t) th.emplace_back([&fn, n, T, t] { fn(n * t / T, n * (t + 1) / T, t); });
+    fn(0, n / T, 0);
+    for (auto &x : th) x.join();
+}
+
+struct Tri {
+    int32_t a, b, c;
+};
+
+bool tri_less(const Tri &p, const Tri &q) {
+    if (p.a != q.a) return p.a < q.a;
+    if (p.b != q.b) return p.b < q.b;
+    return p.c < q.c;
+}
+
 // Hull vertices and the canonical triangulation.  Everything is indexed by
-// point or facet id in flat arrays (no hashing): corners -> incident facets
-// by counting, faces by union-find over coplanar neighbours, each face's
-// boundary walked through a next-vertex array.
+// point or facet id in flat arrays (no hashing) and the independent parts run
+// on host threads: corners -> incident facets by counting, the vertex test per
+// corner, faces by union-find over coplanar neighbours, each face's boundary
+// cycle fanned from its lowest vertex, and the triples sorted.
 qh_status Run::output(int32_t *facets, int64_t *nfacets, int32_t *verts, int64_t *nverts) {
     const int32_t nf = (int32_t)F.size();
     std::vector<int32_t> alive;
-    alive.reserve(nf / 2 + 16);
-    for (int32_t i = 0; i < nf; ++i)
-        if (F[i].alive) alive.push_back(i);
+    {
+        std::vector<std::vector<int32_t>> part(16);
+        par_for(nf, [&](int64_t lo, int64_t hi, int t) {
+            for (int64_t i = lo; i < hi; ++i)
+                if (F[i].alive) part[t].push_back((int32_t)i);
+        });
+        for (auto &v : part) alive.insert(alive.end(), v.begin(), v.end());
+    }
+    const int64_t na = (int64_t)alive.size();
     // incident facets per corner (CSR over point ids)
     std::vector<int32_t> deg((size_t)n + 1, 0);
     for (int32_t f : alive)
@@ -588,25 +617,44 @@ qh_status Run::output(int32_t *facets, int64_t *nfacets, int32_t *verts, int64_t
         for (int32_t f : alive)
             for (int k = 0; k < 3; ++k) inc[fill[F[f].v[k]]++] = f;
     }
+    // the vertex test: at least three distinct planes around a corner
     std::vector<char> isv((size_t)n, 0);
     std::vector<int32_t> vlist;
-    for (int32_t v = 0; v < n; ++v) {
-        const int32_t lo = deg[v], hi = deg[v + 1];
-        if (lo == hi) continue;
-        int32_t planes[3];
-        int np = 0;
-        for (int32_t q = lo; q < hi && np < 3; ++q) {
-            const int32_t f = inc[q];
-            bool dup = false;
-            for (int r = 0; r < np && !dup; ++r) dup = coplanar_dir(F[f].n, F[planes[r]].n);
-            if (!dup) planes[np++] = f;
-        }
-        if (np >= 3) {
-            isv[v] = 1;
-            vlist.push_back(v);
-        }
+    {
+        std::vector<std::vector<int32_t>> part(16);
+        par_for(n, [&](int64_t lo, int64_t hi, int t) {
+            for (int64_t v = lo; v < hi; ++v) {
+                const int32_t a0 = deg[v], a1 = deg[v + 1];
+                if (a0 == a1) continue;
+                int32_t planes[3];
+                int np = 0;
+                for (int32_t q = a0; q < a1 && np < 3; ++q) {
+                    const int32_t f = inc[q];
+                    bool dup = false;
+                    for (int r = 0; r < np && !dup; ++r) dup = coplanar_dir(F[f].n, F[planes[r]].n);
+                    if (!dup) planes[np++] = f;
+                }
+                if (np >= 3) {
+                    isv[v] = 1;
+                    part[t].push_back((int32_t)v);
+                }
+            }
+        });
+        for (auto &v : part) vlist.insert(vlist.end(), v.begin(), v.end());
     }
-    // faces: union-find over facets joined across coplanar edges
+    // faces: coplanar neighbour pairs found in parallel, joined in order
+    std::vector<uint8_t> cop((size_t)na, 0);
+    par_for(na, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t i = lo; i < hi; ++i) {
+            const int32_t f = alive[i];
+            uint8_t m = 0;
+            for (int k = 0; k < 3; ++k) {
+                const int32_t g = F[f].nb[k];
+                if (g > f && coplanar_dir(F[f].n, F[g].n)) m |= (uint8_t)(1u << k);
+            }
+            cop[i] = m;
+        }
+    });
     std::vector<int32_t> parent((size_t)nf);
     for (int32_t f : alive) parent[f] = f;
     auto root = [&](int32_t f) {
@@ -616,67 +664,71 @@ qh_status Run::output(int32_t *facets, int64_t *nfacets, int32_t *verts, int64_t
         }
         return f;
     };
-    for (int32_t f : alive)
-        for (int k = 0; k < 3; ++k) {
-            const int32_t g = F[f].nb[k];
-            if (g > f && coplanar_dir(F[f].n, F[g].n)) {
-                const int32_t a = root(f), b = root(g);
+    for (int64_t i = 0; i < na; ++i) {
+        if (!cop[i]) continue;
+        const int32_t f = alive[i];
+        for (int k = 0; k < 3; ++k)
+            if (cop[i] & (1u << k)) {
+                const int32_t a = root(f), b = root(F[f].nb[k]);
                 if (a != b) parent[std::max(a, b)] = std::min(a, b);
             }
-        }
+    }
     for (int32_t f : alive) parent[f] = root(f);
     // facets grouped by face (counting sort on the root id)
     std::vector<int32_t> fstart((size_t)nf + 1, 0);
-    for (int32_t f : alive) fstart[root(f) + 1]++;
+    for (int32_t f : alive) fstart[parent[f] + 1]++;
     for (int32_t i = 0; i < nf; ++i) fstart[i + 1] += fstart[i];
     std::vector<int32_t> byface(alive.size());
     {
         std::vector<int32_t> fill(fstart.begin(), fstart.end() - 1);
         for (int32_t f : alive) byface[fill[parent[f]]++] = f;
     }
-    struct Tri {
-        int32_t a, b, c;
-    };
-    std::vector<Tri> tri;
-    tri.reserve(2 * vlist.size());
-    std::vector<int32_t> next((size_t)n, -1);
-    std::vector<int32_t> poly, touched;
-    for (int32_t r = 0; r < nf; ++r) {
-        const int32_t lo = fstart[r], hi = fstart[r + 1];
-        if (lo == hi) continue;
-        touched.clear();
-        int32_t start = -1;
-        for (int32_t q = lo; q < hi; ++q) {
-            const HFacet &f = F[byface[q]];
-            for (int k = 0; k < 3; ++k) {
-                if (parent[f.nb[k]] == r) continue;
-                const int32_t u = f.v[k], w2 = f.v[(k + 1) % 3];
-                next[u] = w2;
-                touched.push_back(u);
-                if (start < 0 || u < start) start = u;
+    // every face: boundary cycle over its vertices, fanned from the lowest
+    std::vector<std::vector<Tri>> tparts(16);
+    std::vector<int> tbad(16, 0);
+    par_for(nf, [&](int64_t lo, int64_t hi, int t) {
+        std::vector<std::pair<int32_t, int32_t>> edges;
+        std::vector<int32_t> poly;
+        std::vector<Tri> &out = tparts[t];
+        for (int64_t r = lo; r < hi; ++r) {
+            const int32_t a0 = fstart[r], a1 = fstart[r + 1];
+            if (a0 == a1) continue;
+            edges.clear();
+            for (int32_t q = a0; q < a1; ++q) {
+                const HFacet &f = F[byface[q]];
+                for (int k = 0; k < 3; ++k)
+                    if (parent[f.nb[k]] != r) edges.push_back({f.v[k], f.v[(k + 1) % 3]});
             }
+            if (edges.size() < 3) { tbad[t] = 1; continue; }
+            std::sort(edges.begin(), edges.end());
+            poly.clear();
+            const int32_t start = edges[0].first;
+            int32_t u = start;
+            size_t steps = 0;
+            bool ok = true;
+            do {
+                if (isv[u]) poly.push_back(u);
+                auto it = std::lower_bound(edges.begin(), edges.end(),
+                                           std::pair<int32_t, int32_t>(u, INT32_MIN));
+                if (it == edges.end() || it->first != u || ++steps > edges.size()) { ok = false; break; }
+                u = it->second;
+            } while (u != start);
+            const size_t m = poly.size();
+            if (!ok || m < 3) { tbad[t] = 1; continue; }
+            const size_t l0 = std::min_element(poly.begin(), poly.end()) - poly.begin();
+            for (size_t i = 1; i + 1 < m; ++i)
+                out.push_back({poly[l0], poly[(l0 + i) % m], poly[(l0 + i + 1) % m]});
         }
-        if (start < 0) return QH_EDEVICE;
-        poly.clear();
-        int32_t u = start;
-        size_t steps = 0;
-        do {
-            if (isv[u]) poly.push_back(u);
-            u = next[u];
-            if (u < 0 || ++steps > touched.size()) return QH_EDEVICE;
-        } while (u != start);
-        for (int32_t t : touched) next[t] = -1;
-        const size_t m = poly.size();
-        if (m < 3) return QH_EDEVICE;
-        const size_t l0 = std::min_element(poly.begin(), poly.end()) - poly.begin();
-        for (size_t i = 1; i + 1 < m; ++i)
-            tri.push_back({poly[l0], poly[(l0 + i) % m], poly[(l0 + i + 1) % m]});
-    }
-    std::sort(tri.begin(), tri.end(), [](const Tri &p, const Tri &q) {
-        if (p.a != q.a) return p.a < q.a;
-        if (p.b != q.b) return p.b < q.b;
-        return p.c < q.c;
+        std::sort(out.begin(), out.end(), tri_less);
     });
+    for (int b : tbad)
+        if (b) return QH_EDEVICE;
+    std::vector<Tri> tri;
+    for (auto &v : tparts) {
+        const size_t mid = tri.size();
+        tri.insert(tri.end(), v.begin(), v.end());
+        std::inplace_merge(tri.begin(), tri.begin() + mid, tri.end(), tri_less);
+    }
     const size_t nt = tri.size();
     if (nt != 2 * vlist.size() - 4) return QH_EDEVICE;
     QH3_TRY(w->up.want(sizeof(int32_t) * (3 * nt + vlist.size()) + 512));

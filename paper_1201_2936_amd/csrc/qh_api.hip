@@ -62,6 +62,7 @@ size_t carve(qh_ctx *c, char *base) {
     w.pv_ = cv.take<int32_t>((size_t)4 * (c->tcap + 2));
     w.pp_ = cv.take<int32_t>((size_t)4 * (c->tcap + 2));
     w.kf_ = cv.take<int32_t>((size_t)4 * (c->tcap + 2));
+    w.ml_ = cv.take<int32_t>((size_t)2 * c->tcap);
     w.st5_ = cv.take<uint64_t>((size_t)2 * c->s5cap);
     w.st5b_ = cv.take<uint64_t>((size_t)2 * c->s5cap);
     w.st4_ = cv.take<uint64_t>((size_t)2 * c->s4cap);
@@ -238,7 +239,9 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
         qh_status s = ensure(c, n, k);
         if (s != QH_OK) return s;
         const Ws2 &ws = c->ws;
-        const int grid_seg = std::max(1, std::min((2 * c->scap + kSegBlock - 1) / kSegBlock, c->cus * 2));
+        // few blocks: most rounds have few segment tiles, and every idle block
+        // still costs two claims on the shared counters
+        const int grid_seg = std::max(1, std::min((2 * c->scap + kSegBlock - 1) / kSegBlock, c->cus / 2));
         tm.kind.clear();
         if (single_off) QH_TRY(fill_single_offsets(single_off, n, st));
         QH_TRY(tm.before(st, Timing::kSetup));
@@ -252,7 +255,7 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
         while (true) {
             for (int j = 0; j < batch; ++j, ++r) {
                 QH_TRY(tm.before(st, r == 0 ? Timing::kSplit : Timing::kRound));
-                QH_TRY(launch_round(ws, args, mode, r, grid, st));
+                QH_TRY(launch_round(ws, args, mode, r, grid, c->cus * 2, st));
                 QH_TRY(tm.after(st));
                 QH_TRY(tm.before(st, Timing::kSegments));
                 QH_TRY(launch_segments(ws, args, r, grid_seg, st));

@@ -186,7 +186,7 @@ struct RoundState {
     int32_t npc[2];     // non-empty pieces of region 0 / 1 (rounds after the first split)
     uint32_t seg_ctr;   // dynamic tile counter of the segment kernel
     uint32_t piece_ctr; // dynamic tile counter of the piece scan
-    int32_t pad;
+    int32_t nmulti;     // tiles with several segments (listed for the round kernel)
 };
 
 enum : int32_t {
@@ -213,6 +213,7 @@ struct Control {
     unsigned long long candidates;
     unsigned long long rounds_with_work;
     unsigned int nacc[2][2];          // survivors per region written by the round kernel, by parity
+    int32_t tper[2];                  // tiles per block of the round kernel, by parity
     int32_t H;                        // compact hull ids used
     long long h_total;                // hull vertices of all instances
     int32_t nstamps;

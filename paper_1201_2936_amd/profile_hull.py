@@ -75,8 +75,11 @@ def summarize(args):
             copies = [v for n, v in rows if "copyBuffer" in n or "copy" in _short(n).lower()]
             big = max(copies) if copies else 0.0
             scale[ctr] = copy_kib / big if big > 0 else None
-            vals = [v for n, v in rows if _short(n).startswith(args.kernel)]
-            per_kernel[ctr] = (sum(vals), len(vals))
+            names = args.kernel.split(",")
+            vals = [v for n, v in rows if any(_short(n).startswith(k) for k in names)]
+            # launches are counted on the first kernel name (one per round)
+            nl = len([1 for n, v in rows if _short(n).startswith(names[0])])
+            per_kernel[ctr] = (sum(vals), nl)
         f_kib, nf = per_kernel["FETCH_SIZE"]
         w_kib, nw = per_kernel["WRITE_SIZE"]
         fetch_b = f_kib * 1024 * scale["FETCH_SIZE"] / max(nf, 1)
@@ -112,7 +115,9 @@ def main():
         sp.add_argument("--trace")
         sp.add_argument("--fetch")
         sp.add_argument("--write")
-        sp.add_argument("--kernel", default="k_round")
+        sp.add_argument("--kernel", default="k_round",
+                        help="kernel name prefixes, comma-separated; bytes are summed and "
+                             "divided by the launches of the first")
         sp.add_argument("--copy-mb", type=int, default=256)
         sp.add_argument("--kernel-sha", default="")
         sp.add_argument("--out")
