@@ -161,6 +161,11 @@ __device__ __forceinline__ float wave_max_f(float v) {
     return v;
 }
 
+// number of set bits of a wave mask in the lanes below this one
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // DPP reductions (row shifts and row broadcasts, no LDS): the result is
 // complete in lane 63 only.  A lane whose source is outside its row, or
 // whose row is masked off, receives the operation's identity.
@@ -225,6 +230,15 @@ __device__ __forceinline__ void rb_offer(RunBest &b, uint64_t d, int32_t x, int3
         b.k1 = d;
         b.k2 = k2;
     }
+}
+
+// the same update without branches (take = the point belongs to the child)
+__device__ __forceinline__ void rb_offer_nb(RunBest &b, bool take, uint64_t d, int32_t x, int32_t y,
+                                            int32_t idx, int32_t ex, int32_t ey) {
+    const uint64_t k2 = tie_key(x, y, idx, ex, ey);
+    const bool better = take && (d > b.k1 || (d == b.k1 && k2 < b.k2));
+    b.k1 = better ? d : b.k1;
+    b.k2 = better ? k2 : b.k2;
 }
 
 __device__ __forceinline__ void rb_merge(RunBest &acc, const RunBest &o) {
@@ -309,10 +323,10 @@ struct RoundSmem {
 
 struct FastSmem {
     uint32_t stat[4];
-    int32_t pvs[kTile + 4];         // virtual starts of the tile's input pieces
-    int32_t pps[kTile + 4];         // ... their physical starts
+    int32_t pvs[2][kTile + 4];      // virtual starts of a tile's input pieces (by tile parity)
+    int32_t pps[2][kTile + 4];      // ... their physical starts
     RunBest wrb[kNW][2];            // per-wave argmax of a run
-    uint32_t wcnt[kNW];             // per-wave survivor counts (child 0 | child 1 << 16)
+    uint32_t wcnt[2][kNW];          // per-wave survivor counts (child 0 | child 1 << 16)
 };
 
 struct ExtSmem {
@@ -505,6 +519,7 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
     // tile (the other tiles of the run get empty records).  Tiles that hold
     // several instances are reduced per instance in LDS.
     const int T = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+    if (blockIdx.x == 0 && tid == 0) ctl->tper_ext = T;
     const int tb = blockIdx.x * T, te = min(tb + T, ntiles);
     Best rmn = best_none(), rmx = best_none();
     int cur = -1, run0 = 0, cst = 0, cen = 0;
@@ -566,11 +581,6 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
                 run0 = tile;
                 cst = ti.start;
                 cen = ti.end;
-            } else if (tid < 4) {
-                // inside a run: an empty record (the run's record is at run0)
-                const Best e = best_none();
-                if (tid < 2) ws.recF0[tile * 2 + tid] = e;
-                else ws.recL0[tile * 2 + tid - 2] = e;
             }
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
@@ -678,24 +688,48 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
 // Merge the per-tile partials of one segment over tiles t0 .. t1 (the whole
 // block cooperates; every thread gets the result).  In tile t0 the segment is
 // the tile's last one, in the later tiles its first one.
-__device__ __forceinline__ Best block_merge_tiles(const Best *recF, const Best *recL, int t0, int t1, int c,
-                                  Best *red) {
-    Best acc = best_none();
-    for (int t = t0 + (int)threadIdx.x; t <= t1; t += 4 * kBlock) {
-        Best b[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int tt = t + u * kBlock;
-            b[u] = tt <= t1 ? (tt == t0 ? recL[tt * 2 + c] : recF[tt * 2 + c]) : best_none();
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) rec_merge(acc, b[u]);
+// The extremes records of an instance over tiles t0 < t1: slot 0 is tile t0
+// (its last instance's record if t0 holds several instances, else the record
+// of the run that starts there); slot 1 + j is the run head in the j-th range
+// of T tiles the instance meets (one record per run, at its first tile); the
+// last slot is tile t1 if it holds several instances.  False: no record.
+__device__ __forceinline__ bool ext_record(const Ws2 &ws, int T, int t0, int t1, int k, int c,
+                                           Best &out) {
+    const TileInfo *ti = ws.tinfo(0, 0);
+    const int nb = t1 / T - t0 / T + 1;
+    if (k == 0) {
+        out = ti[t0].single ? ws.recF0[t0 * 2 + c] : ws.recL0[t0 * 2 + c];
+        return true;
     }
-    wave_rec(acc);
+    if (k <= nb) {
+        const int b = t0 / T + (k - 1);
+        const int st = max(b * T, t0 + 1);
+        if (st > t1 || st >= (b + 1) * T || !ti[st].single) return false;
+        if (st != b * T && ti[t0].single) return false;  // same run as t0
+        out = ws.recF0[st * 2 + c];
+        return true;
+    }
+    if (k == nb + 1 && !ti[t1].single) {
+        out = ws.recF0[t1 * 2 + c];
+        return true;
+    }
+    return false;
+}
+
+// merge of the extremes records of one instance with the whole block
+__device__ __forceinline__ Best block_merge_ext(const Ws2 &ws, int T, int t0, int t1, int c,
+                                                Best *red) {
+    Best acc = best_none();
+    const int ns = t1 / T - t0 / T + 3;
+    for (int k = threadIdx.x; k < ns; k += kBlock) {
+        Best b;
+        if (ext_record(ws, T, t0, t1, k, c, b)) best_merge(acc, b);
+    }
+    wave_best(acc);
     if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
     __syncthreads();
     Best r = red[0];
-    for (int w = 1; w < kNW; ++w) rec_merge(r, red[w]);
+    for (int w = 1; w < kNW; ++w) best_merge(r, red[w]);
     __syncthreads();
     return r;
 }
@@ -718,24 +752,12 @@ __device__ __forceinline__ void phase_extremes_final(const Ws2 &ws, const HullAr
             mn = ws.dir0[s * 2 + 0];
             mx = ws.dir0[s * 2 + 1];
         } else {
-            mn = block_merge_tiles(ws.recF0, ws.recL0, t0, t1, 0, sm->red);
-            mx = block_merge_tiles(ws.recF0, ws.recL0, t0, t1, 1, sm->red);
+            const int T = max(1, ctl->tper_ext);
+            mn = block_merge_ext(ws, T, t0, t1, 0, sm->red);
+            mx = block_merge_ext(ws, T, t0, t1, 1, sm->red);
         }
-        // tiles that start inside this instance
-        const int ka = (g.start + kTile - 1) / kTile;
-        const int kb = (g.start + g.len + kTile - 1) / kTile;
-        for (int kk = ka + (int)threadIdx.x; kk < kb; kk += kBlock) {
-            TileInfo ti;
-            ti.seg = s;
-            ti.start = g.start;
-            ti.end = g.start + g.len;
-            ti.single = (int64_t)ti.end >= min((int64_t)(kk + 1) * kTile, (int64_t)a.n) ? 1 : 0;
-            ti.ux = mn.x; ti.uy = mn.y;
-            ti.fx = mx.x; ti.fy = mx.y;
-            ti.vx = mn.x; ti.vy = mn.y;
-            ti.pad0 = ti.pad1 = 0;
-            ws.tinfo(0, 0)[kk] = ti;
-        }
+        // (the first split reads the instance's geometry from this table;
+        // its tile records come from the set-up kernel)
         if (threadIdx.x == 0) {
             g.ux = mn.x; g.uy = mn.y;
             g.vx = mn.x; g.vy = mn.y;
@@ -874,6 +896,33 @@ __device__ __forceinline__ bool filter_cand(int32_t x, int32_t y, uint32_t st, c
     return fkey(__fadd_rn(e, 2.f * B)) >= lmk;
 }
 
+// A load through the scalar data cache (uniform address; the data was
+// written by an earlier kernel and is not written by this one).
+template <typename T>
+__device__ __forceinline__ T scalar_load(const T *ptr) {
+    return *(const __attribute__((address_space(4))) T *)(ptr);
+}
+
+// the record of global tile t of round p (uniform); in the first split the
+// tile records hold the instance only, and the geometry is the instance's
+// segment (u = v = its minimum, f = its maximum)
+template <bool INIT>
+__device__ __forceinline__ TileInfo tile_record(const Ws2 &ws, int p, int t, int nt0) {
+    const int32_t *src = reinterpret_cast<const int32_t *>(t < nt0 ? ws.tinfo(p, 0) + t
+                                                                 : ws.tinfo(p, 1) + (t - nt0));
+    TileInfo ti;
+    int32_t *dst = reinterpret_cast<int32_t *>(&ti);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(TileInfo) / sizeof(int32_t)); ++k) dst[k] = scalar_load(src + k);
+    if (INIT && ti.single) {
+        const int32_t *g = reinterpret_cast<const int32_t *>(ws.geo(0, 0) + ti.seg);
+        ti.ux = scalar_load(g + 2); ti.uy = scalar_load(g + 3);
+        ti.fx = scalar_load(g + 4); ti.fy = scalar_load(g + 5);
+        ti.vx = scalar_load(g + 6); ti.vy = scalar_load(g + 7);
+    }
+    return ti;
+}
+
 // The one-segment tiles may emit their survivors in any order, so their
 // waves work on contiguous quarters of the tile with 64-lane runs: lane l of
 // wave w holds items v = lo + 512 w + 64 i + l (gathered loads and the
@@ -915,19 +964,69 @@ __device__ __forceinline__ uint32_t load_input_wave(const HullArgs &a, int lo, i
     return vm;
 }
 
-// later rounds: gather the tile's virtual range from the pieces kA .. kB of
-// the previous round (see load_pieces); returns the valid-item mask, or
-// 0xffffffff if the piece table does not fit the tile
+// later rounds: the pieces [kA, kA + K) of the previous round that hold tile
+// lt of region R (uniform values, read through the scalar cache); false if
+// the piece table is malformed
+__device__ __forceinline__ bool piece_range(const Ws2 &ws, int p, int R, int lt, int ntR, int npc,
+                                            int &kA, int &K) {
+    const int32_t *kf = ws.kf(p, R);
+    kA = scalar_load(kf + lt);
+    const int kB = (lt + 1 < ntR) ? scalar_load(kf + lt + 1) : npc - 1;
+    K = kB - kA + 1;
+    return kA >= 0 && K >= 1 && K <= kTile + 2 && kB < npc;
+}
+
+// gather the tile's virtual range [lo, hi) from its piece table in LDS (the
+// virtual and physical starts of K pieces); returns the valid-item mask
+__device__ __forceinline__ uint32_t gather_pieces(const Ws2 &ws, int p, int R, int K, int lo, int hi,
+                                                  const int32_t *pvs, const int32_t *pps,
+                                                  int32_t (&X)[kItems], int32_t (&Y)[kItems],
+                                                  int32_t (&I)[kItems]) {
+    // addresses relative to the tile's first piece: a uniform base and a
+    // 32-bit offset per item (the tile's pieces lie within a few tiles)
+    const int64_t cap = ws.cap_pts;
+    const int32_t pb0 = pps[0];
+    const int32_t *sx = ws.px(p, R) + pb0, *sy = ws.py(p, R) + pb0, *si = ws.pi(p, R) + pb0;
+    uint32_t vm = 0;
+    bool bad = false;
+    // the piece of the lane's first item, then a forward walk with the next
+    // piece's start and the current piece's offset kept in registers
+    int j = 0;
+    const int w0 = fast_pos(lo, 0);
+    if (K > 1) j = slot_of(pvs, K, min(w0, hi - 1));
+    int nextv = j + 1 < K ? pvs[j + 1] : INT32_MAX;
+    int delta = pps[j] - pb0 - pvs[j];
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        const int v = fast_pos(lo, i);
+        X[i] = Y[i] = I[i] = 0;
+        if (v >= hi) continue;
+        while (v >= nextv) {
+            ++j;
+            nextv = j + 1 < K ? pvs[j + 1] : INT32_MAX;
+            delta = pps[j] - pb0 - pvs[j];
+        }
+        const int off = v + delta;  // physical position minus the tile's base
+        if (off < 0 || (int64_t)pb0 + off >= cap) { bad = true; continue; }
+        X[i] = sx[(uint32_t)off];
+        Y[i] = sy[(uint32_t)off];
+        I[i] = si[(uint32_t)off];
+        vm |= 1u << i;
+    }
+    if (bad) atomicOr(&ws.ctl->error, kErrInternal);
+    return vm;
+}
+
+// later rounds, without prefetch: the piece table to LDS, then the gather;
+// returns the valid-item mask, or 0xffffffff if the table does not fit
 __device__ __forceinline__ uint32_t load_pieces_wave(const Ws2 &ws, int p, int R, int lt, int ntR,
                                                      int npc, int lo, int hi, int32_t *pvs,
                                                      int32_t *pps, int32_t (&X)[kItems],
                                                      int32_t (&Y)[kItems], int32_t (&I)[kItems]) {
     const int tid = threadIdx.x;
-    const int32_t *kf = ws.kf(p, R);
-    const int kA = kf[lt];
-    const int kB = (lt + 1 < ntR) ? kf[lt + 1] : npc - 1;
-    const int K = kB - kA + 1;
-    const bool ok = kA >= 0 && K >= 1 && K <= kTile + 2 && kB < npc;
+    int kA, K;
+    const bool ok = piece_range(ws, p, R, lt, ntR, npc, kA, K);
+    __syncthreads();  // earlier readers of this table buffer are done
     if (ok) {
         const int32_t *pv = ws.pv(p, R) + kA;
         const int32_t *pp = ws.pp(p, R) + kA;
@@ -941,57 +1040,39 @@ __device__ __forceinline__ uint32_t load_pieces_wave(const Ws2 &ws, int p, int R
         atomicOr(&ws.ctl->error, kErrInternal);
         return 0xffffffffu;
     }
-    const int32_t *sx = ws.px(p, R), *sy = ws.py(p, R), *si = ws.pi(p, R);
-    const int64_t cap = ws.cap_pts;
-    uint32_t vm = 0;
-    bool bad = false;
-    // the piece of the wave's first item, then a short forward walk per item
-    int j = 0;
-    const int w0 = fast_pos(lo, 0);
-    if (K > 1) j = slot_of(pvs, K, min(w0, hi - 1));
-#pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-        const int v = fast_pos(lo, i);
-        X[i] = Y[i] = I[i] = 0;
-        if (v >= hi) continue;
-        while (j + 1 < K && pvs[j + 1] <= v) ++j;
-        const int64_t ph = (int64_t)pps[j] + (v - pvs[j]);
-        if (ph < 0 || ph >= cap) { bad = true; continue; }
-        X[i] = sx[ph];
-        Y[i] = sy[ph];
-        I[i] = si[ph];
-        vm |= 1u << i;
-    }
-    if (bad) atomicOr(&ws.ctl->error, kErrInternal);
-    return vm;
+    return gather_pieces(ws, p, R, K, lo, hi, pvs, pps, X, Y, I);
 }
 
-template <int MODE>
+// The one-segment tiles of a round.  Every block takes a contiguous range of
+// T tiles (the segment kernel finds the argmax record of a run at the run's
+// first tile in each range, so it needs T).  The tiles are software
+// pipelined: the next tile's record and piece table are read while this tile
+// is classified, and its points are loaded before this tile's survivors are
+// stored (a load issued after a burst of stores waits for them, since the
+// wave's memory counter retires in order).
+template <int MODE, bool INIT>
 __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &a, int r, char *smem) {
+    // INIT: the first split, which reads the input (index = position)
     FastSmem *sm = reinterpret_cast<FastSmem *>(smem);
     uint32_t *stat = sm->stat;
-    const bool INIT = r == 0;  // the first split reads the input (index = position)
     Control *ctl = ws.ctl;
     const int p = r & 1, q = p ^ 1;
     const RoundState *rs = &ctl->rs[p];
     const int n0 = rs->n[0], n1 = rs->n[1];
-    const int S0 = rs->s[0], S1 = rs->s[1];
+    const int S0 = rs->s[0];
+    const int npc0 = rs->npc[0], npc1 = rs->npc[1];
     const int nt0 = (n0 + kTile - 1) / kTile, nt1 = (n1 + kTile - 1) / kTile;
     const int ntiles = nt0 + nt1;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
-    int32_t *ox0 = ws.px(q, 0), *oy0 = ws.py(q, 0), *oi0 = ws.pi(q, 0);
-    int32_t *ox1 = ws.px(q, 1), *oy1 = ws.py(q, 1), *oi1 = ws.pi(q, 1);
+    // output planes of this parity: [child][x, y, index][cap]
+    int32_t *const obase = ws.px(q, 0);
     const int64_t cap = ws.cap_pts;
-    (void)S0; (void)S1; (void)lane; (void)wv;
 
     uint32_t ntests = 0, nfall = 0, ncand = 0;
     uint32_t acc0 = 0, acc1 = 0;  // survivors written by this block (thread 0)
     bool oob = false;
     // the multi-segment tiles of the next round are listed afresh by the
     // segment kernel that follows
-    // every block takes a contiguous range of T tiles (the segment kernel
-    // finds the argmax records of a run at the first tile of the run in each
-    // range, so it needs T)
     const int T = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
     if (blockIdx.x == 0 && tid == 0) {
         ctl->rs[q].nmulti = 0;
@@ -1003,21 +1084,29 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
     // reduced once, when the run ends.
     RunBest r0 = rb_none(), r1 = rb_none();
     int cur = -1, run0 = 0, run_lo = 0, run_hi = 0, seg_st = 0, seg_en = 0;
-    for (int tile = tb; tile <= te; ++tile) {
-        // tile == te only closes the last run
-        const bool past = tile == te;
+    // the current tile's record and, when prefetched, its points
+    TileInfo tc;
+    tc.single = 0;
+    if (tb < te) tc = tile_record<INIT>(ws, p, tb, nt0);
+    uint32_t vm = 0;
+    bool have = false;
+    // One tile; the points of the next one go to the other register set (the
+    // loop below alternates the two sets, so no copy waits for the loads).
+    // Returns true after the last tile.
+    auto step = [&](int tile, int32_t(&X)[kItems], int32_t(&Y)[kItems], int32_t(&I)[kItems],
+                    int32_t(&Xn)[kItems], int32_t(&Yn)[kItems], int32_t(&In)[kItems])
+        __attribute__((always_inline)) -> bool {
+        // tile >= te only closes the last run (a block past the last tile
+        // has tb > te)
+        const bool past = tile >= te;
         const int R = tile < nt0 ? 0 : 1;
         const int lt = tile - (R ? nt0 : 0);
         const int NR = R ? n1 : n0;
-        const int SR = R ? S1 : S0;
-        const int gbase = R ? S0 : 0;
         const int lo = lt * kTile;
         const int hi = min(lo + kTile, NR);
-        (void)SR;
-        TileInfo ti;
-        if (!past) ti = ws.tinfo(p, R)[lt];
-        else ti.single = 0;
-        const int gseg = gbase + ti.seg;
+        TileInfo ti = tc;
+        if (past) ti.single = 0;
+        const int gseg = (R ? S0 : 0) + ti.seg;
         if (cur >= 0 && (!ti.single || gseg != cur)) {
             // the run ends: reduce it, record it at its first tile
             wave_rb63(r0);
@@ -1036,8 +1125,7 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
                 b.key2 = m.k2;
                 b.cnt = m.cnt;
                 b.idx = m.k1 ? (int32_t)(uint32_t)m.k2 : 0;
-                b.x = m.k1 ? a.x[b.idx] : 0;
-                b.y = m.k1 ? a.y[b.idx] : 0;
+                b.x = b.y = 0;  // filled in by the segment kernel for the winner
                 if (seg_st >= run_lo && seg_en <= run_hi) ws.adir[cur * 2 + tid] = b;
                 ws.recF[run0 * 2 + tid] = b;
                 ws.recL[run0 * 2 + tid] = b;
@@ -1047,7 +1135,17 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
             r1 = rb_none();
             cur = -1;
         }
-        if (!ti.single) continue;  // uniform: the multi-segment kernel takes it
+        if (past) return true;
+        // the next tile's record (scalar loads, consumed a tile later)
+        const bool nxt = tile + 1 < te;
+        TileInfo tn;
+        tn.single = 0;
+        if (nxt) tn = tile_record<INIT>(ws, p, tile + 1, nt0);
+        if (!ti.single) {  // uniform: the multi-segment kernel takes it
+            tc = tn;
+            have = false;
+            return false;
+        }
         if (cur < 0) {
             cur = gseg;
             run0 = tile;
@@ -1056,100 +1154,129 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
             seg_en = ti.end;
         }
         run_hi = hi;
-        int32_t X[kItems], Y[kItems], I[kItems];
-        const uint32_t vm = INIT ? load_input_wave(a, lo, hi, X, Y, I)
-                                 : load_pieces_wave(ws, p, R, lt, R ? nt1 : nt0, rs->npc[R], lo, hi,
-                                                    sm->pvs, sm->pps, X, Y, I);
-        if (vm == 0xffffffffu) {
-            __syncthreads();
-            continue;
+        const int buf = tile & 1;  // LDS buffers of piece tables and wave counts
+        if (!have) {
+            vm = INIT ? load_input_wave(a, lo, hi, X, Y, I)
+                      : load_pieces_wave(ws, p, R, lt, R ? nt1 : nt0, R ? npc1 : npc0, lo, hi,
+                                         sm->pvs[buf], sm->pps[buf], X, Y, I);
+            if (vm == 0xffffffffu) {
+                tc = tn;
+                return false;
+            }
+            // wait for these loads here: after the join, only the prefetched
+            // loads are outstanding, behind this block's stores
+#pragma unroll
+            for (int i = 0; i < kItems; ++i) asm volatile("" ::"v"(X[i]), "v"(Y[i]), "v"(I[i]));
         }
-        uint32_t stbits = 0xaaaaaaaau;  // 2 bits per point: 0, 1 = child, 2 = dropped
-        uint32_t rk[kItems];            // packed in-tile rank of each item
-        uint32_t total;                 // the tile's survivors (packed)
+        // the next tile's piece table: up to two entries per thread, read now
+        // into registers and put into the other LDS buffer after classifying
+        const int Rn = tile + 1 < nt0 ? 0 : 1;
+        const int ltn = tile + 1 - (Rn ? nt0 : 0);
+        int kAn = 0, Kn = 0;
+        bool pre = nxt && tn.single;
+        int32_t pv0 = 0, pp0 = 0, pv1 = 0, pp1 = 0;
+        if (!INIT && pre) {
+            pre = piece_range(ws, p, Rn, ltn, Rn ? nt1 : nt0, Rn ? npc1 : npc0, kAn, Kn) &&
+                  Kn <= 2 * kBlock;
+            if (pre) {
+                const int32_t *pv = ws.pv(p, Rn) + kAn, *pp = ws.pp(p, Rn) + kAn;
+                if (tid < Kn) { pv0 = pv[tid]; pp0 = pp[tid]; }
+                if (tid + kBlock < Kn) { pv1 = pv[tid + kBlock]; pp1 = pp[tid + kBlock]; }
+            }
+        }
+        // per item two bits: 0, 1 = child, 2 = dropped (3 = undecided in FP32,
+        // only until the exact pass below)
+        uint32_t stb = 0;
+        uint32_t total;       // the tile's survivors (packed child 0 | child 1 << 16)
+        uint32_t bw0, bw1;    // this wave's first in-tile rank in each child
         {
             // one segment covers the tile: uniform geometry, every wave on its own
             const int ux = ti.ux, uy = ti.uy, fx = ti.fx, fy = ti.fy, vx = ti.vx, vy = ti.vy;
             const int e0x = fx - ux, e0y = fy - uy, e1x = vx - fx, e1y = vy - fy;
-            uint32_t tc = 0;  // this lane's survivors in the tile (child 0 | child 1 << 16)
             if (MODE == 0) {
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
-                    if (!((vm >> i) & 1u)) continue;
+                    const bool valid = (vm >> i) & 1u;
                     const int64_t d0 = cross_i64(X[i], Y[i], ux, uy, fx, fy);
-                    uint32_t st = 2;
-                    if (d0 > 0) {
-                        st = 0;
-                        r0.cnt++;
-                        tc += 1u;
-                        rb_offer(r0, (uint64_t)d0, X[i], Y[i], I[i], e0x, e0y);
-                    } else {
-                        const int64_t d1 = cross_i64(X[i], Y[i], fx, fy, vx, vy);
-                        if (d1 > 0) {
-                            st = 1;
-                            r1.cnt++;
-                            tc += 0x10000u;
-                            rb_offer(r1, (uint64_t)d1, X[i], Y[i], I[i], e1x, e1y);
-                        }
-                    }
-                    stbits ^= (st ^ 2u) << (2 * i);
+                    const int64_t d1 = cross_i64(X[i], Y[i], fx, fy, vx, vy);
+                    const bool o0 = valid && d0 > 0;
+                    const bool o1 = valid && !o0 && d1 > 0;
+                    stb |= (o0 ? 0u : (o1 ? 1u : 2u)) << (2 * i);
+                    rb_offer_nb(r0, o0, (uint64_t)d0, X[i], Y[i], I[i], e0x, e0y);
+                    rb_offer_nb(r1, o1, (uint64_t)d1, X[i], Y[i], I[i], e1x, e1y);
                 }
             } else {
+                // FP32 pass: the state where both signs it needs are certain,
+                // the upper bound U of the distance to the point's own edge,
+                // and the best lower bound per child
                 float l0 = -INFINITY, l1 = -INFINITY;
+                float U[kItems];
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
-                    if (!((vm >> i) & 1u)) continue;
-                    float B0;
+                    float B0, B1;
                     const float e0 = cross_f32(X[i], Y[i], ux, uy, fx, fy, B0);
-                    ntests++;
-                    bool out0;
-                    if (e0 > B0) out0 = true;
-                    else if (e0 < -B0) out0 = false;
-                    else { nfall++; out0 = cross_i64(X[i], Y[i], ux, uy, fx, fy) > 0; }
-                    uint32_t st = 2;
-                    if (out0) {
-                        st = 0;
-                        r0.cnt++;
-                        tc += 1u;
-                        l0 = fmaxf(l0, __fsub_rn(e0, 2.f * B0));
-                    } else {
-                        float B1;
-                        const float e1 = cross_f32(X[i], Y[i], fx, fy, vx, vy, B1);
-                        ntests++;
-                        bool out1;
-                        if (e1 > B1) out1 = true;
-                        else if (e1 < -B1) out1 = false;
-                        else { nfall++; out1 = cross_i64(X[i], Y[i], fx, fy, vx, vy) > 0; }
-                        if (out1) {
-                            st = 1;
-                            r1.cnt++;
-                            tc += 0x10000u;
-                            l1 = fmaxf(l1, __fsub_rn(e1, 2.f * B1));
-                        }
-                    }
-                    stbits ^= (st ^ 2u) << (2 * i);
+                    const float e1 = cross_f32(X[i], Y[i], fx, fy, vx, vy, B1);
+                    const bool p0 = e0 > B0, n0 = e0 < -B0, p1 = e1 > B1, n1 = e1 < -B1;
+                    uint32_t sti = p0 ? 0u : (!n0 ? 3u : (p1 ? 1u : (n1 ? 2u : 3u)));
+                    sti = ((vm >> i) & 1u) ? sti : 2u;
+                    stb |= sti << (2 * i);
+                    U[i] = p0 ? __fadd_rn(e0, 2.f * B0) : __fadd_rn(e1, 2.f * B1);
+                    l0 = sti == 0 ? fmaxf(l0, __fsub_rn(e0, 2.f * B0)) : l0;
+                    l1 = sti == 1 ? fmaxf(l1, __fsub_rn(e1, 2.f * B1)) : l1;
+                    // pin the item's results here, so that its FP32 temporaries
+                    // die now instead of being carried past the exact pass
+                    asm volatile("" : "+v"(U[i]), "+v"(l0), "+v"(l1));
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                // the wave's best lower bound per child; only points whose
-                // upper bound reaches it can be the argmax
+                // exact pass over the undecided items (rare): both signs in int64
+                const uint32_t und = stb & (stb >> 1) & 0x5555u;
+                if (__ballot(und != 0)) {
+#pragma unroll
+                    for (int i = 0; i < kItems; ++i) {
+                        if (!((und >> (2 * i)) & 1u)) continue;
+                        // opaque copies: the FP32 values are recomputed here
+                        // rather than kept live from the pass above
+                        int32_t x = X[i], y = Y[i];
+                        asm volatile("" : "+v"(x), "+v"(y));
+                        float B0, B1;
+                        const float e0 = cross_f32(x, y, ux, uy, fx, fy, B0);
+                        const float e1 = cross_f32(x, y, fx, fy, vx, vy, B1);
+                        const bool o0 = cross_i64(x, y, ux, uy, fx, fy) > 0;
+                        const bool o1 = !o0 && cross_i64(x, y, fx, fy, vx, vy) > 0;
+                        nfall += ((e0 > B0 || e0 < -B0) ? 0u : 1u) +
+                                 ((!o0 && !(e1 > B1 || e1 < -B1)) ? 1u : 0u);
+                        stb ^= ((o0 ? 0u : (o1 ? 1u : 2u)) ^ 3u) << (2 * i);
+                        U[i] = INFINITY;  // always a candidate: decided exactly
+                    }
+                }
+                // only points whose upper bound reaches the wave's best lower
+                // bound of their child can be its argmax
                 const float M0 = wave_max_f_dpp(l0), M1 = wave_max_f_dpp(l1);
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
-                    const uint32_t st = (stbits >> (2 * i)) & 3u;
-                    if (st > 1) continue;
-                    float B;
-                    const float e = st == 0 ? cross_f32(X[i], Y[i], ux, uy, fx, fy, B)
-                                            : cross_f32(X[i], Y[i], fx, fy, vx, vy, B);
-                    const float U = __fadd_rn(e, 2.f * B);
-                    if (U < (st == 0 ? M0 : M1)) continue;
-                    ncand++;
-                    if (st == 0)
+                    const uint32_t sti = (stb >> (2 * i)) & 3u;
+                    const bool c = sti < 2 && U[i] >= (sti == 0 ? M0 : M1);
+                    if (!__ballot(c)) continue;
+                    ncand += c ? 1u : 0u;
+                    if (c && sti == 0)
                         rb_offer(r0, (uint64_t)cross_i64(X[i], Y[i], ux, uy, fx, fy), X[i], Y[i], I[i], e0x, e0y);
-                    else
+                    if (c && sti == 1)
                         rb_offer(r1, (uint64_t)cross_i64(X[i], Y[i], fx, fy, vx, vy), X[i], Y[i], I[i], e1x, e1y);
                 }
             }
-            const uint32_t wt = wave_sum(tc);
-            if (lane == 0) sm->wcnt[wv] = wt;
+            // the lane's survivors per child: fields 00 and 01 of stb
+            const uint32_t lc0 = (uint32_t)__popc(~(stb | (stb >> 1)) & 0x5555u);
+            const uint32_t lc1 = (uint32_t)__popc(stb & ~(stb >> 1) & 0x5555u);
+            if (MODE != 0) ntests += 2u * (uint32_t)__popc(vm) - lc0;
+            r0.cnt += (int32_t)lc0;
+            r1.cnt += (int32_t)lc1;
+            const uint32_t wt = wave_sum(lc0 | (lc1 << 16));
+            if (lane == 0) sm->wcnt[buf][wv] = wt;
+            if (!INIT && pre) {
+                int32_t *pvs = sm->pvs[buf ^ 1], *pps = sm->pps[buf ^ 1];
+                if (tid < Kn) { pvs[tid] = pv0; pps[tid] = pp0; }
+                if (tid + kBlock < Kn) { pvs[tid + kBlock] = pv1; pps[tid + kBlock] = pp1; }
+            }
             __syncthreads();
             // any order inside the tile keeps the children contiguous: wave
             // order, then item, then lane (each store instruction is dense)
@@ -1157,30 +1284,46 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
             total = 0;
 #pragma unroll
             for (int w = 0; w < kNW; ++w) {
-                const uint32_t c = sm->wcnt[w];
+                const uint32_t c = sm->wcnt[buf][w];
                 base += (w < wv) ? c : 0u;
                 total += c;
             }
+            bw0 = base & 0xffffu;
+            bw1 = base >> 16;
+        }
+        // the next tile's points, before this tile's stores
+        uint32_t vmn = 0;
+        if (pre) {
+            const int lon = ltn * kTile;
+            const int hin = min(lon + kTile, Rn ? n1 : n0);
+            vmn = INIT ? load_input_wave(a, lon, hin, Xn, Yn, In)
+                       : gather_pieces(ws, p, Rn, Kn, lon, hin, sm->pvs[buf ^ 1], sm->pps[buf ^ 1],
+                                       Xn, Yn, In);
+        }
+        // scatter: child c of this tile goes to region c at tile * kTile; a
+        // survivor's rank is its wave's base plus the set lanes below it.
+        // Every lane stores every item (the others into the last tile slot of
+        // the planes, which no tile uses), so the number of stores after the
+        // next tile's loads is fixed and waiting for those loads does not
+        // wait for the stores.
+        const int64_t pbase = (int64_t)tile * kTile;
+        {
+            const bool fits = pbase + kTile <= cap - kTile;  // else all to the sink
+            oob |= !fits;
+            int32_t *const sink = obase + (cap - kTile) + lane;
+            int32_t *const ob = fits ? obase + pbase : sink;
+            const int64_t creg = fits ? 3 * cap : 0;  // child 1's planes follow child 0's
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
-                const uint32_t st = (stbits >> (2 * i)) & 3u;
-                const uint32_t c = st == 0 ? 1u : (st == 1 ? 0x10000u : 0u);
-                const uint32_t inc = wave_incl_sum(c);
-                rk[i] = base + inc - c;
-                base += wave_read(inc, kWave - 1);
-            }
-        }
-        // scatter: child c of this tile goes to region c at tile * kTile
-        const int64_t pbase = (int64_t)tile * kTile;
-#pragma unroll
-        for (int i = 0; i < kItems; ++i) {
-            const uint32_t st = (stbits >> (2 * i)) & 3u;
-            if (st == 0) {
-                const int64_t e = pbase + (rk[i] & 0xffffu);
-                if (e < cap) { ox0[e] = X[i]; oy0[e] = Y[i]; oi0[e] = I[i]; } else oob = true;
-            } else if (st == 1) {
-                const int64_t e = pbase + (rk[i] >> 16);
-                if (e < cap) { ox1[e] = X[i]; oy1[e] = Y[i]; oi1[e] = I[i]; } else oob = true;
+                const uint32_t sti = (stb >> (2 * i)) & 3u;
+                const uint64_t m0 = __ballot(sti == 0), m1 = __ballot(sti == 1);
+                const uint32_t e = sti == 0 ? bw0 + lanes_below(m0) : bw1 + lanes_below(m1);
+                int32_t *d = (sti < 2 && fits) ? ob + (sti ? creg : (int64_t)0) + e : sink;
+                d[0] = X[i];
+                d[cap] = Y[i];
+                d[2 * cap] = I[i];
+                bw0 += (uint32_t)__popcll(m0);
+                bw1 += (uint32_t)__popcll(m1);
             }
         }
         if (tid == 0) {
@@ -1188,7 +1331,15 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
             acc0 += total & 0xffffu;
             acc1 += total >> 16;
         }
-        __syncthreads();  // LDS is reused by the next tile
+        vm = vmn;
+        have = pre;
+        tc = tn;
+        return false;
+    };
+    int32_t XA[kItems], YA[kItems], IA[kItems], XB[kItems], YB[kItems], IB[kItems];
+    for (int tile = tb;; tile += 2) {
+        if (step(tile, XA, YA, IA, XB, YB, IB)) break;
+        if (step(tile + 1, XB, YB, IB, XA, YA, IA)) break;
     }
     if (oob) atomicOr(&ctl->error, kErrInternal);
     if (tid == 0 && (acc0 | acc1)) {
@@ -1644,6 +1795,9 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             if (tid == own) { b0 = m0; b1 = m1; }
         }
         const int c0 = valid ? b0.cnt : 0, c1 = valid ? b1.cnt : 0;
+        // the winners' coordinates (the one-segment records carry the index only)
+        if (valid && b0.key1) { b0.x = a.x[b0.idx]; b0.y = a.y[b0.idx]; }
+        if (valid && b1.key1) { b1.x = a.x[b1.idx]; b1.y = a.y[b1.idx]; }
 
         // the apex f of this segment joins the hull between u and v
         int fc = 0;
@@ -1978,11 +2132,11 @@ __global__ __launch_bounds__(kBlock) void k_extremes_final(Ws2 ws, HullArgs a) {
     phase_extremes_final(ws, a, reinterpret_cast<char *>(&sm));
 }
 
-template <int MODE>
+template <int MODE, bool INIT>
 __global__ __launch_bounds__(kBlock) void k_round(Ws2 ws, HullArgs a, int32_t r) {
     __shared__ FastSmem sm;
     if (ws.ctl->setup_error) return;
-    phase_round_fast<MODE>(ws, a, r, reinterpret_cast<char *>(&sm));
+    phase_round_fast<MODE, INIT>(ws, a, r, reinterpret_cast<char *>(&sm));
 }
 
 template <int MODE>
@@ -2015,10 +2169,12 @@ hipError_t launch_extremes(const Ws2 &ws, const HullArgs &a, int grid, hipStream
 hipError_t launch_round(const Ws2 &ws, const HullArgs &a, int mode, int32_t r, int grid,
                         int grid_multi, hipStream_t st) {
     if (mode == 0) {
-        hipLaunchKernelGGL(k_round<0>, dim3(grid), dim3(kBlock), 0, st, ws, a, r);
+        if (r == 0) hipLaunchKernelGGL((k_round<0, true>), dim3(grid), dim3(kBlock), 0, st, ws, a, r);
+        else hipLaunchKernelGGL((k_round<0, false>), dim3(grid), dim3(kBlock), 0, st, ws, a, r);
         hipLaunchKernelGGL(k_round_multi<0>, dim3(grid_multi), dim3(kBlock), 0, st, ws, a, r);
     } else {
-        hipLaunchKernelGGL(k_round<1>, dim3(grid), dim3(kBlock), 0, st, ws, a, r);
+        if (r == 0) hipLaunchKernelGGL((k_round<1, true>), dim3(grid), dim3(kBlock), 0, st, ws, a, r);
+        else hipLaunchKernelGGL((k_round<1, false>), dim3(grid), dim3(kBlock), 0, st, ws, a, r);
         hipLaunchKernelGGL(k_round_multi<1>, dim3(grid_multi), dim3(kBlock), 0, st, ws, a, r);
     }
     return hipGetLastError();
@@ -2061,11 +2217,19 @@ hipError_t fill_single_offsets(int64_t *off, int64_t n, hipStream_t st) {
 }
 
 hipError_t round_grid(int mode, int cus, int *grid) {
-    int per = 0;
-    const void *f = mode == 0 ? reinterpret_cast<const void *>(&k_round<0>)
-                              : reinterpret_cast<const void *>(&k_round<1>);
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kBlock, 0);
-    if (e != hipSuccess) return e;
+    // the same grid for the first split and the later rounds: the smaller
+    // residency of the two kernels
+    const void *f[2] = {mode == 0 ? reinterpret_cast<const void *>(&k_round<0, true>)
+                                  : reinterpret_cast<const void *>(&k_round<1, true>),
+                        mode == 0 ? reinterpret_cast<const void *>(&k_round<0, false>)
+                                  : reinterpret_cast<const void *>(&k_round<1, false>)};
+    int per = INT32_MAX;
+    for (int j = 0; j < 2; ++j) {
+        int pj = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pj, f[j], kBlock, 0);
+        if (e != hipSuccess) return e;
+        per = std::min(per, pj);
+    }
     *grid = std::max(1, per) * cus;
     return hipSuccess;
 }

@@ -214,6 +214,7 @@ struct Control {
     unsigned long long rounds_with_work;
     unsigned int nacc[2][2];          // survivors per region written by the round kernel, by parity
     int32_t tper[2];                  // tiles per block of the round kernel, by parity
+    int32_t tper_ext;                 // tiles per block of the extremes kernel
     int32_t H;                        // compact hull ids used
     long long h_total;                // hull vertices of all instances
     int32_t nstamps;
