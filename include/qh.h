@@ -57,9 +57,19 @@ enum {
 
 /* qh_opts.flags */
 enum {
-    QH_FLAG_TIMING = 1u   /* time every kernel launch of the call with HIP
-                             events (qh_stats) */
+    QH_FLAG_TIMING = 1u,    /* time every kernel launch of the call with HIP
+                               events (qh_stats) */
+    QH_FLAG_NO_FINISH = 2u  /* 2D: run every level of the recursion as a
+                               round of the round kernels.  By default, once
+                               no segment holds more than QH_FINISH_CAP
+                               points, one workgroup per segment completes
+                               that segment's recursion in on-chip memory
+                               (the same levels and the same rules as the
+                               rounds, so the same output) */
 };
+
+/* points of a segment that one workgroup finishes (QH_FLAG_NO_FINISH) */
+#define QH_FINISH_CAP 1024
 
 typedef struct qh_ctx qh_ctx;
 
@@ -98,6 +108,8 @@ typedef struct qh_stats {
                                    (qh_hull3d only) */
     double host_output_ms;      /* ... of which the output (vertex test and
                                    canonical triangulation) */
+    int64_t finish_round;       /* 2D: the round whose segments were finished
+                                   by one workgroup each (-1: none) */
 } qh_stats;
 
 typedef struct qh_opts {

@@ -12,6 +12,7 @@ constexpr int kSlots = 128;              // segments per LDS window (multi-segme
 constexpr int kPieceItems = 8;           // tile counts per thread of the piece scan
 constexpr int kSegBlock = 256;           // segments per tile of the segment phase
 constexpr int kRankSmallCap = 4096;      // hull ids ranked inside one block's LDS
+constexpr int kFinCap = 1024;            // points of a segment one block finishes in LDS
 constexpr int32_t kCoordMax2D = (1 << 30) - 1;
 constexpr int kMaxStamps = 256;
 
@@ -96,7 +97,7 @@ struct HullArgs {
     int32_t vec_ok;
     int32_t timing;
     int32_t max_rounds;
-    int32_t pad;
+    int32_t fin_cap;   // finish every segment in one block once none is larger (0: off)
 };
 
 hipError_t launch_setup(const Ws2 &ws, const HullArgs &a, int grid, hipStream_t st);

@@ -27,6 +27,7 @@
 // segment is a range [start, start+len) of one region.  Tiles of 2048 points
 // are claimed from an atomic counter, so the look-back needs no assumption on
 // the order in which blocks run.
+#include "../../include/qh.h"
 #include "qh2d.h"
 
 #include <algorithm>
@@ -359,6 +360,7 @@ struct ScanSmem {
     uint32_t scratch[32];
     unsigned long long carry;
     int32_t bad;
+    int32_t maxlen;
 };
 
 template <typename A, typename B>
@@ -395,7 +397,7 @@ __device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a
     ScanSmem *sm = reinterpret_cast<ScanSmem *>(smem);
     Control *ctl = ws.ctl;
     const int k = a.k;
-    if (threadIdx.x == 0) { sm->carry = 0; sm->bad = 0; }
+    if (threadIdx.x == 0) { sm->carry = 0; sm->bad = 0; sm->maxlen = 0; }
     __syncthreads();
     for (int base = 0; base < k; base += kBlock) {
         const int i = base + (int)threadIdx.x;
@@ -407,6 +409,7 @@ __device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a
             if (lo < 0 || hi < lo || hi > a.n || (i == 0 && lo != 0) || (i == k - 1 && hi != a.n))
                 atomicOr(&sm->bad, 1);
             ne = hi > lo;
+            if (ne) atomicMax(&sm->maxlen, (int)min<int64_t>(hi - lo, INT32_MAX));
         }
         uint32_t v[1] = {ne ? 1u : 0u}, tot[1];
         block_excl_scan<kBlock, 1>(v, tot, sm->scratch);
@@ -453,6 +456,10 @@ __device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a
         ctl->rounds_with_work = 0;
         ctl->H = 0;
         ctl->h_total = 0;
+        ctl->maxseg[0] = sm->maxlen;
+        ctl->maxseg[1] = 0;
+        ctl->fin_ids = 0;
+        ctl->fin_round = -1;
         ctl->nacc[0][0] = ctl->nacc[0][1] = 0;
         ctl->nacc[1][0] = ctl->nacc[1][1] = 0;
     }
@@ -896,6 +903,13 @@ __device__ __forceinline__ bool filter_cand(int32_t x, int32_t y, uint32_t st, c
     return fkey(__fadd_rn(e, 2.f * B)) >= lmk;
 }
 
+// Round r ends the recursion in one pass when no segment has more than
+// fin_cap points (decided alike by every kernel of the round).
+__device__ __forceinline__ bool fin_mode(const Control *ctl, int p, const HullArgs &a) {
+    const RoundState &rs = ctl->rs[p];
+    return a.fin_cap > 0 && rs.s[0] + rs.s[1] > 0 && ctl->maxseg[p] <= a.fin_cap;
+}
+
 // A load through the scalar data cache (uniform address; the data was
 // written by an earlier kernel and is not written by this one).
 template <typename T>
@@ -1073,10 +1087,12 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
     bool oob = false;
     // the multi-segment tiles of the next round are listed afresh by the
     // segment kernel that follows
+    if (fin_mode(ctl, p, a)) return;  // the multi-segment kernel finishes the segments
     const int T = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
     if (blockIdx.x == 0 && tid == 0) {
         ctl->rs[q].nmulti = 0;
         ctl->tper[p] = T;
+        ctl->maxseg[q] = 0;
     }
     const int tb = blockIdx.x * T, te = min(tb + T, ntiles);
     // A run: consecutive one-segment tiles of one segment in this block.  Its
@@ -1635,6 +1651,294 @@ __device__ __forceinline__ void phase_round_multi(const Ws2 &ws, const HullArgs 
 }
 
 
+// ---------------------------------------------------------------------------
+// finishing: once no segment has more than kFinCap points, one block takes
+// each segment and completes its recursion in LDS, level by level (the same
+// rounds, with the same classification and the same argmax rule, but with no
+// launches in between).  Every apex gets a hull id from a counter and is
+// linked between its edge's ends, as the segment kernel does.
+// ---------------------------------------------------------------------------
+static_assert(kFinCap == QH_FINISH_CAP && kFinCap % kBlock == 0, "finishing capacity");
+constexpr int kFinPer = kFinCap / kBlock;          // points per thread
+constexpr int kFinPieces = 2 * (kTile + 2) + 8;    // pieces of the two tiles a segment may meet
+constexpr int kFinChunk = (kFinCap + kBlock - 1) / kBlock;  // sub-segments per thread in the scan
+
+struct FinSmem {
+    int32_t px0[kFinCap], py0[kFinCap], pi0[kFinCap];   // point buffer 0
+    union {
+        struct {
+            int32_t pv[kFinPieces], pp[kFinPieces];     // piece tables (loading only)
+        } ld;
+        struct {
+            int32_t px1[kFinCap], py1[kFinCap], pi1[kFinCap];  // point buffer 1
+            uint16_t sid[2][kFinCap];                   // sub-segment of every point
+            int32_t sst[kFinCap + 1];                   // sub-segment starts
+            uint32_t suv[kFinCap];                      // its ends: vertex slots u | v << 16
+            uint64_t kmax[kFinCap];                     // argmax: distance, then tie key
+            uint64_t kmin[kFinCap];
+            uint32_t cnt[kFinCap];                      // child sizes c0 | c1 << 16
+            int32_t vx[kFinCap + 4], vy[kFinCap + 4];   // vertices: coordinates,
+            int32_t vi[kFinCap + 4], vg[kFinCap + 4];   // input index, hull id
+        } w;
+    };
+    uint32_t scan[kNW];
+    int32_t s_base, s_ns, s_m;
+};
+
+// one segment of round p: its points, its edge u -> v and apex f
+__device__ void finish_segment(const Ws2 &ws, const HullArgs &a, int p, int R, int s, bool init,
+                               int nt0, int nt1, int hbase, FinSmem *sm) {
+    Control *ctl = ws.ctl;
+    const int tid = threadIdx.x;
+    const SegGeo G = ws.geo(p, R)[s];
+    const SegTop Tp = ws.top(p, R)[s];
+    const int len = G.len, start = G.start;
+    if (len < 1 || len > kFinCap) {  // the caller's bound: never
+        if (tid == 0) atomicOr(&ctl->error, kErrInternal);
+        return;
+    }
+    // the points into buffer 0
+    if (init) {
+        for (int j = tid; j < len; j += kBlock) {
+            const int v = start + j;
+            sm->px0[j] = a.x[v];
+            sm->py0[j] = a.y[v];
+            sm->pi0[j] = v;
+        }
+    } else {
+        const int NR = R ? ctl->rs[p].n[1] : ctl->rs[p].n[0];
+        const int ntR = R ? nt1 : nt0;
+        const int npc = ctl->rs[p].npc[R];
+        const int lt0 = start / kTile, lt1 = (start + len - 1) / kTile;
+        const int32_t *kf = ws.kf(p, R);
+        const int kA = kf[lt0];
+        const int kB = (lt1 + 1 < ntR) ? kf[lt1 + 1] : npc - 1;
+        const int K = kB - kA + 1;
+        const bool ok = start + len <= NR && kA >= 0 && K >= 1 && K <= kFinPieces && kB < npc;
+        if (ok) {
+            for (int j = tid; j < K; j += kBlock) {
+                sm->ld.pv[j] = ws.pv(p, R)[kA + j];
+                sm->ld.pp[j] = ws.pp(p, R)[kA + j];
+            }
+        }
+        __syncthreads();
+        if (!ok) {
+            if (tid == 0) atomicOr(&ctl->error, kErrInternal);
+            return;
+        }
+        const int32_t *sx = ws.px(p, R), *sy = ws.py(p, R), *si = ws.pi(p, R);
+        const int64_t cap = ws.cap_pts;
+        int32_t bx[kFinPer], by[kFinPer], bi[kFinPer];
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < kFinPer; ++k) {
+            const int j = tid + k * kBlock;
+            bx[k] = by[k] = bi[k] = 0;
+            if (j >= len) continue;
+            const int v = start + j;
+            const int sl = slot_of(sm->ld.pv, K, v);
+            const int64_t ph = (int64_t)sm->ld.pp[sl] + (v - sm->ld.pv[sl]);
+            if (ph < 0 || ph >= cap) { bad = true; continue; }
+            bx[k] = sx[ph];
+            by[k] = sy[ph];
+            bi[k] = si[ph];
+        }
+        __syncthreads();  // the piece tables share LDS with the buffers below
+#pragma unroll
+        for (int k = 0; k < kFinPer; ++k) {
+            const int j = tid + k * kBlock;
+            if (j < len) { sm->px0[j] = bx[k]; sm->py0[j] = by[k]; sm->pi0[j] = bi[k]; }
+        }
+        if (bad) atomicOr(&ctl->error, kErrInternal);
+    }
+    // vertex slots: 0 = u, 1 = v, then the apexes of each level in order
+    const bool same = G.fx == G.ux && G.fy == G.uy;  // first split of a one-point instance
+    if (tid == 0) {
+        sm->w.vx[0] = G.ux; sm->w.vy[0] = G.uy; sm->w.vg[0] = Tp.uc;
+        sm->w.vx[1] = G.vx; sm->w.vy[1] = G.vy; sm->w.vg[1] = Tp.vc;
+        sm->w.vx[2] = G.fx; sm->w.vy[2] = G.fy; sm->w.vi[2] = Tp.fidx;
+        sm->w.sst[0] = 0;
+        sm->w.suv[0] = 0u | (1u << 16);
+    }
+    for (int j = tid; j < len; j += kBlock) sm->w.sid[0][j] = 0;
+    __syncthreads();
+    int b = 0, m = len, ns = 1, nv = 2;
+    for (int level = 0; ns > 0; ++level) {
+        const int32_t *X = b ? sm->w.px1 : sm->px0;
+        const int32_t *Y = b ? sm->w.py1 : sm->py0;
+        const int32_t *I = b ? sm->w.pi1 : sm->pi0;
+        const uint16_t *SID = sm->w.sid[b];
+        int32_t px[kFinPer], py[kFinPer], pi[kFinPer], ps[kFinPer];
+#pragma unroll
+        for (int k = 0; k < kFinPer; ++k) {
+            const int j = tid + k * kBlock;
+            const bool in = j < m;
+            px[k] = in ? X[j] : 0;
+            py[k] = in ? Y[j] : 0;
+            pi[k] = in ? I[j] : 0;
+            ps[k] = in ? (int)SID[j] : -1;
+        }
+        // A. the apex of every sub-segment: farthest from u -> v, ties by the
+        // tie key (the first level's apex is the segment's own)
+        if (level > 0) {
+            for (int t = tid; t < ns; t += kBlock) {
+                sm->w.kmax[t] = 0;
+                sm->w.kmin[t] = ~0ull;
+            }
+            __syncthreads();
+            uint64_t d[kFinPer];
+#pragma unroll
+            for (int k = 0; k < kFinPer; ++k) {
+                d[k] = 0;
+                if (ps[k] < 0) continue;
+                const uint32_t uv = sm->w.suv[ps[k]];
+                const int u = (int)(uv & 0xffffu), v = (int)(uv >> 16);
+                const int64_t dd = cross_i64(px[k], py[k], sm->w.vx[u], sm->w.vy[u], sm->w.vx[v], sm->w.vy[v]);
+                if (dd <= 0) { atomicOr(&ctl->error, kErrInternal); continue; }
+                d[k] = (uint64_t)dd;
+                atomicMax(&sm->w.kmax[ps[k]], d[k]);
+            }
+            __syncthreads();
+            uint64_t tk[kFinPer];
+#pragma unroll
+            for (int k = 0; k < kFinPer; ++k) {
+                tk[k] = ~0ull;
+                if (ps[k] < 0 || d[k] != sm->w.kmax[ps[k]]) continue;
+                const uint32_t uv = sm->w.suv[ps[k]];
+                const int u = (int)(uv & 0xffffu), v = (int)(uv >> 16);
+                tk[k] = tie_key(px[k], py[k], pi[k], sm->w.vx[v] - sm->w.vx[u], sm->w.vy[v] - sm->w.vy[u]);
+                atomicMin(&sm->w.kmin[ps[k]], tk[k]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kFinPer; ++k) {
+                if (ps[k] < 0 || tk[k] != sm->w.kmin[ps[k]]) continue;
+                const int at = nv + ps[k];
+                sm->w.vx[at] = px[k];
+                sm->w.vy[at] = py[k];
+                sm->w.vi[at] = pi[k];
+            }
+        }
+        // B. hull ids of the apexes, linked between their edge's ends
+        const bool link = !(level == 0 && same);
+        if (tid == 0) sm->s_base = link ? (int)atomicAdd(&ctl->fin_ids, (unsigned)ns) : 0;
+        __syncthreads();
+        for (int t = tid; t < ns; t += kBlock) {
+            const uint32_t uv = sm->w.suv[t];
+            const int u = (int)(uv & 0xffffu), v = (int)(uv >> 16);
+            const int at = nv + t;
+            if (!link) {
+                sm->w.vg[at] = sm->w.vg[u];
+                ws.nxt[sm->w.vg[u]] = sm->w.vg[u];  // a one-point hull
+            } else {
+                const int gid = hbase + sm->s_base + t;
+                sm->w.vg[at] = gid;
+                if (gid < ws.hcap) {
+                    ws.V[gid] = sm->w.vi[at];
+                    ws.hinst[gid] = Tp.inst;
+                    ws.nxt[gid] = sm->w.vg[v];
+                    ws.nxt[sm->w.vg[u]] = gid;
+                } else {
+                    atomicOr(&ctl->error, kErrHullCap);
+                }
+            }
+            sm->w.cnt[t] = 0;
+        }
+        __syncthreads();
+        // C. the children: outside u -> f, else outside f -> v, else dropped
+        uint32_t ch[kFinPer], rk[kFinPer];
+#pragma unroll
+        for (int k = 0; k < kFinPer; ++k) {
+            ch[k] = 2;
+            rk[k] = 0;
+            if (ps[k] < 0) continue;
+            const uint32_t uv = sm->w.suv[ps[k]];
+            const int u = (int)(uv & 0xffffu), v = (int)(uv >> 16), f = nv + ps[k];
+            const int fx = sm->w.vx[f], fy = sm->w.vy[f];
+            if (cross_i64(px[k], py[k], sm->w.vx[u], sm->w.vy[u], fx, fy) > 0) ch[k] = 0;
+            else if (cross_i64(px[k], py[k], fx, fy, sm->w.vx[v], sm->w.vy[v]) > 0) ch[k] = 1;
+            if (ch[k] < 2) {
+                const uint32_t o = atomicAdd(&sm->w.cnt[ps[k]], ch[k] ? 0x10000u : 1u);
+                rk[k] = ch[k] ? (o >> 16) : (o & 0xffffu);
+            }
+        }
+        __syncthreads();
+        // D. the next level's sub-segments: child 0 then child 1 of each, in
+        // order (a scan over contiguous chunks of sub-segments)
+        const int c0s = tid * kFinChunk, c1s = min(c0s + kFinChunk, ns);
+        uint32_t cc[kFinChunk], uvs[kFinChunk];
+        uint32_t loc = 0;  // new sub-segments | their points << 16
+#pragma unroll
+        for (int k = 0; k < kFinChunk; ++k) {
+            const int t = c0s + k;
+            cc[k] = t < c1s ? sm->w.cnt[t] : 0u;
+            uvs[k] = t < c1s ? sm->w.suv[t] : 0u;
+            const uint32_t a0 = cc[k] & 0xffffu, a1 = cc[k] >> 16;
+            loc += (a0 > 0 ? 1u : 0u) + (a1 > 0 ? 1u : 0u) + ((a0 + a1) << 16);
+        }
+        uint32_t sv[1] = {loc}, tot[1];
+        block_excl_scan<kBlock, 1>(sv, tot, sm->scan);
+        uint32_t nid = sv[0] & 0xffffu, npt = sv[0] >> 16;
+#pragma unroll
+        for (int k = 0; k < kFinChunk; ++k) {
+            const int t = c0s + k;
+            if (t >= c1s) continue;
+            const uint32_t a0 = cc[k] & 0xffffu, a1 = cc[k] >> 16;
+            const uint32_t u = uvs[k] & 0xffffu, v = uvs[k] >> 16, f = (uint32_t)(nv + t);
+            uint32_t id0 = 0xffffu, id1 = 0xffffu;
+            const uint32_t st0 = npt, st1 = npt + a0;
+            if (a0 > 0) { id0 = nid; sm->w.sst[nid] = (int)st0; sm->w.suv[nid] = u | (f << 16); ++nid; }
+            if (a1 > 0) { id1 = nid; sm->w.sst[nid] = (int)st1; sm->w.suv[nid] = f | (v << 16); ++nid; }
+            npt += a0 + a1;
+            // where each child's points go (read by the scatter below)
+            sm->w.kmax[t] = (uint64_t)st0 | ((uint64_t)st1 << 32);
+            sm->w.kmin[t] = (uint64_t)id0 | ((uint64_t)id1 << 32);
+        }
+        __syncthreads();
+        // E. the points into the other buffer
+        int32_t *Xo = b ? sm->px0 : sm->w.px1;
+        int32_t *Yo = b ? sm->py0 : sm->w.py1;
+        int32_t *Io = b ? sm->pi0 : sm->w.pi1;
+        uint16_t *SIDo = sm->w.sid[b ^ 1];
+#pragma unroll
+        for (int k = 0; k < kFinPer; ++k) {
+            if (ch[k] > 1) continue;
+            const int pos = (int)((sm->w.kmax[ps[k]] >> (32 * ch[k])) & 0xffffffffu) + (int)rk[k];
+            const int id = (int)((sm->w.kmin[ps[k]] >> (32 * ch[k])) & 0xffffffffu);
+            if (pos >= kFinCap || id >= kFinCap) { atomicOr(&ctl->error, kErrInternal); continue; }
+            Xo[pos] = px[k];
+            Yo[pos] = py[k];
+            Io[pos] = pi[k];
+            SIDo[pos] = (uint16_t)id;
+        }
+        nv += ns;
+        ns = (int)(tot[0] & 0xffffu);
+        m = (int)(tot[0] >> 16);
+        b ^= 1;
+        if (nv + ns > kFinCap + 3) {  // more apexes than points: never
+            if (tid == 0) atomicOr(&ctl->error, kErrInternal);
+            ns = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// every segment of round p, one per block
+__device__ void phase_finish(const Ws2 &ws, const HullArgs &a, int r, FinSmem *sm) {
+    Control *ctl = ws.ctl;
+    const int p = r & 1;
+    if (ctl->error) return;
+    const RoundState *rs = &ctl->rs[p];
+    const int S0 = rs->s[0], S1 = rs->s[1];
+    const int nt0 = (rs->n[0] + kTile - 1) / kTile, nt1 = (rs->n[1] + kTile - 1) / kTile;
+    const int hbase = rs->hbase;
+    for (int g = blockIdx.x; g < S0 + S1; g += gridDim.x) {
+        const int R = g < S0 ? 0 : 1;
+        finish_segment(ws, a, p, R, R ? g - S0 : g, r == 0, nt0, nt1, hbase, sm);
+        __syncthreads();
+    }
+}
+
 // The argmax records of a segment of region R whose points span the tiles
 // t0 < t1 of round p (global tile indices): slot 0 is tile t0 (its last
 // segment's record if t0 holds several segments, else the record of the run
@@ -1705,6 +2009,18 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
     const int nsegt = (Stot + kSegBlock - 1) / kSegBlock;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
 
+    if (fin_mode(ctl, p, a)) {
+        // the segments were finished by the multi-segment kernel: no next round
+        if (blockIdx.x == 0 && tid == 0) {
+            RoundState z = {};
+            z.hbase = hbase + (int32_t)ctl->fin_ids;
+            *rn = z;
+            ctl->nacc[q][0] = 0;
+            ctl->nacc[q][1] = 0;
+            ctl->fin_round = r;
+        }
+        return;
+    }
     if (blockIdx.x == 0 && tid == 0) {
         rn->seg_ctr = 0;
         rn->piece_ctr = 0;
@@ -1838,6 +2154,13 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
         const int st1 = (int)(unpackB(sm->s_ex2) + w[1]);
         const bool ok0 = has0 && id0 < ws.scap, ok1 = has1 && id1 < ws.scap;
         if ((has0 && !ok0) || (has1 && !ok1)) atomicOr(&ctl->error, kErrSegCap);
+        {
+            // the largest segment of the next round
+            uint32_t mc = (uint32_t)max(ok0 ? c0 : 0, ok1 ? c1 : 0);
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) mc = max(mc, (uint32_t)__shfl_xor((int)mc, o));
+            if (lane == 0 && mc) atomicMax(&ctl->maxseg[q], (int32_t)mc);
+        }
 
         // child segments of the next round
         if (ok0) {
@@ -2139,11 +2462,20 @@ __global__ __launch_bounds__(kBlock) void k_round(Ws2 ws, HullArgs a, int32_t r)
     phase_round_fast<MODE, INIT>(ws, a, r, reinterpret_cast<char *>(&sm));
 }
 
+union MultiSmem {
+    RoundSmem round;
+    FinSmem fin;
+};
+
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_round_multi(Ws2 ws, HullArgs a, int32_t r) {
-    __shared__ RoundSmem sm;
+    __shared__ MultiSmem sm;
     if (ws.ctl->setup_error) return;
-    phase_round_multi<MODE>(ws, a, r, reinterpret_cast<char *>(&sm));
+    if (fin_mode(ws.ctl, r & 1, a)) {
+        phase_finish(ws, a, r, &sm.fin);
+        return;
+    }
+    phase_round_multi<MODE>(ws, a, r, reinterpret_cast<char *>(&sm.round));
 }
 
 __global__ __launch_bounds__(kSegBlock) void k_segments(Ws2 ws, HullArgs a, int32_t r) {

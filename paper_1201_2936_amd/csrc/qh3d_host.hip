@@ -885,7 +885,10 @@ extern "C" qh_status qh_hull3d(const int32_t *pts, int64_t n, int32_t *facets, i
     if (nfacets) *nfacets = 0;
     if (nverts) *nverts = 0;
     if (!nfacets || !nverts || n < 0 || n > (int64_t)INT32_MAX / 2 - 4096) return QH_EINVAL;
-    if (opts && opts->stats) memset(opts->stats, 0, sizeof(qh_stats));
+    if (opts && opts->stats) {
+        memset(opts->stats, 0, sizeof(qh_stats));
+        opts->stats->finish_round = -1;  // a 2D option
+    }
     if (opts && opts->mode != QH_EXACT_INT64 && opts->mode != QH_FP32_FILTER) return QH_EINVAL;
     if (n < 4) return QH_EDEGENERATE;
     if (!pts || !facets || !verts) return QH_EINVAL;

@@ -230,6 +230,7 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
     args.n = (int32_t)n;
     args.k = k;
     args.vec_ok = (((uintptr_t)pts & 15u) == 0 && (n & 3) == 0) ? 1 : 0;
+    args.fin_cap = (o && (o->flags & QH_FLAG_NO_FINISH)) ? 0 : kFinCap;
     const int grid = c->grid[mode];
     int64_t syncs = 0;
     int r = 0;
@@ -251,7 +252,10 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
         QH_TRY(launch_extremes(ws, args, grid, st));
         QH_TRY(tm.after(st));
         r = 0;
-        int batch = 9;  // the first split and 8 rounds, then 8 rounds per batch
+        // the first batch: as many rounds as the previous call of this context
+        // needed (no launches left over when the inputs are alike), else the
+        // first split and 4 rounds; then 8 rounds per batch
+        int batch = c->hint_rounds > 0 ? c->hint_rounds : 5;
         while (true) {
             for (int j = 0; j < batch; ++j, ++r) {
                 QH_TRY(tm.before(st, r == 0 ? Timing::kSplit : Timing::kRound));
@@ -285,6 +289,11 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
         break;
     }
     const int32_t H = c->ctl_host->rs[r & 1].hbase;
+    {
+        const Control &hc = *c->ctl_host;
+        const int need = hc.fin_round >= 0 ? hc.fin_round + 1 : (int)hc.rounds_with_work;
+        c->hint_rounds = std::max(1, std::min(need, 64));
+    }
     QH_TRY(tm.before(st, Timing::kOutput));
     QH_TRY(launch_output(c->ws, args, H, st));
     QH_TRY(tm.after(st));
@@ -319,6 +328,7 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
         stats->max_segments = h.max_segments;
         stats->grid_blocks = grid;
         stats->host_syncs = syncs;
+        stats->finish_round = h.fin_round;
     }
     return QH_OK;
 }

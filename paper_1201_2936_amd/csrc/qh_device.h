@@ -215,6 +215,9 @@ struct Control {
     unsigned int nacc[2][2];          // survivors per region written by the round kernel, by parity
     int32_t tper[2];                  // tiles per block of the round kernel, by parity
     int32_t tper_ext;                 // tiles per block of the extremes kernel
+    int32_t maxseg[2];                // largest segment of the round, by parity
+    uint32_t fin_ids;                 // hull ids taken by the finishing pass
+    int32_t fin_round;                // the round that finished every segment (-1: none)
     int32_t H;                        // compact hull ids used
     long long h_total;                // hull vertices of all instances
     int32_t nstamps;

@@ -23,6 +23,8 @@ QH_ECAPACITY = -6
 QH_EXACT_INT64 = 0
 QH_FP32_FILTER = 1
 QH_FLAG_TIMING = 1
+QH_FLAG_NO_FINISH = 2
+QH_FINISH_CAP = 1024
 
 EXPORTED = ["qh_ctx_create", "qh_ctx_destroy", "qh_status_str", "qh_version",
             "qh_hull2d", "qh_hull2d_batched", "qh_hull3d", "qh_test_flag_permute"]
@@ -50,6 +52,7 @@ class QhStats(ctypes.Structure):
         ("host_syncs", ctypes.c_int64),
         ("host_ms", ctypes.c_double),
         ("host_output_ms", ctypes.c_double),
+        ("finish_round", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -138,11 +141,12 @@ class Context:
             pass
 
 
-def _opts(ctx, mode, timing, stream):
+def _opts(ctx, mode, timing, stream, finish=True):
     import torch
     st = torch.cuda.current_stream().cuda_stream if stream is None else stream
     stats = QhStats()
-    o = QhOpts(ctypes.c_void_p(st), mode, QH_FLAG_TIMING if timing else 0,
+    flags = (QH_FLAG_TIMING if timing else 0) | (0 if finish else QH_FLAG_NO_FINISH)
+    o = QhOpts(ctypes.c_void_p(st), mode, flags,
                ctx.ptr if ctx is not None else None, ctypes.pointer(stats))
     return o, stats
 
@@ -157,7 +161,7 @@ def _check_points(pts, dims):
 
 
 def qh_hull2d(pts, mode: int = QH_EXACT_INT64, ctx: Context | None = None,
-              timing: bool = False, stream=None):
+              timing: bool = False, stream=None, finish: bool = True):
     """Counter-clockwise hull vertex indices (int32 tensor on the device) of
     int32[2, n] device points; returns (indices, stats dict)."""
     import torch
@@ -166,7 +170,7 @@ def qh_hull2d(pts, mode: int = QH_EXACT_INT64, ctx: Context | None = None,
     n = pts.shape[1]
     out = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
     h = ctypes.c_int64(0)
-    o, stats = _opts(ctx, mode, timing, stream)
+    o, stats = _opts(ctx, mode, timing, stream, finish)
     st = lib.qh_hull2d(ctypes.c_void_p(pts.data_ptr()), n, ctypes.c_void_p(out.data_ptr()),
                        ctypes.byref(h), ctypes.byref(o))
     if st != QH_OK:
@@ -175,7 +179,7 @@ def qh_hull2d(pts, mode: int = QH_EXACT_INT64, ctx: Context | None = None,
 
 
 def qh_hull2d_batched(pts, offsets, mode: int = QH_EXACT_INT64, ctx: Context | None = None,
-                      timing: bool = False, stream=None):
+                      timing: bool = False, stream=None, finish: bool = True):
     """Hulls of the instances [offsets[i], offsets[i+1]) of int32[2, N] device
     points; offsets is an int64[k + 1] device tensor.  Returns (indices local
     to each instance, int64[k + 1] device hull offsets, stats dict)."""
@@ -190,7 +194,7 @@ def qh_hull2d_batched(pts, offsets, mode: int = QH_EXACT_INT64, ctx: Context | N
     out = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
     hoff = torch.empty(k + 1, dtype=torch.int64, device=pts.device)
     ht = ctypes.c_int64(0)
-    o, stats = _opts(ctx, mode, timing, stream)
+    o, stats = _opts(ctx, mode, timing, stream, finish)
     st = lib.qh_hull2d_batched(ctypes.c_void_p(pts.data_ptr()), n,
                                ctypes.c_void_p(offsets.data_ptr()), k,
                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(hoff.data_ptr()),

@@ -16,7 +16,13 @@ from hullcheck import check_hull2d
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-MODES = [0, 1]
+# bit 0: the arithmetic (0 exact int64, 1 FP32 filter); bit 1: every level
+# as a round of the round kernels (no one-workgroup finishing of small segments)
+MODES = [0, 1, 2, 3]
+
+
+def _kw(m):
+    return dict(mode=m & 1, finish=not (m & 2))
 
 
 @pytest.fixture(scope="module")
@@ -37,7 +43,7 @@ def ctx(qhm):
 
 def _gpu_hull(qhm, ctx, pts, mode):
     t = torch.from_numpy(np.ascontiguousarray(pts)).to("cuda")
-    idx, stats = qhm.qh_hull2d(t, mode=mode, ctx=ctx)
+    idx, stats = qhm.qh_hull2d(t, ctx=ctx, **_kw(mode))
     return idx.cpu().numpy(), stats
 
 
@@ -144,8 +150,24 @@ def test_misaligned_and_odd_sizes(qhm, ctx):
     t = torch.from_numpy(base).to("cuda")
     for mode in MODES:
         sub = t[:, 1:]
-        idx, _ = qhm.qh_hull2d(sub.contiguous(), mode=mode, ctx=ctx)
+        idx, _ = qhm.qh_hull2d(sub.contiguous(), ctx=ctx, **_kw(mode))
         assert idx.cpu().numpy().tolist() == oracle.hull2d(base[:, 1:]).tolist()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_finish_round_reported(qhm, ctx, mode):
+    """Inputs of at most QH_FINISH_CAP points are finished at the first split;
+    larger ones later; never with the option off."""
+    for n, first in [(1, True), (700, True), (1024, True), (1025, False), (30000, False)]:
+        pts = workloads.disk(workloads.rng_for(40 + n), n, 1 << 20)
+        got, st = _gpu_hull(qhm, ctx, pts, mode)
+        assert got.tolist() == oracle.hull2d(pts).tolist()
+        if mode & 2:
+            assert st["finish_round"] == -1
+        elif first:
+            assert st["finish_round"] == 0
+        else:
+            assert st["finish_round"] >= 1
 
 
 def test_deterministic_and_no_ctx(qhm):
@@ -162,7 +184,10 @@ def test_disk_65k(qhm, ctx, mode):
     _say(f"disk_65k mode={mode}")
     got, stats = _gpu_hull(qhm, ctx, pts, mode)
     assert got.tolist() == oracle.hull2d(pts).tolist()
-    assert stats["rounds"] >= 2
+    if mode & 2:
+        assert stats["rounds"] >= 2 and stats["finish_round"] == -1
+    else:
+        assert stats["finish_round"] >= 1
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -172,7 +197,7 @@ def test_square_16m(qhm, ctx, mode):
     got, stats = _gpu_hull(qhm, ctx, pts, mode)
     want = oracle.hull2d(pts)
     assert got.tolist() == want.tolist()
-    if mode == 1:
+    if mode & 1:
         assert stats["filter_tests"] > 0
         _say(f"fallback rate {stats['filter_fallbacks'] / stats['filter_tests']:.3e}")
 
@@ -185,7 +210,7 @@ def test_circle_mix_4m(qhm, ctx, mode):
     want = oracle.hull2d(pts)
     assert got.tolist() == want.tolist()
     check_hull2d(pts, got)
-    if mode == 1:
+    if mode & 1:
         # the exactly collinear support lines force undecided FP32 signs
         assert stats["filter_fallbacks"] > 0
 
@@ -196,7 +221,7 @@ def test_circle_mix_4m(qhm, ctx, mode):
 def _gpu_batched(qhm, ctx, pts, offsets, mode):
     t = torch.from_numpy(np.ascontiguousarray(pts)).to("cuda")
     o = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int64)).to("cuda")
-    idx, hoff, stats = qhm.qh_hull2d_batched(t, o, mode=mode, ctx=ctx)
+    idx, hoff, stats = qhm.qh_hull2d_batched(t, o, ctx=ctx, **_kw(mode))
     return idx.cpu().numpy(), hoff.cpu().numpy(), stats
 
 
@@ -288,7 +313,7 @@ def test_batched_disks_4096(qhm, ctx, mode, batched_full):
     """The full batched workload: 4,096 disks, about 5.1e8 points."""
     pts_t, off_t, want, want_off = batched_full
     _say(f"batched_disks full N={int(off_t[-1])} mode={mode}")
-    idx, hoff, st = qhm.qh_hull2d_batched(pts_t, off_t, mode=mode, ctx=ctx)
+    idx, hoff, st = qhm.qh_hull2d_batched(pts_t, off_t, ctx=ctx, **_kw(mode))
     assert hoff.cpu().numpy().tolist() == want_off.tolist()
     assert np.array_equal(idx.cpu().numpy(), want)
 
