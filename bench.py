@@ -9,8 +9,9 @@ is timed beside it on the same data.
 
 Prints ONE JSON line.  ``roofline`` describes the round (k_round for the tiles
 covered by one segment and k_round_multi for the others, launched together
-for the first split and once per later round), which moves nearly all the
-bytes: algorithmic bytes per round (first split 8 B per point read and 12 B
+for the first split and once per later round; in the last round, once no
+segment holds more than 1,024 points, k_round_multi finishes every segment
+with one workgroup each), which moves nearly all the bytes: algorithmic bytes per round (first split 8 B per point read and 12 B
 per survivor written; later rounds 12 B per point read and 12 B per survivor
 written) over the round's average duration, timed with HIP events around the
 pair of launches on the stream they run on.
@@ -318,7 +319,8 @@ def main():
         "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"]
                           if st_f["filter_tests"] else 0.0),
         "argmax_candidates": int(st_f["argmax_candidates"]),
-        "round_kernel": {"name": "k_round + k_round_multi (first split and every later round)",
+        "finish_round": int(st_f["finish_round"]),
+        "round_kernel": {"name": "k_round + k_round_multi (first split, later rounds, last round finishing small segments)",
                          "launches_per_step": launches / args.steps,
                          "avg_launch_us": round(avg_launch_ms * 1e3, 3),
                          "bytes_per_launch": round(bytes_per_launch),

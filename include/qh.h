@@ -62,10 +62,12 @@ enum {
     QH_FLAG_NO_FINISH = 2u  /* 2D: run every level of the recursion as a
                                round of the round kernels.  By default, once
                                no segment holds more than QH_FINISH_CAP
-                               points, one workgroup per segment completes
-                               that segment's recursion in on-chip memory
-                               (the same levels and the same rules as the
-                               rounds, so the same output) */
+                               points and there are at most two segments per
+                               workgroup of the multi-segment kernel, one
+                               workgroup per segment completes that segment's
+                               recursion in on-chip memory (the same levels
+                               and the same rules as the rounds, so the same
+                               output) */
 };
 
 /* points of a segment that one workgroup finishes (QH_FLAG_NO_FINISH) */

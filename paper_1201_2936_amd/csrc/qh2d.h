@@ -98,6 +98,7 @@ struct HullArgs {
     int32_t timing;
     int32_t max_rounds;
     int32_t fin_cap;   // finish every segment in one block once none is larger (0: off)
+    int32_t fin_segs;  // ... and there are at most this many segments
 };
 
 hipError_t launch_setup(const Ws2 &ws, const HullArgs &a, int grid, hipStream_t st);

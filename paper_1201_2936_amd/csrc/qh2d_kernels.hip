@@ -904,10 +904,13 @@ __device__ __forceinline__ bool filter_cand(int32_t x, int32_t y, uint32_t st, c
 }
 
 // Round r ends the recursion in one pass when no segment has more than
-// fin_cap points (decided alike by every kernel of the round).
+// fin_cap points and there are at most fin_segs segments (a workgroup takes
+// one segment at a time: many small segments go faster as rounds); decided
+// alike by every kernel of the round.
 __device__ __forceinline__ bool fin_mode(const Control *ctl, int p, const HullArgs &a) {
     const RoundState &rs = ctl->rs[p];
-    return a.fin_cap > 0 && rs.s[0] + rs.s[1] > 0 && ctl->maxseg[p] <= a.fin_cap;
+    const int S = rs.s[0] + rs.s[1];
+    return a.fin_cap > 0 && S > 0 && S <= a.fin_segs && ctl->maxseg[p] <= a.fin_cap;
 }
 
 // A load through the scalar data cache (uniform address; the data was

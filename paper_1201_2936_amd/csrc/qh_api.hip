@@ -231,6 +231,7 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
     args.k = k;
     args.vec_ok = (((uintptr_t)pts & 15u) == 0 && (n & 3) == 0) ? 1 : 0;
     args.fin_cap = (o && (o->flags & QH_FLAG_NO_FINISH)) ? 0 : kFinCap;
+    args.fin_segs = 2 * (2 * c->cus);  // two per block of the multi-segment kernel
     const int grid = c->grid[mode];
     int64_t syncs = 0;
     int r = 0;
