@@ -17,14 +17,12 @@ constexpr int32_t kCoordMax2D = (1 << 30) - 1;
 constexpr int kMaxStamps = 256;
 
 // What a tile of the survivor array needs to know before it reads a point:
-// the segment holding its first point and, when that segment covers the whole
-// tile (the common case), its geometry.
+// the segment holding its first point (whose geometry is in the segment
+// table) and whether that segment covers the whole tile (the common case).
 struct TileInfo {
     int32_t seg;     // segment of the tile's first point (index in the region's table)
     int32_t single;  // 1: that segment covers the whole tile
     int32_t start, end;
-    int32_t ux, uy, fx, fy, vx, vy;
-    int32_t pad0, pad1;
 };
 
 // Device pointers of one workspace (passed by value to every kernel).  The

@@ -348,7 +348,7 @@ struct SegSmem {
     int16_t q_map[2 * kSegBlock];
     int32_t o_t0[kSegBlock], o_t1[kSegBlock];
     int32_t o_ka[2 * kSegBlock], o_kb[2 * kSegBlock], o_id[2 * kSegBlock];
-    Best red[kNW];
+    Best red[2 * kNW];
 };
 
 struct RankSmem {
@@ -695,50 +695,67 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
 // Merge the per-tile partials of one segment over tiles t0 .. t1 (the whole
 // block cooperates; every thread gets the result).  In tile t0 the segment is
 // the tile's last one, in the later tiles its first one.
-// The extremes records of an instance over tiles t0 < t1: slot 0 is tile t0
-// (its last instance's record if t0 holds several instances, else the record
-// of the run that starts there); slot 1 + j is the run head in the j-th range
-// of T tiles the instance meets (one record per run, at its first tile); the
-// last slot is tile t1 if it holds several instances.  False: no record.
-__device__ __forceinline__ bool ext_record(const Ws2 &ws, int T, int t0, int t1, int k, int c,
-                                           Best &out) {
-    const TileInfo *ti = ws.tinfo(0, 0);
+// The argmax records of a segment of region R whose points span the tiles
+// t0 < t1 of round p (global tile indices): slot 0 is tile t0 (its last
+// segment's record if t0 holds several segments, else the record of the run
+// that starts there); slot 1 + j is the run head in the j-th range of T tiles
+// the segment meets (the round kernel keeps one record per run, at the run's
+// first tile); the last slot is tile t1 if it holds several segments.  Only
+// t0 and t1 can hold several segments (s0, s1: whether each holds one), so
+// a slot is one record load.  Returns the record's tile and array (recF /
+// recL), or -1 for a slot without a record.
+__device__ __forceinline__ int seg_slot(int T, int t0, int t1, bool s0, bool s1, int k, bool &last) {
     const int nb = t1 / T - t0 / T + 1;
+    last = false;
     if (k == 0) {
-        out = ti[t0].single ? ws.recF0[t0 * 2 + c] : ws.recL0[t0 * 2 + c];
-        return true;
+        last = !s0;
+        return t0;
     }
     if (k <= nb) {
         const int b = t0 / T + (k - 1);
         const int st = max(b * T, t0 + 1);
-        if (st > t1 || st >= (b + 1) * T || !ti[st].single) return false;
-        if (st != b * T && ti[t0].single) return false;  // same run as t0
-        out = ws.recF0[st * 2 + c];
-        return true;
+        if (st > t1 || st >= (b + 1) * T || (st == t1 && !s1)) return -1;
+        if (st != b * T && s0) return -1;  // same run as t0
+        return st;
     }
-    if (k == nb + 1 && !ti[t1].single) {
-        out = ws.recF0[t1 * 2 + c];
-        return true;
-    }
-    return false;
+    if (k == nb + 1 && !s1) return t1;
+    return -1;
 }
 
-// merge of the extremes records of one instance with the whole block
-__device__ __forceinline__ Best block_merge_ext(const Ws2 &ws, int T, int t0, int t1, int c,
-                                                Best *red) {
-    Best acc = best_none();
-    const int ns = t1 / T - t0 / T + 3;
+__device__ __forceinline__ int seg_slots(int T, int t0, int t1) { return t1 / T - t0 / T + 3; }
+
+// The extremes records of an instance over tiles t0 < t1, slot by slot as
+// for the segments' argmax records (seg_slot): tile t0, the run heads of the
+// ranges of T tiles, tile t1 if it holds several instances.
+__device__ __forceinline__ void block_merge_ext(const Ws2 &ws, int T, int t0, int t1, Best *red,
+                                                Best &mn, Best &mx) {
+    const TileInfo *ti = ws.tinfo(0, 0);
+    const bool s0 = ti[t0].single != 0, s1 = ti[t1].single != 0;
+    Best a0 = best_none(), a1 = best_none();
+    const int ns = seg_slots(T, t0, t1);
     for (int k = threadIdx.x; k < ns; k += kBlock) {
-        Best b;
-        if (ext_record(ws, T, t0, t1, k, c, b)) best_merge(acc, b);
+        bool last;
+        const int t = seg_slot(T, t0, t1, s0, s1, k, last);
+        if (t < 0) continue;
+        const Best *rec = last ? ws.recL0 : ws.recF0;
+        const Best b0 = rec[t * 2 + 0], b1 = rec[t * 2 + 1];
+        best_merge(a0, b0);
+        best_merge(a1, b1);
     }
-    wave_best(acc);
-    if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
+    wave_best(a0);
+    wave_best(a1);
+    if (lane_id() == 0) {
+        red[2 * (threadIdx.x / kWave) + 0] = a0;
+        red[2 * (threadIdx.x / kWave) + 1] = a1;
+    }
     __syncthreads();
-    Best r = red[0];
-    for (int w = 1; w < kNW; ++w) best_merge(r, red[w]);
+    mn = red[0];
+    mx = red[1];
+    for (int w = 1; w < kNW; ++w) {
+        best_merge(mn, red[2 * w + 0]);
+        best_merge(mx, red[2 * w + 1]);
+    }
     __syncthreads();
-    return r;
 }
 
 // Every instance segment: finish its extremes, write the first-split segment
@@ -760,8 +777,7 @@ __device__ __forceinline__ void phase_extremes_final(const Ws2 &ws, const HullAr
             mx = ws.dir0[s * 2 + 1];
         } else {
             const int T = max(1, ctl->tper_ext);
-            mn = block_merge_ext(ws, T, t0, t1, 0, sm->red);
-            mx = block_merge_ext(ws, T, t0, t1, 1, sm->red);
+            block_merge_ext(ws, T, t0, t1, sm->red, mn, mx);
         }
         // (the first split reads the instance's geometry from this table;
         // its tile records come from the set-up kernel)
@@ -920,19 +936,27 @@ __device__ __forceinline__ T scalar_load(const T *ptr) {
     return *(const __attribute__((address_space(4))) T *)(ptr);
 }
 
-// the record of global tile t of round p (uniform); in the first split the
-// tile records hold the instance only, and the geometry is the instance's
-// segment (u = v = its minimum, f = its maximum)
-template <bool INIT>
-__device__ __forceinline__ TileInfo tile_record(const Ws2 &ws, int p, int t, int nt0) {
-    const int32_t *src = reinterpret_cast<const int32_t *>(t < nt0 ? ws.tinfo(p, 0) + t
-                                                                 : ws.tinfo(p, 1) + (t - nt0));
-    TileInfo ti;
-    int32_t *dst = reinterpret_cast<int32_t *>(&ti);
-#pragma unroll
-    for (int k = 0; k < (int)(sizeof(TileInfo) / sizeof(int32_t)); ++k) dst[k] = scalar_load(src + k);
-    if (INIT && ti.single) {
-        const int32_t *g = reinterpret_cast<const int32_t *>(ws.geo(0, 0) + ti.seg);
+// a tile's record with its segment's geometry (u, f, v) when one segment
+// covers it
+struct TileGeo {
+    int32_t seg, single, start, end;
+    int32_t ux, uy, fx, fy, vx, vy;
+};
+
+// the record of global tile t of round p (uniform), the geometry from the
+// segment table (in the first split: u = v = the instance's minimum, f = its
+// maximum)
+__device__ __forceinline__ TileGeo tile_record(const Ws2 &ws, int p, int t, int nt0) {
+    const int R = t < nt0 ? 0 : 1;
+    const int32_t *src = reinterpret_cast<const int32_t *>(ws.tinfo(p, R) + (t - (R ? nt0 : 0)));
+    TileGeo ti;
+    ti.seg = scalar_load(src + 0);
+    ti.single = scalar_load(src + 1);
+    ti.start = scalar_load(src + 2);
+    ti.end = scalar_load(src + 3);
+    ti.ux = ti.uy = ti.fx = ti.fy = ti.vx = ti.vy = 0;
+    if (ti.single) {
+        const int32_t *g = reinterpret_cast<const int32_t *>(ws.geo(p, R) + ti.seg);
         ti.ux = scalar_load(g + 2); ti.uy = scalar_load(g + 3);
         ti.fx = scalar_load(g + 4); ti.fy = scalar_load(g + 5);
         ti.vx = scalar_load(g + 6); ti.vy = scalar_load(g + 7);
@@ -1104,9 +1128,9 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
     RunBest r0 = rb_none(), r1 = rb_none();
     int cur = -1, run0 = 0, run_lo = 0, run_hi = 0, seg_st = 0, seg_en = 0;
     // the current tile's record and, when prefetched, its points
-    TileInfo tc;
+    TileGeo tc;
     tc.single = 0;
-    if (tb < te) tc = tile_record<INIT>(ws, p, tb, nt0);
+    if (tb < te) tc = tile_record(ws, p, tb, nt0);
     uint32_t vm = 0;
     bool have = false;
     // One tile; the points of the next one go to the other register set (the
@@ -1123,7 +1147,7 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
         const int NR = R ? n1 : n0;
         const int lo = lt * kTile;
         const int hi = min(lo + kTile, NR);
-        TileInfo ti = tc;
+        TileGeo ti = tc;
         if (past) ti.single = 0;
         const int gseg = (R ? S0 : 0) + ti.seg;
         if (cur >= 0 && (!ti.single || gseg != cur)) {
@@ -1157,9 +1181,9 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
         if (past) return true;
         // the next tile's record (scalar loads, consumed a tile later)
         const bool nxt = tile + 1 < te;
-        TileInfo tn;
+        TileGeo tn;
         tn.single = 0;
-        if (nxt) tn = tile_record<INIT>(ws, p, tile + 1, nt0);
+        if (nxt) tn = tile_record(ws, p, tile + 1, nt0);
         if (!ti.single) {  // uniform: the multi-segment kernel takes it
             tc = tn;
             have = false;
@@ -1942,56 +1966,42 @@ __device__ void phase_finish(const Ws2 &ws, const HullArgs &a, int r, FinSmem *s
     }
 }
 
-// The argmax records of a segment of region R whose points span the tiles
-// t0 < t1 of round p (global tile indices): slot 0 is tile t0 (its last
-// segment's record if t0 holds several segments, else the record of the run
-// that starts there); slot 1 + j is the run head in the j-th range of T tiles
-// the segment meets (the round kernel keeps one record per run, at the run's
-// first tile); the last slot is tile t1 if it holds several segments.  A slot
-// without a record returns false.
-__device__ __forceinline__ bool seg_record(const Ws2 &ws, int p, int R, int nt0, int T, int t0,
-                                           int t1, int k, int c, Best &out) {
-    const TileInfo *ti = ws.tinfo(p, R);
-    const int off = R ? nt0 : 0;
-    const int nb = t1 / T - t0 / T + 1;
-    if (k == 0) {
-        out = ti[t0 - off].single ? ws.recF[t0 * 2 + c] : ws.recL[t0 * 2 + c];
-        return true;
-    }
-    if (k <= nb) {
-        const int b = t0 / T + (k - 1);
-        const int st = max(b * T, t0 + 1);
-        if (st > t1 || st >= (b + 1) * T || !ti[st - off].single) return false;
-        if (st != b * T && ti[t0 - off].single) return false;  // same run as t0
-        out = ws.recF[st * 2 + c];
-        return true;
-    }
-    if (k == nb + 1 && !ti[t1 - off].single) {
-        out = ws.recF[t1 * 2 + c];
-        return true;
-    }
-    return false;
+// merge of a slot's records of both children into acc0 / acc1
+__device__ __forceinline__ void seg_take(const Ws2 &ws, int t, bool last, Best &acc0, Best &acc1) {
+    const Best *rec = last ? ws.recL : ws.recF;
+    const Best b0 = rec[t * 2 + 0], b1 = rec[t * 2 + 1];
+    rec_merge(acc0, b0);
+    rec_merge(acc1, b1);
 }
 
-__device__ __forceinline__ int seg_slots(int T, int t0, int t1) { return t1 / T - t0 / T + 3; }
-
-// Merge the record slots of one segment with the whole block (every thread
-// gets the result).
-__device__ __forceinline__ Best block_merge_seg(const Ws2 &ws, int p, int R, int nt0, int T, int t0,
-                                               int t1, int c, Best *red) {
-    Best acc = best_none();
+// Merge the record slots of one segment, both children, with the whole block
+// (every thread gets the results).
+__device__ __forceinline__ void block_merge_seg(const Ws2 &ws, int p, int R, int nt0, int T, int t0,
+                                                int t1, Best *red, Best &m0, Best &m1) {
+    const TileInfo *ti = ws.tinfo(p, R);
+    const int off = R ? nt0 : 0;
+    const bool s0 = ti[t0 - off].single != 0, s1 = ti[t1 - off].single != 0;
+    Best acc0 = best_none(), acc1 = best_none();
     const int ns = seg_slots(T, t0, t1);
     for (int k = threadIdx.x; k < ns; k += kSegBlock) {
-        Best b;
-        if (seg_record(ws, p, R, nt0, T, t0, t1, k, c, b)) rec_merge(acc, b);
+        bool last;
+        const int t = seg_slot(T, t0, t1, s0, s1, k, last);
+        if (t >= 0) seg_take(ws, t, last, acc0, acc1);
     }
-    wave_rec(acc);
-    if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
+    wave_rec(acc0);
+    wave_rec(acc1);
+    if (lane_id() == 0) {
+        red[2 * (threadIdx.x / kWave) + 0] = acc0;
+        red[2 * (threadIdx.x / kWave) + 1] = acc1;
+    }
     __syncthreads();
-    Best r = red[0];
-    for (int w = 1; w < kSegBlock / kWave; ++w) rec_merge(r, red[w]);
+    m0 = red[0];
+    m1 = red[1];
+    for (int w = 1; w < kSegBlock / kWave; ++w) {
+        rec_merge(m0, red[2 * w + 0]);
+        rec_merge(m1, red[2 * w + 1]);
+    }
     __syncthreads();
-    return r;
 }
 // ---------------------------------------------------------------------------
 // segments: hull insertion, multi-tile argmax, next segment table
@@ -2091,10 +2101,13 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
                 b1 = ws.adir[g * 2 + 1];
             } else if (seg_slots(T, t0, t1) <= 12) {
                 const int ns = seg_slots(T, t0, t1);
+                const TileInfo *ti = ws.tinfo(p, R);
+                const int off = R ? nt0 : 0;
+                const bool s0 = ti[t0 - off].single != 0, s1 = ti[t1 - off].single != 0;
                 for (int k = 0; k < ns; ++k) {
-                    Best r;
-                    if (seg_record(ws, p, R, nt0, T, t0, t1, k, 0, r)) rec_merge(b0, r);
-                    if (seg_record(ws, p, R, nt0, T, t0, t1, k, 1, r)) rec_merge(b1, r);
+                    bool last;
+                    const int t = seg_slot(T, t0, t1, s0, s1, k, last);
+                    if (t >= 0) seg_take(ws, t, last, b0, b1);
                 }
             } else {
                 const int qi = atomicAdd(&sm->qn_apex, 1);
@@ -2109,8 +2122,8 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             const int own = sm->q_apex[qi];
             const int a0 = sm->o_t0[own], a1 = sm->o_t1[own];
             const int Ro = own + tile * kSegBlock < S0 ? 0 : 1;
-            const Best m0 = block_merge_seg(ws, p, Ro, nt0, T, a0, a1, 0, sm->red);
-            const Best m1 = block_merge_seg(ws, p, Ro, nt0, T, a0, a1, 1, sm->red);
+            Best m0, m1;
+            block_merge_seg(ws, p, Ro, nt0, T, a0, a1, sm->red, m0, m1);
             if (tid == own) { b0 = m0; b1 = m1; }
         }
         const int c0 = valid ? b0.cnt : 0, c1 = valid ? b1.cnt : 0;
@@ -2218,10 +2231,6 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
                 ti.seg = id;
                 ti.start = st;
                 ti.end = st + ln;
-                ti.ux = c == 0 ? G.ux : G.fx; ti.uy = c == 0 ? G.uy : G.fy;
-                ti.fx = c == 0 ? b0.x : b1.x; ti.fy = c == 0 ? b0.y : b1.y;
-                ti.vx = c == 0 ? G.fx : G.vx; ti.vy = c == 0 ? G.fy : G.vy;
-                ti.pad0 = ti.pad1 = 0;
                 for (int kk = ka; kk < kb; ++kk) {
                     ti.single = ti.end >= min((kk + 1) * kTile, c == 0 ? Nn0 : Nn1) ? 1 : 0;
                     ws.tinfo(q, c)[kk] = ti;
@@ -2246,8 +2255,6 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             ti.seg = id;
             ti.start = cg.start;
             ti.end = cg.start + cg.len;
-            ti.ux = cg.ux; ti.uy = cg.uy; ti.fx = cg.fx; ti.fy = cg.fy; ti.vx = cg.vx; ti.vy = cg.vy;
-            ti.pad0 = ti.pad1 = 0;
             for (int kk = ka + tid; kk < kb; kk += kSegBlock) {
                 ti.single = ti.end >= min((kk + 1) * kTile, c == 0 ? Nn0 : Nn1) ? 1 : 0;
                 ws.tinfo(q, c)[kk] = ti;
@@ -2458,8 +2465,10 @@ __global__ __launch_bounds__(kBlock) void k_extremes_final(Ws2 ws, HullArgs a) {
     phase_extremes_final(ws, a, reinterpret_cast<char *>(&sm));
 }
 
+// (the exact form fits in 128 registers: four waves per SIMD)
 template <int MODE, bool INIT>
-__global__ __launch_bounds__(kBlock) void k_round(Ws2 ws, HullArgs a, int32_t r) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 4 : 1)))
+void k_round(Ws2 ws, HullArgs a, int32_t r) {
     __shared__ FastSmem sm;
     if (ws.ctl->setup_error) return;
     phase_round_fast<MODE, INIT>(ws, a, r, reinterpret_cast<char *>(&sm));
