@@ -65,6 +65,33 @@ def summarize(args):
         lines.append("|---|---|---|---|")
         for name, (calls, tot) in sorted(stats.items(), key=lambda kv: -kv[1][1]):
             lines.append(f"| {name} | {calls} | {tot:.1f} | {tot / calls:.2f} |")
+    if args.stats_csv:
+        import csv
+        with open(args.stats_csv) as fh:
+            rows = list(csv.DictReader(fh))
+        lines.append("| kernel | calls | total us | average us | % | min us | max us |")
+        lines.append("|---|---|---|---|---|---|---|")
+        for r in rows:
+            lines.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
+                         f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} | "
+                         f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} |")
+    if args.counters:
+        # every counter of the run, summed per dispatch, for the kernels named
+        import sqlite3
+        db = sqlite3.connect(args.counters)
+        cur = db.cursor()
+        cur.execute("select dispatch_id, kernel_name, counter_name, sum(value) from counters_collection "
+                    "group by dispatch_id, counter_name order by dispatch_id")
+        names = args.kernel.split(",")
+        per = {}
+        for disp, kname, cname, val in cur.fetchall():
+            if any(_short(kname).startswith(k) for k in names):
+                per.setdefault((disp, _short(kname)), {})[cname] = val
+        ctrs = sorted({c for v in per.values() for c in v})
+        lines.append("| dispatch | kernel | " + " | ".join(ctrs) + " |")
+        lines.append("|---|---|" + "---|" * len(ctrs))
+        for (disp, kname), v in sorted(per.items()):
+            lines.append(f"| {disp} | {kname} | " + " | ".join(f"{v.get(c, 0):.4g}" for c in ctrs) + " |")
     out = {}
     if args.fetch and args.write:
         copy_kib = args.copy_mb * 1024.0
@@ -90,6 +117,26 @@ def summarize(args):
                "bytes_per_launch": round(fetch_b + write_b)}
         if args.kernel_sha:
             out["kernel_sha"] = args.kernel_sha
+        # per launch of the first kernel name (one per round), the kernels of
+        # that round added: KiB as read, in order
+        names = args.kernel.split(",")
+        per_round = {}
+        for ctr, path in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
+            seq = []
+            for n, v in _counter_rows(path, ctr):
+                sn = _short(n)
+                if sn.startswith(names[0]):
+                    seq.append(v)
+                elif any(sn.startswith(k) for k in names[1:]) and seq:
+                    seq[-1] += v
+            per_round[ctr] = seq
+        nr = min(len(per_round["FETCH_SIZE"]), len(per_round["WRITE_SIZE"]))
+        if nr:
+            lines.append("")
+            lines.append("| launch | FETCH_SIZE KiB | WRITE_SIZE KiB |")
+            lines.append("|---|---|---|")
+            for i in range(nr):
+                lines.append(f"| {i} | {per_round['FETCH_SIZE'][i]:.1f} | {per_round['WRITE_SIZE'][i]:.1f} |")
         lines.append("")
         lines.append(f"HBM traffic of {args.kernel} per launch (FETCH_SIZE x {scale['FETCH_SIZE']:.3f}, "
                      f"WRITE_SIZE x {scale['WRITE_SIZE']:.3f}, factors from a {args.copy_mb} MiB copy): "
@@ -113,6 +160,8 @@ def main():
         sp = argparse.ArgumentParser()
         sp.add_argument("cmd")
         sp.add_argument("--trace")
+        sp.add_argument("--stats-csv", help="rocprofv3 --stats kernel summary (run_kernel_stats.csv)")
+        sp.add_argument("--counters", help="a rocprofv3 --pmc results database: every counter per dispatch")
         sp.add_argument("--fetch")
         sp.add_argument("--write")
         sp.add_argument("--kernel", default="k_round",
