@@ -371,7 +371,14 @@ struct Topo {
         // B: accept in id order
         acc_.clear();
         int32_t *lk = lock.data();
+        constexpr int64_t kAhead = 8;  // candidates whose locks are fetched ahead
         for (int64_t i = 0; i < m; ++i) {
+            if (i + kAhead < m) {
+                const int64_t q = i + kAhead;
+                __builtin_prefetch(&lk[active[q]]);
+                const int32_t *Rq = region(q);
+                for (int32_t j = 0; j < std::min(rcnt_[q], 4); ++j) __builtin_prefetch(&lk[Rq[j]]);
+            }
             if (lk[active[i]] == stamp) continue;
             const int32_t *R = region(i);
             const int32_t k = rcnt_[i];
@@ -387,13 +394,16 @@ struct Topo {
         hthr_.resize(na);
         hoff_.resize(na);
         hcnt_.resize(na);
+        scnt_.resize(na);
         W.run(na, 32, [&](int64_t lo, int64_t hi, int t) {
             std::vector<Edge> &hb = loc_[t].hor;
             for (int64_t a = lo; a < hi; ++a) {
                 const int64_t i = acc_[a];
                 const int32_t *R = region(i);
                 const size_t o = hb.size();
+                int32_t ns = 0;
                 for (int32_t j = 0; j < rcnt_[i]; ++j) {
+                    ns += len[R[j]] > 0;
                     const Facet &f = F[R[j]];
                     for (int e = 0; e < 3; ++e) {
                         const int32_t g = f.nb[e];
@@ -403,16 +413,21 @@ struct Topo {
                 hthr_[a] = (int16_t)t;
                 hoff_[a] = (int64_t)o;
                 hcnt_[a] = (int32_t)(hb.size() - o);
+                scnt_[a] = ns;
             }
         });
         // ids of the cones, in acceptance order
         first = (int32_t)F.size();
         base_.resize(na);
-        int64_t total = 0;
+        sbase_.resize(na);
+        int64_t total = 0, stotal = 0;
         for (int64_t a = 0; a < na; ++a) {
             base_[a] = first + (int32_t)total;
             total += hcnt_[a];
+            sbase_[a] = stotal;
+            stotal += scnt_[a];
         }
+        srcs.resize((size_t)stotal);
         if (!grow((size_t)first + (size_t)total)) return kTopoNoMem;
         count = (int32_t)total;
         // C2: the cones
@@ -423,6 +438,13 @@ struct Topo {
                 const Edge *H = loc_[hthr_[a]].hor.data() + hoff_[a];
                 const int32_t k = hcnt_[a], b0 = base_[a];
                 const int32_t pid = apex[active[acc_[a]]];
+                {
+                    // the outside sets of the region, in walk order
+                    const int32_t *R = region(acc_[a]);
+                    int64_t q = sbase_[a];
+                    for (int32_t j = 0; j < rcnt_[acc_[a]]; ++j)
+                        if (len[R[j]] > 0) srcs[q++] = {start[R[j]], len[R[j]], b0 - first, k};
+                }
                 for (int32_t j = 0; j < k; ++j) {
                     const int32_t id = b0 + j;
                     init_facet(id, H[j].u, H[j].w, pid, stamp);
@@ -468,17 +490,14 @@ struct Topo {
                 }
             }
         });
-        // the outside sets of the removed facets, and the candidates left
-        srcs.clear();
-        for (int64_t a = 0; a < na; ++a) {
-            const int64_t i = acc_[a];
-            const int32_t *R = region(i);
-            for (int32_t j = 0; j < rcnt_[i]; ++j)
-                if (len[R[j]] > 0) srcs.push_back({start[R[j]], len[R[j]], base_[a] - first, hcnt_[a]});
-        }
+        // the candidates left
+        live_.resize(m);
+        W.run(m, 4096, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t i = lo; i < hi; ++i) live_[i] = gone[active[i]] == 0;
+        });
         size_t keep = 0;
         for (int64_t i = 0; i < m; ++i)
-            if (gone[active[i]] == 0) active[keep++] = active[i];
+            if (live_[i]) active[keep++] = active[i];
         active.resize(keep);
         return bad.load() == 0 ? kTopoOk : kTopoBroken;
     }
@@ -732,7 +751,9 @@ struct Topo {
     const int32_t *region(int64_t i) const { return loc_[rthr_[i]].reg.data() + roff_[i]; }
     std::vector<int16_t> rthr_, hthr_;
     std::vector<int64_t> roff_, hoff_;
-    std::vector<int32_t> rcnt_, rall_, hcnt_, base_;
+    std::vector<int32_t> rcnt_, rall_, hcnt_, scnt_, base_;
+    std::vector<int64_t> sbase_;
+    std::vector<uint8_t> live_;
     std::vector<int64_t> acc_;
 };
 
