@@ -94,6 +94,30 @@ def cpu_baseline(pts, budget_s: float = 12.0):
             "sample": f"{WORKLOAD} full ({n} points), {runs} runs in {el:.1f} s, single thread"}
 
 
+def tuned_graph_leg(call, key, want, steps, outs, out_names):
+    """Time a call with QH_FLAG_AUTOTUNE and QH_FLAG_GRAPH on a stream of its
+    own with fixed output buffers (the first call tunes and captures); check
+    the output against ``want``."""
+    import torch
+
+    from paper_1201_2936_amd import qh
+    ctx = qh.Context()
+    st = torch.cuda.Stream()
+    kw = dict(ctx=ctx, autotune=True, graph=True, stream=st.cuda_stream)
+    kw.update(zip(out_names, outs))
+    with torch.cuda.stream(st):
+        first = call(**kw)
+        st.synchronize()
+        sec, last = time_steps(lambda: call(**kw), steps, 2)
+        same = all(bool(torch.equal(a, b)) for a, b in zip(key(last), want))
+    s0, s1 = first[-1], last[-1]
+    ctx.close()
+    return {"ms_per_step": round(sec * 1e3, 4), "tuned_configs": int(s0["tuned_configs"]),
+            "grid_blocks": int(s1["grid_blocks"]), "multi_blocks": int(s1["multi_blocks"]),
+            "finish_segments": int(s1["finish_segments"]),
+            "graph_launches_per_call": int(s1["graph_launches"]), "same_output": same}
+
+
 def batched_leg(steps: int):
     """The batched form on 4,096 disks (sizes log-uniform in [256, 2^20],
     about 5.1e8 points) in one qh_hull2d_batched call, beside 4,096
@@ -119,6 +143,13 @@ def batched_leg(steps: int):
     sec_f, (idx_f, hoff_f, st_f) = time_steps(lambda: run(qh.QH_FP32_FILTER), steps, 1)
     sec_x, (idx_x, hoff_x, _) = time_steps(lambda: run(qh.QH_EXACT_INT64), max(2, steps // 2), 1)
     same = bool(torch.equal(idx_f, idx_x) and torch.equal(hoff_f, hoff_x))
+
+    # the launch configuration picked by the autotuner, the launches replayed
+    # from captured graphs (fixed output buffers, a stream of its own)
+    tuned = tuned_graph_leg(lambda **kw: qh.qh_hull2d_batched(pts, off, mode=qh.QH_FP32_FILTER, **kw),
+                            lambda o: (o[0], o[1]), (idx_f, hoff_f), steps,
+                            [torch.empty(max(N, 1), dtype=torch.int32, device="cuda"),
+                             torch.empty_like(hoff_f)], ["out", "hull_offsets"])
 
     # per-launch kernel timing of the round kernel (separate pass)
     agg = {"round_kernel_bytes": 0.0, "round_kernel_ms": 0.0, "round_launches": 0.0,
@@ -170,6 +201,7 @@ def batched_leg(steps: int):
         "sequential_single_calls": {"value": round(N / sec_seq / 1e6, 3), "unit": "Mpoints/s",
                                     "ms": round(sec_seq * 1e3, 1), "calls": k,
                                     "match_batched": bool(seq_ok)},
+        "autotuned_graph": tuned,
         "modes_identical": same,
         "parity_vs_oracle_sample": {"instances": len(sample), "ok": bool(par)},
         "rounds": int(st_f["rounds"]),
@@ -267,6 +299,9 @@ def main():
 
     sec, (idx_f, st_f) = time_steps(run_filter, args.steps, args.warmup)
     sec_x, (idx_x, st_x) = time_steps(run_exact, max(5, args.steps // 3), 2)
+    tuned = tuned_graph_leg(lambda **kw: qh.qh_hull2d(pts, mode=qh.QH_FP32_FILTER, **kw),
+                            lambda o: (o[0],), (idx_f,), args.steps,
+                            [torch.empty(max(n, 1), dtype=torch.int32, device=dev)], ["out"])
 
     # kernel timing: HIP events around every launch (a separate pass of the
     # same steps, so the events do not perturb the headline time)
@@ -313,6 +348,7 @@ def main():
                    "coords": "int32 uniform in [-2^20, 2^20]^2", "form": "fp32_filter"},
         "exact_int64": {"value": round(n / sec_x / 1e6, 3), "unit": "Mpoints/s",
                         "ms_per_step": round(sec_x * 1e3, 4), "dtype": "i64"},
+        "autotuned_graph": tuned,
         "hull_vertices": int(len(want)),
         "parity_vs_oracle": parity,
         "rounds": int(st_f["rounds"]),

@@ -59,7 +59,7 @@ enum {
 enum {
     QH_FLAG_TIMING = 1u,    /* time every kernel launch of the call with HIP
                                events (qh_stats) */
-    QH_FLAG_NO_FINISH = 2u  /* 2D: run every level of the recursion as a
+    QH_FLAG_NO_FINISH = 2u, /* 2D: run every level of the recursion as a
                                round of the round kernels.  By default, once
                                no segment holds more than QH_FINISH_CAP
                                points and there are at most two segments per
@@ -68,6 +68,26 @@ enum {
                                recursion in on-chip memory (the same levels
                                and the same rules as the rounds, so the same
                                output) */
+    QH_FLAG_GRAPH = 4u,     /* 2D: replay the call's launches from HIP graphs
+                               that the context captured on an earlier call
+                               with the same arguments, buffers and workspace
+                               (captured on first use: the set-up, extremes
+                               and first batch of rounds as one graph, every
+                               later batch of rounds as another).  Needs a
+                               non-null qh_opts.stream (QH_EINVAL otherwise);
+                               ignored with QH_FLAG_TIMING.  The graphs keep
+                               the buffer addresses: the caller may change
+                               the inputs' contents between calls, and a call
+                               with other buffers captures anew */
+    QH_FLAG_AUTOTUNE = 8u   /* 2D: pick the launch configuration (round-kernel
+                               blocks, multi-segment-kernel blocks, segments
+                               per workgroup for finishing) by timing every
+                               candidate on this call's input, the first time
+                               the context sees the call's size class (mode,
+                               point count and instance count rounded up to
+                               powers of two); later calls of that class reuse
+                               the choice.  Every configuration gives the same
+                               output */
 };
 
 /* points of a segment that one workgroup finishes (QH_FLAG_NO_FINISH) */
@@ -112,6 +132,13 @@ typedef struct qh_stats {
                                    canonical triangulation) */
     int64_t finish_round;       /* 2D: the round whose segments were finished
                                    by one workgroup each (-1: none) */
+    int64_t multi_blocks;       /* 2D: blocks of a multi-segment-kernel launch */
+    int64_t finish_segments;    /* 2D: most segments that a round may finish
+                                   (one workgroup each, in turn) */
+    int64_t graph_launches;     /* 2D, QH_FLAG_GRAPH: captured graphs replayed
+                                   by the call */
+    int64_t tuned_configs;      /* 2D, QH_FLAG_AUTOTUNE: configurations timed by
+                                   the call (0 once the size class is tuned) */
 } qh_stats;
 
 typedef struct qh_opts {

@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <new>
 #include <vector>
 
@@ -149,8 +150,15 @@ qh_status ctx_init(qh_ctx *c) {
     return QH_OK;
 }
 
+void drop_graphs(qh_ctx *c) {
+    for (QhGraph &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+    c->gkey.clear();
+}
+
 void ctx_free(qh_ctx *c) {
     if (!c) return;
+    drop_graphs(c);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->dmem) (void)hipFree(c->dmem);
     if (c->single_off) (void)hipFree(c->single_off);
@@ -167,6 +175,7 @@ void ctx_free(qh_ctx *c) {
 namespace {
 
 using qhi::ctx_free;
+using qhi::drop_graphs;
 using qhi::ctx_init;
 
 #define QH_TRY(expr)                                  \
@@ -210,16 +219,25 @@ struct Timing {
     }
 };
 
+// The bytes a cached graph depends on: every kernel argument and the stream.
+template <typename T>
+void key_add(std::vector<unsigned char> &key, const T &v) {
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(&v);
+    key.insert(key.end(), b, b + sizeof(T));
+}
+
 qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets, int32_t k,
                 int32_t *hull_idx, int64_t *hull_offsets, int64_t *h_total, int64_t *single_off,
-                const qh_opts *o) {
+                const qh_opts *o, const QhLaunch &cfg, int64_t tuned_configs) {
     hipStream_t st = o ? (hipStream_t)o->stream : nullptr;
     const int mode = o ? (int)o->mode : 0;
     const bool timing = o && (o->flags & QH_FLAG_TIMING);
+    const bool graph = o && (o->flags & QH_FLAG_GRAPH) && !timing;
     qh_stats *stats = o ? o->stats : nullptr;
     if (stats) memset(stats, 0, sizeof(*stats));
     if (h_total) *h_total = 0;
     if (mode != QH_EXACT_INT64 && mode != QH_FP32_FILTER) return QH_EINVAL;
+    int64_t graph_launches = 0;
 
     HullArgs args = {};
     args.x = pts;
@@ -231,8 +249,8 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
     args.k = k;
     args.vec_ok = (((uintptr_t)pts & 15u) == 0 && (n & 3) == 0) ? 1 : 0;
     args.fin_cap = (o && (o->flags & QH_FLAG_NO_FINISH)) ? 0 : kFinCap;
-    args.fin_segs = 2 * (2 * c->cus);  // two per block of the multi-segment kernel
-    const int grid = c->grid[mode];
+    args.fin_segs = cfg.fin_segs;
+    const int grid = cfg.grid;
     int64_t syncs = 0;
     int r = 0;
     Timing tm{c, timing, {}};
@@ -245,27 +263,76 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
         // still costs two claims on the shared counters
         const int grid_seg = std::max(1, std::min((2 * c->scap + kSegBlock - 1) / kSegBlock, c->cus / 2));
         tm.kind.clear();
-        if (single_off) QH_TRY(fill_single_offsets(single_off, n, st));
-        QH_TRY(tm.before(st, Timing::kSetup));
-        QH_TRY(launch_setup(ws, args, grid, st));
-        QH_TRY(tm.after(st));
-        QH_TRY(tm.before(st, Timing::kExtremes));
-        QH_TRY(launch_extremes(ws, args, grid, st));
-        QH_TRY(tm.after(st));
+        // the launches of a batch: with prefix, the set-up and extremes first
+        auto enqueue = [&](bool prefix, int r0, int len) -> hipError_t {
+            hipError_t e = hipSuccess;
+            auto ok = [&e](hipError_t x) { return (e = x) == hipSuccess; };
+            if (prefix) {
+                if (single_off && !ok(fill_single_offsets(single_off, n, st))) return e;
+                if (!ok(tm.before(st, Timing::kSetup)) || !ok(launch_setup(ws, args, grid, st)) ||
+                    !ok(tm.after(st)))
+                    return e;
+                if (!ok(tm.before(st, Timing::kExtremes)) || !ok(launch_extremes(ws, args, grid, st)) ||
+                    !ok(tm.after(st)))
+                    return e;
+            }
+            for (int rr = r0; rr < r0 + len; ++rr) {
+                if (!ok(tm.before(st, rr == 0 ? Timing::kSplit : Timing::kRound)) ||
+                    !ok(launch_round(ws, args, mode, rr, grid, cfg.grid_multi, st)) || !ok(tm.after(st)))
+                    return e;
+                if (!ok(tm.before(st, Timing::kSegments)) || !ok(launch_segments(ws, args, rr, grid_seg, st)) ||
+                    !ok(tm.after(st)))
+                    return e;
+            }
+            return e;
+        };
+        // the same batch from a graph the context captured with the same
+        // arguments (captured now if there is none)
+        auto run_batch = [&](bool prefix, int r0, int len) -> hipError_t {
+            if (!graph) return enqueue(prefix, r0, len);
+            for (const QhGraph &g : c->graphs)
+                if (g.prefix == (int)prefix && g.r0 == r0 && g.len == len) {
+                    ++graph_launches;
+                    return hipGraphLaunch(g.exec, st);
+                }
+            hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return e;
+            e = enqueue(prefix, r0, len);
+            hipGraph_t gr = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(st, &gr);
+            if (e == hipSuccess) e = e2;
+            hipGraphExec_t ex = nullptr;
+            if (e == hipSuccess) e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            if (gr) (void)hipGraphDestroy(gr);
+            if (e != hipSuccess) return e;
+            c->graphs.push_back({(int)prefix, r0, len, ex});
+            ++graph_launches;
+            return hipGraphLaunch(ex, st);
+        };
+        if (graph) {
+            std::vector<unsigned char> key;
+            key_add(key, args);
+            key_add(key, ws);
+            key_add(key, cfg);
+            key_add(key, mode);
+            key_add(key, grid_seg);
+            key_add(key, st);
+            key_add(key, single_off);
+            if (key != c->gkey) {
+                drop_graphs(c);
+                c->gkey = key;
+            }
+        }
         r = 0;
         // the first batch: as many rounds as the previous call of this context
         // needed (no launches left over when the inputs are alike), else the
         // first split and 4 rounds; then 8 rounds per batch
         int batch = c->hint_rounds > 0 ? c->hint_rounds : 5;
+        bool prefix = true;
         while (true) {
-            for (int j = 0; j < batch; ++j, ++r) {
-                QH_TRY(tm.before(st, r == 0 ? Timing::kSplit : Timing::kRound));
-                QH_TRY(launch_round(ws, args, mode, r, grid, c->cus * 2, st));
-                QH_TRY(tm.after(st));
-                QH_TRY(tm.before(st, Timing::kSegments));
-                QH_TRY(launch_segments(ws, args, r, grid_seg, st));
-                QH_TRY(tm.after(st));
-            }
+            QH_TRY(run_batch(prefix, r, batch));
+            prefix = false;
+            r += batch;
             QH_TRY(hipMemcpyAsync(c->ctl_host, ws.ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
             QH_TRY(hipStreamSynchronize(st));
             ++syncs;
@@ -330,8 +397,66 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
         stats->grid_blocks = grid;
         stats->host_syncs = syncs;
         stats->finish_round = h.fin_round;
+        stats->multi_blocks = cfg.grid_multi;
+        stats->finish_segments = args.fin_cap > 0 ? cfg.fin_segs : 0;
+        stats->graph_launches = graph_launches;
+        stats->tuned_configs = tuned_configs;
     }
     return QH_OK;
+}
+
+// The size class of a call: mode, and the point and instance counts rounded
+// up to powers of two.
+uint64_t size_class(int mode, int64_t n, int32_t k) {
+    uint64_t ln = 0, lk = 0;
+    while ((1ll << ln) < n) ++ln;
+    while ((1ll << lk) < k) ++lk;
+    return (uint64_t)mode | (ln << 8) | (lk << 16);
+}
+
+// A call with the context's launch configuration for its size class
+// (QH_FLAG_AUTOTUNE), else the default one: the resident blocks of the round
+// kernel, two blocks per CU for the multi-segment kernel and two segments
+// per block of it for finishing.
+qh_status run2d_tuned(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets, int32_t k,
+                      int32_t *hull_idx, int64_t *hull_offsets, int64_t *h_total,
+                      int64_t *single_off, const qh_opts *o) {
+    const int mode = o ? (int)o->mode : 0;
+    if (mode != QH_EXACT_INT64 && mode != QH_FP32_FILTER) return QH_EINVAL;
+    if (o && (o->flags & QH_FLAG_GRAPH) && !o->stream) return QH_EINVAL;
+    const QhLaunch dflt = {c->grid[mode], 2 * c->cus, 2 * (2 * c->cus)};
+    if (!o || !(o->flags & QH_FLAG_AUTOTUNE))
+        return run2d(c, pts, n, offsets, k, hull_idx, hull_offsets, h_total, single_off, o, dflt, 0);
+    const uint64_t key = size_class(mode, n, k);
+    for (const QhTuned &t : c->tuned)
+        if (t.key == key)
+            return run2d(c, pts, n, offsets, k, hull_idx, hull_offsets, h_total, single_off, o, t.cfg, 0);
+    // time every candidate (the better of two calls) and keep the fastest
+    qh_opts quiet = *o;
+    quiet.flags &= ~(uint32_t)(QH_FLAG_AUTOTUNE | QH_FLAG_TIMING | QH_FLAG_GRAPH);
+    quiet.stats = nullptr;
+    QhLaunch pick = dflt;
+    double best = 1e300;
+    int64_t tried = 0;
+    for (int gm = 1; gm <= 2; ++gm)
+        for (int mm = 2; mm <= 4; mm += 2)
+            for (int fp = 1; fp <= 4; fp *= 2) {
+                const QhLaunch cand = {c->grid[mode] * gm, mm * c->cus, fp * mm * c->cus};
+                for (int rep = 0; rep < 2; ++rep) {
+                    const auto t0 = std::chrono::steady_clock::now();
+                    qh_status s = run2d(c, pts, n, offsets, k, hull_idx, hull_offsets, h_total, single_off,
+                                        &quiet, cand, 0);
+                    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                    if (s != QH_OK) return s;
+                    if (t < best) {
+                        best = t;
+                        pick = cand;
+                    }
+                }
+                ++tried;
+            }
+    c->tuned.push_back({key, pick});
+    return run2d(c, pts, n, offsets, k, hull_idx, hull_offsets, h_total, single_off, o, pick, tried);
 }
 
 }  // namespace
@@ -392,13 +517,14 @@ qh_status qh_hull2d(const int32_t *pts, int64_t n, int32_t *hull_idx, int64_t *h
     if (h) *h = 0;
     if (!h || n < 0 || n > (int64_t)INT32_MAX - 65536) return QH_EINVAL;
     if (n > 0 && (!pts || !hull_idx)) return QH_EINVAL;
+    if (opts && (opts->flags & QH_FLAG_GRAPH) && !opts->stream) return QH_EINVAL;
     if (opts && opts->stats) memset(opts->stats, 0, sizeof(qh_stats));
     if (n == 0) return QH_OK;
     TempCtx t;
     qh_status s = get_ctx(opts, t);
     if (s != QH_OK) return s;
     int64_t ht = 0;
-    s = run2d(t.c, pts, n, t.c->single_off, 1, hull_idx, t.c->single_hoff, &ht, t.c->single_off, opts);
+    s = run2d_tuned(t.c, pts, n, t.c->single_off, 1, hull_idx, t.c->single_hoff, &ht, t.c->single_off, opts);
     if (s != QH_OK) return s;
     *h = ht;
     return QH_OK;
@@ -410,11 +536,12 @@ qh_status qh_hull2d_batched(const int32_t *pts, int64_t n_total, const int64_t *
     if (h_total) *h_total = 0;
     if (k < 1 || k > (1 << 24) || n_total < 0 || n_total > (int64_t)INT32_MAX - 65536) return QH_EINVAL;
     if (!offsets || !hull_offsets || (n_total > 0 && (!pts || !hull_idx))) return QH_EINVAL;
+    if (opts && (opts->flags & QH_FLAG_GRAPH) && !opts->stream) return QH_EINVAL;
     if (opts && opts->stats) memset(opts->stats, 0, sizeof(qh_stats));
     TempCtx t;
     qh_status s = get_ctx(opts, t);
     if (s != QH_OK) return s;
-    return run2d(t.c, pts, n_total, offsets, k, hull_idx, hull_offsets, h_total, nullptr, opts);
+    return run2d_tuned(t.c, pts, n_total, offsets, k, hull_idx, hull_offsets, h_total, nullptr, opts);
 }
 
 }  // extern "C"

@@ -13,6 +13,26 @@ namespace qh3 {
 struct Ctx3;
 }
 
+// launch configuration of a 2D call
+struct QhLaunch {
+    int grid;        // blocks of the round kernel
+    int grid_multi;  // blocks of the multi-segment kernel
+    int fin_segs;    // most segments a round may finish, one workgroup each
+};
+
+// a captured batch of launches (QH_FLAG_GRAPH)
+struct QhGraph {
+    int prefix;  // 1: set-up and extremes come first
+    int r0, len; // rounds r0 .. r0 + len - 1
+    hipGraphExec_t exec;
+};
+
+// a tuned size class (QH_FLAG_AUTOTUNE)
+struct QhTuned {
+    uint64_t key;
+    QhLaunch cfg;
+};
+
 struct qh_ctx {
     int device = 0;
     int cus = 256;
@@ -32,6 +52,9 @@ struct qh_ctx {
     int grid[2] = {0, 0};             // resident blocks of the round kernel, per mode
     int hint_rounds = 0;              // rounds the last 2D call needed (first batch size)
     qh3::Ctx3 *c3 = nullptr;          // 3D workspace, made on the first 3D call
+    std::vector<unsigned char> gkey;  // launch arguments of the cached graphs
+    std::vector<QhGraph> graphs;
+    std::vector<QhTuned> tuned;
 };
 
 namespace qhi {

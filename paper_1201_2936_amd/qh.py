@@ -24,6 +24,8 @@ QH_EXACT_INT64 = 0
 QH_FP32_FILTER = 1
 QH_FLAG_TIMING = 1
 QH_FLAG_NO_FINISH = 2
+QH_FLAG_GRAPH = 4
+QH_FLAG_AUTOTUNE = 8
 QH_FINISH_CAP = 1024
 
 EXPORTED = ["qh_ctx_create", "qh_ctx_destroy", "qh_status_str", "qh_version",
@@ -53,6 +55,10 @@ class QhStats(ctypes.Structure):
         ("host_ms", ctypes.c_double),
         ("host_output_ms", ctypes.c_double),
         ("finish_round", ctypes.c_int64),
+        ("multi_blocks", ctypes.c_int64),
+        ("finish_segments", ctypes.c_int64),
+        ("graph_launches", ctypes.c_int64),
+        ("tuned_configs", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -141,11 +147,12 @@ class Context:
             pass
 
 
-def _opts(ctx, mode, timing, stream, finish=True):
+def _opts(ctx, mode, timing, stream, finish=True, graph=False, autotune=False):
     import torch
     st = torch.cuda.current_stream().cuda_stream if stream is None else stream
     stats = QhStats()
-    flags = (QH_FLAG_TIMING if timing else 0) | (0 if finish else QH_FLAG_NO_FINISH)
+    flags = ((QH_FLAG_TIMING if timing else 0) | (0 if finish else QH_FLAG_NO_FINISH)
+             | (QH_FLAG_GRAPH if graph else 0) | (QH_FLAG_AUTOTUNE if autotune else 0))
     o = QhOpts(ctypes.c_void_p(st), mode, flags,
                ctx.ptr if ctx is not None else None, ctypes.pointer(stats))
     return o, stats
@@ -160,17 +167,31 @@ def _check_points(pts, dims):
     return pts.contiguous()
 
 
-def qh_hull2d(pts, mode: int = QH_EXACT_INT64, ctx: Context | None = None,
-              timing: bool = False, stream=None, finish: bool = True):
-    """Counter-clockwise hull vertex indices (int32 tensor on the device) of
-    int32[2, n] device points; returns (indices, stats dict)."""
+def _out_buffer(out, size, dtype, device, name):
     import torch
+    if out is None:
+        return torch.empty(size, dtype=dtype, device=device)
+    if (not isinstance(out, torch.Tensor) or out.dtype != dtype or out.device != device
+            or out.dim() != 1 or out.shape[0] < size or not out.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor of at least {size} "
+                        f"elements on {device}")
+    return out
+
+
+def qh_hull2d(pts, mode: int = QH_EXACT_INT64, ctx: Context | None = None,
+              timing: bool = False, stream=None, finish: bool = True, graph: bool = False,
+              autotune: bool = False, out=None):
+    """Counter-clockwise hull vertex indices (int32 tensor on the device) of
+    int32[2, n] device points; returns (indices, stats dict).  ``out`` is an
+    optional int32 output buffer of at least max(n, 1) elements (graph replay
+    needs the same buffers on every call)."""
     lib = load()
     pts = _check_points(pts, 2)
     n = pts.shape[1]
-    out = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
+    import torch
+    out = _out_buffer(out, max(n, 1), torch.int32, pts.device, "out")
     h = ctypes.c_int64(0)
-    o, stats = _opts(ctx, mode, timing, stream, finish)
+    o, stats = _opts(ctx, mode, timing, stream, finish, graph, autotune)
     st = lib.qh_hull2d(ctypes.c_void_p(pts.data_ptr()), n, ctypes.c_void_p(out.data_ptr()),
                        ctypes.byref(h), ctypes.byref(o))
     if st != QH_OK:
@@ -179,10 +200,14 @@ def qh_hull2d(pts, mode: int = QH_EXACT_INT64, ctx: Context | None = None,
 
 
 def qh_hull2d_batched(pts, offsets, mode: int = QH_EXACT_INT64, ctx: Context | None = None,
-                      timing: bool = False, stream=None, finish: bool = True):
+                      timing: bool = False, stream=None, finish: bool = True,
+                      graph: bool = False, autotune: bool = False, out=None,
+                      hull_offsets=None):
     """Hulls of the instances [offsets[i], offsets[i+1]) of int32[2, N] device
     points; offsets is an int64[k + 1] device tensor.  Returns (indices local
-    to each instance, int64[k + 1] device hull offsets, stats dict)."""
+    to each instance, int64[k + 1] device hull offsets, stats dict).  ``out``
+    (int32, at least max(N, 1)) and ``hull_offsets`` (int64, k + 1) are
+    optional output buffers."""
     import torch
     lib = load()
     pts = _check_points(pts, 2)
@@ -191,10 +216,10 @@ def qh_hull2d_batched(pts, offsets, mode: int = QH_EXACT_INT64, ctx: Context | N
     offsets = offsets.contiguous()
     k = offsets.shape[0] - 1
     n = pts.shape[1]
-    out = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
-    hoff = torch.empty(k + 1, dtype=torch.int64, device=pts.device)
+    out = _out_buffer(out, max(n, 1), torch.int32, pts.device, "out")
+    hoff = _out_buffer(hull_offsets, k + 1, torch.int64, pts.device, "hull_offsets")[: k + 1]
     ht = ctypes.c_int64(0)
-    o, stats = _opts(ctx, mode, timing, stream, finish)
+    o, stats = _opts(ctx, mode, timing, stream, finish, graph, autotune)
     st = lib.qh_hull2d_batched(ctypes.c_void_p(pts.data_ptr()), n,
                                ctypes.c_void_p(offsets.data_ptr()), k,
                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(hoff.data_ptr()),

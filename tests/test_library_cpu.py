@@ -72,3 +72,48 @@ def test_no_oracle_import_in_product():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
                 assert "qh_oracle" not in text and "qho_" not in text, fn
+
+
+def test_graph_flag_needs_a_stream():
+    lib = qh.load()
+    h = ctypes.c_int64(9)
+    dummy = ctypes.c_void_p(16)  # never dereferenced: the check comes first
+    o = qh.QhOpts(None, qh.QH_EXACT_INT64, qh.QH_FLAG_GRAPH, None, None)
+    assert lib.qh_hull2d(dummy, 5, dummy, ctypes.byref(h), ctypes.byref(o)) == qh.QH_EINVAL
+    assert h.value == 0
+    assert lib.qh_hull2d_batched(dummy, 5, dummy, 1, dummy, dummy, ctypes.byref(h),
+                                 ctypes.byref(o)) == qh.QH_EINVAL
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of qh_stats and qh_opts, and the flag values, agree
+    with include/qh.h as a C compiler lays them out."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    stats = [name for name, _ in qh.QhStats._fields_]
+    opts = [name for name, _ in qh.QhOpts._fields_]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "qh.h"', "int main(void) {",
+             'printf("stats %zu\\n", sizeof(qh_stats));', 'printf("opts %zu\\n", sizeof(qh_opts));']
+    lines += [f'printf("s.{f} %zu\\n", offsetof(qh_stats, {f}));' for f in stats]
+    lines += [f'printf("o.{f} %zu\\n", offsetof(qh_opts, {f}));' for f in opts]
+    flags = ["QH_FLAG_TIMING", "QH_FLAG_NO_FINISH", "QH_FLAG_GRAPH", "QH_FLAG_AUTOTUNE",
+             "QH_EXACT_INT64", "QH_FP32_FILTER", "QH_FINISH_CAP"]
+    lines += [f'printf("c.{f} %d\\n", (int){f});' for f in flags]
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.splitlines())
+    assert int(got["stats"]) == ctypes.sizeof(qh.QhStats)
+    assert int(got["opts"]) == ctypes.sizeof(qh.QhOpts)
+    for f in stats:
+        assert int(got["s." + f]) == getattr(qh.QhStats, f).offset, f
+    for f in opts:
+        assert int(got["o." + f]) == getattr(qh.QhOpts, f).offset, f
+    for f in flags:
+        assert int(got["c." + f]) == getattr(qh, f), f
