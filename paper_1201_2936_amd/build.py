@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqh.so")
 SOURCES = ["qh2d_kernels.hip", "qh_api.hip", "qh3d_kernels.hip", "qh3d_host.hip",
            "qh_flag_permute.hip"]
-HEADERS = ["qh_device.h", "qh2d.h", "qh_ctx.h", "qh3d.h"]
+HEADERS = ["qh_device.h", "qh2d.h", "qh_ctx.h", "qh3d.h", "qh3d_topo.h"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
