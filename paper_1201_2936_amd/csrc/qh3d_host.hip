@@ -24,6 +24,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <memory>
 #include <new>
@@ -274,28 +275,60 @@ qh_status Run::classify(const std::vector<SrcRec> &srcs_in, int from_input, int3
     ++syncs;
     pts_in += total;
 
-    // ranges of the new outside sets, after the live data
+    // ranges of the new outside sets, after the live data, and the list of
+    // new facets with points (prefix sums over chunks, on the host threads)
     int64_t *hr = reinterpret_cast<int64_t *>(w->up.as<char>() + o_rng);
-    std::vector<SegRec> segs;
-    int32_t seg_tiles = 0;
-    int64_t written = 0;
-    for (int32_t j = 0; j < nf; ++j) {
-        const int32_t id = first + j;
-        Tp.len[id] = (int32_t)hc[j];
-        Tp.start[id] = top + written;
-        hr[j] = top + written;
-        written += hc[j];
-        if (hc[j]) {
-            SegRec sg;
-            sg.start = Tp.start[id];
-            sg.len = (int32_t)hc[j];
-            sg.facet = j;
-            sg.tile0 = seg_tiles;
-            sg.pad = 0;
-            seg_tiles += (sg.len + kTile - 1) / kTile;
-            segs.push_back(sg);
+    constexpr int32_t kChunk = 8192;
+    const int32_t nchunk = (nf + kChunk - 1) / kChunk;
+    std::vector<int64_t> cpts((size_t)nchunk + 1, 0);
+    std::vector<int32_t> cseg((size_t)nchunk + 1, 0), ctil((size_t)nchunk + 1, 0);
+    W->run(nchunk, 1, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t c = lo; c < hi; ++c) {
+            int64_t np = 0;
+            int32_t ng = 0, nt = 0;
+            for (int32_t j = (int32_t)c * kChunk; j < std::min<int32_t>(nf, (int32_t)(c + 1) * kChunk); ++j) {
+                np += hc[j];
+                if (hc[j]) {
+                    ++ng;
+                    nt += (int32_t)((hc[j] + kTile - 1) / kTile);
+                }
+            }
+            cpts[c + 1] = np;
+            cseg[c + 1] = ng;
+            ctil[c + 1] = nt;
         }
+    });
+    for (int32_t c = 0; c < nchunk; ++c) {
+        cpts[c + 1] += cpts[c];
+        cseg[c + 1] += cseg[c];
+        ctil[c + 1] += ctil[c];
     }
+    const int64_t written = cpts[nchunk];
+    const int32_t seg_tiles = ctil[nchunk];
+    std::vector<SegRec> segs((size_t)cseg[nchunk]);
+    W->run(nchunk, 1, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t c = lo; c < hi; ++c) {
+            int64_t at = top + cpts[c];
+            int32_t q = cseg[c], tl = ctil[c];
+            for (int32_t j = (int32_t)c * kChunk; j < std::min<int32_t>(nf, (int32_t)(c + 1) * kChunk); ++j) {
+                const int32_t id = first + j;
+                Tp.len[id] = (int32_t)hc[j];
+                Tp.start[id] = at;
+                hr[j] = at;
+                if (hc[j]) {
+                    SegRec sg;
+                    sg.start = at;
+                    sg.len = (int32_t)hc[j];
+                    sg.facet = j;
+                    sg.tile0 = tl;
+                    sg.pad = 0;
+                    tl += (sg.len + kTile - 1) / kTile;
+                    segs[q++] = sg;
+                }
+                at += hc[j];
+            }
+        }
+    });
     if (top + written > w->pool_cap) return QH_ECAPACITY;  // cannot happen after compaction
     QH3_TRY(hipMemcpyAsync(w->range.p, hr, sizeof(int64_t) * (size_t)nf, hipMemcpyHostToDevice, st));
     QH3_TRY(ev_begin(0));
@@ -327,18 +360,22 @@ qh_status Run::classify(const std::vector<SrcRec> &srcs_in, int from_input, int3
         QH3_TRY(hipStreamSynchronize(st));
         ++syncs;
         apex_pts += written;
-        for (int32_t s = 0; s < ns; ++s) {
-            const ApexKey &k = hk[s];
-            // an outside set holds only points above its facet
-            if (k.idx < 0 || k.idx >= n || k.d <= 0) return QH_EDEVICE;
-            Tp.apex[first + segs[s].facet] = k.idx;
-            Tp.set_point(k.idx, k.x, k.y, k.z);
-        }
+        std::atomic<int> bad{0};
+        W->run(ns, 4096, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t s = lo; s < hi; ++s) {
+                const ApexKey &k = hk[s];
+                // an outside set holds only points above its facet
+                if (k.idx < 0 || k.idx >= n || k.d <= 0)
+                    bad.store(1);
+                else
+                    Tp.set_apex(first + segs[s].facet, k.idx, k.x, k.y, k.z);
+            }
+        });
+        if (bad.load()) return QH_EDEVICE;
     } else {
         QH3_TRY(hipStreamSynchronize(st));
     }
-    for (int32_t j = 0; j < nf; ++j)
-        if (Tp.len[first + j] > 0) Tp.active.push_back(first + j);
+    for (const SegRec &sg : segs) Tp.active.push_back(first + sg.facet);
     return QH_OK;
 }
 

@@ -221,6 +221,10 @@ static_assert(sizeof(Facet) == 64, "a facet is one cache line");
 
 enum { kTopoOk = 0, kTopoBroken = 1, kTopoNoMem = 2 };
 
+struct P3 {
+    int32_t x, y, z;
+};
+
 // The outside set of a removed facet and the cone its points go to.
 struct TopoSrc {
     int64_t start;   // pool position
@@ -251,6 +255,7 @@ struct Topo {
     PodVec<int64_t> start;        // per facet: its outside set's pool range
     PodVec<int32_t> len;
     PodVec<int32_t> apex;         // per facet: its farthest outside point, -1 = none
+    PodVec<P3> apc;               // ... and that point's coordinates
     std::vector<int32_t> vc;      // x, y, z of every point that is a corner or an apex
     std::vector<int32_t> active;  // facets with outside points, ascending id
 
@@ -270,8 +275,16 @@ struct Topo {
         start.clear();
         len.clear();
         apex.clear();
+        apc.clear();
         active.clear();
         if (vc.size() < 3 * (size_t)npts) vc.resize(3 * (size_t)npts);
+    }
+
+    // the apex of facet f (coordinates kept with the facet; they become a
+    // corner's when the apex is inserted)
+    void set_apex(int32_t f, int32_t id, int32_t x, int32_t y, int32_t z) {
+        apex[f] = id;
+        apc[f] = {x, y, z};
     }
 
     // the plane of facet f from its corners' coordinates
@@ -344,7 +357,7 @@ struct Topo {
             IdSet &seen = loc_[t].seen;
             for (int64_t i = lo; i < hi; ++i) {
                 const int32_t c = active[i];
-                const int32_t *p = coords(apex[c]);
+                const int32_t *p = &apc[c].x;
                 const size_t o = buf.size();
                 seen.clear();
                 seen.insert(c);
@@ -438,6 +451,10 @@ struct Topo {
                 const Edge *H = loc_[hthr_[a]].hor.data() + hoff_[a];
                 const int32_t k = hcnt_[a], b0 = base_[a];
                 const int32_t pid = apex[active[acc_[a]]];
+                {
+                    const P3 &q = apc[active[acc_[a]]];
+                    set_point(pid, q.x, q.y, q.z);
+                }
                 {
                     // the outside sets of the region, in walk order
                     const int32_t *R = region(acc_[a]);
@@ -735,7 +752,7 @@ struct Topo {
 
     bool grow(size_t nf) {
         return F.resize(nf) && lock.resize(nf) && gone.resize(nf) && start.resize(nf) &&
-               len.resize(nf) && apex.resize(nf);
+               len.resize(nf) && apex.resize(nf) && apc.resize(nf);
     }
 
     // per-thread scratch, one cache line apart (kept for its capacity)
