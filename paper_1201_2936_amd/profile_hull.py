@@ -175,7 +175,8 @@ def main():
         summarize(sp.parse_args())
         return
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="square_16m")
+    ap.add_argument("--workload", default="square_16m",
+                    help="a single-hull workload, or batched_disks (one batched call per step)")
     ap.add_argument("--mode", type=int, default=1, help="0 exact int64, 1 FP32 filter")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--copy-mb", type=int, default=0, help="also run one device copy of this size")
@@ -187,7 +188,12 @@ def main():
     from paper_1201_2936_amd import qh
 
     qh.load()
-    pts = torch.from_numpy(workloads.WORKLOADS[args.workload]()).cuda()
+    if args.workload == "batched_disks":
+        pts_np, off_np = workloads.batched_disks()
+        off = torch.from_numpy(off_np).cuda()
+    else:
+        pts_np, off = workloads.WORKLOADS[args.workload](), None
+    pts = torch.from_numpy(pts_np).cuda()
     ctx = qh.Context()
     if args.copy_mb:
         n = args.copy_mb * (1 << 20) // 4
@@ -198,7 +204,10 @@ def main():
         torch.cuda.synchronize()
         print(f"copy of {args.copy_mb} MiB done", flush=True)
     for i in range(args.steps):
-        idx, st = qh.qh_hull2d(pts, mode=args.mode, ctx=ctx)
+        if off is None:
+            idx, st = qh.qh_hull2d(pts, mode=args.mode, ctx=ctx)
+        else:
+            idx, _, st = qh.qh_hull2d_batched(pts, off, mode=args.mode, ctx=ctx)
         torch.cuda.synchronize()
         print(f"hull {i}: h={idx.numel()} rounds={st['rounds']} "
               f"round_kernel_bytes={st['round_kernel_bytes']} launches={st['round_launches']}",
