@@ -107,5 +107,7 @@ hipError_t launch_segments(const Ws2 &ws, const HullArgs &a, int32_t r, int grid
 hipError_t launch_output(const Ws2 &ws, const HullArgs &a, int32_t H, hipStream_t st);
 // resident blocks of the round kernel on the whole device
 hipError_t round_grid(int mode, int cus, int *grid);
+// resident blocks of the extremes kernel
+hipError_t extremes_grid(int cus, int *grid);
 
 }  // namespace qh

@@ -79,6 +79,13 @@ __device__ __forceinline__ uint64_t coord_key(int32_t x, int32_t y) {
     return ((uint64_t)((uint32_t)x ^ 0x80000000u) << 32) | (uint64_t)((uint32_t)y ^ 0x80000000u);
 }
 
+// A load through the scalar data cache (uniform address; the data was
+// written by an earlier kernel and is not written by this one).
+template <typename T>
+__device__ __forceinline__ T scalar_load(const T *ptr) {
+    return *(const __attribute__((address_space(4))) T *)(ptr);
+}
+
 // largest i in [0, m) with s[i] <= v  (s[0] <= v, s nondecreasing)
 __device__ __forceinline__ int slot_of(const int32_t *s, int m, int32_t v) {
     int a = 0, b = m;
@@ -519,7 +526,6 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
     const int S = ctl->rs[0].s[0];
     const int ntiles = (n + kTile - 1) / kTile;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
-    bool bad = false;
     // Every block takes a contiguous range of tiles.  Consecutive tiles of
     // one instance form a run whose minimum and maximum stay in registers;
     // the block reduces once per run and writes the run's record at its first
@@ -528,9 +534,26 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
     const int T = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
     if (blockIdx.x == 0 && tid == 0) ctl->tper_ext = T;
     const int tb = blockIdx.x * T, te = min(tb + T, ntiles);
-    Best rmn = best_none(), rmx = best_none();
+    // a run's extremes per lane: the smallest and largest coordinate key and
+    // the first index that has it (each lane sees its points in index order)
+    uint64_t kmn = ~0ull, kmx = 0ull;
+    int32_t imn = -1, imx = -1;
+    uint32_t span = 0;  // largest |coordinate| + bound seen, for the range check
     int cur = -1, run0 = 0, cst = 0, cen = 0;
+    auto as_best = [](uint64_t key1, uint64_t ck, int32_t idx) {
+        Best b = best_none();
+        if (idx >= 0) {
+            b.key1 = key1;
+            b.key2 = (uint32_t)idx;
+            b.x = (int32_t)((uint32_t)(ck >> 32) ^ 0x80000000u);
+            b.y = (int32_t)((uint32_t)ck ^ 0x80000000u);
+            b.idx = idx;
+            b.cnt = 0;
+        }
+        return b;
+    };
     auto flush = [&](int tend) {
+        Best rmn = as_best(~kmn, kmn, imn), rmx = as_best(kmx, kmx, imx);
         wave_rec63(rmn);
         wave_rec63(rmx);
         if (lane == kWave - 1) { sm->red[wv][0] = rmn; sm->red[wv][1] = rmx; }
@@ -549,13 +572,15 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
             }
         }
         __syncthreads();
-        rmn = best_none();
-        rmx = best_none();
+        kmn = ~0ull;
+        kmx = 0ull;
+        imn = -1;
+        imx = -1;
     };
-    for (int tile = tb; tile < te; ++tile) {
+    // the points of a tile (4-point vectors where the input allows) and its record
+    auto load_tile = [&](int tile, int32_t (&X)[kItems], int32_t (&Y)[kItems], TileInfo &ti) {
         const int lo = tile * kTile;
         const int hi = min(lo + kTile, n);
-        int32_t X[kItems], Y[kItems];
 #pragma unroll
         for (int qq = 0; qq < kQ; ++qq) {
             const int v0 = lo + qq * kBlock * 4 + tid * 4;
@@ -573,13 +598,37 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
                 }
             }
         }
-        const TileInfo ti = ws.tinfo(0, 0)[tile];
+        // the record through the scalar cache: a vector load here would make
+        // the wait for it also wait for the points just requested
+        const int32_t *rec = reinterpret_cast<const int32_t *>(ws.tinfo(0, 0) + tile);
+        ti.seg = scalar_load(rec + 0);
+        ti.single = scalar_load(rec + 1);
+        ti.start = scalar_load(rec + 2);
+        ti.end = scalar_load(rec + 3);
+    };
+    // software pipelined: the next tile's points are requested before this
+    // tile is reduced
+    int32_t Xn[kItems], Yn[kItems];
+    TileInfo tin = {};
+    if (tb < te) load_tile(tb, Xn, Yn, tin);
+    for (int tile = tb; tile < te; ++tile) {
+        const int lo = tile * kTile;
+        const int hi = min(lo + kTile, n);
+        int32_t X[kItems], Y[kItems];
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
-            const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-            if (v < hi)
-                bad |= (X[i] > kCoordMax2D) | (X[i] < -kCoordMax2D) | (Y[i] > kCoordMax2D) |
-                       (Y[i] < -kCoordMax2D);
+            X[i] = Xn[i];
+            Y[i] = Yn[i];
+        }
+        const TileInfo ti = tin;
+        if (tile + 1 < te) load_tile(tile + 1, Xn, Yn, tin);
+        const bool full = hi - lo == kTile;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            // |c| <= bound  <=>  c + bound in [0, 2 bound], modulo 2^32 (points
+            // past the end load as 0)
+            span = max(span, (uint32_t)X[i] + (uint32_t)kCoordMax2D);
+            span = max(span, (uint32_t)Y[i] + (uint32_t)kCoordMax2D);
         }
         if (ti.single) {
             if (ti.seg != cur) {
@@ -592,13 +641,10 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
                 const int v = lo + (i >> 2) * kBlock * 4 + tid * 4 + (i & 3);
-                if (v >= hi) continue;
+                if (!full && v >= hi) continue;
                 const uint64_t ck = coord_key(X[i], Y[i]);
-                Best c;
-                c.key1 = ~ck; c.key2 = (uint32_t)v; c.x = X[i]; c.y = Y[i]; c.idx = v; c.cnt = 0;
-                best_merge(rmn, c);
-                c.key1 = ck;
-                best_merge(rmx, c);
+                if (ck < kmn) { kmn = ck; imn = v; }
+                if (ck > kmx) { kmx = ck; imx = v; }
             }
             continue;
         }
@@ -686,6 +732,7 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
         }
     }
     if (cur >= 0) flush(te);
+    const bool bad = span > 2u * (uint32_t)kCoordMax2D;
     if (__syncthreads_or(bad) && threadIdx.x == 0) {
         atomicOr(&ctl->error, kErrRange);
         atomicOr(&ctl->setup_error, kErrRange);
@@ -929,12 +976,6 @@ __device__ __forceinline__ bool fin_mode(const Control *ctl, int p, const HullAr
     return a.fin_cap > 0 && S > 0 && S <= a.fin_segs && ctl->maxseg[p] <= a.fin_cap;
 }
 
-// A load through the scalar data cache (uniform address; the data was
-// written by an earlier kernel and is not written by this one).
-template <typename T>
-__device__ __forceinline__ T scalar_load(const T *ptr) {
-    return *(const __attribute__((address_space(4))) T *)(ptr);
-}
 
 // a tile's record with its segment's geometry (u, f, v) when one segment
 // covers it
@@ -2558,6 +2599,15 @@ __global__ void k_fill_offsets(int64_t *off, int64_t n) {
 hipError_t fill_single_offsets(int64_t *off, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_offsets, dim3(1), dim3(64), 0, st, off, n);
     return hipGetLastError();
+}
+
+hipError_t extremes_grid(int cus, int *grid) {
+    int per = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(&k_extremes),
+                                                                kBlock, 0);
+    if (e != hipSuccess) return e;
+    *grid = std::max(1, per) * cus;
+    return hipSuccess;
 }
 
 hipError_t round_grid(int mode, int cus, int *grid) {

@@ -140,6 +140,7 @@ qh_status ctx_init(qh_ctx *c) {
         c->cus = cus;
     for (int m = 0; m < 2; ++m)
         if (round_grid(m, c->cus, &c->grid[m]) != hipSuccess || c->grid[m] <= 0) return QH_EDEVICE;
+    if (extremes_grid(c->cus, &c->grid_ext) != hipSuccess || c->grid_ext <= 0) return QH_EDEVICE;
     if (hipHostMalloc((void **)&c->ctl_host, sizeof(Control), hipHostMallocDefault) != hipSuccess)
         return QH_ENOMEM;
     if (hipHostMalloc((void **)&c->h_host, sizeof(int64_t) * 2, hipHostMallocDefault) != hipSuccess)
@@ -272,7 +273,7 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
                 if (!ok(tm.before(st, Timing::kSetup)) || !ok(launch_setup(ws, args, grid, st)) ||
                     !ok(tm.after(st)))
                     return e;
-                if (!ok(tm.before(st, Timing::kExtremes)) || !ok(launch_extremes(ws, args, grid, st)) ||
+                if (!ok(tm.before(st, Timing::kExtremes)) || !ok(launch_extremes(ws, args, c->grid_ext, st)) ||
                     !ok(tm.after(st)))
                     return e;
             }
