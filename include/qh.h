@@ -139,6 +139,8 @@ typedef struct qh_stats {
                                    by the call */
     int64_t tuned_configs;      /* 2D, QH_FLAG_AUTOTUNE: configurations timed by
                                    the call (0 once the size class is tuned) */
+    int64_t degenerate_instances; /* qh_hull3d_batched: instances without a hull
+                                   (fewer than four affinely independent points) */
 } qh_stats;
 
 typedef struct qh_opts {
@@ -222,6 +224,37 @@ qh_status qh_hull2d_batched(const int32_t *pts, int64_t n_total, const int64_t *
  */
 qh_status qh_hull3d(const int32_t *pts, int64_t n, int32_t *facets, int64_t *nfacets,
                     int32_t *verts, int64_t *nverts, const qh_opts *opts);
+
+/*
+ * 3D convex hulls of k independent point sets in one call: the batched form
+ * of qh_hull3d (the segments of the method, Section 3, are the facets of all
+ * instances together).  Instance i is the points [offsets[i], offsets[i+1])
+ * of pts; each round serves the facets of every instance at once, so the
+ * rounds and host synchronisations of a call do not grow with k.
+ *
+ *   pts            device int32[3*N], N = n_total: x[0..N), y[0..N), z[0..N);
+ *                  |coordinate| <= 2^19 (else QH_ERANGE)
+ *   n_total        N, 0 <= N <= 2^30 - 2^12
+ *   offsets        device int64[k+1]: offsets[0] = 0, nondecreasing,
+ *                  offsets[k] = N (else QH_EINVAL; read back to the host)
+ *   k              instances, 1 <= k <= 2^20
+ *   facets         device int32[6*N] (room for 3 (2 n_i - 4) per instance):
+ *                  the triples of instance i at
+ *                  [3 facet_offsets[i], 3 facet_offsets[i+1]), indices local
+ *                  to the instance, in qh_hull3d's canonical order
+ *   facet_offsets  device int64[k+1]: triangle offsets of the instances
+ *   verts          device int32[N]: the vertices of instance i (local,
+ *                  ascending) at [vert_offsets[i], vert_offsets[i+1])
+ *   vert_offsets   device int64[k+1]
+ *
+ * An instance with fewer than four affinely independent points has no
+ * facets and no vertices (qh_stats.degenerate_instances counts them; its
+ * coordinates are range-checked only when it has four points or more); the
+ * call still returns QH_OK.  Results equal those of k qh_hull3d calls.
+ */
+qh_status qh_hull3d_batched(const int32_t *pts, int64_t n_total, const int64_t *offsets, int32_t k,
+                            int32_t *facets, int64_t *facet_offsets, int32_t *verts,
+                            int64_t *vert_offsets, const qh_opts *opts);
 
 /*
  * The k-state segmented stable partition on its own (flagPermute, Section

@@ -26,6 +26,8 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <initializer_list>
+#include <utility>
 #include <memory>
 #include <new>
 #include <vector>
@@ -213,7 +215,6 @@ struct Run {
 
     qh_status classify(const std::vector<SrcRec> &srcs, int from_input, int32_t first, int32_t nf);
     qh_status compact(const std::vector<SrcRec> &srcs_in, std::vector<SrcRec> &srcs_out);
-    qh_status output(int32_t *facets, int64_t *nfacets, int32_t *verts, int64_t *nverts);
 };
 
 // Classify the points of srcs against the new facets [first, first + nf)
@@ -427,27 +428,34 @@ qh_status Run::compact(const std::vector<SrcRec> &srcs_in, std::vector<SrcRec> &
     return QH_OK;
 }
 
-// Hull vertices and the canonical triangulation, to the caller's buffers.
-qh_status Run::output(int32_t *facets, int64_t *nfacets, int32_t *verts, int64_t *nverts) {
-    std::vector<int32_t> tri, vlist;
-    if (!T->output(*W, tri, vlist)) return QH_EDEVICE;
-    const size_t nt = tri.size() / 3;
-    QH3_TRY(w->up.want(sizeof(int32_t) * (3 * nt + vlist.size()) + 512));
-    int32_t *ht = w->up.as<int32_t>();
-    memcpy(ht, tri.data(), sizeof(int32_t) * 3 * nt);
-    int32_t *hv = ht + 3 * nt;
-    std::copy(vlist.begin(), vlist.end(), hv);
-    QH3_TRY(hipMemcpyAsync(facets, ht, sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, st));
-    QH3_TRY(hipMemcpyAsync(verts, hv, sizeof(int32_t) * vlist.size(), hipMemcpyHostToDevice, st));
+// Host data to device buffers through the pinned staging buffer (pieces of
+// `bytes` each, copied in order), then a wait.
+qh_status put_all(Ctx3 *w, hipStream_t st, std::initializer_list<std::pair<void *, std::pair<const void *, size_t>>> parts) {
+    size_t total = 0;
+    for (const auto &pt : parts) total += (pt.second.second + 255) & ~(size_t)255;
+    QH3_TRY(w->up.want(total + 256));
+    char *h = w->up.as<char>();
+    size_t o = 0;
+    for (const auto &pt : parts) {
+        const size_t b = pt.second.second;
+        if (b) {
+            memcpy(h + o, pt.second.first, b);
+            QH3_TRY(hipMemcpyAsync(pt.first, h + o, b, hipMemcpyHostToDevice, st));
+        }
+        o += (b + 255) & ~(size_t)255;
+    }
     QH3_TRY(hipStreamSynchronize(st));
-    ++syncs;
-    *nfacets = (int64_t)nt;
-    *nverts = (int64_t)vlist.size();
     return QH_OK;
 }
 
-qh_status run3d(qh_ctx *c, const int32_t *pts, int64_t n, int32_t *facets, int64_t *nfacets,
-                int32_t *verts, int64_t *nverts, const qh_opts *o) {
+// The hulls of the instances [off[i], off[i+1]) of the n points (one
+// instance for qh_hull3d; every round serves the facets of all of them):
+// the sorted index triples and the ascending vertices, in point ids of the
+// whole array; degen[i] = 1 for an instance with fewer than four affinely
+// independent points (it has no hull).
+qh_status run3d(qh_ctx *c, const int32_t *pts, int64_t n, const std::vector<int64_t> &off,
+                std::vector<int32_t> &tri, std::vector<int32_t> &vlist, std::vector<uint8_t> &degen,
+                const qh_opts *o) {
     using clk = std::chrono::steady_clock;
     if (!c->c3) {
         c->c3 = new (std::nothrow) Ctx3();
@@ -476,25 +484,31 @@ qh_status run3d(qh_ctx *c, const int32_t *pts, int64_t n, int32_t *facets, int64
         QH3_TRY(w->pool[1].want(sizeof(int32_t) * 4 * (size_t)cap));
         w->pool_cap = cap;
     }
-    const int grid = std::max(1, std::min<int>(c->cus * 4, (int)((n + kBlock - 1) / kBlock)));
-    QH3_TRY(w->init.want(init_scratch_bytes(grid) + sizeof(InitRes) + 512));
+    const int32_t k = (int32_t)off.size() - 1;
+    auto grid_for = [&](int64_t m) { return std::max(1, std::min<int>(c->cus * 4, (int)((m + kBlock - 1) / kBlock))); };
+    int gmax = 1;
+    for (int32_t i = 0; i < k; ++i) gmax = std::max(gmax, grid_for(off[i + 1] - off[i]));
+    const size_t res_at = (init_scratch_bytes(gmax) + 255) & ~(size_t)255;
+    QH3_TRY(w->init.want(res_at + sizeof(InitRes) * (size_t)k + 512));
     QH3_TRY(w->filt.want(64));
     QH3_TRY(hipMemsetAsync(w->filt.p, 0, 16, st));
-    InitRes *dres = reinterpret_cast<InitRes *>(w->init.as<char>() + ((init_scratch_bytes(grid) + 255) & ~(size_t)255));
+    InitRes *dres = reinterpret_cast<InitRes *>(w->init.as<char>() + res_at);
+    // the first simplex of every instance (the scratch is reused in turn)
     QH3_TRY(R.ev_begin(3));
-    QH3_TRY(launch_init(R.x, R.y, R.z, (int32_t)n, w->init.p, dres, grid, st));
+    for (int32_t i = 0; i < k; ++i) {
+        const int64_t ni = off[i + 1] - off[i];
+        if (ni < 4) continue;
+        QH3_TRY(launch_init(R.x + off[i], R.y + off[i], R.z + off[i], (int32_t)ni, w->init.p, dres + i,
+                            grid_for(ni), st));
+        R.launches += 7;
+    }
     QH3_TRY(R.ev_end());
-    R.launches += 7;
-    QH3_TRY(w->down.want(sizeof(InitRes) + 256));
+    QH3_TRY(w->down.want(sizeof(InitRes) * (size_t)k + 256));
     InitRes *hres = w->down.as<InitRes>();
-    QH3_TRY(hipMemcpyAsync(hres, dres, sizeof(InitRes), hipMemcpyDeviceToHost, st));
+    QH3_TRY(hipMemcpyAsync(hres, dres, sizeof(InitRes) * (size_t)k, hipMemcpyDeviceToHost, st));
     QH3_TRY(hipStreamSynchronize(st));
     ++R.syncs;
-    if (hres->error) return QH_ERANGE;
-    if (hres->a < 0 || hres->c < 0 || hres->d < 0) return QH_EDEGENERATE;
-    const InitRes res = *hres;
 
-    // the first simplex: each facet oriented away from the opposite corner
     if (!w->workers) {
         w->workers.reset(new (std::nothrow) Workers());
         if (!w->workers) return QH_ENOMEM;
@@ -503,22 +517,37 @@ qh_status run3d(qh_ctx *c, const int32_t *pts, int64_t n, int32_t *facets, int64
     R.T = &Tp;
     R.W = w->workers.get();
     Tp.reset((int32_t)n);
-    const int32_t T4[4] = {res.a, res.b, res.c, res.d};
-    for (int k = 0; k < 4; ++k) {
-        if (T4[k] < 0 || T4[k] >= n) return QH_EDEVICE;
-        Tp.set_point(T4[k], res.coords[k][0], res.coords[k][1], res.coords[k][2]);
+    degen.assign((size_t)k, 1);
+    std::vector<SrcRec> srcs0;
+    int64_t hulls = 0;
+    for (int32_t i = 0; i < k; ++i) {
+        const int64_t ni = off[i + 1] - off[i];
+        if (ni < 4) continue;
+        const InitRes &res = hres[i];
+        if (res.error) return QH_ERANGE;
+        if (res.a < 0 || res.c < 0 || res.d < 0) continue;
+        // each facet turned away from the opposite corner
+        const int32_t T4[4] = {(int32_t)(res.a + off[i]), (int32_t)(res.b + off[i]),
+                               (int32_t)(res.c + off[i]), (int32_t)(res.d + off[i])};
+        for (int q = 0; q < 4; ++q) {
+            if (T4[q] < off[i] || T4[q] >= off[i + 1]) return QH_EDEVICE;
+            Tp.set_point(T4[q], res.coords[q][0], res.coords[q][1], res.coords[q][2]);
+        }
+        if (!Tp.simplex(T4)) return QH_ENOMEM;
+        SrcRec sr;
+        sr.start = off[i];
+        sr.len = (int32_t)ni;
+        sr.gfirst = (int32_t)(4 * hulls);
+        sr.gcount = 4;
+        sr.tile0 = 0;
+        srcs0.push_back(sr);
+        degen[(size_t)i] = 0;
+        ++hulls;
     }
-    if (!Tp.simplex(T4)) return QH_ENOMEM;
-    {
-        std::vector<SrcRec> srcs(1);
-        srcs[0].start = 0;
-        srcs[0].len = (int32_t)n;
-        srcs[0].gfirst = 0;
-        srcs[0].gcount = 4;
-        srcs[0].tile0 = 0;
-        R.cur = 0;
-        R.top = 0;
-        qh_status s = R.classify(srcs, 1, 0, 4);
+    R.cur = 0;
+    R.top = 0;
+    if (hulls) {
+        qh_status s = R.classify(srcs0, 1, 0, (int32_t)(4 * hulls));
         if (s != QH_OK) return s;
     }
     std::vector<TopoSrc> tsrcs;
@@ -546,10 +575,11 @@ qh_status run3d(qh_ctx *c, const int32_t *pts, int64_t n, int32_t *facets, int64
         if (s != QH_OK) return s;
     }
     const auto t0 = clk::now();
-    qh_status s = R.output(facets, nfacets, verts, nverts);
+    tri.clear();
+    vlist.clear();
+    if (hulls && !Tp.output(*R.W, tri, vlist, hulls)) return QH_EDEVICE;
     R.output_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
     R.host_ms += R.output_ms;
-    if (s != QH_OK) return s;
 
     if (o && o->stats) {
         qh_stats *S = o->stats;
@@ -570,6 +600,8 @@ qh_status run3d(qh_ctx *c, const int32_t *pts, int64_t n, int32_t *facets, int64
         S->host_syncs = R.syncs;
         S->host_ms = R.host_ms;
         S->host_output_ms = R.output_ms;
+        S->degenerate_instances = 0;
+        for (uint8_t d : degen) S->degenerate_instances += d;
         if (R.timing) {
             double ms[4] = {0, 0, 0, 0};
             for (size_t j = 0; j < R.evk.size(); ++j) {
@@ -604,5 +636,99 @@ extern "C" qh_status qh_hull3d(const int32_t *pts, int64_t n, int32_t *facets, i
     qhi::TempCtx t;
     qh_status s = qhi::get_ctx(opts, t);
     if (s != QH_OK) return s;
-    return qh3::run3d(t.c, pts, n, facets, nfacets, verts, nverts, opts);
+    const std::vector<int64_t> off = {0, n};
+    std::vector<int32_t> tri, vl;
+    std::vector<uint8_t> degen;
+    s = qh3::run3d(t.c, pts, n, off, tri, vl, degen, opts);
+    if (s != QH_OK) return s;
+    if (degen[0]) {
+        if (opts && opts->stats) opts->stats->degenerate_instances = 0;
+        return QH_EDEGENERATE;
+    }
+    hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+    s = qh3::put_all(t.c->c3, st, {{facets, {tri.data(), sizeof(int32_t) * tri.size()}},
+                                    {verts, {vl.data(), sizeof(int32_t) * vl.size()}}});
+    if (s != QH_OK) return s;
+    if (opts && opts->stats) {
+        opts->stats->host_syncs += 1;
+        opts->stats->degenerate_instances = 0;
+    }
+    *nfacets = (int64_t)(tri.size() / 3);
+    *nverts = (int64_t)vl.size();
+    return QH_OK;
+}
+
+extern "C" qh_status qh_hull3d_batched(const int32_t *pts, int64_t n_total, const int64_t *offsets, int32_t k,
+                                       int32_t *facets, int64_t *facet_offsets, int32_t *verts,
+                                       int64_t *vert_offsets, const qh_opts *opts) {
+    if (k < 1 || k > (1 << 20) || n_total < 0 || n_total > (int64_t)INT32_MAX / 2 - 4096) return QH_EINVAL;
+    if (!offsets || !facet_offsets || !vert_offsets || (n_total > 0 && (!pts || !facets || !verts)))
+        return QH_EINVAL;
+    if (opts && opts->stats) {
+        memset(opts->stats, 0, sizeof(qh_stats));
+        opts->stats->finish_round = -1;  // a 2D option
+    }
+    if (opts && opts->mode != QH_EXACT_INT64 && opts->mode != QH_FP32_FILTER) return QH_EINVAL;
+    qhi::TempCtx t;
+    qh_status s = qhi::get_ctx(opts, t);
+    if (s != QH_OK) return s;
+    hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+    // the instance bounds, checked on the host
+    std::vector<int64_t> off((size_t)k + 1);
+    if (hipMemcpyAsync(off.data(), offsets, sizeof(int64_t) * off.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipGetLastError();
+        return QH_EDEVICE;
+    }
+    if (off[0] != 0 || off[(size_t)k] != n_total) return QH_EINVAL;
+    for (int32_t i = 0; i < k; ++i)
+        if (off[(size_t)i + 1] < off[(size_t)i]) return QH_EINVAL;
+    std::vector<int32_t> tri, vl;
+    std::vector<uint8_t> degen((size_t)k, 1);
+    if (n_total > 0) {
+        s = qh3::run3d(t.c, pts, n_total, off, tri, vl, degen, opts);
+        if (s != QH_OK) return s;
+    } else if (opts && opts->stats) {
+        opts->stats->degenerate_instances = k;
+    }
+    // every instance's triples and vertices, in its own point indices: the
+    // vertices are sorted and so are the triples by their first vertex, so
+    // each instance is one contiguous range of both
+    std::vector<int64_t> foff((size_t)k + 1, 0), voff((size_t)k + 1, 0);
+    const size_t nt = tri.size() / 3;
+    size_t tpos = 0, vpos = 0;
+    for (int32_t i = 0; i < k; ++i) {
+        const int64_t lo = off[(size_t)i], hi = off[(size_t)i + 1];
+        const size_t v0 = vpos, t0 = tpos;
+        while (vpos < vl.size() && vl[vpos] < hi) {
+            if (vl[vpos] < lo) return QH_EDEVICE;
+            vl[vpos] = (int32_t)(vl[vpos] - lo);
+            ++vpos;
+        }
+        while (tpos < nt && tri[3 * tpos] < hi) {
+            for (int q = 0; q < 3; ++q) {
+                int32_t &x = tri[3 * tpos + q];
+                if (x < lo || x >= hi) return QH_EDEVICE;
+                x = (int32_t)(x - lo);
+            }
+            ++tpos;
+        }
+        const int64_t nv = (int64_t)(vpos - v0), nti = (int64_t)(tpos - t0);
+        if (degen[(size_t)i] ? (nv != 0 || nti != 0) : (nv < 4 || nti != 2 * nv - 4)) return QH_EDEVICE;
+        foff[(size_t)i + 1] = (int64_t)tpos;
+        voff[(size_t)i + 1] = (int64_t)vpos;
+    }
+    if (vpos != vl.size() || tpos != nt) return QH_EDEVICE;
+    if (!t.c->c3) {
+        t.c->c3 = new (std::nothrow) qh3::Ctx3();
+        if (!t.c->c3) return QH_ENOMEM;
+    }
+    s = qh3::put_all(t.c->c3, st,
+                     {{facets, {tri.data(), sizeof(int32_t) * tri.size()}},
+                      {verts, {vl.data(), sizeof(int32_t) * vl.size()}},
+                      {facet_offsets, {foff.data(), sizeof(int64_t) * foff.size()}},
+                      {vert_offsets, {voff.data(), sizeof(int64_t) * voff.size()}}});
+    if (s != QH_OK) return s;
+    if (opts && opts->stats) opts->stats->host_syncs += 2;
+    return QH_OK;
 }

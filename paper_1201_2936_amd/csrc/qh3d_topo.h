@@ -312,22 +312,24 @@ struct Topo {
         apex[id] = -1;
     }
 
-    // The first simplex on the points T (coordinates already set): four
-    // facets, each turned away from the opposite corner, with neighbours.
+    // A first simplex on the points T (coordinates already set), appended
+    // to the table: four facets, each turned away from the opposite corner,
+    // with neighbours among themselves (one per instance of a batch).
     bool simplex(const int32_t T[4]) {
         static const int tri[4][4] = {{0, 1, 2, 3}, {0, 1, 3, 2}, {0, 2, 3, 1}, {1, 2, 3, 0}};
-        if (!grow(4)) return false;
+        const int32_t b = (int32_t)F.size();
+        if (!grow((size_t)b + 4)) return false;
         for (int k = 0; k < 4; ++k) {
             const int p = tri[k][0], q = tri[k][1], r = tri[k][2], s = tri[k][3];
-            init_facet(k, T[p], T[q], T[r], 0);
-            if (side(F[k], coords(T[s])) > 0) init_facet(k, T[p], T[r], T[q], 0);
+            init_facet(b + k, T[p], T[q], T[r], 0);
+            if (side(F[b + k], coords(T[s])) > 0) init_facet(b + k, T[p], T[r], T[q], 0);
         }
         for (int k = 0; k < 4; ++k)
             for (int i = 0; i < 3; ++i) {
-                const int32_t u = F[k].v[i], v = F[k].v[(i + 1) % 3];
+                const int32_t u = F[b + k].v[i], v = F[b + k].v[(i + 1) % 3];
                 for (int g = 0; g < 4; ++g)
                     for (int j = 0; j < 3; ++j)
-                        if (g != k && F[g].v[j] == v && F[g].v[(j + 1) % 3] == u) F[k].nb[i] = g;
+                        if (g != k && F[b + g].v[j] == v && F[b + g].v[(j + 1) % 3] == u) F[b + k].nb[i] = b + g;
             }
         return true;
     }
@@ -523,8 +525,10 @@ struct Topo {
     // triples): the corners whose facets span at least three planes are the
     // vertices; every face (edge-connected coplanar facets) is fanned from its
     // lowest vertex over its vertices, counter-clockwise seen from outside.
-    // False if a face's boundary is not one cycle.
-    bool output(Workers &W, std::vector<int32_t> &tri, std::vector<int32_t> &verts) {
+    // The table may hold several hulls (disjoint point sets); false if a
+    // face's boundary is not one cycle or the triangles do not number
+    // 2 V - 4 per hull.
+    bool output(Workers &W, std::vector<int32_t> &tri, std::vector<int32_t> &verts, int64_t hulls = 1) {
         const int T = W.threads();
         if ((int)loc_.size() < T) loc_.resize(T);
         const int32_t nf = (int32_t)F.size();
@@ -742,7 +746,7 @@ struct Topo {
                 }
             }
         });
-        return verts.size() >= 4 && nt == 2 * verts.size() - 4;
+        return (int64_t)verts.size() >= 4 * hulls && (int64_t)nt == 2 * (int64_t)verts.size() - 4 * hulls;
     }
 
   private:

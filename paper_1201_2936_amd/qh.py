@@ -29,7 +29,8 @@ QH_FLAG_AUTOTUNE = 8
 QH_FINISH_CAP = 1024
 
 EXPORTED = ["qh_ctx_create", "qh_ctx_destroy", "qh_status_str", "qh_version",
-            "qh_hull2d", "qh_hull2d_batched", "qh_hull3d", "qh_test_flag_permute"]
+            "qh_hull2d", "qh_hull2d_batched", "qh_hull3d", "qh_hull3d_batched",
+            "qh_test_flag_permute"]
 
 
 class QhStats(ctypes.Structure):
@@ -59,6 +60,7 @@ class QhStats(ctypes.Structure):
         ("finish_segments", ctypes.c_int64),
         ("graph_launches", ctypes.c_int64),
         ("tuned_configs", ctypes.c_int64),
+        ("degenerate_instances", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -109,6 +111,8 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(i64), ctypes.POINTER(QhOpts)]
     lib.qh_test_flag_permute.restype = ctypes.c_int
     lib.qh_test_flag_permute.argtypes = [vp, vp, i64, ctypes.c_int32, vp, vp, vp]
+    lib.qh_hull3d_batched.restype = ctypes.c_int
+    lib.qh_hull3d_batched.argtypes = [vp, i64, vp, ctypes.c_int32, vp, vp, vp, vp, ctypes.POINTER(QhOpts)]
     lib.qh_hull3d.restype = ctypes.c_int
     lib.qh_hull3d.argtypes = [vp, i64, vp, ctypes.POINTER(i64), vp, ctypes.POINTER(i64),
                               ctypes.POINTER(QhOpts)]
@@ -248,6 +252,37 @@ def qh_hull3d(pts, mode: int = QH_EXACT_INT64, ctx: Context | None = None,
     if st != QH_OK:
         raise QhError(st, "qh_hull3d")
     return fac[: 3 * nf.value].view(-1, 3), ver[: nv.value], stats.as_dict()
+
+
+def qh_hull3d_batched(pts, offsets, mode: int = QH_EXACT_INT64, ctx: Context | None = None,
+                      timing: bool = False, stream=None):
+    """3D hulls of the instances [offsets[i], offsets[i+1]) of int32[3, N]
+    device points; offsets is an int64[k + 1] device tensor.  Returns
+    (facets int32[F, 3], facet offsets int64[k + 1], vertices int32[V],
+    vertex offsets int64[k + 1], stats dict), all on the device, indices local
+    to each instance."""
+    import torch
+    lib = load()
+    pts = _check_points(pts, 3)
+    if offsets.dtype != torch.int64 or not offsets.is_cuda or offsets.dim() != 1:
+        raise TypeError("offsets must be an int64 CUDA tensor of shape (k + 1,)")
+    offsets = offsets.contiguous()
+    k = offsets.shape[0] - 1
+    n = pts.shape[1]
+    fac = torch.empty(max(6 * n, 3), dtype=torch.int32, device=pts.device)
+    ver = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
+    foff = torch.empty(k + 1, dtype=torch.int64, device=pts.device)
+    voff = torch.empty(k + 1, dtype=torch.int64, device=pts.device)
+    o, stats = _opts(ctx, mode, timing, stream)
+    st = lib.qh_hull3d_batched(ctypes.c_void_p(pts.data_ptr()), n, ctypes.c_void_p(offsets.data_ptr()), k,
+                               ctypes.c_void_p(fac.data_ptr()), ctypes.c_void_p(foff.data_ptr()),
+                               ctypes.c_void_p(ver.data_ptr()), ctypes.c_void_p(voff.data_ptr()),
+                               ctypes.byref(o))
+    if st != QH_OK:
+        raise QhError(st, "qh_hull3d_batched")
+    nf = int(foff[-1].item())
+    nv = int(voff[-1].item())
+    return fac[: 3 * nf].view(-1, 3), foff, ver[: nv], voff, stats.as_dict()
 
 
 def qh_test_flag_permute(f, s, k: int, stream=None):

@@ -117,3 +117,16 @@ def test_binding_structs_match_the_header(tmp_path):
         assert int(got["o." + f]) == getattr(qh.QhOpts, f).offset, f
     for f in flags:
         assert int(got["c." + f]) == getattr(qh, f), f
+
+
+def test_batched3d_argument_validation_without_device():
+    lib = qh.load()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: the checks come first
+    # k out of range, negative n, missing offsets or outputs
+    assert lib.qh_hull3d_batched(dummy, 10, dummy, 0, dummy, dummy, dummy, dummy, None) == qh.QH_EINVAL
+    assert lib.qh_hull3d_batched(dummy, -1, dummy, 1, dummy, dummy, dummy, dummy, None) == qh.QH_EINVAL
+    assert lib.qh_hull3d_batched(dummy, 10, None, 1, dummy, dummy, dummy, dummy, None) == qh.QH_EINVAL
+    assert lib.qh_hull3d_batched(dummy, 10, dummy, 1, None, dummy, dummy, dummy, None) == qh.QH_EINVAL
+    assert lib.qh_hull3d_batched(dummy, 10, dummy, 1, dummy, None, dummy, dummy, None) == qh.QH_EINVAL
+    o = qh.QhOpts(None, 9, 0, None, None)
+    assert lib.qh_hull3d_batched(dummy, 10, dummy, 1, dummy, dummy, dummy, dummy, ctypes.byref(o)) == qh.QH_EINVAL
