@@ -266,6 +266,59 @@ def hull3d_leg(steps: int):
     }
 
 
+def hull3d_batched_leg(steps: int):
+    """The batched 3D form on 512 ball-and-sphere sets (sizes log-uniform in
+    [64, 16384], 1,650,780 points) in one qh_hull3d_batched call, beside
+    512 sequential qh_hull3d calls on the same device-resident instances."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1201_2936_amd import qh
+
+    pts_np, off_np = workloads.batched_balls3d()
+    k = len(off_np) - 1
+    N = int(off_np[-1])
+    pts = torch.from_numpy(pts_np).cuda()
+    off = torch.from_numpy(off_np).cuda()
+    ctx = qh.Context()
+    sec_b, (fac, foff, ver, voff, st) = time_steps(
+        lambda: qh.qh_hull3d_batched(pts, off, mode=qh.QH_EXACT_INT64, ctx=ctx), steps, 1)
+    fac, foff, ver, voff = fac.cpu().numpy(), foff.cpu().numpy(), ver.cpu().numpy(), voff.cpu().numpy()
+    singles = [pts[:, off_np[i]:off_np[i + 1]].contiguous() for i in range(k)]
+    sctx = qh.Context()
+    qh.qh_hull3d(singles[0], ctx=sctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    same = True
+    outs = [qh.qh_hull3d(s, mode=qh.QH_EXACT_INT64, ctx=sctx) for s in singles]
+    torch.cuda.synchronize()
+    sec_seq = time.perf_counter() - t0
+    for i, (f1, v1, _) in enumerate(outs):
+        same &= (np.array_equal(f1.cpu().numpy(), fac[foff[i]:foff[i + 1]]) and
+                 np.array_equal(v1.cpu().numpy(), ver[voff[i]:voff[i + 1]]))
+    import oracle  # checker only
+    sample = list(range(0, k, 37))
+    par = True
+    for i in sample:
+        wf, wv = oracle.hull3d(pts_np[:, off_np[i]:off_np[i + 1]])
+        par &= np.array_equal(wf, fac[foff[i]:foff[i + 1]]) and np.array_equal(wv, ver[voff[i]:voff[i + 1]])
+    sctx.close()
+    ctx.close()
+    return {
+        "workload": "batched_balls3d: 512 sets, 3/4 in the ball of radius 2^16 and 1/4 on its sphere, "
+                    "sizes log-uniform in [64, 16384]",
+        "n_total": N, "k": k,
+        "exact_int64": {"value": round(N / sec_b / 1e6, 3), "unit": "Mpoints/s",
+                        "ms_per_step": round(sec_b * 1e3, 2), "steps": steps},
+        "sequential_single_calls": {"value": round(N / sec_seq / 1e6, 3), "unit": "Mpoints/s",
+                                    "ms": round(sec_seq * 1e3, 1), "calls": k, "match_batched": bool(same)},
+        "parity_vs_oracle_sample": {"instances": len(sample), "ok": bool(par)},
+        "rounds": int(st["rounds"]), "facets": int(foff[-1]), "vertices": int(voff[-1]),
+        "host_topology_ms": round(st["host_ms"], 2),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -386,6 +439,7 @@ def main():
         line["batched"] = batched_leg(max(2, min(args.steps, 5)))
     if not args.no_3d:
         line["hull3d"] = hull3d_leg(max(2, min(args.steps, 3)))
+        line["hull3d_batched"] = hull3d_batched_leg(max(2, min(args.steps, 3)))
     print(json.dumps(line), flush=True)
 
 

@@ -235,6 +235,24 @@ def batched_disks(k: int = N_INSTANCES, sizes: np.ndarray | None = None):
     return pts, offsets
 
 
+def batched_balls3d(k: int = 512):
+    """k independent 3D point sets (seed 6): sizes floor(exp(U(ln 64, ln 16384))),
+    instance i (from SeedSequence(6).spawn(k)[i]) is three quarters uniform in
+    the ball of radius 2^16 and one quarter snapped to its sphere.
+
+    Returns (pts int32[3, N], offsets int64[k + 1])."""
+    rng = rng_for(6)
+    sizes = np.floor(np.exp(rng.uniform(np.log(64), np.log(16384), size=k))).astype(np.int64)
+    offsets = np.zeros(k + 1, np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    pts = np.empty((3, int(offsets[-1])), np.int32)
+    for i, ss in enumerate(np.random.SeedSequence(6).spawn(k)):
+        g = rng_for(ss)
+        m = int(sizes[i])
+        pts[:, offsets[i]:offsets[i + 1]] = np.concatenate([ball(g, m - m // 4), sphere(g, m // 4)], axis=1)
+    return pts, offsets
+
+
 WORKLOADS = {
     "disk_65k": disk_65k,
     "square_16m": square_16m,
