@@ -250,8 +250,9 @@ inline bool coplanar_dir(const int64_t a[3], const int64_t b[3]) {
 struct Topo {
     int32_t n = 0;                // points
     PodVec<Facet> F;              // every facet made so far (removed ones stay)
-    PodVec<int32_t> lock;         // per facet: the round that last locked it
-    PodVec<int32_t> gone;         // per facet: 0 while on the hull, else the round that removed it
+    PodVec<uint16_t> lock;        // per facet: the round that last locked it, modulo 2^16 (an
+                                  // older lock read as this round's only defers a candidate)
+    PodVec<uint8_t> gone;         // per facet: 1 once removed from the hull
     PodVec<int64_t> start;        // per facet: its outside set's pool range
     PodVec<int32_t> len;
     PodVec<int32_t> apex;         // per facet: its farthest outside point, -1 = none
@@ -305,7 +306,7 @@ struct Topo {
         f.v[2] = c;
         f.nb[0] = f.nb[1] = f.nb[2] = -1;
         set_plane(f);
-        lock[id] = stamp;
+        lock[id] = (uint16_t)stamp;
         gone[id] = 0;
         start[id] = 0;
         len[id] = 0;
@@ -385,24 +386,27 @@ struct Topo {
         });
         // B: accept in id order
         acc_.clear();
-        int32_t *lk = lock.data();
+        uint16_t *lk = lock.data();
+        const uint16_t st16 = (uint16_t)stamp;
+        // (the regions' addresses first: a flat array, read in order)
+        rptr_.resize(m);
+        for (int64_t i = 0; i < m; ++i) rptr_[i] = region(i);
         constexpr int64_t kAhead = 8;  // candidates whose locks are fetched ahead
         for (int64_t i = 0; i < m; ++i) {
             if (i + kAhead < m) {
-                const int64_t q = i + kAhead;
-                __builtin_prefetch(&lk[active[q]]);
-                const int32_t *Rq = region(q);
-                for (int32_t j = 0; j < std::min(rcnt_[q], 4); ++j) __builtin_prefetch(&lk[Rq[j]]);
+                const int32_t *Rq = rptr_[i + kAhead];
+                __builtin_prefetch(&lk[Rq[0]]);
+                __builtin_prefetch(&lk[Rq[rcnt_[i + kAhead] > 1 ? 1 : 0]]);
             }
-            if (lk[active[i]] == stamp) continue;
-            const int32_t *R = region(i);
+            if (lk[active[i]] == st16) continue;
+            const int32_t *R = rptr_[i];
             const int32_t k = rcnt_[i];
             bool clash = false;
-            for (int32_t j = 0; j < k && !clash; ++j) clash = lk[R[j]] == stamp;
+            for (int32_t j = 0; j < k && !clash; ++j) clash = lk[R[j]] == st16;
             if (clash) continue;
             acc_.push_back(i);
-            for (int32_t j = 0; j < k; ++j) gone[R[j]] = stamp;
-            for (int32_t j = 0; j < rall_[i]; ++j) lk[R[j]] = stamp;
+            for (int32_t j = 0; j < k; ++j) gone[R[j]] = 1;
+            for (int32_t j = 0; j < rall_[i]; ++j) lk[R[j]] = st16;
         }
         const int64_t na = (int64_t)acc_.size();
         // C1: horizon edges of every accepted region (walk order)
@@ -776,6 +780,7 @@ struct Topo {
     std::vector<int64_t> sbase_;
     std::vector<uint8_t> live_;
     std::vector<int64_t> acc_;
+    std::vector<const int32_t *> rptr_;
 };
 
 }  // namespace qh3
