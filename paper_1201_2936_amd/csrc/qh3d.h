@@ -18,6 +18,7 @@ constexpr int kItems = 4;
 constexpr int kTile = kBlock * kItems;   // points per tile
 constexpr int kGroupLds = 512;           // cone facets counted in LDS per block
 constexpr int32_t kCoordMax = 1 << 19;   // |coordinate| bound of the exact int64 predicates
+constexpr int64_t kInitSmall = 32768;    // instances up to this size get one init block each
 
 // A facet as the kernels see it: outward normal n = (b - a) x (c - a),
 // off = n . a (a point p is strictly above iff n . p > off), the corner a and
@@ -82,5 +83,9 @@ hipError_t launch_apex(Pool pool, const SegRec *seg, int32_t nseg, int32_t ntile
 hipError_t launch_gather(Pool in, Pool out, const SegRec *seg, int32_t nseg, int32_t ntiles,
                          const int64_t *dst, hipStream_t st);
 size_t init_scratch_bytes(int grid);
+// the first simplex of the instances list[0..count) (each [off[i], off[i+1]),
+// at least 4 and at most kInitSmall points), one block each, results at res[i]
+hipError_t launch_init_small(const int32_t *x, const int32_t *y, const int32_t *z, const int64_t *off,
+                             const int32_t *list, int32_t count, InitRes *res, hipStream_t st);
 
 }  // namespace qh3

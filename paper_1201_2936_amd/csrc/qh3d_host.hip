@@ -106,7 +106,7 @@ struct HBuf {
 struct Ctx3 {
     DBuf pool[2];      // point pools: x, y, z, idx planes of pool_cap each
     int64_t pool_cap = 0;
-    DBuf fac, src, seg, counts, cursor, range, tkeys, skeys, gdst, init, filt;
+    DBuf fac, src, seg, counts, cursor, range, tkeys, skeys, gdst, init, filt, ilist;
     HBuf up, down;
     std::vector<hipEvent_t> ev;
     Topo topo;                         // facet table (kept for its capacity)
@@ -130,6 +130,7 @@ void ctx3_free(qh3::Ctx3 *c3) {
     c3->gdst.release();
     c3->init.release();
     c3->filt.release();
+    c3->ilist.release();
     c3->up.release();
     c3->down.release();
     for (hipEvent_t e : c3->ev) (void)hipEventDestroy(e);
@@ -454,8 +455,8 @@ qh_status put_all(Ctx3 *w, hipStream_t st, std::initializer_list<std::pair<void 
 // whole array; degen[i] = 1 for an instance with fewer than four affinely
 // independent points (it has no hull).
 qh_status run3d(qh_ctx *c, const int32_t *pts, int64_t n, const std::vector<int64_t> &off,
-                std::vector<int32_t> &tri, std::vector<int32_t> &vlist, std::vector<uint8_t> &degen,
-                const qh_opts *o) {
+                const int64_t *off_dev, std::vector<int32_t> &tri, std::vector<int32_t> &vlist,
+                std::vector<uint8_t> &degen, const qh_opts *o) {
     using clk = std::chrono::steady_clock;
     if (!c->c3) {
         c->c3 = new (std::nothrow) Ctx3();
@@ -493,14 +494,30 @@ qh_status run3d(qh_ctx *c, const int32_t *pts, int64_t n, const std::vector<int6
     QH3_TRY(w->filt.want(64));
     QH3_TRY(hipMemsetAsync(w->filt.p, 0, 16, st));
     InitRes *dres = reinterpret_cast<InitRes *>(w->init.as<char>() + res_at);
-    // the first simplex of every instance (the scratch is reused in turn)
+    // the first simplex of every instance: the large ones one after the
+    // other over the whole device (the scratch is reused in turn), the small
+    // ones (with the instance bounds on the device) one block each in one launch
+    std::vector<int32_t> small;
     QH3_TRY(R.ev_begin(3));
     for (int32_t i = 0; i < k; ++i) {
         const int64_t ni = off[i + 1] - off[i];
         if (ni < 4) continue;
+        if (off_dev && ni <= kInitSmall) {
+            small.push_back(i);
+            continue;
+        }
         QH3_TRY(launch_init(R.x + off[i], R.y + off[i], R.z + off[i], (int32_t)ni, w->init.p, dres + i,
                             grid_for(ni), st));
         R.launches += 7;
+    }
+    if (!small.empty()) {
+        const size_t lb = sizeof(int32_t) * small.size();
+        QH3_TRY(w->ilist.want(lb));
+        QH3_TRY(w->up.want(lb + 256));
+        memcpy(w->up.p, small.data(), lb);
+        QH3_TRY(hipMemcpyAsync(w->ilist.p, w->up.p, lb, hipMemcpyHostToDevice, st));
+        QH3_TRY(launch_init_small(R.x, R.y, R.z, off_dev, w->ilist.as<int32_t>(), (int32_t)small.size(), dres, st));
+        R.launches += 1;
     }
     QH3_TRY(R.ev_end());
     QH3_TRY(w->down.want(sizeof(InitRes) * (size_t)k + 256));
@@ -639,7 +656,7 @@ extern "C" qh_status qh_hull3d(const int32_t *pts, int64_t n, int32_t *facets, i
     const std::vector<int64_t> off = {0, n};
     std::vector<int32_t> tri, vl;
     std::vector<uint8_t> degen;
-    s = qh3::run3d(t.c, pts, n, off, tri, vl, degen, opts);
+    s = qh3::run3d(t.c, pts, n, off, nullptr, tri, vl, degen, opts);
     if (s != QH_OK) return s;
     if (degen[0]) {
         if (opts && opts->stats) opts->stats->degenerate_instances = 0;
@@ -686,7 +703,7 @@ extern "C" qh_status qh_hull3d_batched(const int32_t *pts, int64_t n_total, cons
     std::vector<int32_t> tri, vl;
     std::vector<uint8_t> degen((size_t)k, 1);
     if (n_total > 0) {
-        s = qh3::run3d(t.c, pts, n_total, off, tri, vl, degen, opts);
+        s = qh3::run3d(t.c, pts, n_total, off, offsets, tri, vl, degen, opts);
         if (s != QH_OK) return s;
     } else if (opts && opts->stats) {
         opts->stats->degenerate_instances = k;

@@ -102,26 +102,67 @@ struct InitScratch {
     IKey part[1];  // [2 * grid]
 };
 
+// The per-point keys of the three searches (index i, coordinates p):
+// the lexicographic minimum and maximum (ties to the smaller index) ...
+__device__ __forceinline__ void ext_keys(int32_t i, int32_t px, int32_t py, int32_t pz, IKey &kmin, IKey &kmax) {
+    const unsigned __int128 all = ((unsigned __int128)1 << 63) * 2 - 1;
+    const unsigned __int128 k = lex_pack(px, py, pz);
+    kmin.k = all - k;  // smaller coordinates win
+    kmin.s1 = kmin.s2 = 0;
+    kmin.idx = i;
+    kmax.k = k;
+    kmax.s1 = kmax.s2 = 0;
+    kmax.idx = i;
+}
+
+__device__ __forceinline__ bool out_of_range(int32_t px, int32_t py, int32_t pz) {
+    return px < -kCoordMax || px > kCoordMax || py < -kCoordMax || py > kCoordMax || pz < -kCoordMax ||
+           pz > kCoordMax;
+}
+
+// ... the distance from the line a + t e (squared |e x r|, r = p - a; then
+// the smallest r . e); false for a point on the line ...
+__device__ __forceinline__ bool line_key(int32_t i, int32_t px, int32_t py, int32_t pz, int64_t ax, int64_t ay,
+                                         int64_t az, int64_t ex, int64_t ey, int64_t ez, IKey &k) {
+    const int64_t rx = px - ax, ry = py - ay, rz = pz - az;
+    const int64_t wx = ey * rz - ez * ry, wy = ez * rx - ex * rz, wz = ex * ry - ey * rx;
+    if ((wx | wy | wz) == 0) return false;
+    k.k = (unsigned __int128)((__int128)wx * wx) + (unsigned __int128)((__int128)wy * wy) +
+          (unsigned __int128)((__int128)wz * wz);
+    k.s1 = rx * ex + ry * ey + rz * ez;
+    k.s2 = 0;
+    k.idx = i;
+    return true;
+}
+
+// ... and the distance from the plane through a with normal n (|n . r|;
+// then the smallest r . b', r . c' with b', c' the edges from a); false for
+// a point on the plane
+__device__ __forceinline__ bool plane_key(int32_t i, int32_t px, int32_t py, int32_t pz, int64_t ax, int64_t ay,
+                                          int64_t az, int64_t nx, int64_t ny, int64_t nz, int64_t bx, int64_t by,
+                                          int64_t bz, int64_t cx, int64_t cy, int64_t cz, IKey &k) {
+    const int64_t rx = px - ax, ry = py - ay, rz = pz - az;
+    int64_t s = nx * rx + ny * ry + nz * rz;
+    if (s == 0) return false;
+    if (s < 0) s = -s;
+    k.k = (unsigned __int128)(uint64_t)s;
+    k.s1 = rx * bx + ry * by + rz * bz;
+    k.s2 = rx * cx + ry * cy + rz * cz;
+    k.idx = i;
+    return true;
+}
+
 __global__ __launch_bounds__(kBlock) void k3_ext_partial(const int32_t *x, const int32_t *y,
                                                          const int32_t *z, int32_t n, IKey *part,
                                                          InitRes *res) {
     __shared__ IKey lds[2 * kBlock];
     IKey v[2] = {ikey_empty(), ikey_empty()};
     bool bad = false;
-    const unsigned __int128 all = ((unsigned __int128)1 << 63) * 2 - 1;
     for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         const int32_t px = x[i], py = y[i], pz = z[i];
-        bad |= px < -kCoordMax || px > kCoordMax || py < -kCoordMax || py > kCoordMax ||
-               pz < -kCoordMax || pz > kCoordMax;
-        const unsigned __int128 k = lex_pack(px, py, pz);
-        IKey kmin;
-        kmin.k = all - k;  // smaller coordinates win
-        kmin.s1 = kmin.s2 = 0;
-        kmin.idx = i;
-        IKey kmax;
-        kmax.k = k;
-        kmax.s1 = kmax.s2 = 0;
-        kmax.idx = i;
+        bad |= out_of_range(px, py, pz);
+        IKey kmin, kmax;
+        ext_keys(i, px, py, pz, kmin, kmax);
         ikey_take(v[0], kmin);
         ikey_take(v[1], kmax);
     }
@@ -169,16 +210,8 @@ __global__ __launch_bounds__(kBlock) void k3_line_partial(const int32_t *x, cons
                   ez = res->coords[1][2] - az;
     if (res->error == 0) {
         for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-            const int64_t rx = x[i] - ax, ry = y[i] - ay, rz = z[i] - az;
-            const int64_t wx = ey * rz - ez * ry, wy = ez * rx - ex * rz, wz = ex * ry - ey * rx;
-            if ((wx | wy | wz) == 0) continue;
             IKey k;
-            k.k = (unsigned __int128)((__int128)wx * wx) + (unsigned __int128)((__int128)wy * wy) +
-                  (unsigned __int128)((__int128)wz * wz);
-            k.s1 = rx * ex + ry * ey + rz * ez;
-            k.s2 = 0;
-            k.idx = i;
-            ikey_take(v[0], k);
+            if (line_key(i, x[i], y[i], z[i], ax, ay, az, ex, ey, ez, k)) ikey_take(v[0], k);
         }
     }
     block_best<1>(v, lds);
@@ -216,16 +249,9 @@ __global__ __launch_bounds__(kBlock) void k3_plane_partial(const int32_t *x, con
                       cz = res->coords[2][2] - az;
         const int64_t nx = by * cz - bz * cy, ny = bz * cx - bx * cz, nz = bx * cy - by * cx;
         for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-            const int64_t rx = x[i] - ax, ry = y[i] - ay, rz = z[i] - az;
-            int64_t s = nx * rx + ny * ry + nz * rz;
-            if (s == 0) continue;
-            if (s < 0) s = -s;
             IKey k;
-            k.k = (unsigned __int128)(uint64_t)s;
-            k.s1 = rx * bx + ry * by + rz * bz;
-            k.s2 = rx * cx + ry * cy + rz * cz;
-            k.idx = i;
-            ikey_take(v[0], k);
+            if (plane_key(i, x[i], y[i], z[i], ax, ay, az, nx, ny, nz, bx, by, bz, cx, cy, cz, k))
+                ikey_take(v[0], k);
         }
     }
     block_best<1>(v, lds);
@@ -253,6 +279,89 @@ __global__ void k3_init_clear(InitRes *res) {
         res->a = res->b = res->c = res->d = -1;
         res->error = 0;
     }
+}
+
+// The first simplex of many small instances, one block each: the same three
+// searches and keys as above, in turn, with block reductions only.  Instance
+// list[blockIdx.x] is the points [off[i], off[i+1]); its indices are local.
+__global__ __launch_bounds__(kBlock) void k3_init_small(const int32_t *x, const int32_t *y, const int32_t *z,
+                                                        const int64_t *off, const int32_t *list, InitRes *res) {
+    __shared__ IKey lds[2 * kBlock];
+    __shared__ int32_t sp[4][3];
+    const int32_t inst = list[blockIdx.x];
+    const int64_t lo = off[inst];
+    const int32_t n = (int32_t)(off[inst + 1] - lo);
+    const int32_t *px = x + lo, *py = y + lo, *pz = z + lo;
+    InitRes *r = res + inst;
+    // a, b: the lexicographic extremes, and the range check
+    IKey v[2] = {ikey_empty(), ikey_empty()};
+    bool bad = false;
+    for (int32_t i = threadIdx.x; i < n; i += kBlock) {
+        bad |= out_of_range(px[i], py[i], pz[i]);
+        IKey kmin, kmax;
+        ext_keys(i, px[i], py[i], pz[i], kmin, kmax);
+        ikey_take(v[0], kmin);
+        ikey_take(v[1], kmax);
+    }
+    const bool anybad = __syncthreads_or(bad);
+    block_best<2>(v, lds);
+    const int32_t ia = v[0].idx, ib = v[1].idx;
+    if (threadIdx.x == 0) {
+        sp[0][0] = px[ia]; sp[0][1] = py[ia]; sp[0][2] = pz[ia];
+        sp[1][0] = px[ib]; sp[1][1] = py[ib]; sp[1][2] = pz[ib];
+    }
+    __syncthreads();
+    const int64_t ax = sp[0][0], ay = sp[0][1], az = sp[0][2];
+    // c: farthest from the line ab
+    IKey w[1] = {ikey_empty()};
+    if (!anybad) {
+        const int64_t ex = sp[1][0] - ax, ey = sp[1][1] - ay, ez = sp[1][2] - az;
+        for (int32_t i = threadIdx.x; i < n; i += kBlock) {
+            IKey k;
+            if (line_key(i, px[i], py[i], pz[i], ax, ay, az, ex, ey, ez, k)) ikey_take(w[0], k);
+        }
+    }
+    block_best<1>(w, lds);
+    const int32_t ic = w[0].idx;
+    if (threadIdx.x == 0 && ic >= 0) { sp[2][0] = px[ic]; sp[2][1] = py[ic]; sp[2][2] = pz[ic]; }
+    __syncthreads();
+    // d: farthest from the plane abc
+    IKey u[1] = {ikey_empty()};
+    if (!anybad && ic >= 0) {
+        const int64_t bx = sp[1][0] - ax, by = sp[1][1] - ay, bz = sp[1][2] - az;
+        const int64_t cx = sp[2][0] - ax, cy = sp[2][1] - ay, cz = sp[2][2] - az;
+        const int64_t nx = by * cz - bz * cy, ny = bz * cx - bx * cz, nz = bx * cy - by * cx;
+        for (int32_t i = threadIdx.x; i < n; i += kBlock) {
+            IKey k;
+            if (plane_key(i, px[i], py[i], pz[i], ax, ay, az, nx, ny, nz, bx, by, bz, cx, cy, cz, k))
+                ikey_take(u[0], k);
+        }
+    }
+    block_best<1>(u, lds);
+    if (threadIdx.x == 0) {
+        const int32_t id = u[0].idx;
+        r->a = ia;
+        r->b = ib;
+        r->c = ic;
+        r->d = id;
+        for (int q = 0; q < 3; ++q) {
+            r->coords[0][q] = sp[0][q];
+            r->coords[1][q] = sp[1][q];
+            r->coords[2][q] = ic >= 0 ? sp[2][q] : 0;
+        }
+        r->coords[3][0] = id >= 0 ? px[id] : 0;
+        r->coords[3][1] = id >= 0 ? py[id] : 0;
+        r->coords[3][2] = id >= 0 ? pz[id] : 0;
+        r->error = anybad ? 1 : 0;
+        r->pad[0] = r->pad[1] = r->pad[2] = 0;
+    }
+}
+
+hipError_t launch_init_small(const int32_t *x, const int32_t *y, const int32_t *z, const int64_t *off,
+                             const int32_t *list, int32_t count, InitRes *res, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k3_init_small, dim3(count), dim3(kBlock), 0, st, x, y, z, off, list, res);
+    return hipGetLastError();
 }
 
 size_t init_scratch_bytes(int grid) { return sizeof(IKey) * 2 * (size_t)grid; }

@@ -159,3 +159,16 @@ def test_batched3d_empty_and_bad(qhm, ctx):
     with pytest.raises(qhm.QhError) as ei:
         qhm.qh_hull3d_batched(torch.from_numpy(p).to("cuda"), torch.from_numpy(o).to("cuda"), ctx=ctx)
     assert ei.value.status == qhm.QH_ERANGE
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batched3d_init_paths(qhm, ctx, mode):
+    """Instances at and above the size where the first simplex stops being
+    found by one block each, and the smallest ones, in one call."""
+    insts = []
+    for j, n in enumerate([32768, 32769, 4, 7, 16]):
+        g = workloads.rng_for(950 + j)
+        insts.append(np.ascontiguousarray(np.concatenate(
+            [workloads.ball(g, n - n // 4, 1 << 19), workloads.sphere(g, n // 4, 1 << 19)], axis=1)).astype(np.int32))
+    _say(f"3d batched init paths mode={mode}")
+    _check(qhm, ctx, insts, mode)
