@@ -279,6 +279,50 @@ qh_status qh_hull3d_batched(const int32_t *pts, int64_t n_total, const int64_t *
 qh_status qh_test_flag_permute(const int32_t *f, const uint8_t *s, int64_t n, int32_t k,
                                int32_t *p, uint8_t *s_new, void *stream);
 
+/*
+ * The segmented compact on its own (Section 4.2, Algorithm 3): the elements
+ * with b[i] = 0 are dropped.  For tests and for callers of the primitive.
+ *
+ *   b       device uint8[n]: keep flags (non-zero = keep)
+ *   s       device uint8[n]: head flags (element 0 always starts a segment)
+ *   n       elements, 0 <= n <= 2^30
+ *   p       device int32[n]: p[i] = #{j < i : b[j] != 0}, the new position
+ *           of every kept element
+ *   s_new   device uint8[n]: its first *m entries flag the first kept element
+ *           of every segment that keeps one (a segment with none vanishes)
+ *   m       host: elements kept
+ *   stream  hipStream_t or NULL; the call returns when the outputs are written
+ *
+ * Scratch device memory of about 8 n bytes is allocated and freed inside the
+ * call.
+ */
+qh_status qh_test_compact(const uint8_t *b, const uint8_t *s, int64_t n, int32_t *p, uint8_t *s_new,
+                          int64_t *m, void *stream);
+
+/*
+ * Order statistics of many segments at once: k-median finding in the
+ * permute-and-segment framework (Section 6 names it as a use of flagPermute
+ * followed by compact).  Every round picks a pseudo-random pivot in each
+ * open segment, groups the segment below / equal to / above it with a
+ * 3-state flagPermute, closes the segment when the wanted rank falls on the
+ * pivot's group and otherwise keeps only the group that holds it (compact).
+ *
+ *   vals     device int32[n], n <= 2^29
+ *   offsets  device int64[k+1]: offsets[0] = 0, offsets[k] = n, every segment
+ *            [offsets[i], offsets[i+1]) non-empty (else QH_EINVAL)
+ *   k        segments, 1 <= k <= 2^24
+ *   ranks    device int64[k]: 0 <= ranks[i] < the length of segment i
+ *            (else QH_EINVAL)
+ *   out      device int32[k]: out[i] = the ranks[i]-th smallest value of
+ *            segment i, counted from 0 (duplicates count separately)
+ *   stream   hipStream_t or NULL; the call returns when out is written
+ *
+ * Scratch device memory of about 60 n bytes is allocated and freed inside
+ * the call.
+ */
+qh_status qh_select(const int32_t *vals, int64_t n, const int64_t *offsets, int32_t k,
+                    const int64_t *ranks, int32_t *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

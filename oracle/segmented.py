@@ -147,6 +147,19 @@ def compact(b, s):
     return p, n_new, sp, s_new
 
 
+def select(vals, offsets, ranks):
+    """Order statistics (Section 6, k-median finding): the ranks[i]-th
+    smallest value, counted from 0, of every segment [offsets[i],
+    offsets[i+1]) -- by definition, the entry at that rank of the segment in
+    sorted order."""
+    vals = np.asarray(vals, np.int64)
+    out = np.zeros(len(ranks), np.int64)
+    for i, r in enumerate(ranks):
+        seg = sorted(vals[int(offsets[i]):int(offsets[i + 1])].tolist())
+        out[i] = seg[int(r)]
+    return out
+
+
 def apply_permutation(values, p):
     out = np.empty_like(np.asarray(values))
     out[np.asarray(p)] = values

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqh.so")
 SOURCES = ["qh2d_kernels.hip", "qh_api.hip", "qh3d_kernels.hip", "qh3d_host.hip",
-           "qh_flag_permute.hip"]
+           "qh_flag_permute.hip", "qh_select.hip"]
 HEADERS = ["qh_device.h", "qh2d.h", "qh_ctx.h", "qh3d.h", "qh3d_topo.h"]
 
 HIPCC_FLAGS = [

@@ -135,7 +135,110 @@ __global__ void k_fp_apply(const int32_t *f, int32_t n, int32_t k, const int32_t
     if (rank == 0) s_new[pos] = 1;
 }
 
+// compact (Section 4.2): P = exclusive sum of the keep flags b (n + 1
+// entries), head = each element's segment head, as in the sweep above
+__global__ __launch_bounds__(kB) void k_cp_sweep(const uint8_t *b, const uint8_t *s, int32_t n, int32_t *P,
+                                                 int32_t *head) {
+    __shared__ uint32_t red[kB / kWave];
+    __shared__ int32_t mx[kB];
+    __shared__ uint32_t carry;
+    __shared__ int32_t hcarry;
+    if (threadIdx.x == 0) {
+        carry = 0;
+        hcarry = 0;
+    }
+    __syncthreads();
+    for (int32_t base = 0; base < n; base += kB) {
+        const int32_t i = base + (int32_t)threadIdx.x;
+        const bool in = i < n;
+        const uint32_t m = (in && b[i]) ? 1u : 0u;
+        const uint32_t inc = block_incl_sum(m, red);
+        if (in) P[i] = (int32_t)(carry + inc - m);
+        __syncthreads();
+        if (threadIdx.x == kB - 1) carry += inc;
+        __syncthreads();
+        const int32_t hv = (in && (s[i] || i == 0)) ? i : hcarry;
+        const int32_t h = block_incl_max(hv, mx);
+        if (in) head[i] = h;
+        __syncthreads();
+        if (threadIdx.x == kB - 1) hcarry = h;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) P[n] = (int32_t)carry;
+}
+
+// p[i] = P[i]; a kept element with no kept element between its segment's
+// head and itself starts the segment in the compacted array
+__global__ void k_cp_apply(const uint8_t *b, int32_t n, const int32_t *P, const int32_t *head, int32_t *p,
+                           uint8_t *s_new) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t pi = P[i];
+    p[i] = pi;
+    if (b[i] && pi == P[head[i]]) s_new[pi] = 1;
+}
+
+size_t fp_scratch_bytes(int64_t n, int32_t k) {
+    return sizeof(int32_t) * ((size_t)k * (size_t)(n + 1) + 2 * (size_t)n + 64);
+}
+
+// flagPermute into caller scratch (fp_scratch_bytes); *err_dev gets 1 for a
+// state outside [0, k) (s_new must be zero on entry)
+hipError_t fp_enqueue(const int32_t *f, const uint8_t *s, int32_t n, int32_t k, int32_t *p, uint8_t *s_new,
+                      void *scratch, int32_t *err_dev, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int32_t *G = reinterpret_cast<int32_t *>(scratch);
+    int32_t *head = G + (size_t)k * (size_t)(n + 1);
+    int32_t *end = head + n;
+    hipLaunchKernelGGL(k_fp_sweep, dim3(1), dim3(kB), 0, st, f, s, n, k, G, head, end, err_dev);
+    hipLaunchKernelGGL(k_fp_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, f, n, k, G, head,
+                       end, p, s_new);
+    return hipGetLastError();
+}
+
+size_t cp_scratch_bytes(int64_t n) { return sizeof(int32_t) * (2 * (size_t)n + 64); }
+
+// compact into caller scratch (cp_scratch_bytes); the kept count is left at
+// *count_dev (s_new must be zero on entry)
+hipError_t cp_enqueue(const uint8_t *b, const uint8_t *s, int32_t n, int32_t *p, uint8_t *s_new, void *scratch,
+                      int32_t *count_dev, hipStream_t st) {
+    int32_t *P = reinterpret_cast<int32_t *>(scratch);
+    int32_t *head = P + n + 1;
+    if (n <= 0) return hipMemsetAsync(count_dev, 0, sizeof(int32_t), st);
+    hipLaunchKernelGGL(k_cp_sweep, dim3(1), dim3(kB), 0, st, b, s, n, P, head);
+    hipLaunchKernelGGL(k_cp_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, b, n, P, head, p,
+                       s_new);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    return hipMemcpyAsync(count_dev, P + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+}
+
 }  // namespace qhfp
+
+extern "C" qh_status qh_test_compact(const uint8_t *b, const uint8_t *s, int64_t n, int32_t *p, uint8_t *s_new,
+                                     int64_t *m, void *stream) {
+    if (m) *m = 0;
+    if (!m || n < 0 || n > (int64_t)INT32_MAX / 2) return QH_EINVAL;
+    if (n == 0) return QH_OK;
+    if (!b || !s || !p || !s_new) return QH_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    char *buf = nullptr;
+    if (hipMalloc((void **)&buf, qhfp::cp_scratch_bytes(n) + 256) != hipSuccess) {
+        (void)hipGetLastError();
+        return QH_ENOMEM;
+    }
+    int32_t *cnt = reinterpret_cast<int32_t *>(buf + qhfp::cp_scratch_bytes(n));
+    int32_t hc = 0;
+    qh_status rc = QH_OK;
+    if (hipMemsetAsync(s_new, 0, (size_t)n, st) != hipSuccess ||
+        qhfp::cp_enqueue(b, s, (int32_t)n, p, s_new, buf, cnt, st) != hipSuccess ||
+        hipMemcpyAsync(&hc, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        rc = QH_EDEVICE;
+    (void)hipGetLastError();
+    (void)hipFree(buf);
+    if (rc == QH_OK) *m = hc;
+    return rc;
+}
 
 extern "C" qh_status qh_test_flag_permute(const int32_t *f, const uint8_t *s, int64_t n, int32_t k,
                                           int32_t *p, uint8_t *s_new, void *stream) {

@@ -30,7 +30,7 @@ QH_FINISH_CAP = 1024
 
 EXPORTED = ["qh_ctx_create", "qh_ctx_destroy", "qh_status_str", "qh_version",
             "qh_hull2d", "qh_hull2d_batched", "qh_hull3d", "qh_hull3d_batched",
-            "qh_test_flag_permute"]
+            "qh_test_flag_permute", "qh_test_compact", "qh_select"]
 
 
 class QhStats(ctypes.Structure):
@@ -111,6 +111,10 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(i64), ctypes.POINTER(QhOpts)]
     lib.qh_test_flag_permute.restype = ctypes.c_int
     lib.qh_test_flag_permute.argtypes = [vp, vp, i64, ctypes.c_int32, vp, vp, vp]
+    lib.qh_test_compact.restype = ctypes.c_int
+    lib.qh_test_compact.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(i64), vp]
+    lib.qh_select.restype = ctypes.c_int
+    lib.qh_select.argtypes = [vp, i64, vp, ctypes.c_int32, vp, vp, vp]
     lib.qh_hull3d_batched.restype = ctypes.c_int
     lib.qh_hull3d_batched.argtypes = [vp, i64, vp, ctypes.c_int32, vp, vp, vp, vp, ctypes.POINTER(QhOpts)]
     lib.qh_hull3d.restype = ctypes.c_int
@@ -306,3 +310,53 @@ def qh_test_flag_permute(f, s, k: int, stream=None):
     if rc != QH_OK:
         raise QhError(rc, "qh_test_flag_permute")
     return p[:n], s_new[:n]
+
+
+def qh_test_compact(b, s, stream=None):
+    """Segmented compact of device uint8 keep flags b and head flags s:
+    returns (p int32[n], s_new uint8[m], m)."""
+    import torch
+    lib = load()
+    if (not isinstance(b, torch.Tensor) or not b.is_cuda or b.dtype != torch.uint8 or b.dim() != 1
+            or not isinstance(s, torch.Tensor) or not s.is_cuda or s.dtype != torch.uint8
+            or s.shape != b.shape):
+        raise TypeError("b and s must be uint8 CUDA tensors of one shape (n,)")
+    b = b.contiguous()
+    s = s.contiguous()
+    n = b.shape[0]
+    p = torch.empty(max(n, 1), dtype=torch.int32, device=b.device)
+    s_new = torch.empty(max(n, 1), dtype=torch.uint8, device=b.device)
+    m = ctypes.c_int64(0)
+    st = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    rc = lib.qh_test_compact(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(s.data_ptr()), n,
+                             ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(s_new.data_ptr()),
+                             ctypes.byref(m), ctypes.c_void_p(st))
+    if rc != QH_OK:
+        raise QhError(rc, "qh_test_compact")
+    return p[:n], s_new[: m.value], m.value
+
+
+def qh_select(vals, offsets, ranks, stream=None):
+    """The ranks[i]-th smallest value (from 0) of every segment
+    [offsets[i], offsets[i+1]) of the device int32 tensor vals: an int32[k]
+    device tensor."""
+    import torch
+    lib = load()
+    if not isinstance(vals, torch.Tensor) or not vals.is_cuda or vals.dtype != torch.int32 or vals.dim() != 1:
+        raise TypeError("vals must be an int32 CUDA tensor of shape (n,)")
+    for t, name in ((offsets, "offsets"), (ranks, "ranks")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int64 or t.dim() != 1:
+            raise TypeError(f"{name} must be an int64 CUDA tensor")
+    vals = vals.contiguous()
+    offsets = offsets.contiguous()
+    ranks = ranks.contiguous()
+    k = offsets.shape[0] - 1
+    if ranks.shape[0] != k:
+        raise TypeError("ranks must have one entry per segment")
+    out = torch.empty(max(k, 1), dtype=torch.int32, device=vals.device)
+    st = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    rc = lib.qh_select(ctypes.c_void_p(vals.data_ptr()), vals.shape[0], ctypes.c_void_p(offsets.data_ptr()), k,
+                       ctypes.c_void_p(ranks.data_ptr()), ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st))
+    if rc != QH_OK:
+        raise QhError(rc, "qh_select")
+    return out[:k]

@@ -130,3 +130,17 @@ def test_batched3d_argument_validation_without_device():
     assert lib.qh_hull3d_batched(dummy, 10, dummy, 1, dummy, None, dummy, dummy, None) == qh.QH_EINVAL
     o = qh.QhOpts(None, 9, 0, None, None)
     assert lib.qh_hull3d_batched(dummy, 10, dummy, 1, dummy, dummy, dummy, dummy, ctypes.byref(o)) == qh.QH_EINVAL
+
+
+def test_segmented_primitives_argument_validation_without_device():
+    lib = qh.load()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: the checks come first
+    m = ctypes.c_int64(5)
+    assert lib.qh_test_compact(dummy, dummy, -1, dummy, dummy, ctypes.byref(m), None) == qh.QH_EINVAL
+    assert m.value == 0
+    assert lib.qh_test_compact(dummy, dummy, 0, dummy, dummy, ctypes.byref(m), None) == qh.QH_OK
+    assert lib.qh_test_compact(dummy, dummy, 4, None, dummy, ctypes.byref(m), None) == qh.QH_EINVAL
+    assert lib.qh_select(dummy, 10, dummy, 0, dummy, dummy, None) == qh.QH_EINVAL
+    assert lib.qh_select(dummy, 10, None, 1, dummy, dummy, None) == qh.QH_EINVAL
+    assert lib.qh_select(dummy, 10, dummy, 1, dummy, None, None) == qh.QH_EINVAL
+    assert lib.qh_select(None, 10, dummy, 1, dummy, dummy, None) == qh.QH_EINVAL

@@ -107,3 +107,29 @@ def test_compact_brute(seed):
         else:
             assert sp[a] == segmented.INF
     assert s_new.tolist() == exp_heads.tolist()
+
+
+@pytest.mark.parametrize("seed", range(50))
+def test_select_by_counting(seed):
+    """The order statistic v of rank r is the value with
+    #{x < v} <= r < #{x <= v} (brute force over the segment)."""
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(1, 6))
+    sizes = rng.integers(1, 25, size=k)
+    offsets = np.concatenate([[0], np.cumsum(sizes)])
+    vals = rng.integers(-5, 5, size=int(offsets[-1]))
+    ranks = np.array([rng.integers(0, sz) for sz in sizes])
+    got = segmented.select(vals, offsets, ranks)
+    for i in range(k):
+        seg = vals[offsets[i]:offsets[i + 1]]
+        v = got[i]
+        assert v in seg
+        assert (seg < v).sum() <= ranks[i] < (seg <= v).sum()
+
+
+def test_select_worked_example():
+    # the median of an odd segment, and the extremes of an even one
+    vals = np.array([7, 1, 5, 3, 9, 4, 4, 8, 2])
+    offsets = np.array([0, 5, 9])
+    assert segmented.select(vals, offsets, [2, 0]).tolist() == [5, 2]
+    assert segmented.select(vals, offsets, [4, 3]).tolist() == [9, 8]
