@@ -319,6 +319,30 @@ def hull3d_batched_leg(steps: int):
     }
 
 
+def select_leg(steps: int):
+    """Order statistics from flagPermute + compact (qh_select): the medians
+    of 1,024 segments of 1,024 random int32 values each (1,048,576 values)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1201_2936_amd import qh
+
+    rng = workloads.rng_for(9)
+    k, m = 1024, 1024
+    vals_np = rng.integers(-(1 << 30), 1 << 30, size=k * m).astype(np.int32)
+    off_np = (np.arange(k + 1, dtype=np.int64) * m)
+    rk_np = np.full(k, m // 2, np.int64)
+    vals = torch.from_numpy(vals_np).cuda()
+    off = torch.from_numpy(off_np).cuda()
+    rk = torch.from_numpy(rk_np).cuda()
+    sec, out = time_steps(lambda: qh.qh_select(vals, off, rk), steps, 1)
+    want = np.sort(vals_np.reshape(k, m), axis=1)[:, m // 2]
+    return {"workload": "select_medians: 1,024 segments x 1,024 int32 values (seed 9), rank 512 each",
+            "value": round(k * m / sec / 1e6, 3), "unit": "Mvalues/s", "ms_per_step": round(sec * 1e3, 3),
+            "steps": steps, "matches_sort": bool(np.array_equal(out.cpu().numpy(), want))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -440,6 +464,7 @@ def main():
     if not args.no_3d:
         line["hull3d"] = hull3d_leg(max(2, min(args.steps, 3)))
         line["hull3d_batched"] = hull3d_batched_leg(max(2, min(args.steps, 3)))
+    line["select"] = select_leg(5)
     print(json.dumps(line), flush=True)
 
 
