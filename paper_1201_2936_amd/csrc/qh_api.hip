@@ -160,6 +160,7 @@ void drop_graphs(qh_ctx *c) {
 void ctx_free(qh_ctx *c) {
     if (!c) return;
     drop_graphs(c);
+    if (c->digest) (void)hipFree(c->digest);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->dmem) (void)hipFree(c->dmem);
     if (c->single_off) (void)hipFree(c->single_off);
@@ -406,6 +407,56 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
     return QH_OK;
 }
 
+// An order-independent digest of a call's outputs (the hull indices and the
+// hull offsets, each entry mixed with its position by SplitMix64's output
+// function, Steele, Lea and Flood 2014, and summed): the autotuner checks
+// that every configuration it times gives the same output.
+__device__ __forceinline__ uint64_t out_mix(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_out_digest(const int32_t *idx, int64_t h, const int64_t *hoff, int32_t k,
+                                                    unsigned long long *acc) {
+    __shared__ unsigned long long part[256 / kWave];
+    unsigned long long v = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < h; i += (int64_t)gridDim.x * 256)
+        v += out_mix(((uint64_t)i << 32) ^ (uint32_t)idx[i]);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i <= k; i += (int64_t)gridDim.x * 256)
+        v += out_mix(~(((uint64_t)i << 40) ^ (uint64_t)hoff[i]));
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane_id() == 0) part[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < 256 / kWave; ++w) t += part[w];
+        atomicAdd(acc, t);
+    }
+}
+
+// the digest of the outputs of the last call (h hull entries, k + 1 offsets)
+qh_status out_digest(qh_ctx *c, hipStream_t st, const int32_t *idx, int64_t h, const int64_t *hoff, int32_t k,
+                     unsigned long long *out) {
+    if (!c->digest && hipMalloc((void **)&c->digest, sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipGetLastError();
+        c->digest = nullptr;
+        return QH_ENOMEM;
+    }
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(c->cus, (std::max<int64_t>(h, k + 1) + 255) / 256));
+    if (hipMemsetAsync(c->digest, 0, sizeof(unsigned long long), st) != hipSuccess) return QH_EDEVICE;
+    hipLaunchKernelGGL(k_out_digest, dim3(grid), dim3(256), 0, st, idx, h, hoff, k, c->digest);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(c->ctl_host, c->digest, sizeof(unsigned long long), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipGetLastError();
+        return QH_EDEVICE;
+    }
+    memcpy(out, c->ctl_host, sizeof(unsigned long long));
+    return QH_OK;
+}
+
 // The size class of a call: mode, and the point and instance counts rounded
 // up to powers of two.
 uint64_t size_class(int mode, int64_t n, int32_t k) {
@@ -432,7 +483,11 @@ qh_status run2d_tuned(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *o
     for (const QhTuned &t : c->tuned)
         if (t.key == key)
             return run2d(c, pts, n, offsets, k, hull_idx, hull_offsets, h_total, single_off, o, t.cfg, 0);
-    // time every candidate (the better of two calls) and keep the fastest
+    // time every candidate (the better of two calls) and keep the fastest;
+    // every candidate must give the first one's output (checked by digest)
+    hipStream_t st = (hipStream_t)o->stream;
+    unsigned long long ref = 0;
+    int64_t ref_h = -1;
     qh_opts quiet = *o;
     quiet.flags &= ~(uint32_t)(QH_FLAG_AUTOTUNE | QH_FLAG_TIMING | QH_FLAG_GRAPH);
     quiet.stats = nullptr;
@@ -453,6 +508,16 @@ qh_status run2d_tuned(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *o
                         best = t;
                         pick = cand;
                     }
+                }
+                const int64_t h = h_total ? *h_total : 0;
+                unsigned long long dg = 0;
+                qh_status s = out_digest(c, st, hull_idx, h, hull_offsets, k, &dg);
+                if (s != QH_OK) return s;
+                if (ref_h < 0) {
+                    ref = dg;
+                    ref_h = h;
+                } else if (dg != ref || h != ref_h) {
+                    return QH_EDEVICE;  // a launch configuration changed the output
                 }
                 ++tried;
             }

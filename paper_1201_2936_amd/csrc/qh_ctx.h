@@ -56,6 +56,7 @@ struct qh_ctx {
     std::vector<unsigned char> gkey;  // launch arguments of the cached graphs
     std::vector<QhGraph> graphs;
     std::vector<QhTuned> tuned;
+    unsigned long long *digest = nullptr;  // device: output digest of the autotuner's check
 };
 
 namespace qhi {
