@@ -16,7 +16,9 @@ per survivor written; later rounds 12 B per point read and 12 B per survivor
 written) over the round's average duration, timed with HIP events around the
 pair of launches on the stream they run on.
 ``cpu_baseline`` is the oracle (plain single-threaded C Quickhull) on the
-same points.  ``batched`` is the batched form on 4,096 disks (about 5.1e8
+same points; the same leg, the only one that runs the oracle, checks every
+GPU leg's output against it.  ``regimes`` times the disk and circle inputs
+(65,536 and 4,194,304 points in a disk, 4,194,304 on and near a circle).  ``batched`` is the batched form on 4,096 disks (about 5.1e8
 points) in one qh_hull2d_batched call, beside 4,096 sequential qh_hull2d
 calls; its round-kernel figures are timed the same way.  ``hull3d`` is the
 3D form (qh_hull3d) on 5,242,880 ball and sphere points.
@@ -81,21 +83,52 @@ def time_steps(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps, out
 
 
-def cpu_baseline(pts, budget_s: float = 12.0):
+def oracle_leg(line, checks, budget_s: float = 12.0):
+    """The leg that runs the oracle (a plain single-threaded C Quickhull,
+    test infrastructure that no GPU leg calls): ``cpu_baseline`` times it on
+    the headline workload, and every GPU leg's output is compared with its
+    result, whole or on a sample of instances."""
+    import numpy as np
+
     import oracle
+
+    pts = checks["headline"][0]
     oracle.hull2d(pts[:, :1000])  # load / build outside the timing
     n = pts.shape[1]
     runs = 0
     t0 = time.perf_counter()
     while True:
-        oracle.hull2d(pts)
+        want = oracle.hull2d(pts)
         runs += 1
         el = time.perf_counter() - t0
         if el >= budget_s or runs >= 50:
             break
-    return {"value": round(n * runs / el / 1e6, 3), "unit": "Mpoints/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{WORKLOAD} full ({n} points), {runs} runs in {el:.1f} s, single thread"}
+    line["cpu_baseline"] = {
+        "value": round(n * runs / el / 1e6, 3), "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
+        "sample": f"{WORKLOAD} full ({n} points), {runs} runs in {el:.1f} s, single thread"}
+    line["parity_vs_oracle"] = bool(all(np.array_equal(got, want) for got in checks["headline"][1:]))
+    if "batched" in checks:
+        ok = all(np.array_equal(oracle.hull2d(p), got) for p, got in checks["batched"])
+        line["batched"]["parity_vs_oracle_sample"] = {"instances": len(checks["batched"]), "ok": bool(ok)}
+    if "hull3d" in checks:
+        p, gf, gv = checks["hull3d"][0]
+        t0 = time.perf_counter()
+        wf, wv = oracle.hull3d(p)
+        line["hull3d"]["oracle_s"] = round(time.perf_counter() - t0, 2)
+        line["hull3d"]["parity_vs_oracle"] = bool(np.array_equal(wf, gf) and np.array_equal(wv, gv))
+    if "hull3d_batched" in checks:
+        ok = True
+        for p, gf, gv in checks["hull3d_batched"]:
+            wf, wv = oracle.hull3d(p)
+            ok &= bool(np.array_equal(wf, gf) and np.array_equal(wv, gv))
+        line["hull3d_batched"]["parity_vs_oracle_sample"] = {"instances": len(checks["hull3d_batched"]),
+                                                             "ok": bool(ok)}
+    if "regimes" in checks:
+        for name, (p, got) in checks["regimes"].items():
+            t0 = time.perf_counter()
+            want = oracle.hull2d(p)
+            line["regimes"][name]["oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+            line["regimes"][name]["parity_vs_oracle"] = bool(np.array_equal(want, got))
 
 
 def tuned_graph_leg(call, key, want, steps, outs, out_names):
@@ -185,11 +218,9 @@ def batched_leg(steps: int):
     torch.cuda.synchronize()
     sec_seq = time.perf_counter() - t0
 
-    # oracle parity on a sample of instances
-    import oracle  # checker only
-    sample = list(range(0, k, 97))
-    par = all(np.array_equal(oracle.hull2d(pts_np[:, off_np[i]:off_np[i + 1]]),
-                             idx_host[hoff_host[i]:hoff_host[i + 1]]) for i in sample)
+    # a sample of instances for the oracle leg
+    check = [(np.ascontiguousarray(pts_np[:, off_np[i]:off_np[i + 1]]),
+              idx_host[hoff_host[i]:hoff_host[i + 1]].copy()) for i in range(0, k, 97)]
     sctx.close()
     ctx.close()
     del singles, pts, off
@@ -207,7 +238,7 @@ def batched_leg(steps: int):
                                     "match_batched": bool(seq_ok)},
         "autotuned_graph": tuned,
         "modes_identical": same,
-        "parity_vs_oracle_sample": {"instances": len(sample), "ok": bool(par)},
+        "parity_vs_oracle_sample": None,
         "rounds": int(st_f["rounds"]),
         "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"]) if st_f["filter_tests"] else 0.0,
         "round_kernel": {"launches_per_step": launches / tsteps, "avg_launch_us": round(avg_ms * 1e3, 2),
@@ -216,7 +247,52 @@ def batched_leg(steps: int):
         "device_time_us": {"all_kernels": round(agg["kernel_ms"] / tsteps * 1e3, 1),
                            "extremes": round(agg["extremes_ms"] / tsteps * 1e3, 1),
                            "segments": round(agg["segment_ms"] / tsteps * 1e3, 1)},
-    }
+    }, check
+
+
+def regimes_leg(steps: int):
+    """The input regimes the paper times (Section 5): points in a disk against
+    points on and near a circle, at the same size (4,194,304), and the small
+    disk.  Both forms on each; the circle's slowdown over the disk is the
+    figure the paper reports for its own GPU (Section 6)."""
+    import torch
+
+    import workloads
+    from paper_1201_2936_amd import qh
+
+    cases = [("disk_65k", workloads.disk_65k), ("disk_4m", workloads.disk_4m),
+             ("circle_mix_4m", workloads.circle_mix_4m)]
+    ctx = qh.Context()
+    out, check = {}, {}
+    for name, gen in cases:
+        p_np = gen()
+        n = p_np.shape[1]
+        p = torch.from_numpy(p_np).cuda()
+        sec_f, (idx_f, st_f) = time_steps(lambda: qh.qh_hull2d(p, mode=qh.QH_FP32_FILTER, ctx=ctx), steps, 2)
+        sec_x, (idx_x, _) = time_steps(lambda: qh.qh_hull2d(p, mode=qh.QH_EXACT_INT64, ctx=ctx), steps, 2)
+        _, tt = qh.qh_hull2d(p, mode=qh.QH_FP32_FILTER, ctx=ctx, timing=True)
+        out[name] = {
+            "n": n, "hull_vertices": int(idx_f.numel()), "rounds": int(st_f["rounds"]),
+            "finish_round": int(st_f["finish_round"]),
+            "fp32_filter": {"value": round(n / sec_f / 1e6, 3), "unit": "Mpoints/s",
+                            "ms_per_step": round(sec_f * 1e3, 4)},
+            "exact_int64": {"value": round(n / sec_x / 1e6, 3), "unit": "Mpoints/s",
+                            "ms_per_step": round(sec_x * 1e3, 4)},
+            "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"]) if st_f["filter_tests"] else 0.0,
+            "device_time_us": {"all_kernels": round(tt["kernel_ms"] * 1e3, 1),
+                               "rounds": round(tt["round_kernel_ms"] * 1e3, 1),
+                               "segments": round(tt["segment_ms"] * 1e3, 1)},
+            "modes_identical": bool(torch.equal(idx_f, idx_x)),
+            "parity_vs_oracle": None,
+        }
+        check[name] = (p_np, idx_f.cpu().numpy())
+        del p
+    ctx.close()
+    torch.cuda.empty_cache()
+    out["circle_over_disk_4m"] = {
+        form: round(out["circle_mix_4m"][form]["ms_per_step"] / out["disk_4m"][form]["ms_per_step"], 2)
+        for form in ("fp32_filter", "exact_int64")}
+    return out, check
 
 
 def hull3d_leg(steps: int):
@@ -239,11 +315,7 @@ def hull3d_leg(steps: int):
                                          steps, 1)
     same = bool(torch.equal(f_x, f_f) and torch.equal(v_x, v_f))
     _, _, tt = qh.qh_hull3d(pts, mode=qh.QH_EXACT_INT64, ctx=ctx, timing=True)
-    import oracle  # checker only
-    t0 = time.perf_counter()
-    want_f, want_v = oracle.hull3d(pts_np)
-    oracle_s = time.perf_counter() - t0
-    par = bool(np.array_equal(v_x.cpu().numpy(), want_v) and np.array_equal(f_x.cpu().numpy(), want_f))
+    check = [(pts_np, f_x.cpu().numpy(), v_x.cpu().numpy())]
     ctx.close()
     return {
         "workload": "ball_sphere_5m: 4,194,304 in the ball of radius 2^16 + 1,048,576 on its sphere",
@@ -254,7 +326,7 @@ def hull3d_leg(steps: int):
                         "ms_per_step": round(sec_f * 1e3, 2),
                         "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"])
                         if st_f["filter_tests"] else 0.0},
-        "modes_identical": same, "parity_vs_oracle": par,
+        "modes_identical": same, "parity_vs_oracle": None,
         "rounds": int(st_x["rounds"]), "host_syncs": int(st_x["host_syncs"]),
         "max_active_facets": int(st_x["max_segments"]),
         "host_topology_ms": round(tt["host_ms"], 2),
@@ -262,8 +334,7 @@ def hull3d_leg(steps: int):
                       "init": round(tt["extremes_ms"], 3), "all": round(tt["kernel_ms"], 3)},
         "classify_apex_GBs": round(tt["round_kernel_bytes"] / ((tt["round_kernel_ms"] + tt["segment_ms"]) * 1e-3) / 1e9, 1)
         if tt["round_kernel_ms"] > 0 else None,
-        "oracle_s": round(oracle_s, 2),
-    }
+    }, check
 
 
 def hull3d_batched_leg(steps: int):
@@ -297,12 +368,8 @@ def hull3d_batched_leg(steps: int):
     for i, (f1, v1, _) in enumerate(outs):
         same &= (np.array_equal(f1.cpu().numpy(), fac[foff[i]:foff[i + 1]]) and
                  np.array_equal(v1.cpu().numpy(), ver[voff[i]:voff[i + 1]]))
-    import oracle  # checker only
-    sample = list(range(0, k, 37))
-    par = True
-    for i in sample:
-        wf, wv = oracle.hull3d(pts_np[:, off_np[i]:off_np[i + 1]])
-        par &= np.array_equal(wf, fac[foff[i]:foff[i + 1]]) and np.array_equal(wv, ver[voff[i]:voff[i + 1]])
+    check = [(np.ascontiguousarray(pts_np[:, off_np[i]:off_np[i + 1]]), fac[foff[i]:foff[i + 1]].copy(),
+              ver[voff[i]:voff[i + 1]].copy()) for i in range(0, k, 37)]
     sctx.close()
     ctx.close()
     return {
@@ -313,10 +380,10 @@ def hull3d_batched_leg(steps: int):
                         "ms_per_step": round(sec_b * 1e3, 2), "steps": steps},
         "sequential_single_calls": {"value": round(N / sec_seq / 1e6, 3), "unit": "Mpoints/s",
                                     "ms": round(sec_seq * 1e3, 1), "calls": k, "match_batched": bool(same)},
-        "parity_vs_oracle_sample": {"instances": len(sample), "ok": bool(par)},
+        "parity_vs_oracle_sample": None,
         "rounds": int(st["rounds"]), "facets": int(foff[-1]), "vertices": int(voff[-1]),
         "host_topology_ms": round(st["host_ms"], 2),
-    }
+    }, check
 
 
 def select_leg(steps: int):
@@ -406,10 +473,7 @@ def main():
     later_ms = agg["round_kernel_ms"] - agg["split_ms"]
     later_bytes = agg["round_kernel_bytes"] - split_bytes
 
-    import oracle  # checker only: parity of the timed output, and the CPU baseline
-    want = oracle.hull2d(pts_np)
-    parity = bool(np.array_equal(idx_f.cpu().numpy(), want) and
-                  np.array_equal(idx_x.cpu().numpy(), want))
+    checks = {"headline": (pts_np, idx_f.cpu().numpy(), idx_x.cpu().numpy())}
 
     traffic = load_traffic()
     line = {
@@ -430,8 +494,8 @@ def main():
         "exact_int64": {"value": round(n / sec_x / 1e6, 3), "unit": "Mpoints/s",
                         "ms_per_step": round(sec_x * 1e3, 4), "dtype": "i64"},
         "autotuned_graph": tuned,
-        "hull_vertices": int(len(want)),
-        "parity_vs_oracle": parity,
+        "hull_vertices": int(idx_f.numel()),
+        "parity_vs_oracle": None,
         "rounds": int(st_f["rounds"]),
         "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"]
                           if st_f["filter_tests"] else 0.0),
@@ -454,17 +518,18 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
     }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(pts_np)
     ctx.close()
     del pts
     torch.cuda.empty_cache()
+    line["regimes"], checks["regimes"] = regimes_leg(max(3, min(args.steps, 10)))
     if not args.no_batched:
-        line["batched"] = batched_leg(max(2, min(args.steps, 5)))
+        line["batched"], checks["batched"] = batched_leg(max(2, min(args.steps, 5)))
     if not args.no_3d:
-        line["hull3d"] = hull3d_leg(max(2, min(args.steps, 3)))
-        line["hull3d_batched"] = hull3d_batched_leg(max(2, min(args.steps, 3)))
+        line["hull3d"], checks["hull3d"] = hull3d_leg(max(2, min(args.steps, 3)))
+        line["hull3d_batched"], checks["hull3d_batched"] = hull3d_batched_leg(max(2, min(args.steps, 3)))
     line["select"] = select_leg(5)
+    if not args.no_cpu_baseline:
+        oracle_leg(line, checks)
     print(json.dumps(line), flush=True)
 
 

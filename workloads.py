@@ -180,6 +180,13 @@ def _support_lines(pts: np.ndarray, rng: np.random.Generator,
     return np.stack([lx, ly]).astype(np.int32)
 
 
+def disk_4m() -> np.ndarray:
+    """2D, n = 4,194,304 uniform in the disk of radius 2^20 (seed 11): the
+    points-in-a-disk input at the size of circle_mix_4m, so the two regimes
+    compare at one size."""
+    return disk(rng_for(11), N_CIRCLE_MIX)
+
+
 def circle_mix_4m() -> np.ndarray:
     """2D, n = 4,194,304: snapped circle + disk + 64 exactly collinear lines.
 
@@ -256,6 +263,7 @@ def batched_balls3d(k: int = 512):
 WORKLOADS = {
     "disk_65k": disk_65k,
     "square_16m": square_16m,
+    "disk_4m": disk_4m,
     "circle_mix_4m": circle_mix_4m,
     "ball_sphere_5m": ball_sphere_5m,
 }
