@@ -11,7 +11,7 @@ constexpr int kTile = kBlock * kItems;   // points per tile
 constexpr int kSlots = 128;              // segments per LDS window (multi-segment tiles)
 constexpr int kPieceItems = 8;           // tile counts per thread of the piece scan
 constexpr int kSegBlock = 256;           // segments per tile of the segment phase
-constexpr int kRankSmallCap = 4096;      // hull ids ranked inside one block's LDS
+constexpr int kRankSmallCap = 8192;      // hull ids ranked inside one block's LDS (64 KB)
 constexpr int kFinCap = 1024;            // points of a segment one block finishes in LDS
 constexpr int32_t kCoordMax2D = (1 << 30) - 1;
 constexpr int kMaxStamps = 256;

@@ -355,6 +355,8 @@ struct SegSmem {
     int16_t q_map[2 * kSegBlock];
     int32_t o_t0[kSegBlock], o_t1[kSegBlock];
     int32_t o_ka[2 * kSegBlock], o_kb[2 * kSegBlock], o_id[2 * kSegBlock];
+    int32_t o_st[2 * kSegBlock], o_en[2 * kSegBlock];
+    Best qres[2 * kSegBlock];   // merged records of the queued segments (by owner)
     Best red[2 * kNW];
 };
 
@@ -2007,42 +2009,41 @@ __device__ void phase_finish(const Ws2 &ws, const HullArgs &a, int r, FinSmem *s
     }
 }
 
-// merge of a slot's records of both children into acc0 / acc1
-__device__ __forceinline__ void seg_take(const Ws2 &ws, int t, bool last, Best &acc0, Best &acc1) {
-    const Best *rec = last ? ws.recL : ws.recF;
-    const Best b0 = rec[t * 2 + 0], b1 = rec[t * 2 + 1];
-    rec_merge(acc0, b0);
-    rec_merge(acc1, b1);
-}
-
-// Merge the record slots of one segment, both children, with the whole block
-// (every thread gets the results).
-__device__ __forceinline__ void block_merge_seg(const Ws2 &ws, int p, int R, int nt0, int T, int t0,
-                                                int t1, Best *red, Best &m0, Best &m1) {
+// Merge the record slots of one segment, both children, with one wave (the
+// result is valid in its last lane).
+__device__ __forceinline__ void wave_merge_seg(const Ws2 &ws, int p, int R, int nt0, int T, int t0,
+                                               int t1, Best &m0, Best &m1) {
     const TileInfo *ti = ws.tinfo(p, R);
     const int off = R ? nt0 : 0;
     const bool s0 = ti[t0 - off].single != 0, s1 = ti[t1 - off].single != 0;
     Best acc0 = best_none(), acc1 = best_none();
     const int ns = seg_slots(T, t0, t1);
-    for (int k = threadIdx.x; k < ns; k += kSegBlock) {
-        bool last;
-        const int t = seg_slot(T, t0, t1, s0, s1, k, last);
-        if (t >= 0) seg_take(ws, t, last, acc0, acc1);
+    // four slots per lane requested at a time, then merged (order-free)
+    for (int k0 = lane_id(); k0 < ns; k0 += 4 * kWave) {
+        Best c0[4], c1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c0[u] = best_none();
+            c1[u] = best_none();
+            bool last;
+            const int k = k0 + u * kWave;
+            const int t = k < ns ? seg_slot(T, t0, t1, s0, s1, k, last) : -1;
+            if (t >= 0) {
+                const Best *rec = last ? ws.recL : ws.recF;
+                c0[u] = rec[t * 2 + 0];
+                c1[u] = rec[t * 2 + 1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            rec_merge(acc0, c0[u]);
+            rec_merge(acc1, c1[u]);
+        }
     }
-    wave_rec(acc0);
-    wave_rec(acc1);
-    if (lane_id() == 0) {
-        red[2 * (threadIdx.x / kWave) + 0] = acc0;
-        red[2 * (threadIdx.x / kWave) + 1] = acc1;
-    }
-    __syncthreads();
-    m0 = red[0];
-    m1 = red[1];
-    for (int w = 1; w < kSegBlock / kWave; ++w) {
-        rec_merge(m0, red[2 * w + 0]);
-        rec_merge(m1, red[2 * w + 1]);
-    }
-    __syncthreads();
+    wave_rec63(acc0);
+    wave_rec63(acc1);
+    m0 = acc0;
+    m1 = acc1;
 }
 // ---------------------------------------------------------------------------
 // segments: hull insertion, multi-tile argmax, next segment table
@@ -2145,10 +2146,27 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
                 const TileInfo *ti = ws.tinfo(p, R);
                 const int off = R ? nt0 : 0;
                 const bool s0 = ti[t0 - off].single != 0, s1 = ti[t1 - off].single != 0;
-                for (int k = 0; k < ns; ++k) {
-                    bool last;
-                    const int t = seg_slot(T, t0, t1, s0, s1, k, last);
-                    if (t >= 0) seg_take(ws, t, last, b0, b1);
+                // four slots' records requested at a time, then merged (the
+                // merge is order-free), so a thread waits ns / 4 times, not ns
+                for (int k0 = 0; k0 < ns; k0 += 4) {
+                    Best c0[4], c1[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        c0[u] = best_none();
+                        c1[u] = best_none();
+                        bool last;
+                        const int t = k0 + u < ns ? seg_slot(T, t0, t1, s0, s1, k0 + u, last) : -1;
+                        if (t >= 0) {
+                            const Best *rec = last ? ws.recL : ws.recF;
+                            c0[u] = rec[t * 2 + 0];
+                            c1[u] = rec[t * 2 + 1];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        rec_merge(b0, c0[u]);
+                        rec_merge(b1, c1[u]);
+                    }
                 }
             } else {
                 const int qi = atomicAdd(&sm->qn_apex, 1);
@@ -2158,14 +2176,23 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             }
         }
         __syncthreads();
+        // segments over many slots: one wave each, the block's waves side by side
         const int nqa = sm->qn_apex;
-        for (int qi = 0; qi < nqa; ++qi) {
+        for (int qi = wv; qi < nqa; qi += kSegBlock / kWave) {
             const int own = sm->q_apex[qi];
             const int a0 = sm->o_t0[own], a1 = sm->o_t1[own];
             const int Ro = own + tile * kSegBlock < S0 ? 0 : 1;
             Best m0, m1;
-            block_merge_seg(ws, p, Ro, nt0, T, a0, a1, sm->red, m0, m1);
-            if (tid == own) { b0 = m0; b1 = m1; }
+            wave_merge_seg(ws, p, Ro, nt0, T, a0, a1, m0, m1);
+            if (lane == kWave - 1) {
+                sm->qres[own * 2 + 0] = m0;
+                sm->qres[own * 2 + 1] = m1;
+            }
+        }
+        __syncthreads();
+        if (valid && t0 != t1 && seg_slots(T, t0, t1) > 12) {
+            b0 = sm->qres[tid * 2 + 0];
+            b1 = sm->qres[tid * 2 + 1];
         }
         const int c0 = valid ? b0.cnt : 0, c1 = valid ? b1.cnt : 0;
         // the winners' coordinates (the one-segment records carry the index only)
@@ -2282,6 +2309,8 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
                 sm->o_ka[tid * 2 + c] = ka;
                 sm->o_kb[tid * 2 + c] = kb;
                 sm->o_id[tid * 2 + c] = id;
+                sm->o_st[tid * 2 + c] = st;
+                sm->o_en[tid * 2 + c] = st + ln;
             }
         }
         __syncthreads();
@@ -2290,12 +2319,11 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             const int o = sm->q_map[qi];
             const int c = o & 1;
             const int ka = sm->o_ka[o], kb = sm->o_kb[o], id = sm->o_id[o];
-            // the owner wrote the child's table entry before the barrier
-            const SegGeo cg = ws.geo(q, c)[id];
+            // the child's extent from LDS: no wait on a global load per child
             TileInfo ti;
             ti.seg = id;
-            ti.start = cg.start;
-            ti.end = cg.start + cg.len;
+            ti.start = sm->o_st[o];
+            ti.end = sm->o_en[o];
             for (int kk = ka + tid; kk < kb; kk += kSegBlock) {
                 ti.single = ti.end >= min((kk + 1) * kTile, c == 0 ? Nn0 : Nn1) ? 1 : 0;
                 ws.tinfo(q, c)[kk] = ti;

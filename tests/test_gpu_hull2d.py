@@ -282,6 +282,32 @@ def test_batched_many_tiny_instances(qhm, ctx, mode):
     assert got.tolist() == want.tolist()
 
 
+def _polygon_instance(rng, m, r):
+    """m vertices of a strictly convex polygon (a regular m-gon of radius r,
+    rounded to the grid) and 3m points strictly inside, shuffled."""
+    t = 2 * np.pi * np.arange(m) / m
+    ring = np.stack([np.rint(r * np.cos(t)), np.rint(r * np.sin(t))]).astype(np.int64)
+    inner = rng.integers(-r // 3, r // 3, size=(2, 3 * m), endpoint=True)
+    pts = np.concatenate([ring, inner], axis=1)
+    return np.ascontiguousarray(pts[:, rng.permutation(pts.shape[1])]).astype(np.int32)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("k", [511, 512, 513])
+def test_batched_hull_ids_around_rank_cap(qhm, ctx, mode, k):
+    """16 hull vertices per instance: 8,176, 8,192 and 8,208 hull ids in all,
+    on both sides of the 8,192 ids the output ranks in one block's LDS."""
+    rng = np.random.default_rng(880 + k)
+    insts = [_polygon_instance(rng, 16, 1000) for _ in range(k)]
+    pts, offsets = _concat(insts)
+    _say(f"batched rank cap k={k} mode={mode}")
+    want, want_off = oracle.hull2d_batched(pts, offsets)
+    got, got_off, _ = _gpu_batched(qhm, ctx, pts, offsets, mode)
+    assert int(want_off[-1]) == 16 * k
+    assert got_off.tolist() == want_off.tolist()
+    assert got.tolist() == want.tolist()
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_batched_equals_single_calls(qhm, ctx, mode):
     sizes = np.array([256, 300, 5000, 70000, 2048, 2049, 1 << 17, 999], np.int64)
