@@ -782,14 +782,27 @@ __device__ __forceinline__ void block_merge_ext(const Ws2 &ws, int T, int t0, in
     const bool s0 = ti[t0].single != 0, s1 = ti[t1].single != 0;
     Best a0 = best_none(), a1 = best_none();
     const int ns = seg_slots(T, t0, t1);
-    for (int k = threadIdx.x; k < ns; k += kBlock) {
-        bool last;
-        const int t = seg_slot(T, t0, t1, s0, s1, k, last);
-        if (t < 0) continue;
-        const Best *rec = last ? ws.recL0 : ws.recF0;
-        const Best b0 = rec[t * 2 + 0], b1 = rec[t * 2 + 1];
-        best_merge(a0, b0);
-        best_merge(a1, b1);
+    // four slots per thread requested at a time, then merged (order-free)
+    for (int k0 = threadIdx.x; k0 < ns; k0 += 4 * kBlock) {
+        Best c0[4], c1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c0[u] = best_none();
+            c1[u] = best_none();
+            bool last;
+            const int k = k0 + u * kBlock;
+            const int t = k < ns ? seg_slot(T, t0, t1, s0, s1, k, last) : -1;
+            if (t >= 0) {
+                const Best *rec = last ? ws.recL0 : ws.recF0;
+                c0[u] = rec[t * 2 + 0];
+                c1[u] = rec[t * 2 + 1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            best_merge(a0, c0[u]);
+            best_merge(a1, c1[u]);
+        }
     }
     wave_best(a0);
     wave_best(a1);
@@ -2436,17 +2449,19 @@ __device__ __forceinline__ void rank_init_one(const Ws2 &ws, int x, int32_t &su,
 // ---------------------------------------------------------------------------
 // output kernels
 // ---------------------------------------------------------------------------
-// small hulls: pointer jumping in one block's LDS
-__global__ __launch_bounds__(kBlock) void k_rank_small(Ws2 ws, int32_t H, int32_t steps) {
+// small hulls: pointer jumping in one block's LDS (a block of the device's
+// largest size, so each jump is a few LDS loads per thread)
+constexpr int kRankBlock = 1024;
+__global__ __launch_bounds__(kRankBlock) void k_rank_small(Ws2 ws, int32_t H, int32_t steps) {
     __shared__ RankSmem sm;
-    for (int x = threadIdx.x; x < H; x += kBlock) rank_init_one(ws, x, sm.su[x], sm.di[x]);
+    for (int x = threadIdx.x; x < H; x += kRankBlock) rank_init_one(ws, x, sm.su[x], sm.di[x]);
     __syncthreads();
-    constexpr int PER = kRankSmallCap / kBlock;
+    constexpr int PER = kRankSmallCap / kRankBlock;
     for (int itr = 0; itr < steps; ++itr) {
         int ns[PER], nd[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const int x = threadIdx.x + j * kBlock;
+            const int x = threadIdx.x + j * kRankBlock;
             if (x < H) {
                 const int s = sm.su[x];
                 nd[j] = sm.di[x] + sm.di[s];
@@ -2456,12 +2471,12 @@ __global__ __launch_bounds__(kBlock) void k_rank_small(Ws2 ws, int32_t H, int32_
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const int x = threadIdx.x + j * kBlock;
+            const int x = threadIdx.x + j * kRankBlock;
             if (x < H) { sm.su[x] = ns[j]; sm.di[x] = nd[j]; }
         }
         __syncthreads();
     }
-    for (int x = threadIdx.x; x < H; x += kBlock) ws.dist(0)[x] = sm.di[x];
+    for (int x = threadIdx.x; x < H; x += kRankBlock) ws.dist(0)[x] = sm.di[x];
 }
 
 __global__ void k_rank_init(Ws2 ws, int32_t H) {
@@ -2604,7 +2619,7 @@ hipError_t launch_output(const Ws2 &ws, const HullArgs &a, int32_t H, hipStream_
     int src = 0;
     if (H > 0) {
         if (H <= kRankSmallCap) {
-            hipLaunchKernelGGL(k_rank_small, dim3(1), dim3(kBlock), 0, st, ws, H, steps);
+            hipLaunchKernelGGL(k_rank_small, dim3(1), dim3(kRankBlock), 0, st, ws, H, steps);
         } else {
             const int grid = (H + 255) / 256;
             hipLaunchKernelGGL(k_rank_init, dim3(grid), dim3(256), 0, st, ws, H);
