@@ -419,6 +419,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched 4,096-instance leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D leg")
+    ap.add_argument("--no-regimes", action="store_true", help="skip the disk and circle leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the hull of one point set "
@@ -521,7 +522,8 @@ def main():
     ctx.close()
     del pts
     torch.cuda.empty_cache()
-    line["regimes"], checks["regimes"] = regimes_leg(max(3, min(args.steps, 10)))
+    if not args.no_regimes:
+        line["regimes"], checks["regimes"] = regimes_leg(max(3, min(args.steps, 10)))
     if not args.no_batched:
         line["batched"], checks["batched"] = batched_leg(max(2, min(args.steps, 5)))
     if not args.no_3d:
