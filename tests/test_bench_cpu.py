@@ -1,0 +1,62 @@
+"""The bench's oracle leg on the CPU: it must report parity only when every
+kept GPU output equals the oracle's, and name the leg that differs.
+
+The "GPU outputs" here are the oracle's own results (or altered copies), so
+the test needs no GPU; it checks the bookkeeping of bench.oracle_leg.
+"""
+import numpy as np
+
+import bench
+import oracle
+import workloads
+
+
+def _checks():
+    p = workloads.small_random(21, 3000, 1 << 20)
+    w = oracle.hull2d(p)
+    inst = [workloads.small_random(30 + i, 200, 1000) for i in range(3)]
+    p3 = workloads.small_ball3(5, 300, 1000)
+    f3, v3 = oracle.hull3d(p3)
+    return {
+        "headline": (p, w.copy(), w.copy()),
+        "batched": [(q, oracle.hull2d(q)) for q in inst],
+        "hull3d": [(p3, f3.copy(), v3.copy())],
+        "hull3d_batched": [(p3, f3.copy(), v3.copy())],
+        "regimes": {"disk_65k": (p, w.copy())},
+    }
+
+
+def _line():
+    return {"batched": {}, "hull3d": {}, "hull3d_batched": {}, "regimes": {"disk_65k": {}}}
+
+
+def test_oracle_leg_all_equal():
+    line = _line()
+    bench.oracle_leg(line, _checks(), budget_s=0.05)
+    assert line["parity_vs_oracle"] is True
+    assert line["batched"]["parity_vs_oracle_sample"] == {"instances": 3, "ok": True}
+    assert line["hull3d"]["parity_vs_oracle"] is True
+    assert line["hull3d_batched"]["parity_vs_oracle_sample"]["ok"] is True
+    assert line["regimes"]["disk_65k"]["parity_vs_oracle"] is True
+    cb = line["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["value"] > 0
+
+
+def test_oracle_leg_reports_each_mismatch():
+    c = _checks()
+    p, w, _ = c["headline"]
+    c["headline"] = (p, w, w[::-1].copy())                 # the exact form differs
+    q, g = c["batched"][1]
+    c["batched"][1] = (q, g[:-1])                          # one instance lost a vertex
+    p3, f3, v3 = c["hull3d"][0]
+    f3b = f3.copy()
+    f3b[0] = f3b[0][::-1]                                  # one facet flipped
+    c["hull3d"] = [(p3, f3b, v3)]
+    line = _line()
+    bench.oracle_leg(line, c, budget_s=0.05)
+    assert line["parity_vs_oracle"] is False
+    assert line["batched"]["parity_vs_oracle_sample"]["ok"] is False
+    assert line["hull3d"]["parity_vs_oracle"] is False
+    assert line["hull3d_batched"]["parity_vs_oracle_sample"]["ok"] is True
+    assert line["regimes"]["disk_65k"]["parity_vs_oracle"] is True
+    assert isinstance(np.bool_(line["parity_vs_oracle"]).item(), bool)
