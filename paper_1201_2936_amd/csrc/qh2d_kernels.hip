@@ -971,16 +971,6 @@ __device__ __forceinline__ int64_t child_d(int32_t x, int32_t y, uint32_t st, co
     return st == 0 ? cross_i64(x, y, g[0], g[1], g[2], g[3]) : cross_i64(x, y, g[2], g[3], g[4], g[5]);
 }
 
-// FP32 filter: is the point a possible argmax of its child (upper bound of its
-// distance reaches the best lower bound lmk of the child)?
-__device__ __forceinline__ bool filter_cand(int32_t x, int32_t y, uint32_t st, const int32_t *g,
-                                            uint32_t lmk) {
-    float B;
-    const float e = st == 0 ? cross_f32(x, y, g[0], g[1], g[2], g[3], B)
-                            : cross_f32(x, y, g[2], g[3], g[4], g[5], B);
-    return fkey(__fadd_rn(e, 2.f * B)) >= lmk;
-}
-
 // Round r ends the recursion in one pass when no segment has more than
 // fin_cap points and there are at most fin_segs segments (a workgroup takes
 // one segment at a time: many small segments go faster as rounds); decided
@@ -1558,9 +1548,16 @@ __device__ __forceinline__ void phase_round_multi(const Ws2 &ws, const HullArgs 
                     (&sm->scnt[0][0])[j] = 0;
                 }
                 __syncthreads();
-                // classify; the best distance (exact) or lower bound (filter) per slot
+                // classify; the best distance (exact) or lower bound (filter) per
+                // slot.  The filter keeps each survivor's upper bound key, the
+                // value the argmax steps below compare with the slot's best
+                // lower bound.
+                uint32_t ckey[kItems];
+                uint64_t dd[kItems];  // exact distance to the child's edge (candidates)
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
+                    ckey[i] = 0;
+                    dd[i] = 0;
                     const int v = item_pos(lo, i);
                     const int sl = (int)((slotpk[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
                     if (v >= hi || sl < w0 || sl >= w0 + wn) continue;
@@ -1573,11 +1570,13 @@ __device__ __forceinline__ void phase_round_multi(const Ws2 &ws, const HullArgs 
                         const int64_t d0 = cross_i64(X[i], Y[i], ux, uy, fx, fy);
                         if (d0 > 0) {
                             st = 0;
+                            dd[i] = (uint64_t)d0;
                             atomicMax(&sm->k1[0][ls], (uint64_t)d0);
                         } else {
                             const int64_t d1 = cross_i64(X[i], Y[i], fx, fy, vx, vy);
                             if (d1 > 0) {
                                 st = 1;
+                                dd[i] = (uint64_t)d1;
                                 atomicMax(&sm->k1[1][ls], (uint64_t)d1);
                             }
                         }
@@ -1592,6 +1591,7 @@ __device__ __forceinline__ void phase_round_multi(const Ws2 &ws, const HullArgs 
                         if (out0) {
                             st = 0;
                             atomicMax(&sm->lm[0][ls], fkey(__fsub_rn(e0, 2.f * B0)));
+                            ckey[i] = fkey(__fadd_rn(e0, 2.f * B0));
                         } else {
                             float B1;
                             const float e1 = cross_f32(X[i], Y[i], fx, fy, vx, vy, B1);
@@ -1603,6 +1603,7 @@ __device__ __forceinline__ void phase_round_multi(const Ws2 &ws, const HullArgs 
                             if (out1) {
                                 st = 1;
                                 atomicMax(&sm->lm[1][ls], fkey(__fsub_rn(e1, 2.f * B1)));
+                                ckey[i] = fkey(__fadd_rn(e1, 2.f * B1));
                             }
                         }
                     }
@@ -1619,14 +1620,14 @@ __device__ __forceinline__ void phase_round_multi(const Ws2 &ws, const HullArgs 
                         const uint32_t st = (stbits >> (2 * i)) & 3u;
                         if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
                         const int ls = sl - w0;
-                        if (!filter_cand(X[i], Y[i], st, sm->lgeo[ls], sm->lm[st][ls])) continue;
+                        if (ckey[i] < sm->lm[st][ls]) continue;
                         ncand++;
-                        atomicMax(&sm->k1[st][ls], (uint64_t)child_d(X[i], Y[i], st, sm->lgeo[ls]));
+                        dd[i] = (uint64_t)child_d(X[i], Y[i], st, sm->lgeo[ls]);
+                        atomicMax(&sm->k1[st][ls], dd[i]);
                     }
                     __syncthreads();
                 }
-                // tie-break among the farthest points, then the winner (the
-                // exact distances are recomputed rather than kept)
+                // tie-break among the farthest points, then the winner
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
                     const int v = item_pos(lo, i);
@@ -1634,8 +1635,8 @@ __device__ __forceinline__ void phase_round_multi(const Ws2 &ws, const HullArgs 
                     const uint32_t st = (stbits >> (2 * i)) & 3u;
                     if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
                     const int ls = sl - w0;
-                    if (MODE != 0 && !filter_cand(X[i], Y[i], st, sm->lgeo[ls], sm->lm[st][ls])) continue;
-                    if ((uint64_t)child_d(X[i], Y[i], st, sm->lgeo[ls]) != sm->k1[st][ls]) continue;
+                    if (MODE != 0 && ckey[i] < sm->lm[st][ls]) continue;
+                    if (dd[i] != sm->k1[st][ls]) continue;
                     const int ex = st == 0 ? sm->lgeo[ls][2] - sm->lgeo[ls][0] : sm->lgeo[ls][4] - sm->lgeo[ls][2];
                     const int ey = st == 0 ? sm->lgeo[ls][3] - sm->lgeo[ls][1] : sm->lgeo[ls][5] - sm->lgeo[ls][3];
                     atomicMin(&sm->k2[st][ls], tie_key(X[i], Y[i], I[i], ex, ey));
@@ -1648,8 +1649,8 @@ __device__ __forceinline__ void phase_round_multi(const Ws2 &ws, const HullArgs 
                     const uint32_t st = (stbits >> (2 * i)) & 3u;
                     if (v >= hi || st > 1 || sl < w0 || sl >= w0 + wn) continue;
                     const int ls = sl - w0;
-                    if (MODE != 0 && !filter_cand(X[i], Y[i], st, sm->lgeo[ls], sm->lm[st][ls])) continue;
-                    if ((uint64_t)child_d(X[i], Y[i], st, sm->lgeo[ls]) != sm->k1[st][ls]) continue;
+                    if (MODE != 0 && ckey[i] < sm->lm[st][ls]) continue;
+                    if (dd[i] != sm->k1[st][ls]) continue;
                     const int ex = st == 0 ? sm->lgeo[ls][2] - sm->lgeo[ls][0] : sm->lgeo[ls][4] - sm->lgeo[ls][2];
                     const int ey = st == 0 ? sm->lgeo[ls][3] - sm->lgeo[ls][1] : sm->lgeo[ls][5] - sm->lgeo[ls][3];
                     if (tie_key(X[i], Y[i], I[i], ex, ey) == sm->k2[st][ls]) {
