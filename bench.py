@@ -83,6 +83,43 @@ def time_steps(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps, out
 
 
+def _oracle_batched(oracle, pts, off, got, got_off):
+    """The oracle on every instance of a batch: once in one call on one core,
+    once over a pool of host threads (contiguous instance ranges of about
+    equal point counts, several per thread; the C oracle runs without the
+    interpreter lock).  Returns (the timings, parity of the whole batch)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    n = int(off[-1])
+    k = len(off) - 1
+    t0 = time.perf_counter()
+    want, want_off = oracle.hull2d_batched(pts, off)
+    t1 = time.perf_counter() - t0
+    threads = max(1, min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "0")) or 10**6))
+    parts = 4 * threads
+    cuts = np.searchsorted(off, np.linspace(0, n, parts + 1)[1:-1])
+    bounds = np.unique(np.concatenate([[0], cuts, [k]]))
+    ranges = [(int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+
+    def part(r):
+        a, b = r
+        sub = np.ascontiguousarray(pts[:, off[a]:off[b]])
+        return oracle.hull2d_batched(sub, off[a:b + 1] - off[a])
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(part, ranges))
+    t2 = time.perf_counter() - t0
+    pooled = np.concatenate([r[0] for r in res]) if res else np.zeros(0, np.int32)
+    ok = bool(np.array_equal(want, got) and np.array_equal(want_off, got_off) and np.array_equal(pooled, want))
+    timing = {"kind": "oracle", "unit": "Mpoints/s", "sample": f"all {k} instances ({n} points)",
+              "single_core": {"value": round(n / t1 / 1e6, 3), "ms": round(t1 * 1e3, 1), "cores": 1},
+              "thread_pool": {"value": round(n / t2 / 1e6, 3), "ms": round(t2 * 1e3, 1), "cores": threads}}
+    return timing, ok
+
+
 def oracle_leg(line, checks, budget_s: float = 12.0):
     """The leg that runs the oracle (a plain single-threaded C Quickhull,
     test infrastructure that no GPU leg calls): ``cpu_baseline`` times it on
@@ -108,8 +145,11 @@ def oracle_leg(line, checks, budget_s: float = 12.0):
         "sample": f"{WORKLOAD} full ({n} points), {runs} runs in {el:.1f} s, single thread"}
     line["parity_vs_oracle"] = bool(all(np.array_equal(got, want) for got in checks["headline"][1:]))
     if "batched" in checks:
-        ok = all(np.array_equal(oracle.hull2d(p), got) for p, got in checks["batched"])
-        line["batched"]["parity_vs_oracle_sample"] = {"instances": len(checks["batched"]), "ok": bool(ok)}
+        sample = checks["batched"]["sample"]
+        ok = all(np.array_equal(oracle.hull2d(p), got) for p, got in sample)
+        line["batched"]["parity_vs_oracle_sample"] = {"instances": len(sample), "ok": bool(ok)}
+        line["batched"]["cpu_baseline"], line["batched"]["parity_vs_oracle"] = \
+            _oracle_batched(oracle, *checks["batched"]["full"])
     if "hull3d" in checks:
         p, gf, gv = checks["hull3d"][0]
         t0 = time.perf_counter()
@@ -218,9 +258,10 @@ def batched_leg(steps: int):
     torch.cuda.synchronize()
     sec_seq = time.perf_counter() - t0
 
-    # a sample of instances for the oracle leg
-    check = [(np.ascontiguousarray(pts_np[:, off_np[i]:off_np[i + 1]]),
-              idx_host[hoff_host[i]:hoff_host[i + 1]].copy()) for i in range(0, k, 97)]
+    # a sample of instances, and the whole batch, for the oracle leg
+    check = {"sample": [(np.ascontiguousarray(pts_np[:, off_np[i]:off_np[i + 1]]),
+                         idx_host[hoff_host[i]:hoff_host[i + 1]].copy()) for i in range(0, k, 97)],
+             "full": (pts_np, off_np, idx_host, hoff_host)}
     sctx.close()
     ctx.close()
     del singles, pts, off
@@ -239,6 +280,7 @@ def batched_leg(steps: int):
         "autotuned_graph": tuned,
         "modes_identical": same,
         "parity_vs_oracle_sample": None,
+        "parity_vs_oracle": None,
         "rounds": int(st_f["rounds"]),
         "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"]) if st_f["filter_tests"] else 0.0,
         "round_kernel": {"launches_per_step": launches / tsteps, "avg_launch_us": round(avg_ms * 1e3, 2),

@@ -11,6 +11,14 @@ import oracle
 import workloads
 
 
+def _full(inst):
+    off = np.zeros(len(inst) + 1, np.int64)
+    np.cumsum([q.shape[1] for q in inst], out=off[1:])
+    pts = np.ascontiguousarray(np.concatenate(inst, axis=1))
+    got, got_off = oracle.hull2d_batched(pts, off)
+    return pts, off, got, got_off
+
+
 def _checks():
     p = workloads.small_random(21, 3000, 1 << 20)
     w = oracle.hull2d(p)
@@ -19,7 +27,7 @@ def _checks():
     f3, v3 = oracle.hull3d(p3)
     return {
         "headline": (p, w.copy(), w.copy()),
-        "batched": [(q, oracle.hull2d(q)) for q in inst],
+        "batched": {"sample": [(q, oracle.hull2d(q)) for q in inst], "full": _full(inst)},
         "hull3d": [(p3, f3.copy(), v3.copy())],
         "hull3d_batched": [(p3, f3.copy(), v3.copy())],
         "regimes": {"disk_65k": (p, w.copy())},
@@ -35,6 +43,10 @@ def test_oracle_leg_all_equal():
     bench.oracle_leg(line, _checks(), budget_s=0.05)
     assert line["parity_vs_oracle"] is True
     assert line["batched"]["parity_vs_oracle_sample"] == {"instances": 3, "ok": True}
+    assert line["batched"]["parity_vs_oracle"] is True
+    cbb = line["batched"]["cpu_baseline"]
+    assert cbb["single_core"]["cores"] == 1 and cbb["thread_pool"]["cores"] >= 1
+    assert cbb["single_core"]["value"] > 0 and cbb["thread_pool"]["value"] > 0
     assert line["hull3d"]["parity_vs_oracle"] is True
     assert line["hull3d_batched"]["parity_vs_oracle_sample"]["ok"] is True
     assert line["regimes"]["disk_65k"]["parity_vs_oracle"] is True
@@ -46,8 +58,10 @@ def test_oracle_leg_reports_each_mismatch():
     c = _checks()
     p, w, _ = c["headline"]
     c["headline"] = (p, w, w[::-1].copy())                 # the exact form differs
-    q, g = c["batched"][1]
-    c["batched"][1] = (q, g[:-1])                          # one instance lost a vertex
+    q, g = c["batched"]["sample"][1]
+    c["batched"]["sample"][1] = (q, g[:-1])                # one instance lost a vertex
+    pts, off, got, got_off = c["batched"]["full"]
+    c["batched"]["full"] = (pts, off, got[::-1].copy(), got_off)  # the whole batch reordered
     p3, f3, v3 = c["hull3d"][0]
     f3b = f3.copy()
     f3b[0] = f3b[0][::-1]                                  # one facet flipped
@@ -56,6 +70,7 @@ def test_oracle_leg_reports_each_mismatch():
     bench.oracle_leg(line, c, budget_s=0.05)
     assert line["parity_vs_oracle"] is False
     assert line["batched"]["parity_vs_oracle_sample"]["ok"] is False
+    assert line["batched"]["parity_vs_oracle"] is False
     assert line["hull3d"]["parity_vs_oracle"] is False
     assert line["hull3d_batched"]["parity_vs_oracle_sample"]["ok"] is True
     assert line["regimes"]["disk_65k"]["parity_vs_oracle"] is True
