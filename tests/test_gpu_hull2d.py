@@ -191,6 +191,15 @@ def test_disk_65k(qhm, ctx, mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_disk_4m(qhm, ctx, mode):
+    """The disk input of the regimes benchmark (4,194,304 points)."""
+    pts = workloads.disk_4m()
+    _say(f"disk_4m mode={mode}")
+    got, _ = _gpu_hull(qhm, ctx, pts, mode)
+    assert got.tolist() == oracle.hull2d(pts).tolist()
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_square_16m(qhm, ctx, mode):
     pts = workloads.square_16m()
     _say(f"square_16m mode={mode}")
