@@ -23,19 +23,22 @@ def _figure1():
 
 def test_figure1_rows():
     fig = _figure1()
-    p, s_new, rows = segmented.flag_permute(fig["f"], fig["s"], 3)
+    rows = segmented.figure1_rows(fig["f"], fig["s"], 3)
     for name in ["s_t", "s_h", "mask[0]", "scan[0]", "mask[1]", "scan[1]",
-                 "mask[2]", "scan[2]"]:
+                 "mask[2]", "scan[2]", "p", "s'"]:
         assert rows[name].tolist() == fig[name].tolist(), name
+    p, s_new = segmented.flag_permute(fig["f"], fig["s"], 3)
     assert p.tolist() == fig["p"].tolist()
     assert s_new.tolist() == fig["s'"].tolist()
 
 
-def test_figure1_printed_backscan_is_literal_exclusive_max():
+def test_figure1_printed_backscan_reading():
+    """The printed backscan rows count a state over the segment without its
+    last element (reading R1); the p and s' rows need the full count."""
     fig = _figure1()
+    rows = segmented.figure1_rows(fig["f"], fig["s"], 3)
     for i in (0, 1):
-        got = segmented.literal_backscan(fig["f"], fig["s"], i)
-        assert got.tolist() == fig[f"backscan[{i}]"].tolist()
+        assert rows[f"backscan[{i}]"].tolist() == fig[f"backscan[{i}]"].tolist()
 
 
 def _brute_partition(f, s, k):
@@ -66,11 +69,32 @@ def test_flag_permute_is_stable_partition(seed):
     f = rng.integers(0, k, size=n)
     s = (rng.random(n) < 0.3).astype(np.int64)
     s[0] = 1
-    p, s_new, _ = segmented.flag_permute(f, s, k)
+    p, s_new = segmented.flag_permute(f, s, k)
     bp, bs = _brute_partition(f, s, k)
     assert p.tolist() == bp.tolist()
     assert s_new.tolist() == bs.tolist()
     assert sorted(p.tolist()) == list(range(n))
+
+
+@pytest.mark.parametrize("seed", range(100))
+def test_flag_permute_matches_stable_sort(seed):
+    """A second formulation through a library primitive: sorting the
+    elements stably by (segment, state) lists them in their new order."""
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(1, 400))
+    k = int(rng.integers(1, 17))
+    f = rng.integers(0, k, size=n)
+    s = (rng.random(n) < rng.choice([0.0, 0.05, 0.5])).astype(np.int64)
+    s[0] = 1
+    seg = np.cumsum(s) - 1
+    order = np.lexsort((np.arange(n), f, seg))
+    p, s_new = segmented.flag_permute(f, s, k)
+    assert (order[p] == np.arange(n)).all()
+    # new heads: where the (segment, state) pair changes along the new order
+    key = seg[order] * 64 + f[order]
+    want = np.ones(n, np.int64)
+    want[1:] = (key[1:] != key[:-1]).astype(np.int64)
+    assert s_new.tolist() == want.tolist()
 
 
 def test_compact_scenarios():
