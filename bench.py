@@ -1,27 +1,29 @@
 """Benchmark of the segmented Quickhull on one MI355X.
 
-One step = one whole hull (extremes, first split, every round, output) of the
-2D workload of
-16,777,216 points uniform in [-2^20, 2^20]^2, with the points already resident
-in device memory, through the C ABI (qh_hull2d).  The headline form is the
-FP32 filter with exact int64 fallback (bit-exact); the plain exact-int64 form
-is timed beside it on the same data.
+One step = one qh_hull2d_batched call on the batched workload: 4,096
+independent 2D point sets (sizes log-uniform in [256, 2^20], 511,371,962
+points in total, each uniform in a disk of radius 2^20), every instance an
+initial segment of one set of rounds (extremes, first split, every round,
+output), with the points already resident in device memory.  The headline
+form is the FP32 filter with exact int64 fallback (bit-exact); the plain
+exact-int64 form is timed beside it on the same data.
 
 Prints ONE JSON line.  ``roofline`` describes the round (k_round for the tiles
 covered by one segment and k_round_multi for the others, launched together
 for the first split and once per later round; in the last round, once no
 segment holds more than 1,024 points, k_round_multi finishes every segment
-with one workgroup each), which moves nearly all the bytes: algorithmic bytes per round (first split 8 B per point read and 12 B
-per survivor written; later rounds 12 B per point read and 12 B per survivor
-written) over the round's average duration, timed with HIP events around the
-pair of launches on the stream they run on.
+with one workgroup each), which moves nearly all the bytes: algorithmic bytes
+per round over the round's average duration, timed with HIP events around the
+pair of launches on the stream they run on.  ``traffic`` is the counter-
+measured HBM traffic per round from the committed rocprofv3 summary, null when
+the kernel sources changed since it was taken.
 ``cpu_baseline`` is the oracle (plain single-threaded C Quickhull) on the
-same points; the same leg, the only one that runs the oracle, checks every
-GPU leg's output against it.  ``regimes`` times the disk and circle inputs
-(65,536 and 4,194,304 points in a disk, 4,194,304 on and near a circle).  ``batched`` is the batched form on 4,096 disks (about 5.1e8
-points) in one qh_hull2d_batched call, beside 4,096 sequential qh_hull2d
-calls; its round-kernel figures are timed the same way.  ``hull3d`` is the
-3D form (qh_hull3d) on 5,242,880 ball and sphere points.
+whole batch on one host core (a thread-pool figure beside it); the same leg,
+the only one that runs the oracle, checks every GPU leg's output against it.
+Sub-legs: ``square_16m`` (one hull of 16,777,216 points uniform in a square,
+with its own roofline), ``regimes`` (65,536 and 4,194,304 points in a disk,
+4,194,304 on and near a circle), ``hull3d`` (5,242,880 ball and sphere points
+through qh_hull3d), ``hull3d_batched`` and ``select``.
 """
 from __future__ import annotations
 
@@ -36,9 +38,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = "square_16m"
+WORKLOAD = "batched_disks"
+SQUARE = "square_16m"
 METRIC = "Mpoints/s per hull + HBM GB/s; FP32-filtered/batched vs exact-int64, bit-exact"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_round_square_16m.json")
+TRAFFIC_FILES = {w: os.path.join(ROOT, "profiles", f"traffic_round_{w}.json") for w in (WORKLOAD, SQUARE)}
 CSRC = os.path.join(ROOT, "paper_1201_2936_amd", "csrc")
 
 
@@ -57,11 +60,12 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic():
-    """HBM bytes per round-kernel launch from the committed PMC summary, or
-    None when it is missing or was taken from another kernel source."""
+def load_traffic(workload: str):
+    """HBM bytes per round-kernel launch on ``workload`` from the committed
+    PMC summary, or None when it is missing or was taken from another kernel
+    source."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(TRAFFIC_FILES[workload]) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -122,34 +126,43 @@ def _oracle_batched(oracle, pts, off, got, got_off):
 
 def oracle_leg(line, checks, budget_s: float = 12.0):
     """The leg that runs the oracle (a plain single-threaded C Quickhull,
-    test infrastructure that no GPU leg calls): ``cpu_baseline`` times it on
-    the headline workload, and every GPU leg's output is compared with its
-    result, whole or on a sample of instances."""
+    test infrastructure that no GPU leg calls).  ``cpu_baseline`` times it
+    on the whole batch of the headline (one core, and a thread pool beside
+    it); the square leg times it on its points for up to ``budget_s``; every
+    GPU leg's output is compared with its result, whole or on a sample of
+    instances."""
     import numpy as np
 
     import oracle
 
-    pts = checks["headline"][0]
-    oracle.hull2d(pts[:, :1000])  # load / build outside the timing
-    n = pts.shape[1]
-    runs = 0
-    t0 = time.perf_counter()
-    while True:
-        want = oracle.hull2d(pts)
-        runs += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or runs >= 50:
-            break
-    line["cpu_baseline"] = {
-        "value": round(n * runs / el / 1e6, 3), "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
-        "sample": f"{WORKLOAD} full ({n} points), {runs} runs in {el:.1f} s, single thread"}
-    line["parity_vs_oracle"] = bool(all(np.array_equal(got, want) for got in checks["headline"][1:]))
+    oracle.hull2d(np.zeros((2, 4), np.int32))  # load / build outside the timing
     if "batched" in checks:
         sample = checks["batched"]["sample"]
-        ok = all(np.array_equal(oracle.hull2d(p), got) for p, got in sample)
-        line["batched"]["parity_vs_oracle_sample"] = {"instances": len(sample), "ok": bool(ok)}
-        line["batched"]["cpu_baseline"], line["batched"]["parity_vs_oracle"] = \
-            _oracle_batched(oracle, *checks["batched"]["full"])
+        line["parity_vs_oracle_sample"] = {
+            "instances": len(sample), "ok": bool(all(np.array_equal(oracle.hull2d(p), got) for p, got in sample))}
+        timing, ok = _oracle_batched(oracle, *checks["batched"]["full"])
+        line["parity_vs_oracle"] = ok
+        one = timing["single_core"]
+        line["cpu_baseline"] = {"value": one["value"], "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{WORKLOAD}: {timing['sample']}, one run on one core "
+                                          f"({one['ms'] / 1e3:.1f} s)",
+                                "thread_pool": timing["thread_pool"]}
+    if "square" in checks:
+        pts = checks["square"][0]
+        n = pts.shape[1]
+        runs = 0
+        t0 = time.perf_counter()
+        while True:
+            want = oracle.hull2d(pts)
+            runs += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or runs >= 50:
+                break
+        sq = line[SQUARE]
+        sq["cpu_baseline"] = {
+            "value": round(n * runs / el / 1e6, 3), "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
+            "sample": f"{SQUARE} full ({n} points), {runs} runs in {el:.1f} s, single thread"}
+        sq["parity_vs_oracle"] = bool(all(np.array_equal(got, want) for got in checks["square"][1:]))
     if "hull3d" in checks:
         p, gf, gv = checks["hull3d"][0]
         t0 = time.perf_counter()
@@ -169,6 +182,18 @@ def oracle_leg(line, checks, budget_s: float = 12.0):
             want = oracle.hull2d(p)
             line["regimes"][name]["oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
             line["regimes"][name]["parity_vs_oracle"] = bool(np.array_equal(want, got))
+
+
+def round_roofline(timed_stats, traffic):
+    """The round kernel's roofline from the per-launch HIP-event timings of
+    some calls (QH_FLAG_TIMING): algorithmic bytes per launch over the
+    average launch duration."""
+    bpl = sum(s["round_kernel_bytes"] for s in timed_stats) / max(1, sum(s["round_launches"] for s in timed_stats))
+    avg_ms = sum(s["round_kernel_ms"] for s in timed_stats) / max(1, sum(s["round_launches"] for s in timed_stats))
+    ach = bpl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic}
+    return roof, bpl, avg_ms
 
 
 def tuned_graph_leg(call, key, want, steps, outs, out_names):
@@ -195,10 +220,12 @@ def tuned_graph_leg(call, key, want, steps, outs, out_names):
             "graph_launches_per_call": int(s1["graph_launches"]), "same_output": same}
 
 
-def batched_leg(steps: int):
-    """The batched form on 4,096 disks (sizes log-uniform in [256, 2^20],
-    about 5.1e8 points) in one qh_hull2d_batched call, beside 4,096
-    sequential qh_hull2d calls on the same device-resident instances."""
+def batched_leg(steps: int, warmup: int):
+    """The headline: the batched form on 4,096 disks (sizes log-uniform in
+    [256, 2^20], 511,371,962 points) in one qh_hull2d_batched call per step,
+    FP32 filter; the exact form, the tuned launch configuration with graph
+    replay and 4,096 sequential qh_hull2d calls on the same device-resident
+    instances beside it."""
     import numpy as np
     import torch
 
@@ -217,28 +244,26 @@ def batched_leg(steps: int):
     def run(mode):
         return qh.qh_hull2d_batched(pts, off, mode=mode, ctx=ctx)
 
-    sec_f, (idx_f, hoff_f, st_f) = time_steps(lambda: run(qh.QH_FP32_FILTER), steps, 1)
-    sec_x, (idx_x, hoff_x, _) = time_steps(lambda: run(qh.QH_EXACT_INT64), max(2, steps // 2), 1)
+    sec_f, (idx_f, hoff_f, st_f) = time_steps(lambda: run(qh.QH_FP32_FILTER), steps, warmup)
+    sec_x, (idx_x, hoff_x, _) = time_steps(lambda: run(qh.QH_EXACT_INT64), max(3, min(steps, 10)), 1)
     same = bool(torch.equal(idx_f, idx_x) and torch.equal(hoff_f, hoff_x))
 
     # the launch configuration picked by the autotuner, the launches replayed
     # from captured graphs (fixed output buffers, a stream of its own)
     tuned = tuned_graph_leg(lambda **kw: qh.qh_hull2d_batched(pts, off, mode=qh.QH_FP32_FILTER, **kw),
-                            lambda o: (o[0], o[1]), (idx_f, hoff_f), steps,
+                            lambda o: (o[0], o[1]), (idx_f, hoff_f), max(3, min(steps, 10)),
                             [torch.empty(max(N, 1), dtype=torch.int32, device="cuda"),
                              torch.empty_like(hoff_f)], ["out", "hull_offsets"])
 
-    # per-launch kernel timing of the round kernel (separate pass)
-    agg = {"round_kernel_bytes": 0.0, "round_kernel_ms": 0.0, "round_launches": 0.0,
-           "kernel_ms": 0.0, "split_ms": 0.0, "extremes_ms": 0.0, "segment_ms": 0.0}
-    tsteps = max(1, steps // 2)
-    for _ in range(tsteps):
-        _, _, s = qh.qh_hull2d_batched(pts, off, mode=qh.QH_FP32_FILTER, ctx=ctx, timing=True)
-        for key in agg:
-            agg[key] += s[key]
-    launches = max(agg["round_launches"], 1)
-    avg_ms = agg["round_kernel_ms"] / launches
-    bpl = agg["round_kernel_bytes"] / launches
+    # per-launch kernel timing (HIP events around every launch, on the
+    # stream the kernels run on): a separate pass of the same call
+    timed = [qh.qh_hull2d_batched(pts, off, mode=qh.QH_FP32_FILTER, ctx=ctx, timing=True)[2]
+             for _ in range(3)]
+    roof, bpl, avg_ms = round_roofline(timed, load_traffic(WORKLOAD))
+    nt = len(timed)
+
+    def tavg(key):
+        return sum(s[key] for s in timed) / nt
 
     # 4,096 sequential single-hull calls on contiguous per-instance copies
     singles = [torch.stack([pts[0, off_np[i]:off_np[i + 1]], pts[1, off_np[i]:off_np[i + 1]]]).contiguous()
@@ -266,29 +291,90 @@ def batched_leg(steps: int):
     ctx.close()
     del singles, pts, off
     torch.cuda.empty_cache()
-    ach = bpl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    return {
-        "workload": "batched_disks: 4,096 disks of radius 2^20, sizes log-uniform in [256, 2^20]",
-        "n_total": N, "k": k, "generate_s": round(gen_s, 1),
-        "fp32_filter": {"value": round(N / sec_f / 1e6, 3), "unit": "Mpoints/s",
-                        "ms_per_step": round(sec_f * 1e3, 3), "steps": steps},
+    part = {
+        "value": round(N / sec_f / 1e6, 3),
+        "ms_per_step": round(sec_f * 1e3, 4),
+        "config": {"workload": WORKLOAD, "instances": k, "n_total": N, "dims": 2,
+                   "sizes": "log-uniform in [256, 2^20] (seed 5)",
+                   "coords": "int32 uniform in the disk of radius 2^20", "form": "fp32_filter",
+                   "call": "qh_hull2d_batched"},
         "exact_int64": {"value": round(N / sec_x / 1e6, 3), "unit": "Mpoints/s",
-                        "ms_per_step": round(sec_x * 1e3, 3)},
+                        "ms_per_step": round(sec_x * 1e3, 4), "dtype": "i64"},
+        "autotuned_graph": tuned,
         "sequential_single_calls": {"value": round(N / sec_seq / 1e6, 3), "unit": "Mpoints/s",
                                     "ms": round(sec_seq * 1e3, 1), "calls": k,
                                     "match_batched": bool(seq_ok)},
-        "autotuned_graph": tuned,
         "modes_identical": same,
+        "generate_s": round(gen_s, 1),
+        "hull_vertices": int(hoff_host[-1]),
         "parity_vs_oracle_sample": None,
         "parity_vs_oracle": None,
         "rounds": int(st_f["rounds"]),
         "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"]) if st_f["filter_tests"] else 0.0,
-        "round_kernel": {"launches_per_step": launches / tsteps, "avg_launch_us": round(avg_ms * 1e3, 2),
-                         "bytes_per_launch": round(bpl), "achieved_GBs": round(ach, 1),
-                         "frac_of_8TBs": round(ach / HBM_PEAK_GBS, 4)},
-        "device_time_us": {"all_kernels": round(agg["kernel_ms"] / tsteps * 1e3, 1),
-                           "extremes": round(agg["extremes_ms"] / tsteps * 1e3, 1),
-                           "segments": round(agg["segment_ms"] / tsteps * 1e3, 1)},
+        "argmax_candidates": int(st_f["argmax_candidates"]),
+        "round_kernel": {"name": "k_round + k_round_multi (first split, later rounds, last round finishing "
+                                 "small segments)",
+                         "launches_per_step": tavg("round_launches"), "avg_launch_us": round(avg_ms * 1e3, 2),
+                         "bytes_per_launch": round(bpl), "grid_blocks": int(st_f["grid_blocks"]),
+                         "first_split_us": round(tavg("split_ms") * 1e3, 1)},
+        "device_time_us": {"all_kernels": round(tavg("kernel_ms") * 1e3, 1),
+                           "rounds": round(tavg("round_kernel_ms") * 1e3, 1),
+                           "extremes": round(tavg("extremes_ms") * 1e3, 1),
+                           "segments": round(tavg("segment_ms") * 1e3, 1)},
+        "hull_GBs_device": round(tavg("hull_bytes") / (tavg("kernel_ms") * 1e-3) / 1e9, 1)
+        if tavg("kernel_ms") > 0 else None,
+        "roofline": roof,
+    }
+    return part, check
+
+
+def square_leg(steps: int):
+    """One hull of 16,777,216 points uniform in [-2^20, 2^20]^2 through
+    qh_hull2d, both forms, with its own round-kernel roofline."""
+    import torch
+
+    import workloads
+    from paper_1201_2936_amd import qh
+
+    pts_np = workloads.WORKLOADS[SQUARE]()
+    n = pts_np.shape[1]
+    pts = torch.from_numpy(pts_np).cuda()
+    ctx = qh.Context()
+    sec, (idx_f, st_f) = time_steps(lambda: qh.qh_hull2d(pts, mode=qh.QH_FP32_FILTER, ctx=ctx), steps, 3)
+    sec_x, (idx_x, _) = time_steps(lambda: qh.qh_hull2d(pts, mode=qh.QH_EXACT_INT64, ctx=ctx), steps, 3)
+    tuned = tuned_graph_leg(lambda **kw: qh.qh_hull2d(pts, mode=qh.QH_FP32_FILTER, **kw),
+                            lambda o: (o[0],), (idx_f,), steps,
+                            [torch.empty(max(n, 1), dtype=torch.int32, device="cuda")], ["out"])
+    timed = [qh.qh_hull2d(pts, mode=qh.QH_FP32_FILTER, ctx=ctx, timing=True)[1] for _ in range(steps)]
+    roof, bpl, avg_ms = round_roofline(timed, load_traffic(SQUARE))
+    nt = len(timed)
+    split_ms = sum(s["split_ms"] for s in timed) / nt
+    split_bytes = 8 * n + 12 * timed[0]["split_points_out"]
+    check = (pts_np, idx_f.cpu().numpy(), idx_x.cpu().numpy())
+    ctx.close()
+    del pts
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"{SQUARE}: {n} points, int32 uniform in [-2^20, 2^20]^2, one qh_hull2d call",
+        "n": n,
+        "fp32_filter": {"value": round(n / sec / 1e6, 3), "unit": "Mpoints/s", "ms_per_step": round(sec * 1e3, 4)},
+        "exact_int64": {"value": round(n / sec_x / 1e6, 3), "unit": "Mpoints/s",
+                        "ms_per_step": round(sec_x * 1e3, 4)},
+        "autotuned_graph": tuned,
+        "hull_vertices": int(idx_f.numel()),
+        "parity_vs_oracle": None,
+        "modes_identical": bool(torch.equal(idx_f, idx_x)),
+        "rounds": int(st_f["rounds"]),
+        "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"] if st_f["filter_tests"] else 0.0),
+        "argmax_candidates": int(st_f["argmax_candidates"]),
+        "round_kernel": {"launches_per_step": sum(s["round_launches"] for s in timed) / nt,
+                         "avg_launch_us": round(avg_ms * 1e3, 3), "bytes_per_launch": round(bpl),
+                         "first_split_us": round(split_ms * 1e3, 2),
+                         "first_split_GBs": round(split_bytes / (split_ms * 1e-3) / 1e9, 1) if split_ms > 0 else None},
+        "device_time_us": {"all_kernels": round(sum(s["kernel_ms"] for s in timed) / nt * 1e3, 2),
+                           "extremes": round(sum(s["extremes_ms"] for s in timed) / nt * 1e3, 2),
+                           "segments": round(sum(s["segment_ms"] for s in timed) / nt * 1e3, 2)},
+        "roofline": roof,
     }, check
 
 
@@ -455,119 +541,46 @@ def select_leg(steps: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true",
-                    help="skip the batched 4,096-instance leg")
-    ap.add_argument("--no-3d", action="store_true", help="skip the 3D leg")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D legs")
     ap.add_argument("--no-regimes", action="store_true", help="skip the disk and circle leg")
+    ap.add_argument("--no-square", action="store_true", help="skip the 16.7M-point square leg")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the hull of one point set "
+        print("bench.py: this build runs on one GPU only (the hulls of one batch "
               "on one MI355X); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-
-    import workloads
     from paper_1201_2936_amd import qh
 
     qh.load()
-    pts_np = workloads.WORKLOADS[WORKLOAD]()
-    n = pts_np.shape[1]
-    dev = torch.device("cuda:0")
-    pts = torch.from_numpy(pts_np).to(dev)
-    ctx = qh.Context()
-
-    # headline: FP32 filter + int64 fallback
-    def run_filter():
-        return qh.qh_hull2d(pts, mode=qh.QH_FP32_FILTER, ctx=ctx)
-
-    def run_exact():
-        return qh.qh_hull2d(pts, mode=qh.QH_EXACT_INT64, ctx=ctx)
-
-    sec, (idx_f, st_f) = time_steps(run_filter, args.steps, args.warmup)
-    sec_x, (idx_x, st_x) = time_steps(run_exact, max(5, args.steps // 3), 2)
-    tuned = tuned_graph_leg(lambda **kw: qh.qh_hull2d(pts, mode=qh.QH_FP32_FILTER, **kw),
-                            lambda o: (o[0],), (idx_f,), args.steps,
-                            [torch.empty(max(n, 1), dtype=torch.int32, device=dev)], ["out"])
-
-    # kernel timing: HIP events around every launch (a separate pass of the
-    # same steps, so the events do not perturb the headline time)
-    agg = {k: 0.0 for k in ("round_kernel_bytes", "round_kernel_ms", "round_launches", "kernel_ms",
-                            "split_ms", "extremes_ms", "segment_ms", "hull_bytes")}
-    split_bytes = 0.0
-    for _ in range(args.steps):
-        _, s = qh.qh_hull2d(pts, mode=qh.QH_FP32_FILTER, ctx=ctx, timing=True)
-        for key in agg:
-            agg[key] += s[key]
-        split_bytes += 8 * n + 12 * s["split_points_out"]
-    torch.cuda.synchronize()
-    launches = agg["round_launches"]
-    avg_launch_ms = agg["round_kernel_ms"] / max(launches, 1)
-    bytes_per_launch = agg["round_kernel_bytes"] / max(launches, 1)
-    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if avg_launch_ms > 0 else 0.0
-
-    def gbs(nbytes, ms):
-        return round(nbytes / (ms * 1e-3) / 1e9, 1) if ms > 0 else None
-
-    later_ms = agg["round_kernel_ms"] - agg["split_ms"]
-    later_bytes = agg["round_kernel_bytes"] - split_bytes
-
-    checks = {"headline": (pts_np, idx_f.cpu().numpy(), idx_x.cpu().numpy())}
-
-    traffic = load_traffic()
+    head, check_b = batched_leg(args.steps, args.warmup)
+    checks = {"batched": check_b}
     line = {
         "metric": METRIC,
-        "value": round(n / sec / 1e6, 3),
+        "value": head.pop("value"),
         "unit": "Mpoints/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(sec * 1e3, 4),
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+i64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": n, "dims": 2,
-                   "coords": "int32 uniform in [-2^20, 2^20]^2", "form": "fp32_filter"},
-        "exact_int64": {"value": round(n / sec_x / 1e6, 3), "unit": "Mpoints/s",
-                        "ms_per_step": round(sec_x * 1e3, 4), "dtype": "i64"},
-        "autotuned_graph": tuned,
-        "hull_vertices": int(idx_f.numel()),
-        "parity_vs_oracle": None,
-        "rounds": int(st_f["rounds"]),
-        "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"]
-                          if st_f["filter_tests"] else 0.0),
-        "argmax_candidates": int(st_f["argmax_candidates"]),
-        "finish_round": int(st_f["finish_round"]),
-        "round_kernel": {"name": "k_round + k_round_multi (first split, later rounds, last round finishing small segments)",
-                         "launches_per_step": launches / args.steps,
-                         "avg_launch_us": round(avg_launch_ms * 1e3, 3),
-                         "bytes_per_launch": round(bytes_per_launch),
-                         "grid_blocks": int(st_f["grid_blocks"]),
-                         "first_split_us": round(agg["split_ms"] / args.steps * 1e3, 2),
-                         "first_split_GBs": gbs(split_bytes, agg["split_ms"]),
-                         "later_rounds_us": round(later_ms / args.steps * 1e3, 2),
-                         "later_rounds_GBs": gbs(later_bytes, later_ms)},
-        "device_time_us": {"all_kernels": round(agg["kernel_ms"] / args.steps * 1e3, 2),
-                           "extremes": round(agg["extremes_ms"] / args.steps * 1e3, 2),
-                           "segments": round(agg["segment_ms"] / args.steps * 1e3, 2)},
-        "hull_GBs_device": gbs(agg["hull_bytes"], agg["kernel_ms"]),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+        "config": head.pop("config"),
+        "roofline": head.pop("roofline"),
+        "cpu_baseline": None,
     }
-    ctx.close()
-    del pts
-    torch.cuda.empty_cache()
+    line.update(head)
+    sub = max(3, min(args.steps, 10))
+    if not args.no_square:
+        line[SQUARE], checks["square"] = square_leg(sub)
     if not args.no_regimes:
-        line["regimes"], checks["regimes"] = regimes_leg(max(3, min(args.steps, 10)))
-    if not args.no_batched:
-        line["batched"], checks["batched"] = batched_leg(max(2, min(args.steps, 5)))
+        line["regimes"], checks["regimes"] = regimes_leg(sub)
     if not args.no_3d:
         line["hull3d"], checks["hull3d"] = hull3d_leg(max(2, min(args.steps, 3)))
         line["hull3d_batched"], checks["hull3d_batched"] = hull3d_batched_leg(max(2, min(args.steps, 3)))

@@ -23,10 +23,12 @@
 // state back once per batch.
 //
 // Survivors are structure-of-arrays int32 x[], y[], idx[] in two regions per
-// round (children of state 0 and of state 1), each filled front to back; a
-// segment is a range [start, start+len) of one region.  Tiles of 2048 points
-// are claimed from an atomic counter, so the look-back needs no assumption on
-// the order in which blocks run.
+// round (children of state 0 and of state 1); a segment is a range
+// [start, start+len) of one region in compacted order.  Each block of the
+// round kernel takes a fixed contiguous range of 2048-point tiles (no atomics)
+// and writes the survivors of tile t at t * 2048 of each region (a piece);
+// the segment kernel's scans (decoupled look-back over dynamically claimed
+// scan tiles) turn the pieces' counts into the next round's piece table.
 #include "../../include/qh.h"
 #include "qh2d.h"
 
@@ -304,9 +306,6 @@ __device__ __forceinline__ void best_offer(Best &b, uint64_t d, int32_t x, int32
     }
 }
 
-// ---------------------------------------------------------------------------
-// grid barrier of the cooperative kernel
-// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // LDS layouts of the phases (they share one buffer)
 // ---------------------------------------------------------------------------

@@ -601,7 +601,8 @@ qh_status run3d(qh_ctx *c, const int32_t *pts, int64_t n, const std::vector<int6
     if (o && o->stats) {
         qh_stats *S = o->stats;
         unsigned long long fc[2] = {0, 0};
-        QH3_TRY(hipMemcpy(fc, w->filt.p, sizeof(fc), hipMemcpyDeviceToHost));
+        QH3_TRY(hipMemcpyAsync(fc, w->filt.p, sizeof(fc), hipMemcpyDeviceToHost, R.st));
+        QH3_TRY(hipStreamSynchronize(R.st));
         S->rounds = R.rounds;
         S->round_launches = R.launches;
         S->round_points_in = R.pts_in;

@@ -26,7 +26,7 @@ def _checks():
     p3 = workloads.small_ball3(5, 300, 1000)
     f3, v3 = oracle.hull3d(p3)
     return {
-        "headline": (p, w.copy(), w.copy()),
+        "square": (p, w.copy(), w.copy()),
         "batched": {"sample": [(q, oracle.hull2d(q)) for q in inst], "full": _full(inst)},
         "hull3d": [(p3, f3.copy(), v3.copy())],
         "hull3d_batched": [(p3, f3.copy(), v3.copy())],
@@ -35,29 +35,29 @@ def _checks():
 
 
 def _line():
-    return {"batched": {}, "hull3d": {}, "hull3d_batched": {}, "regimes": {"disk_65k": {}}}
+    return {bench.SQUARE: {}, "hull3d": {}, "hull3d_batched": {}, "regimes": {"disk_65k": {}}}
 
 
 def test_oracle_leg_all_equal():
     line = _line()
     bench.oracle_leg(line, _checks(), budget_s=0.05)
     assert line["parity_vs_oracle"] is True
-    assert line["batched"]["parity_vs_oracle_sample"] == {"instances": 3, "ok": True}
-    assert line["batched"]["parity_vs_oracle"] is True
-    cbb = line["batched"]["cpu_baseline"]
-    assert cbb["single_core"]["cores"] == 1 and cbb["thread_pool"]["cores"] >= 1
-    assert cbb["single_core"]["value"] > 0 and cbb["thread_pool"]["value"] > 0
+    assert line["parity_vs_oracle_sample"] == {"instances": 3, "ok": True}
+    assert line[bench.SQUARE]["parity_vs_oracle"] is True
+    cb = line["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["value"] > 0 and cb["unit"] == "Mpoints/s"
+    assert cb["thread_pool"]["cores"] >= 1 and cb["thread_pool"]["value"] > 0
     assert line["hull3d"]["parity_vs_oracle"] is True
     assert line["hull3d_batched"]["parity_vs_oracle_sample"]["ok"] is True
     assert line["regimes"]["disk_65k"]["parity_vs_oracle"] is True
-    cb = line["cpu_baseline"]
-    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["value"] > 0
+    cs = line[bench.SQUARE]["cpu_baseline"]
+    assert cs["kind"] == "oracle" and cs["cores"] == 1 and cs["value"] > 0
 
 
 def test_oracle_leg_reports_each_mismatch():
     c = _checks()
-    p, w, _ = c["headline"]
-    c["headline"] = (p, w, w[::-1].copy())                 # the exact form differs
+    p, w, _ = c["square"]
+    c["square"] = (p, w, w[::-1].copy())                   # the exact form differs
     q, g = c["batched"]["sample"][1]
     c["batched"]["sample"][1] = (q, g[:-1])                # one instance lost a vertex
     pts, off, got, got_off = c["batched"]["full"]
@@ -68,10 +68,10 @@ def test_oracle_leg_reports_each_mismatch():
     c["hull3d"] = [(p3, f3b, v3)]
     line = _line()
     bench.oracle_leg(line, c, budget_s=0.05)
+    assert line[bench.SQUARE]["parity_vs_oracle"] is False
+    assert line["parity_vs_oracle_sample"]["ok"] is False
     assert line["parity_vs_oracle"] is False
-    assert line["batched"]["parity_vs_oracle_sample"]["ok"] is False
-    assert line["batched"]["parity_vs_oracle"] is False
     assert line["hull3d"]["parity_vs_oracle"] is False
     assert line["hull3d_batched"]["parity_vs_oracle_sample"]["ok"] is True
     assert line["regimes"]["disk_65k"]["parity_vs_oracle"] is True
-    assert isinstance(np.bool_(line["parity_vs_oracle"]).item(), bool)
+    assert isinstance(line["parity_vs_oracle"], bool)
