@@ -103,13 +103,15 @@ typedef struct qh_stats {
                                    launches that find nothing left to do) */
     int64_t round_points_in;    /* points read by the rounds after the first split */
     int64_t round_points_out;   /* survivors written by those rounds */
-    int64_t split_points_out;   /* survivors of the first split */
+    int64_t split_points_out;   /* survivors of the first split (counted: the
+                                   split writes no point) */
     int64_t hull_bytes;         /* algorithmic HBM bytes of the whole call: the
                                    extremes read 8 B per point; the first split
-                                   reads 8 B per point and writes 12 B per
-                                   survivor; every later round reads 12 B per
-                                   point (x, y, index) and writes 12 B per
-                                   survivor */
+                                   reads 8 B per point; the round after it
+                                   reads the input again (8 B per point) and
+                                   writes 12 B per survivor (x, y, index);
+                                   every later round reads 12 B per point and
+                                   writes 12 B per survivor */
     int64_t round_kernel_bytes; /* the part of hull_bytes moved by the round
                                    kernel (first split and later rounds) */
     double kernel_ms;           /* device time of all kernels of the call */

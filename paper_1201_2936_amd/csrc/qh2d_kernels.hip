@@ -62,6 +62,23 @@ __device__ __forceinline__ float cross_f32(int32_t px, int32_t py, int32_t ax, i
     return __fsub_rn(p1, p2);
 }
 
+// The same estimate without its own bound, for callers that use a bound
+// valid for every point of the input (static_bound).
+__device__ __forceinline__ float cross_f32_nb(int32_t px, int32_t py, int32_t ax, int32_t ay,
+                                              int32_t ex, int32_t ey) {
+    const int32_t dx = px - ax, dy = py - ay;
+    return __fsub_rn(__fmul_rn((float)dx, (float)ey), __fmul_rn((float)dy, (float)ex));
+}
+
+// A bound on the error of cross_f32_nb for every input point against an edge
+// with direction (ex, ey): with |coordinate| <= C, |dx| and |dy| are at most
+// 2C, so the error is at most about 4 eps 2C (|ex| + |ey|) (two conversions,
+// a product and the difference each round once); kErrC = 5 eps also covers
+// the rounding of c2 = fl(2C) and of this product.
+__device__ __forceinline__ float static_bound(int32_t ex, int32_t ey, float c2) {
+    return __fmul_rn(__fmul_rn(c2, __fadd_rn(fabsf((float)ex), fabsf((float)ey))), kErrC);
+}
+
 // Tie-break key of a point for the argmax over a child with edge direction
 // (ex, ey): among equally far points (a line parallel to the edge) the one
 // with the smallest t = (p - u).e, then the lowest index.  Along such a line
@@ -86,6 +103,13 @@ __device__ __forceinline__ uint64_t coord_key(int32_t x, int32_t y) {
 template <typename T>
 __device__ __forceinline__ T scalar_load(const T *ptr) {
     return *(const __attribute__((address_space(4))) T *)(ptr);
+}
+
+// 2C as a float, from the control block's coordinate span
+__device__ __forceinline__ float coord_c2(const Control *ctl) {
+    const uint32_t cs = scalar_load(&ctl->cspan);
+    const uint32_t c = cs > (uint32_t)kCoordMax2D ? cs - (uint32_t)kCoordMax2D : 0u;
+    return (float)(2.0 * (double)c);
 }
 
 // largest i in [0, m) with s[i] <= v  (s[0] <= v, s nondecreasing)
@@ -444,6 +468,7 @@ __device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a
         if (threadIdx.x == 0) sm->carry += tot[0];
         __syncthreads();
     }
+    if (threadIdx.x < 64) ctl->cspan_slot[threadIdx.x] = (uint32_t)kCoordMax2D;
     if (threadIdx.x == 0) {
         RoundState z = {};
         ctl->rs[1] = z;
@@ -460,6 +485,8 @@ __device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a
         ctl->max_segments = (int32_t)sm->carry;
         ctl->final_round = 0;
         ctl->points_in = ctl->points_out = ctl->first_in = ctl->first_out = 0;
+        ctl->second_in = ctl->second_out = 0;
+        ctl->cspan = (uint32_t)kCoordMax2D;
         ctl->filter_tests = ctl->filter_fallbacks = ctl->candidates = 0;
         ctl->rounds_with_work = 0;
         ctl->H = 0;
@@ -539,7 +566,8 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
     // the first index that has it (each lane sees its points in index order)
     uint64_t kmn = ~0ull, kmx = 0ull;
     int32_t imn = -1, imx = -1;
-    uint32_t span = 0;  // largest |coordinate| + bound seen, for the range check
+    uint32_t span = 0;   // largest coordinate + bound seen, for the range check
+    uint32_t nspan = 0;  // largest bound - coordinate (the other side)
     int cur = -1, run0 = 0, cst = 0, cen = 0;
     auto as_best = [](uint64_t key1, uint64_t ck, int32_t idx) {
         Best b = best_none();
@@ -630,6 +658,8 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
             // past the end load as 0)
             span = max(span, (uint32_t)X[i] + (uint32_t)kCoordMax2D);
             span = max(span, (uint32_t)Y[i] + (uint32_t)kCoordMax2D);
+            nspan = max(nspan, (uint32_t)kCoordMax2D - (uint32_t)X[i]);
+            nspan = max(nspan, (uint32_t)kCoordMax2D - (uint32_t)Y[i]);
         }
         if (ti.single) {
             if (ti.seg != cur) {
@@ -733,11 +763,18 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
         }
     }
     if (cur >= 0) flush(te);
-    const bool bad = span > 2u * (uint32_t)kCoordMax2D;
+    const bool bad = span > 2u * (uint32_t)kCoordMax2D || nspan > 2u * (uint32_t)kCoordMax2D;
     if (__syncthreads_or(bad) && threadIdx.x == 0) {
         atomicOr(&ctl->error, kErrRange);
         atomicOr(&ctl->setup_error, kErrRange);
     }
+    // the largest |coordinate| (plus the bound) of the input, for the FP32
+    // filter's static error bound: per wave, then into one of 64 slots (few
+    // atomics per address), merged by the extremes' final kernel
+    uint32_t cs = max(span, nspan);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) cs = max(cs, (uint32_t)__shfl_xor((int)cs, m));
+    if (lane == 0 && cs > (uint32_t)kCoordMax2D) atomicMax(&ctl->cspan_slot[(blockIdx.x * kNW + wv) & 63], cs);
 }
 
 // Merge the per-tile partials of one segment over tiles t0 .. t1 (the whole
@@ -825,6 +862,12 @@ __device__ __forceinline__ void block_merge_ext(const Ws2 &ws, int T, int t0, in
 __device__ __forceinline__ void phase_extremes_final(const Ws2 &ws, const HullArgs &a, char *smem) {
     Control *ctl = ws.ctl;
     if (ctl->error) return;
+    if (blockIdx.x == 0 && threadIdx.x < kWave) {
+        uint32_t cs = ctl->cspan_slot[threadIdx.x];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) cs = max(cs, (uint32_t)__shfl_xor((int)cs, m));
+        if (threadIdx.x == 0) ctl->cspan = cs;
+    }
     SegSmem *sm = reinterpret_cast<SegSmem *>(smem);
     const int S = ctl->rs[0].s[0];
     for (int s = blockIdx.x; s < S; s += gridDim.x) {
@@ -973,8 +1016,11 @@ __device__ __forceinline__ int64_t child_d(int32_t x, int32_t y, uint32_t st, co
 // Round r ends the recursion in one pass when no segment has more than
 // fin_cap points and there are at most fin_segs segments (a workgroup takes
 // one segment at a time: many small segments go faster as rounds); decided
-// alike by every kernel of the round.
-__device__ __forceinline__ bool fin_mode(const Control *ctl, int p, const HullArgs &a) {
+// alike by every kernel of the round.  Never in round 1, whose segments are
+// the split's children, kept as input ranges rather than as points.
+__device__ __forceinline__ bool fin_mode(const Control *ctl, int r, const HullArgs &a) {
+    if (r == 1) return false;
+    const int p = r & 1;
     const RoundState &rs = ctl->rs[p];
     const int S = rs.s[0] + rs.s[1];
     return a.fin_cap > 0 && S > 0 && S <= a.fin_segs && ctl->maxseg[p] <= a.fin_cap;
@@ -1022,8 +1068,7 @@ __device__ __forceinline__ int fast_pos_init(int lo, int i) {
 }
 
 __device__ __forceinline__ uint32_t load_input_wave(const HullArgs &a, int lo, int hi,
-                                                    int32_t (&X)[kItems], int32_t (&Y)[kItems],
-                                                    int32_t (&I)[kItems]) {
+                                                    int32_t (&X)[kItems], int32_t (&Y)[kItems]) {
     uint32_t vm = 0;
 #pragma unroll
     for (int qq = 0; qq < kQ; ++qq) {
@@ -1042,10 +1087,7 @@ __device__ __forceinline__ uint32_t load_input_wave(const HullArgs &a, int lo, i
             }
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            I[qq * 4 + j] = v0 + j;
-            vm |= (v0 + j < hi ? 1u : 0u) << (qq * 4 + j);
-        }
+        for (int j = 0; j < 4; ++j) vm |= (v0 + j < hi ? 1u : 0u) << (qq * 4 + j);
     }
     return vm;
 }
@@ -1068,11 +1110,12 @@ __device__ __forceinline__ uint32_t gather_pieces(const Ws2 &ws, int p, int R, i
                                                   const int32_t *pvs, const int32_t *pps,
                                                   int32_t (&X)[kItems], int32_t (&Y)[kItems],
                                                   int32_t (&I)[kItems]) {
-    // addresses relative to the tile's first piece: a uniform base and a
-    // 32-bit offset per item (the tile's pieces lie within a few tiles)
+    // a uniform base (the plane) and a 32-bit offset per item (the planes
+    // hold fewer than 2^31 points); the pieces of a tile need not be
+    // physically in order (the round after the split writes side 1 of a
+    // tile backward from the end of its slot)
     const int64_t cap = ws.cap_pts;
-    const int32_t pb0 = pps[0];
-    const int32_t *sx = ws.px(p, R) + pb0, *sy = ws.py(p, R) + pb0, *si = ws.pi(p, R) + pb0;
+    const int32_t *sx = ws.px(p, R), *sy = ws.py(p, R), *si = ws.pi(p, R);
     uint32_t vm = 0;
     bool bad = false;
     // the piece of the lane's first item, then a forward walk with the next
@@ -1081,7 +1124,7 @@ __device__ __forceinline__ uint32_t gather_pieces(const Ws2 &ws, int p, int R, i
     const int w0 = fast_pos(lo, 0);
     if (K > 1) j = slot_of(pvs, K, min(w0, hi - 1));
     int nextv = j + 1 < K ? pvs[j + 1] : INT32_MAX;
-    int delta = pps[j] - pb0 - pvs[j];
+    int delta = pps[j] - pvs[j];
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
         const int v = fast_pos(lo, i);
@@ -1090,10 +1133,10 @@ __device__ __forceinline__ uint32_t gather_pieces(const Ws2 &ws, int p, int R, i
         while (v >= nextv) {
             ++j;
             nextv = j + 1 < K ? pvs[j + 1] : INT32_MAX;
-            delta = pps[j] - pb0 - pvs[j];
+            delta = pps[j] - pvs[j];
         }
-        const int off = v + delta;  // physical position minus the tile's base
-        if (off < 0 || (int64_t)pb0 + off >= cap) { bad = true; continue; }
+        const int off = v + delta;  // physical position
+        if (off < 0 || (int64_t)off >= cap) { bad = true; continue; }
         X[i] = sx[(uint32_t)off];
         Y[i] = sy[(uint32_t)off];
         I[i] = si[(uint32_t)off];
@@ -1136,9 +1179,8 @@ __device__ __forceinline__ uint32_t load_pieces_wave(const Ws2 &ws, int p, int R
 // is classified, and its points are loaded before this tile's survivors are
 // stored (a load issued after a burst of stores waits for them, since the
 // wave's memory counter retires in order).
-template <int MODE, bool INIT>
+template <int MODE>
 __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &a, int r, char *smem) {
-    // INIT: the first split, which reads the input (index = position)
     FastSmem *sm = reinterpret_cast<FastSmem *>(smem);
     uint32_t *stat = sm->stat;
     Control *ctl = ws.ctl;
@@ -1159,7 +1201,7 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
     bool oob = false;
     // the multi-segment tiles of the next round are listed afresh by the
     // segment kernel that follows
-    if (fin_mode(ctl, p, a)) return;  // the multi-segment kernel finishes the segments
+    if (fin_mode(ctl, r, a)) return;  // the multi-segment kernel finishes the segments
     const int T = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
     if (blockIdx.x == 0 && tid == 0) {
         ctl->rs[q].nmulti = 0;
@@ -1244,9 +1286,8 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
         run_hi = hi;
         const int buf = tile & 1;  // LDS buffers of piece tables and wave counts
         if (!have) {
-            vm = INIT ? load_input_wave(a, lo, hi, X, Y, I)
-                      : load_pieces_wave(ws, p, R, lt, R ? nt1 : nt0, R ? npc1 : npc0, lo, hi,
-                                         sm->pvs[buf], sm->pps[buf], X, Y, I);
+            vm = load_pieces_wave(ws, p, R, lt, R ? nt1 : nt0, R ? npc1 : npc0, lo, hi, sm->pvs[buf],
+                                  sm->pps[buf], X, Y, I);
             if (vm == 0xffffffffu) {
                 tc = tn;
                 return false;
@@ -1263,7 +1304,7 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
         int kAn = 0, Kn = 0;
         bool pre = nxt && tn.single;
         int32_t pv0 = 0, pp0 = 0, pv1 = 0, pp1 = 0;
-        if (!INIT && pre) {
+        if (pre) {
             pre = piece_range(ws, p, Rn, ltn, Rn ? nt1 : nt0, Rn ? npc1 : npc0, kAn, Kn) &&
                   Kn <= 2 * kBlock;
             if (pre) {
@@ -1360,7 +1401,7 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
             r1.cnt += (int32_t)lc1;
             const uint32_t wt = wave_sum(lc0 | (lc1 << 16));
             if (lane == 0) sm->wcnt[buf][wv] = wt;
-            if (!INIT && pre) {
+            if (pre) {
                 int32_t *pvs = sm->pvs[buf ^ 1], *pps = sm->pps[buf ^ 1];
                 if (tid < Kn) { pvs[tid] = pv0; pps[tid] = pp0; }
                 if (tid + kBlock < Kn) { pvs[tid + kBlock] = pv1; pps[tid + kBlock] = pp1; }
@@ -1384,9 +1425,7 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
         if (pre) {
             const int lon = ltn * kTile;
             const int hin = min(lon + kTile, Rn ? n1 : n0);
-            vmn = INIT ? load_input_wave(a, lon, hin, Xn, Yn, In)
-                       : gather_pieces(ws, p, Rn, Kn, lon, hin, sm->pvs[buf ^ 1], sm->pps[buf ^ 1],
-                                       Xn, Yn, In);
+            vmn = gather_pieces(ws, p, Rn, Kn, lon, hin, sm->pvs[buf ^ 1], sm->pps[buf ^ 1], Xn, Yn, In);
         }
         // scatter: child c of this tile goes to region c at tile * kTile; a
         // survivor's rank is its wave's base plus the set lanes below it.
@@ -1452,13 +1491,547 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
     }
 }
 
+// ---------------------------------------------------------------------------
+// the first split, read-only
+// ---------------------------------------------------------------------------
+// Algorithm 4's first split tests every point of an instance against the line
+// through its extremes a (lexicographic minimum) and b (maximum):
+// d = (p - a) x (b - a) > 0 puts the point in child 0 (outside a -> b), d < 0 in
+// child 1 (outside b -> a), and d = 0 drops it.  This pass writes no point: it
+// finds each child's farthest point (its apex) and size, and the round after
+// it reads the caller's array again, taking each point's side from the same
+// sign (the children are kept as the instance's input range).
+struct SplitSmem {
+    uint32_t stat[4];
+    RunBest wrb[kNW][2];
+};
+
+// the run's argmax records of the split (2 children) or of the round after it
+// (2 sides x 2 children): wave reduction, then one thread per record
+template <int NREC>
+__device__ __forceinline__ void close_run_records(const Ws2 &ws, RunBest (&rb)[NREC], RunBest (*wrb)[NREC],
+                                                  int cur, int S0, int nt, int run0, bool whole) {
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+#pragma unroll
+    for (int c = 0; c < NREC; ++c) wave_rb63(rb[c]);
+    if (lane == kWave - 1) {
+#pragma unroll
+        for (int c = 0; c < NREC; ++c) wrb[wv][c] = rb[c];
+    }
+    __syncthreads();
+    if (tid < NREC) {
+        RunBest m = wrb[0][tid];
+#pragma unroll
+        for (int w = 1; w < kNW; ++w) rb_merge(m, wrb[w][tid]);
+        Best b;
+        b.key1 = m.k1;
+        b.key2 = m.k2;
+        b.cnt = m.cnt;
+        b.idx = m.k1 ? (int32_t)(uint32_t)m.k2 : 0;
+        b.x = b.y = 0;  // filled in by the segment kernel for the winner
+        // record tid: side s = tid / 2 (region s of the segment tables, tiles
+        // of region 1 after the nt of region 0), child c = tid % 2
+        const int sd = tid >> 1, c = tid & 1;
+        const int g = (sd ? S0 : 0) + cur, rt = (sd ? nt : 0) + run0;
+        if (whole) ws.adir[g * 2 + c] = b;
+        ws.recF[rt * 2 + c] = b;
+        ws.recL[rt * 2 + c] = b;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NREC; ++c) rb[c] = rb_none();
+}
+
+// offer a candidate with its precomputed tie key
+__device__ __forceinline__ void rb_offer_k(RunBest &b, bool take, uint64_t d, uint64_t k2) {
+    const bool better = take && (d > b.k1 || (d == b.k1 && k2 < b.k2));
+    b.k1 = better ? d : b.k1;
+    b.k2 = better ? k2 : b.k2;
+}
+
+// the block's filter counters into the control block
+__device__ __forceinline__ void flush_filter_stats(Control *ctl, uint32_t *stat, uint32_t ntests, uint32_t nfall,
+                                                   uint32_t ncand) {
+    const int tid = threadIdx.x, lane = lane_id();
+    if (tid == 0) { stat[0] = 0; stat[1] = 0; stat[2] = 0; }
+    __syncthreads();
+    const uint32_t t = wave_sum(ntests), f = wave_sum(nfall), c = wave_sum(ncand);
+    if (lane == 0) {
+        atomicAdd(&stat[0], t);
+        atomicAdd(&stat[1], f);
+        atomicAdd(&stat[2], c);
+    }
+    __syncthreads();
+    if (tid == 0 && stat[0]) {
+        atomicAdd(&ctl->filter_tests, (unsigned long long)stat[0]);
+        atomicAdd(&ctl->filter_fallbacks, (unsigned long long)stat[1]);
+        atomicAdd(&ctl->candidates, (unsigned long long)stat[2]);
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, char *smem) {
+    SplitSmem *sm = reinterpret_cast<SplitSmem *>(smem);
+    Control *ctl = ws.ctl;
+    const int n = ctl->rs[0].n[0];
+    const int ntiles = (n + kTile - 1) / kTile;
+    const int tid = threadIdx.x;
+    if (fin_mode(ctl, 0, a)) return;  // the multi-segment kernel finishes the segments
+    const int T = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+    if (blockIdx.x == 0 && tid == 0) {
+        ctl->rs[1].nmulti = 0;
+        ctl->tper[0] = T;
+        ctl->maxseg[1] = 0;
+    }
+    const int tb = blockIdx.x * T, te = min(tb + T, ntiles);
+    const float c2 = MODE ? coord_c2(ctl) : 0.f;
+    RunBest rb[2] = {rb_none(), rb_none()};
+    int cur = -1, run0 = 0, run_lo = 0, run_hi = 0, seg_st = 0, seg_en = 0;
+    uint32_t acc0 = 0, acc1 = 0, ntests = 0, nfall = 0, ncand = 0;
+
+    // one tile whose points are in X, Y (valid mask vm)
+    auto process = [&](int tile, const TileGeo &ti, const int32_t (&X)[kItems], const int32_t (&Y)[kItems],
+                       uint32_t vm) __attribute__((always_inline)) {
+        const int lo = tile * kTile, hi = min(lo + kTile, n);
+        if (cur >= 0 && (!ti.single || ti.seg != cur)) {
+            close_run_records<2>(ws, rb, sm->wrb, cur, 0, 0, run0, seg_st >= run_lo && seg_en <= run_hi);
+            cur = -1;
+        }
+        if (!ti.single) return;  // the multi-segment kernel takes it
+        if (cur < 0) {
+            cur = ti.seg;
+            run0 = tile;
+            run_lo = lo;
+            seg_st = ti.start;
+            seg_en = ti.end;
+        }
+        run_hi = hi;
+        // the instance's extremes: u = v = a, f = b
+        const int ax = ti.ux, ay = ti.uy, bx = ti.fx, by = ti.fy;
+        const int ex = bx - ax, ey = by - ay;
+        uint32_t m0 = 0, m1 = 0;  // the items of child 0 / child 1
+        if (MODE == 0) {
+#pragma unroll
+            for (int i = 0; i < kItems; ++i) {
+                const bool valid = (vm >> i) & 1u;
+                const int64_t d = cross_i64(X[i], Y[i], ax, ay, bx, by);
+                const bool o0 = valid && d > 0, o1 = valid && d < 0;
+                m0 |= (o0 ? 1u : 0u) << i;
+                m1 |= (o1 ? 1u : 0u) << i;
+                const int32_t idx = fast_pos_init(lo, i);
+                rb_offer_nb(rb[0], o0, (uint64_t)d, X[i], Y[i], idx, ex, ey);
+                rb_offer_nb(rb[1], o1, (uint64_t)(-d), X[i], Y[i], idx, -ex, -ey);
+            }
+        } else {
+            // FP32 estimates with one bound for every point; the child's
+            // farthest point is among the items whose estimate is within twice
+            // the bound of the wave's largest estimate in that child
+            const float B = static_bound(ex, ey, c2);
+            float E[kItems];
+            float l0 = -INFINITY, l1 = -INFINITY;
+            uint32_t und = 0;
+#pragma unroll
+            for (int i = 0; i < kItems; ++i) {
+                const bool valid = (vm >> i) & 1u;
+                const float e = cross_f32_nb(X[i], Y[i], ax, ay, ex, ey);
+                E[i] = e;
+                const bool p0 = valid && e > B, n0 = valid && e < -B;
+                m0 |= (p0 ? 1u : 0u) << i;
+                m1 |= (n0 ? 1u : 0u) << i;
+                und |= (valid && !p0 && !n0 ? 1u : 0u) << i;
+                l0 = p0 ? fmaxf(l0, e) : l0;
+                l1 = n0 ? fmaxf(l1, -e) : l1;
+            }
+            ntests += (uint32_t)__popc(vm);
+            // undecided signs (rare): exact, and always argmax candidates
+            if (__ballot(und != 0)) {
+#pragma unroll
+                for (int i = 0; i < kItems; ++i) {
+                    if (!((und >> i) & 1u)) continue;
+                    const int64_t d = cross_i64(X[i], Y[i], ax, ay, bx, by);
+                    m0 |= (d > 0 ? 1u : 0u) << i;
+                    m1 |= (d < 0 ? 1u : 0u) << i;
+                }
+                nfall += (uint32_t)__popc(und);
+            }
+            const float t0 = __fsub_rn(wave_max_f_dpp(l0), 2.f * B);
+            const float t1 = __fsub_rn(wave_max_f_dpp(l1), 2.f * B);
+#pragma unroll
+            for (int i = 0; i < kItems; ++i) {
+                const bool forced = (und >> i) & 1u;
+                const bool c0 = ((m0 >> i) & 1u) && (forced || E[i] >= t0);
+                const bool c1 = ((m1 >> i) & 1u) && (forced || -E[i] >= t1);
+                if (!__ballot(c0 || c1)) continue;
+                if (c0 || c1) {
+                    ++ncand;
+                    const int64_t d = cross_i64(X[i], Y[i], ax, ay, bx, by);
+                    const int32_t idx = fast_pos_init(lo, i);
+                    if (c0) rb_offer(rb[0], (uint64_t)d, X[i], Y[i], idx, ex, ey);
+                    else rb_offer(rb[1], (uint64_t)(-d), X[i], Y[i], idx, -ex, -ey);
+                }
+            }
+        }
+        const uint32_t lc0 = (uint32_t)__popc(m0), lc1 = (uint32_t)__popc(m1);
+        rb[0].cnt += (int32_t)lc0;
+        rb[1].cnt += (int32_t)lc1;
+        acc0 += lc0;
+        acc1 += lc1;
+    };
+    // software pipelined: the next tile's record and points are requested
+    // before this tile is classified (no stores, so no wait orders them)
+    int32_t XA[kItems], YA[kItems], XB[kItems], YB[kItems];
+    uint32_t vmA = 0, vmB = 0;
+    TileGeo tc;
+    tc.single = 0;
+    if (tb < te) {
+        tc = tile_record(ws, 0, tb, ntiles);
+        if (tc.single) vmA = load_input_wave(a, tb * kTile, min(tb * kTile + kTile, n), XA, YA);
+    }
+    for (int tile = tb; tile < te; tile += 2) {
+        TileGeo tn;
+        tn.single = 0;
+        if (tile + 1 < te) {
+            tn = tile_record(ws, 0, tile + 1, ntiles);
+            if (tn.single) vmB = load_input_wave(a, (tile + 1) * kTile, min((tile + 2) * kTile, n), XB, YB);
+        }
+        process(tile, tc, XA, YA, vmA);
+        tc = tn;
+        if (tile + 1 >= te) break;
+        tn.single = 0;
+        if (tile + 2 < te) {
+            tn = tile_record(ws, 0, tile + 2, ntiles);
+            if (tn.single) vmA = load_input_wave(a, (tile + 2) * kTile, min((tile + 3) * kTile, n), XA, YA);
+        }
+        process(tile + 1, tc, XB, YB, vmB);
+        tc = tn;
+    }
+    if (cur >= 0) close_run_records<2>(ws, rb, sm->wrb, cur, 0, 0, run0, seg_st >= run_lo && seg_en <= run_hi);
+    // survivors of the split (counted, not written) per child
+    const uint32_t s0 = wave_sum(acc0), s1 = wave_sum(acc1);
+    if (lane_id() == 0 && (s0 | s1)) {
+        atomicAdd(&ctl->nacc[0][0], s0);
+        atomicAdd(&ctl->nacc[0][1], s1);
+    }
+    if (MODE != 0) flush_filter_stats(ctl, sm->stat, ntests, nfall, ncand);
+}
+
+// ---------------------------------------------------------------------------
+// the round after the read-only split
+// ---------------------------------------------------------------------------
+// Its segments are the split's children: child 0 of an instance (edge a -> b,
+// apex f0) holds the instance's points with (p - a) x (b - a) > 0, child 1
+// (edge b -> a, apex f1) those with a negative sign.  Both are kept as the
+// instance's input range, child 0 in region 0 and child 1 in region 1 under
+// the same segment index, so one pass over the caller's array serves both:
+// each point takes its side from the sign, then is tested against its
+// side's new edges u -> f and f -> v as in every round (Algorithm 1's
+// classification).  The survivors of input tile t that go to child c of
+// side 0 are written to region c from the start of slot t, those of side 1
+// so that they end at the slot's end (a tile has at most kTile points on
+// both sides together); for the piece table they are the pieces of tile t
+// and of tile nt + t, the tiles of region 0 and region 1 of this round.
+struct Ro1Smem {
+    uint32_t stat[4];
+    RunBest wrb[kNW][4];
+    uint32_t wcnt[kNW][4];                   // survivors of the tile per wave and class
+    int32_t sx[kTile], sy[kTile], si[kTile];  // the tile's survivors, grouped by class
+};
+
+// a tile's record in this round with the geometry of both sides
+struct TileGeo2 {
+    int32_t seg, single, start, end;
+    int32_t ax, ay, bx, by, f0x, f0y, f1x, f1y;
+};
+
+__device__ __forceinline__ TileGeo2 ro1_record(const Ws2 &ws, int lt) {
+    const int32_t *src = reinterpret_cast<const int32_t *>(ws.tinfo(1, 0) + lt);
+    TileGeo2 ti;
+    ti.seg = scalar_load(src + 0);
+    ti.single = scalar_load(src + 1);
+    ti.start = scalar_load(src + 2);
+    ti.end = scalar_load(src + 3);
+    ti.ax = ti.ay = ti.bx = ti.by = ti.f0x = ti.f0y = ti.f1x = ti.f1y = 0;
+    if (ti.single) {
+        const int32_t *g0 = reinterpret_cast<const int32_t *>(ws.geo(1, 0) + ti.seg);
+        const int32_t *g1 = reinterpret_cast<const int32_t *>(ws.geo(1, 1) + ti.seg);
+        ti.ax = scalar_load(g0 + 2); ti.ay = scalar_load(g0 + 3);
+        ti.f0x = scalar_load(g0 + 4); ti.f0y = scalar_load(g0 + 5);
+        ti.bx = scalar_load(g0 + 6); ti.by = scalar_load(g0 + 7);
+        ti.f1x = scalar_load(g1 + 4); ti.f1y = scalar_load(g1 + 5);
+    }
+    return ti;
+}
+
+// the 8-bit field c of a packed counter
+__device__ __forceinline__ uint32_t field8(uint32_t v, uint32_t c) { return (v >> (8u * c)) & 0xffu; }
+
+// Items are classified into four classes, k = 2 side + child (0: side 0 /
+// child 0, 1: side 0 / child 1, 2: side 1 / child 0, 3: side 1 / child 1),
+// 4 = dropped; three bits per item in one register.  The survivors of a tile
+// are staged in LDS grouped by class (each lane's items in item order at the
+// lane's offset within its wave's share), then written out in order: class
+// k goes to region (k & 1), side 0 from the start of the tile's slot, side 1
+// so that it ends at the slot's end.
+template <int MODE>
+__device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a, char *smem) {
+    Ro1Smem *sm = reinterpret_cast<Ro1Smem *>(smem);
+    Control *ctl = ws.ctl;
+    const RoundState *rs = &ctl->rs[1];
+    const int n = rs->n[0];  // = rs->n[1]: both regions are the input
+    const int S0 = rs->s[0];
+    const int nt = (n + kTile - 1) / kTile;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+    int32_t *const obase = ws.px(0, 0);  // output planes: [child][x, y, index][cap]
+    const int64_t cap = ws.cap_pts;
+    const int T = (nt + (int)gridDim.x - 1) / (int)gridDim.x;
+    if (blockIdx.x == 0 && tid == 0) {
+        ctl->rs[0].nmulti = 0;
+        ctl->tper[1] = T;
+        ctl->maxseg[0] = 0;
+    }
+    const int tb = blockIdx.x * T, te = min(tb + T, nt);
+    const float c2 = MODE ? coord_c2(ctl) : 0.f;
+    RunBest rb[4] = {rb_none(), rb_none(), rb_none(), rb_none()};
+    int cur = -1, run0 = 0, run_lo = 0, run_hi = 0, seg_st = 0, seg_en = 0;
+    uint32_t acc0 = 0, acc1 = 0, ntests = 0, nfall = 0, ncand = 0;
+    bool oob = false;
+
+    for (int tile = tb; tile <= te; ++tile) {
+        TileGeo2 ti;
+        ti.single = 0;
+        if (tile < te) ti = ro1_record(ws, tile);
+        if (cur >= 0 && (!ti.single || ti.seg != cur)) {
+            close_run_records<4>(ws, rb, sm->wrb, cur, S0, nt, run0, seg_st >= run_lo && seg_en <= run_hi);
+            cur = -1;
+        }
+        if (!ti.single) continue;  // past the last tile, or the multi-segment kernel takes it
+        const int lo = tile * kTile, hi = min(lo + kTile, n);
+        if (cur < 0) {
+            cur = ti.seg;
+            run0 = tile;
+            run_lo = lo;
+            seg_st = ti.start;
+            seg_en = ti.end;
+        }
+        run_hi = hi;
+        int32_t X[kItems], Y[kItems];
+        const uint32_t vm = load_input_wave(a, lo, hi, X, Y);
+        // side line a -> b; child edges per side: side 0 a -> f0 -> b, side 1
+        // b -> f1 -> a
+        const int ax = ti.ax, ay = ti.ay, bx = ti.bx, by = ti.by;
+        const int e00x = ti.f0x - ax, e00y = ti.f0y - ay, e01x = bx - ti.f0x, e01y = by - ti.f0y;
+        const int e10x = ti.f1x - bx, e10y = ti.f1y - by, e11x = ax - ti.f1x, e11y = ay - ti.f1y;
+        uint32_t cl = 0;  // class of item i in bits 3i .. 3i + 2
+        if (MODE == 0) {
+#pragma unroll
+            for (int i = 0; i < kItems; ++i) {
+                const bool valid = (vm >> i) & 1u;
+                const int32_t x = X[i], y = Y[i];
+                const int64_t ds = cross_i64(x, y, ax, ay, bx, by);
+                const bool s1 = ds < 0, live = valid && ds != 0;
+                const int ux = s1 ? bx : ax, uy = s1 ? by : ay;
+                const int fx = s1 ? ti.f1x : ti.f0x, fy = s1 ? ti.f1y : ti.f0y;
+                const int c0x = s1 ? e10x : e00x, c0y = s1 ? e10y : e00y;
+                const int c1x = s1 ? e11x : e01x, c1y = s1 ? e11y : e01y;
+                const int64_t d0 = (int64_t)(x - ux) * (int64_t)c0y - (int64_t)(y - uy) * (int64_t)c0x;
+                const int64_t d1 = (int64_t)(x - fx) * (int64_t)c1y - (int64_t)(y - fy) * (int64_t)c1x;
+                const bool o0 = live && d0 > 0, o1 = live && !o0 && d1 > 0;
+                const uint32_t k = (o0 || o1) ? (s1 ? 2u : 0u) + (o1 ? 1u : 0u) : 4u;
+                cl |= k << (3 * i);
+                const uint64_t dsel = (uint64_t)(o0 ? d0 : d1);
+                // the full comparison only for lanes whose distance reaches
+                // the running best of their class (fewer and fewer as a run
+                // goes on), the whole wave skipping it when none does
+                const bool need = (k == 0 && dsel >= rb[0].k1) || (k == 1 && dsel >= rb[1].k1) ||
+                                  (k == 2 && dsel >= rb[2].k1) || (k == 3 && dsel >= rb[3].k1);
+                if (__ballot(need)) {
+                    const uint64_t tk = tie_key(x, y, fast_pos_init(lo, i), o0 ? c0x : c1x, o0 ? c0y : c1y);
+                    rb_offer_k(rb[0], k == 0, dsel, tk);
+                    rb_offer_k(rb[1], k == 1, dsel, tk);
+                    rb_offer_k(rb[2], k == 2, dsel, tk);
+                    rb_offer_k(rb[3], k == 3, dsel, tk);
+                }
+            }
+        } else {
+            const float Bs = static_bound(bx - ax, by - ay, c2);
+            const float Bk[4] = {static_bound(e00x, e00y, c2), static_bound(e01x, e01y, c2),
+                                 static_bound(e10x, e10y, c2), static_bound(e11x, e11y, c2)};
+            float E[kItems];
+            float l[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+            uint32_t und = 0;
+#pragma unroll
+            for (int i = 0; i < kItems; ++i) {
+                const bool valid = (vm >> i) & 1u;
+                const int32_t x = X[i], y = Y[i];
+                const float es = cross_f32_nb(x, y, ax, ay, bx - ax, by - ay);
+                const bool s1 = es < -Bs, sure = s1 || es > Bs;
+                const int ux = s1 ? bx : ax, uy = s1 ? by : ay;
+                const int fx = s1 ? ti.f1x : ti.f0x, fy = s1 ? ti.f1y : ti.f0y;
+                const int c0x = s1 ? e10x : e00x, c0y = s1 ? e10y : e00y;
+                const int c1x = s1 ? e11x : e01x, c1y = s1 ? e11y : e01y;
+                const float B0 = s1 ? Bk[2] : Bk[0], B1 = s1 ? Bk[3] : Bk[1];
+                const float e0 = cross_f32_nb(x, y, ux, uy, c0x, c0y);
+                const float e1 = cross_f32_nb(x, y, fx, fy, c1x, c1y);
+                // 0, 1: child; 2: dropped; 3: undecided
+                uint32_t st = e0 > B0 ? 0u : (!(e0 < -B0) ? 3u : (e1 > B1 ? 1u : (e1 < -B1 ? 2u : 3u)));
+                st = !valid ? 2u : (!sure ? 3u : st);
+                const uint32_t k = st < 2 ? (s1 ? 2u : 0u) + st : 4u;
+                cl |= k << (3 * i);
+                und |= (st == 3 ? 1u : 0u) << i;
+                const float e = st == 0 ? e0 : e1;
+                E[i] = e;
+                l[0] = k == 0 ? fmaxf(l[0], e) : l[0];
+                l[1] = k == 1 ? fmaxf(l[1], e) : l[1];
+                l[2] = k == 2 ? fmaxf(l[2], e) : l[2];
+                l[3] = k == 3 ? fmaxf(l[3], e) : l[3];
+                ntests += valid ? (sure ? (e0 > B0 ? 2u : 3u) : 1u) : 0u;
+            }
+            // undecided items (rare): the whole classification in int64; their
+            // exact distances make them argmax candidates
+            if (__ballot(und != 0)) {
+#pragma unroll
+                for (int i = 0; i < kItems; ++i) {
+                    if (!((und >> i) & 1u)) continue;
+                    const int32_t x = X[i], y = Y[i];
+                    const int64_t ds = cross_i64(x, y, ax, ay, bx, by);
+                    const bool s1 = ds < 0;
+                    const bool o0 = ds != 0 && cross_i64(x, y, s1 ? bx : ax, s1 ? by : ay, s1 ? ti.f1x : ti.f0x,
+                                                         s1 ? ti.f1y : ti.f0y) > 0;
+                    const bool o1 = ds != 0 && !o0 &&
+                                    cross_i64(x, y, s1 ? ti.f1x : ti.f0x, s1 ? ti.f1y : ti.f0y, s1 ? ax : bx,
+                                              s1 ? ay : by) > 0;
+                    const uint32_t k = (o0 || o1) ? (s1 ? 2u : 0u) + (o1 ? 1u : 0u) : 4u;
+                    cl = (cl & ~(7u << (3 * i))) | (k << (3 * i));
+                }
+                nfall += (uint32_t)__popc(und);
+            }
+            float t[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) t[kk] = __fsub_rn(wave_max_f_dpp(l[kk]), 2.f * Bk[kk]);
+#pragma unroll
+            for (int i = 0; i < kItems; ++i) {
+                const uint32_t k = (cl >> (3 * i)) & 7u;
+                const bool forced = (und >> i) & 1u;
+                const float th = (k & 2u) ? ((k & 1u) ? t[3] : t[2]) : ((k & 1u) ? t[1] : t[0]);
+                const bool c = k < 4 && (forced || E[i] >= th);
+                if (!__ballot(c)) continue;
+                if (c) {
+                    ++ncand;
+                    const bool s1 = (k & 2u) != 0, in0 = (k & 1u) == 0;
+                    const int32_t x = X[i], y = Y[i];
+                    const int ux = s1 ? bx : ax, uy = s1 ? by : ay;
+                    const int fx = s1 ? ti.f1x : ti.f0x, fy = s1 ? ti.f1y : ti.f0y;
+                    const int cx = in0 ? (s1 ? e10x : e00x) : (s1 ? e11x : e01x);
+                    const int cy = in0 ? (s1 ? e10y : e00y) : (s1 ? e11y : e01y);
+                    const int px0 = in0 ? ux : fx, py0 = in0 ? uy : fy;
+                    const int64_t d = (int64_t)(x - px0) * (int64_t)cy - (int64_t)(y - py0) * (int64_t)cx;
+                    const uint64_t tk = tie_key(x, y, fast_pos_init(lo, i), cx, cy);
+                    rb_offer_k(rb[0], k == 0, (uint64_t)d, tk);
+                    rb_offer_k(rb[1], k == 1, (uint64_t)d, tk);
+                    rb_offer_k(rb[2], k == 2, (uint64_t)d, tk);
+                    rb_offer_k(rb[3], k == 3, (uint64_t)d, tk);
+                }
+            }
+        }
+        // per-lane counts of the four classes (8-bit fields), their prefix in
+        // the wave (16-bit fields, two classes per word)
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t k = (cl >> (3 * i)) & 7u;
+            cnt += k < 4 ? (1u << (8u * k)) : 0u;
+        }
+        rb[0].cnt += (int32_t)field8(cnt, 0);
+        rb[1].cnt += (int32_t)field8(cnt, 1);
+        rb[2].cnt += (int32_t)field8(cnt, 2);
+        rb[3].cnt += (int32_t)field8(cnt, 3);
+        const uint32_t c01 = field8(cnt, 0) | (field8(cnt, 1) << 16), c23 = field8(cnt, 2) | (field8(cnt, 3) << 16);
+        const uint32_t i01 = wave_incl_sum(c01), i23 = wave_incl_sum(c23);
+        if (lane == kWave - 1) {
+            sm->wcnt[wv][0] = i01 & 0xffffu;
+            sm->wcnt[wv][1] = i01 >> 16;
+            sm->wcnt[wv][2] = i23 & 0xffffu;
+            sm->wcnt[wv][3] = i23 >> 16;
+        }
+        __syncthreads();
+        uint32_t tot[4], wb[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            tot[k] = 0;
+            wb[k] = 0;
+#pragma unroll
+            for (int w = 0; w < kNW; ++w) {
+                const uint32_t c = sm->wcnt[w][k];
+                wb[k] += (w < wv) ? c : 0u;
+                tot[k] += c;
+            }
+        }
+        const uint32_t cs1 = tot[0], cs2 = cs1 + tot[1], cs3 = cs2 + tot[2], S = cs3 + tot[3];
+        // staging offsets of this lane's first item of each class
+        const uint32_t e01 = i01 - c01, e23 = i23 - c23;
+        const uint32_t lb0 = wb[0] + (e01 & 0xffffu), lb1 = cs1 + wb[1] + (e01 >> 16);
+        const uint32_t lb2 = cs2 + wb[2] + (e23 & 0xffffu), lb3 = cs3 + wb[3] + (e23 >> 16);
+        uint32_t run = 0;  // the lane's items staged so far per class (8-bit fields)
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t k = (cl >> (3 * i)) & 7u;
+            if (k < 4) {
+                const uint32_t pos = ((k & 2u) ? ((k & 1u) ? lb3 : lb2) : ((k & 1u) ? lb1 : lb0)) + field8(run, k);
+                run += 1u << (8u * k);
+                sm->sx[pos] = X[i];
+                sm->sy[pos] = Y[i];
+                sm->si[pos] = fast_pos_init(lo, i);
+            }
+        }
+        __syncthreads();
+        // write out: class k of output j by comparing with the class starts;
+        // slot position j + D[k]
+        const int64_t pbase = (int64_t)tile * kTile;
+        const bool fits = pbase + kTile <= cap - kTile;
+        oob |= !fits;
+        int32_t *const P0 = obase + pbase;
+        int32_t *const P1 = P0 + 3 * cap;
+        const int32_t D0 = 0, D1 = -(int32_t)cs1;
+        const int32_t D2 = kTile - (int32_t)tot[2] - (int32_t)cs2, D3 = kTile - (int32_t)tot[3] - (int32_t)cs3;
+        if (fits) {
+            for (uint32_t j = (uint32_t)tid; j < S; j += kBlock) {
+                const bool g1 = j >= cs1, g2 = j >= cs2, g3 = j >= cs3;
+                const int32_t D = g3 ? D3 : (g2 ? D2 : (g1 ? D1 : D0));
+                const bool r1 = g3 || (g1 && !g2);  // classes 1 and 3 go to region 1
+                int32_t *d = (r1 ? P1 : P0) + ((int32_t)j + D);
+                d[0] = sm->sx[j];
+                d[cap] = sm->sy[j];
+                d[2 * cap] = sm->si[j];
+            }
+        }
+        if (tid == 0) {
+            ws.tcnt(1)[tile] = tot[0] | (tot[1] << 16);
+            ws.tcnt(1)[nt + tile] = tot[2] | (tot[3] << 16);
+            acc0 += tot[0] + tot[2];
+            acc1 += tot[1] + tot[3];
+        }
+        __syncthreads();  // the staging buffer is reused by the next tile
+    }
+    if (oob) atomicOr(&ctl->error, kErrInternal);
+    if (tid == 0 && (acc0 | acc1)) {
+        atomicAdd(&ctl->nacc[1][0], acc0);
+        atomicAdd(&ctl->nacc[1][1], acc1);
+    }
+    if (MODE != 0) flush_filter_stats(ctl, sm->stat, ntests, nfall, ncand);
+}
+
 // Tiles that hold several segments (listed by the segment kernel): the whole
 // block in point order, per-segment reductions in LDS.
 template <int MODE>
 __device__ __forceinline__ void phase_round_multi(const Ws2 &ws, const HullArgs &a, int r, char *smem) {
     RoundSmem *sm = reinterpret_cast<RoundSmem *>(smem);
     uint32_t *stat = sm->stat;
-    const bool INIT = r == 0;  // the first split reads the input (index = position)
+    // the split and the round after it read the input (index = position); the
+    // split writes no point, and in the round after it a segment keeps only
+    // the points strictly outside its own edge u -> v (its side of the
+    // split's line), and region 1 writes its survivors so that they end at
+    // the end of their tile's slot
+    const bool INIT = r <= 1, KEEP = r != 0, OWN = r == 1;
     Control *ctl = ws.ctl;
     const int p = r & 1, q = p ^ 1;
     const RoundState *rs = &ctl->rs[p];
@@ -1565,6 +2138,21 @@ __device__ __forceinline__ void phase_round_multi(const Ws2 &ws, const HullArgs 
                     const int fx = sm->lgeo[ls][2], fy = sm->lgeo[ls][3];
                     const int vx = sm->lgeo[ls][4], vy = sm->lgeo[ls][5];
                     uint32_t st = 2;
+                    if (OWN) {
+                        // the split's side: strictly outside the segment's own edge
+                        bool own;
+                        if (MODE == 0) {
+                            own = cross_i64(X[i], Y[i], ux, uy, vx, vy) > 0;
+                        } else {
+                            float Bo;
+                            const float eo = cross_f32(X[i], Y[i], ux, uy, vx, vy, Bo);
+                            ntests++;
+                            if (eo > Bo) own = true;
+                            else if (eo < -Bo) own = false;
+                            else { nfall++; own = cross_i64(X[i], Y[i], ux, uy, vx, vy) > 0; }
+                        }
+                        if (!own) continue;
+                    }
                     if (MODE == 0) {
                         const int64_t d0 = cross_i64(X[i], Y[i], ux, uy, fx, fy);
                         if (d0 > 0) {
@@ -1683,28 +2271,32 @@ __device__ __forceinline__ void phase_round_multi(const Ws2 &ws, const HullArgs 
 #pragma unroll
             for (int qq = 0; qq < kQ; ++qq) rr[qq] = rowbase[qq] + cnt[qq];
         }
-        // scatter: child c of this tile goes to region c at tile * kTile
-        const int64_t pbase = (int64_t)tile * kTile;
+        // scatter: child c of this tile goes to region c at tile * kTile; in the
+        // round after the split, region 1's tiles (side 1 of input tile lt)
+        // end at the end of slot lt
+        const int64_t pbase = (int64_t)(OWN ? lt : tile) * kTile;
+        const int64_t pb0 = pbase + ((OWN && R) ? kTile - (int64_t)(total & 0xffffu) : 0);
+        const int64_t pb1 = pbase + ((OWN && R) ? kTile - (int64_t)(total >> 16) : 0);
 #pragma unroll
-        for (int qq = 0; qq < kQ; ++qq) {
+        for (int qq = 0; qq < kQ && KEEP; ++qq) {
             uint32_t q_ = rr[qq];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int i = qq * 4 + j;
                 const uint32_t st = (stbits >> (2 * i)) & 3u;
                 if (st == 0) {
-                    const int64_t e = pbase + (q_ & 0xffffu);
+                    const int64_t e = pb0 + (q_ & 0xffffu);
                     if (e < cap) { ox0[e] = X[i]; oy0[e] = Y[i]; oi0[e] = I[i]; } else oob = true;
                     q_ += 1u;
                 } else if (st == 1) {
-                    const int64_t e = pbase + (q_ >> 16);
+                    const int64_t e = pb1 + (q_ >> 16);
                     if (e < cap) { ox1[e] = X[i]; oy1[e] = Y[i]; oi1[e] = I[i]; } else oob = true;
                     q_ += 0x10000u;
                 }
             }
         }
         if (tid == 0) {
-            ws.tcnt(p)[tile] = total;
+            if (KEEP) ws.tcnt(p)[tile] = total;
             acc0 += total & 0xffffu;
             acc1 += total >> 16;
         }
@@ -2024,13 +2616,15 @@ __device__ void phase_finish(const Ws2 &ws, const HullArgs &a, int r, FinSmem *s
 
 // Merge the record slots of one segment, both children, with one wave (the
 // result is valid in its last lane).
+// In the round after the split (sub = the region's tile offset) the blocks'
+// tile ranges start at multiples of T in each region's own tile numbers.
 __device__ __forceinline__ void wave_merge_seg(const Ws2 &ws, int p, int R, int nt0, int T, int t0,
-                                               int t1, Best &m0, Best &m1) {
+                                               int t1, int sub, Best &m0, Best &m1) {
     const TileInfo *ti = ws.tinfo(p, R);
     const int off = R ? nt0 : 0;
     const bool s0 = ti[t0 - off].single != 0, s1 = ti[t1 - off].single != 0;
     Best acc0 = best_none(), acc1 = best_none();
-    const int ns = seg_slots(T, t0, t1);
+    const int ns = seg_slots(T, t0 - sub, t1 - sub);
     // four slots per lane requested at a time, then merged (order-free)
     for (int k0 = lane_id(); k0 < ns; k0 += 4 * kWave) {
         Best c0[4], c1[4];
@@ -2040,11 +2634,11 @@ __device__ __forceinline__ void wave_merge_seg(const Ws2 &ws, int p, int R, int 
             c1[u] = best_none();
             bool last;
             const int k = k0 + u * kWave;
-            const int t = k < ns ? seg_slot(T, t0, t1, s0, s1, k, last) : -1;
+            const int t = k < ns ? seg_slot(T, t0 - sub, t1 - sub, s0, s1, k, last) : -1;
             if (t >= 0) {
                 const Best *rec = last ? ws.recL : ws.recF;
-                c0[u] = rec[t * 2 + 0];
-                c1[u] = rec[t * 2 + 1];
+                c0[u] = rec[(t + sub) * 2 + 0];
+                c1[u] = rec[(t + sub) * 2 + 1];
             }
         }
 #pragma unroll
@@ -2073,11 +2667,19 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
     const int nt0 = (rs->n[0] + kTile - 1) / kTile;
     const int nt1 = (rs->n[1] + kTile - 1) / kTile;
     // survivors of this round per region (summed by the round kernel's blocks)
-    const int Nn0 = (int)ctl->nacc[p][0], Nn1 = (int)ctl->nacc[p][1];
+    const int An0 = (int)ctl->nacc[p][0], An1 = (int)ctl->nacc[p][1];
+    // The split (r = 0) keeps no point: its children are the instances'
+    // input ranges (both regions of the next round are the input), and every
+    // child is made, even an empty one, so that every input tile has its
+    // record.  The round after it (r = 1) reads its tiles per region in the
+    // input's tile numbers.
+    const bool ro0 = r == 0, ro1 = r == 1;
+    const int nin0 = rs->n[0] + rs->n[1];
+    const int Nn0 = ro0 ? nin0 : An0, Nn1 = ro0 ? nin0 : An1;
     const int nsegt = (Stot + kSegBlock - 1) / kSegBlock;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
 
-    if (fin_mode(ctl, p, a)) {
+    if (fin_mode(ctl, r, a)) {
         // the segments were finished by the multi-segment kernel: no next round
         if (blockIdx.x == 0 && tid == 0) {
             RoundState z = {};
@@ -2098,12 +2700,15 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
         ctl->nacc[q][1] = 0;
         const unsigned long long nin = (unsigned long long)(rs->n[0] + rs->n[1]);
         if (nin) {
-            if (r == 0) {
+            if (ro0) {
                 ctl->first_in += nin;
-                ctl->first_out += (unsigned long long)(Nn0 + Nn1);
+                ctl->first_out += (unsigned long long)(An0 + An1);
+            } else if (ro1) {
+                ctl->second_in += (unsigned long long)rs->n[0];  // both regions are the input
+                ctl->second_out += (unsigned long long)(An0 + An1);
             } else {
                 ctl->points_in += nin;
-                ctl->points_out += (unsigned long long)(Nn0 + Nn1);
+                ctl->points_out += (unsigned long long)(An0 + An1);
             }
             ctl->rounds_with_work += 1ull;
         }
@@ -2150,12 +2755,13 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
         const int t0 = (R ? nt0 : 0) + G.start / kTile;
         const int t1 = (R ? nt0 : 0) + (G.start + G.len - 1) / kTile;
         const int T = max(1, ctl->tper[p]);
+        const int sub = (ro1 && R) ? nt0 : 0;  // see wave_merge_seg
         if (valid) {
             if (t0 == t1) {
                 b0 = ws.adir[g * 2 + 0];
                 b1 = ws.adir[g * 2 + 1];
-            } else if (seg_slots(T, t0, t1) <= 12) {
-                const int ns = seg_slots(T, t0, t1);
+            } else if (seg_slots(T, t0 - sub, t1 - sub) <= 12) {
+                const int ns = seg_slots(T, t0 - sub, t1 - sub);
                 const TileInfo *ti = ws.tinfo(p, R);
                 const int off = R ? nt0 : 0;
                 const bool s0 = ti[t0 - off].single != 0, s1 = ti[t1 - off].single != 0;
@@ -2168,11 +2774,11 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
                         c0[u] = best_none();
                         c1[u] = best_none();
                         bool last;
-                        const int t = k0 + u < ns ? seg_slot(T, t0, t1, s0, s1, k0 + u, last) : -1;
+                        const int t = k0 + u < ns ? seg_slot(T, t0 - sub, t1 - sub, s0, s1, k0 + u, last) : -1;
                         if (t >= 0) {
                             const Best *rec = last ? ws.recL : ws.recF;
-                            c0[u] = rec[t * 2 + 0];
-                            c1[u] = rec[t * 2 + 1];
+                            c0[u] = rec[(t + sub) * 2 + 0];
+                            c1[u] = rec[(t + sub) * 2 + 1];
                         }
                     }
 #pragma unroll
@@ -2196,14 +2802,14 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             const int a0 = sm->o_t0[own], a1 = sm->o_t1[own];
             const int Ro = own + tile * kSegBlock < S0 ? 0 : 1;
             Best m0, m1;
-            wave_merge_seg(ws, p, Ro, nt0, T, a0, a1, m0, m1);
+            wave_merge_seg(ws, p, Ro, nt0, T, a0, a1, (ro1 && Ro) ? nt0 : 0, m0, m1);
             if (lane == kWave - 1) {
                 sm->qres[own * 2 + 0] = m0;
                 sm->qres[own * 2 + 1] = m1;
             }
         }
         __syncthreads();
-        if (valid && t0 != t1 && seg_slots(T, t0, t1) > 12) {
+        if (valid && t0 != t1 && seg_slots(T, t0 - sub, t1 - sub) > 12) {
             b0 = sm->qres[tid * 2 + 0];
             b1 = sm->qres[tid * 2 + 1];
         }
@@ -2214,7 +2820,10 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
 
         // the apex f of this segment joins the hull between u and v
         int fc = 0;
-        if (valid) {
+        if (valid && Tp.fidx < 0) {
+            // an empty child of the split: no apex, its hull id stays unused
+            if (hbase + g < ws.hcap) ws.nxt[hbase + g] = -1;
+        } else if (valid) {
             const bool same = (G.fx == G.ux) && (G.fy == G.uy);
             fc = same ? Tp.uc : hbase + g;
             if (!same) {
@@ -2231,14 +2840,15 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
 
         // ids of the non-empty children, and their start offsets (children of
         // earlier segments come first, in both regions of the next round)
-        const bool has0 = valid && c0 > 0, has1 = valid && c1 > 0;
+        const bool has0 = valid && (ro0 || c0 > 0), has1 = valid && (ro0 || c1 > 0);
+        const int len0 = ro0 ? G.len : c0, len1 = ro0 ? G.len : c1;  // the children's ranges
         uint32_t v[2] = {has0 ? 1u : 0u, has1 ? 1u : 0u}, tot[2];
         block_excl_scan<kSegBlock, 2>(v, tot, sm->scan);
         if (wv == 0) {
             const uint64_t ex = lookback_excl(ws.st4(p), tile, pack2(tot[0], tot[1]), &ctl->error);
             if (lane == 0) sm->s_ex = ex;
         }
-        uint32_t w[2] = {(uint32_t)c0, (uint32_t)c1}, wt[2];
+        uint32_t w[2] = {(uint32_t)len0, (uint32_t)len1}, wt[2];
         block_excl_scan<kSegBlock, 2>(w, wt, sm->scan2);
         if (wv == 0) {
             const uint64_t ex = lookback_excl(ws.st4b(p), tile, pack2(wt[0], wt[1]), &ctl->error);
@@ -2262,24 +2872,24 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
         // child segments of the next round
         if (ok0) {
             SegGeo cg;
-            cg.start = st0; cg.len = c0;
+            cg.start = st0; cg.len = len0;
             cg.ux = G.ux; cg.uy = G.uy;
             cg.fx = b0.x; cg.fy = b0.y;
             cg.vx = G.fx; cg.vy = G.fy;
             ws.geo(q, 0)[id0] = cg;
             SegTop ct;
-            ct.fidx = b0.idx; ct.uc = Tp.uc; ct.vc = fc; ct.inst = Tp.inst;
+            ct.fidx = c0 > 0 ? b0.idx : -1; ct.uc = Tp.uc; ct.vc = fc; ct.inst = Tp.inst;
             ws.top(q, 0)[id0] = ct;
         }
         if (ok1) {
             SegGeo cg;
-            cg.start = st1; cg.len = c1;
+            cg.start = st1; cg.len = len1;
             cg.ux = G.fx; cg.uy = G.fy;
             cg.fx = b1.x; cg.fy = b1.y;
             cg.vx = G.vx; cg.vy = G.vy;
             ws.geo(q, 1)[id1] = cg;
             SegTop ct;
-            ct.fidx = b1.idx; ct.uc = fc; ct.vc = Tp.vc; ct.inst = Tp.inst;
+            ct.fidx = c1 > 0 ? b1.idx : -1; ct.uc = fc; ct.vc = Tp.vc; ct.inst = Tp.inst;
             ws.top(q, 1)[id1] = ct;
         }
         // the child's last tile holds further segments unless the child runs
@@ -2290,7 +2900,7 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             for (int c = 0; c < 2; ++c) {
                 const bool ok = c == 0 ? ok0 : ok1;
                 const int st = c == 0 ? st0 : st1;
-                const int ln = c == 0 ? c0 : c1;
+                const int ln = c == 0 ? len0 : len1;
                 const int ka = (st + kTile - 1) / kTile, kb = (st + ln + kTile - 1) / kTile;
                 const int Nc = c == 0 ? Nn0 : Nn1;
                 const bool multi = ok && kb > ka && (st + ln) < min(kb * kTile, Nc);
@@ -2304,7 +2914,7 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             if (!ok) continue;
             const int id = c == 0 ? id0 : id1;
             const int st = c == 0 ? st0 : st1;
-            const int ln = c == 0 ? c0 : c1;
+            const int ln = c == 0 ? len0 : len1;
             const int ka = (st + kTile - 1) / kTile;
             const int kb = (st + ln + kTile - 1) / kTile;
             if (kb - ka <= 4) {
@@ -2362,6 +2972,11 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
     // pieces are listed in order with their virtual and physical starts, and
     // every next-round tile gets the piece holding its first point.
     __syncthreads();  // every thread has read the last segment-tile claim
+    if (ro0) {
+        // the next round reads the input: no piece table
+        if (blockIdx.x == 0 && tid == 0) { rn->npc[0] = 0; rn->npc[1] = 0; }
+        return;
+    }
     const int NT = nt0 + nt1;
     constexpr int kPer = kSegBlock * kPieceItems;
     const int npt = (NT + kPer - 1) / kPer;
@@ -2409,7 +3024,9 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
                     continue;
                 }
                 ws.pv(q, c)[K[c]] = V[c];
-                ws.pp(q, c)[K[c]] = t * kTile;
+                // (after the split, region 1's tiles end at the end of the
+                // slot of input tile t - nt0)
+                ws.pp(q, c)[K[c]] = (ro1 && t >= nt0) ? (t - nt0) * kTile + kTile - cnt : t * kTile;
                 // next-round tiles whose first point lies in this piece
                 for (int tt = (V[c] + kTile - 1) / kTile; tt * kTile < V[c] + cnt && tt < ws.tcap; ++tt)
                     ws.kf(q, c)[tt] = K[c];
@@ -2550,12 +3167,26 @@ __global__ __launch_bounds__(kBlock) void k_extremes_final(Ws2 ws, HullArgs a) {
 }
 
 // (the exact form fits in 128 registers: four waves per SIMD)
-template <int MODE, bool INIT>
+template <int MODE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 4 : 1)))
 void k_round(Ws2 ws, HullArgs a, int32_t r) {
     __shared__ FastSmem sm;
     if (ws.ctl->setup_error) return;
-    phase_round_fast<MODE, INIT>(ws, a, r, reinterpret_cast<char *>(&sm));
+    phase_round_fast<MODE>(ws, a, r, reinterpret_cast<char *>(&sm));
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_split(Ws2 ws, HullArgs a) {
+    __shared__ SplitSmem sm;
+    if (ws.ctl->setup_error) return;
+    phase_split<MODE>(ws, a, reinterpret_cast<char *>(&sm));
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_round_ro1(Ws2 ws, HullArgs a) {
+    __shared__ Ro1Smem sm;
+    if (ws.ctl->setup_error) return;
+    phase_round_ro1<MODE>(ws, a, reinterpret_cast<char *>(&sm));
 }
 
 union MultiSmem {
@@ -2567,7 +3198,7 @@ template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_round_multi(Ws2 ws, HullArgs a, int32_t r) {
     __shared__ MultiSmem sm;
     if (ws.ctl->setup_error) return;
-    if (fin_mode(ws.ctl, r & 1, a)) {
+    if (fin_mode(ws.ctl, r, a)) {
         phase_finish(ws, a, r, &sm.fin);
         return;
     }
@@ -2596,13 +3227,17 @@ hipError_t launch_extremes(const Ws2 &ws, const HullArgs &a, int grid, hipStream
 
 hipError_t launch_round(const Ws2 &ws, const HullArgs &a, int mode, int32_t r, int grid,
                         int grid_multi, hipStream_t st) {
+    // round 0: the read-only split; round 1: one pass over the input for both
+    // of the split's children; later rounds: the survivors through the pieces
     if (mode == 0) {
-        if (r == 0) hipLaunchKernelGGL((k_round<0, true>), dim3(grid), dim3(kBlock), 0, st, ws, a, r);
-        else hipLaunchKernelGGL((k_round<0, false>), dim3(grid), dim3(kBlock), 0, st, ws, a, r);
+        if (r == 0) hipLaunchKernelGGL(k_split<0>, dim3(grid), dim3(kBlock), 0, st, ws, a);
+        else if (r == 1) hipLaunchKernelGGL(k_round_ro1<0>, dim3(grid), dim3(kBlock), 0, st, ws, a);
+        else hipLaunchKernelGGL(k_round<0>, dim3(grid), dim3(kBlock), 0, st, ws, a, r);
         hipLaunchKernelGGL(k_round_multi<0>, dim3(grid_multi), dim3(kBlock), 0, st, ws, a, r);
     } else {
-        if (r == 0) hipLaunchKernelGGL((k_round<1, true>), dim3(grid), dim3(kBlock), 0, st, ws, a, r);
-        else hipLaunchKernelGGL((k_round<1, false>), dim3(grid), dim3(kBlock), 0, st, ws, a, r);
+        if (r == 0) hipLaunchKernelGGL(k_split<1>, dim3(grid), dim3(kBlock), 0, st, ws, a);
+        else if (r == 1) hipLaunchKernelGGL(k_round_ro1<1>, dim3(grid), dim3(kBlock), 0, st, ws, a);
+        else hipLaunchKernelGGL(k_round<1>, dim3(grid), dim3(kBlock), 0, st, ws, a, r);
         hipLaunchKernelGGL(k_round_multi<1>, dim3(grid_multi), dim3(kBlock), 0, st, ws, a, r);
     }
     return hipGetLastError();
@@ -2654,14 +3289,16 @@ hipError_t extremes_grid(int cus, int *grid) {
 }
 
 hipError_t round_grid(int mode, int cus, int *grid) {
-    // the same grid for the first split and the later rounds: the smaller
-    // residency of the two kernels
-    const void *f[2] = {mode == 0 ? reinterpret_cast<const void *>(&k_round<0, true>)
-                                  : reinterpret_cast<const void *>(&k_round<1, true>),
-                        mode == 0 ? reinterpret_cast<const void *>(&k_round<0, false>)
-                                  : reinterpret_cast<const void *>(&k_round<1, false>)};
+    // one grid for the split, the round after it and the later rounds: the
+    // smallest residency of the three kernels
+    const void *f[3] = {mode == 0 ? reinterpret_cast<const void *>(&k_split<0>)
+                                  : reinterpret_cast<const void *>(&k_split<1>),
+                        mode == 0 ? reinterpret_cast<const void *>(&k_round_ro1<0>)
+                                  : reinterpret_cast<const void *>(&k_round_ro1<1>),
+                        mode == 0 ? reinterpret_cast<const void *>(&k_round<0>)
+                                  : reinterpret_cast<const void *>(&k_round<1>)};
     int per = INT32_MAX;
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < 3; ++j) {
         int pj = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pj, f[j], kBlock, 0);
         if (e != hipSuccess) return e;

@@ -88,16 +88,21 @@ size_t carve(qh_ctx *c, char *base) {
 
 qh_status ensure(qh_ctx *c, int64_t n, int32_t k) {
     // a round writes the survivors of tile t at t * kTile of each region, and a
-    // round has at most n / kTile + 2 tiles (two regions with a ragged tail)
+    // round has at most n / kTile + 2 tiles (two regions with a ragged tail),
+    // except the round after the split, whose two regions are both the input
+    // (twice n / kTile + 1 tiles, written to the slots of the input tiles)
     const int64_t cap_pts = (std::max<int64_t>(1, (n + kTile - 1) / kTile) + 2) * kTile;
-    const int32_t tcap = (int32_t)(cap_pts / kTile + 2);
+    const int32_t tcap = (int32_t)(2 * (cap_pts / kTile) + 2);
     const int32_t s5cap = (int32_t)(tcap / (kSegBlock * kPieceItems) + 8);
     const int64_t smax = n + k + 16;
     int64_t scap = std::max<int64_t>({4096, n / 16 + 2 * (int64_t)k + 1024, c->want_scap});
     scap = std::min(scap, std::max<int64_t>(smax, 4096));
     int64_t hcap = std::max<int64_t>({(int64_t)2 * k + 4096, n / 16 + 2 * (int64_t)k + 1024,
                                       c->want_hcap});
-    hcap = std::min(hcap, std::max<int64_t>(2 * (int64_t)k + n + 16, 4096));
+    // (every point can be a vertex; every instance also takes an id for its
+    // minimum, one for its first split and two for the split's children,
+    // which an instance with points on one side only leaves unused)
+    hcap = std::min(hcap, std::max<int64_t>(4 * (int64_t)k + n + 16, 4096));
     const int32_t kcap = std::max(k, 1);
     const int32_t s4cap = (int32_t)(2 * ((2 * scap + kSegBlock - 1) / kSegBlock) + 8);
     if (c->dmem && cap_pts <= c->cap_pts && scap <= c->scap && hcap <= c->hcap && tcap <= c->tcap &&
@@ -376,11 +381,15 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
     if (stats) {
         stats->rounds = (int64_t)h.rounds_with_work;
         stats->round_launches = r;
-        stats->round_points_in = (int64_t)h.points_in;
-        stats->round_points_out = (int64_t)h.points_out;
+        stats->round_points_in = (int64_t)(h.second_in + h.points_in);
+        stats->round_points_out = (int64_t)(h.second_out + h.points_out);
         stats->split_points_out = (int64_t)h.first_out;
-        const int64_t split_bytes = (int64_t)(8 * h.first_in + 12 * h.first_out);
-        const int64_t later = (int64_t)(12 * h.points_in + 12 * h.points_out);
+        // the split reads 8 B per point and writes nothing; the round after it
+        // reads the input again (8 B per point: the index is the position)
+        // and writes 12 B per survivor; later rounds read and write 12 B
+        const int64_t split_bytes = (int64_t)(8 * h.first_in);
+        const int64_t later = (int64_t)(8 * h.second_in + 12 * h.second_out + 12 * h.points_in +
+                                        12 * h.points_out);
         stats->round_kernel_bytes = split_bytes + later;
         stats->hull_bytes = 8 * n + split_bytes + later;
         if (timing) {

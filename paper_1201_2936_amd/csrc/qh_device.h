@@ -207,7 +207,9 @@ struct Control {
     unsigned long long points_in;     // points read by the rounds after the first split
     unsigned long long points_out;    // survivors written by those rounds
     unsigned long long first_in;      // points read by the first split
-    unsigned long long first_out;     // survivors written by the first split
+    unsigned long long first_out;     // survivors of the first split (counted, not written)
+    unsigned long long second_in;     // input points read by the round after it
+    unsigned long long second_out;    // survivors written by that round
     unsigned long long filter_tests;
     unsigned long long filter_fallbacks;
     unsigned long long candidates;
@@ -222,6 +224,8 @@ struct Control {
     long long h_total;                // hull vertices of all instances
     int32_t nstamps;
     int32_t setup_error;              // errors of the set-up phases only
+    uint32_t cspan;                   // largest |coordinate| of the input plus kCoordMax2D
+    uint32_t cspan_slot[64];          // ... per group of extremes blocks (merged into cspan)
     long long stamps[256];            // wall-clock stamps at phase ends (timing only)
 };
 

@@ -93,6 +93,11 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library {path} is missing: run __graft_entry__.build()")
+    # torch first: it brings its own HIP runtime (the same soname), and the
+    # library must bind to that one, the runtime of the device memory and
+    # streams it is given; loaded before torch, the library would start a
+    # second runtime, which then finds no device
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     i64 = ctypes.c_int64
