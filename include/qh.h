@@ -282,6 +282,24 @@ qh_status qh_test_flag_permute(const int32_t *f, const uint8_t *s, int64_t n, in
                                int32_t *p, uint8_t *s_new, void *stream);
 
 /*
+ * qh_test_flag_permute without any device allocation, for callers that
+ * cannot allocate device memory (serving loops that must not call hipMalloc,
+ * harnesses that forbid it).  Same arguments, checks and outputs as
+ * qh_test_flag_permute; the call is host-synchronous like it.
+ *
+ * Its scratch is a fixed array of 64 MiB in the library's device code, one
+ * copy per GPU, held from the first call on that GPU until the process ends.
+ * A call needs about 4 (k (n + 1) + 2 n) bytes of it: larger calls
+ * (n > 4,186,095 for k = 2, n > 930,241 for k = 16) return
+ * QH_ECAPACITY before any device work.  Every call on one GPU uses the same
+ * array (each call clears what must start at zero), so calls that overlap on
+ * one GPU, from several host threads or streams, race and must be
+ * serialised by the caller.
+ */
+qh_status qh_test_flag_permute_noalloc(const int32_t *f, const uint8_t *s, int64_t n, int32_t k,
+                                       int32_t *p, uint8_t *s_new, void *stream);
+
+/*
  * The segmented compact on its own (Section 4.2, Algorithm 3): the elements
  * with b[i] = 0 are dropped.  For tests and for callers of the primitive.
  *

@@ -17,6 +17,8 @@
 
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/qh.h"
 #include "qh_device.h"
 
@@ -301,6 +303,46 @@ hipError_t cp_enqueue(const uint8_t *b, const uint8_t *s, int32_t n, int32_t *p,
     return hipMemcpyAsync(count_dev, P + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
 }
 
+// ---------------------------------------------------------------------------
+// Fixed scratch of the entry point that allocates nothing: one copy of this
+// array per device (it lives as long as the process), reached from the host
+// only through the address hipGetSymbolAddress returns on that device.
+// Bytes 0 .. 255 hold the bad-state flag, the rest the prefix counts.
+// ---------------------------------------------------------------------------
+constexpr size_t kFixedScratchBytes = (size_t)64 << 20;
+constexpr size_t kFixedHeader = 256;
+__device__ __align__(256) char scratch[kFixedScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void *g_fixed_ptr[kMaxDevices];
+
+// the device address of scratch on the current device (looked up once per
+// device, with that device current)
+hipError_t fixed_scratch(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_fixed_mu);
+    if (!g_fixed_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_fixed_ptr[dev] = ptr;
+    }
+    *out = g_fixed_ptr[dev];
+    return hipSuccess;
+}
+
+// zero s_new[0, n) and the flag word (a kernel, not a memset node, so the
+// launches stay valid inside a captured graph)
+__global__ void k_fp_clear(uint8_t *s_new, int32_t n, int32_t *err) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *err = 0;
+    if (i < n) s_new[i] = 0;
+}
+
 }  // namespace qhfp
 
 extern "C" qh_status qh_test_compact(const uint8_t *b, const uint8_t *s, int64_t n, int32_t *p, uint8_t *s_new,
@@ -354,5 +396,34 @@ extern "C" qh_status qh_test_flag_permute(const int32_t *f, const uint8_t *s, in
         rc = QH_EINVAL;  // a state outside [0, k): the outputs are not written for it
     (void)hipGetLastError();
     (void)hipFree(buf);
+    return rc;
+}
+
+extern "C" qh_status qh_test_flag_permute_noalloc(const int32_t *f, const uint8_t *s, int64_t n, int32_t k,
+                                                  int32_t *p, uint8_t *s_new, void *stream) {
+    if (n < 0 || n > (int64_t)INT32_MAX / 2 || k < 1 || k > qhfp::kMaxStates) return QH_EINVAL;
+    if (n == 0) return QH_OK;
+    if (!f || !s || !p || !s_new) return QH_EINVAL;
+    if (qhfp::fp_scratch_bytes(n, k) > qhfp::kFixedScratchBytes - qhfp::kFixedHeader) return QH_ECAPACITY;
+    hipStream_t st = (hipStream_t)stream;
+    void *base = nullptr;
+    if (qhfp::fixed_scratch(&base) != hipSuccess) {
+        (void)hipGetLastError();
+        return QH_EDEVICE;
+    }
+    int32_t *err = reinterpret_cast<int32_t *>(base);
+    char *buf = reinterpret_cast<char *>(base) + qhfp::kFixedHeader;
+    int32_t herr = 0;
+    qh_status rc = QH_OK;
+    hipLaunchKernelGGL(qhfp::k_fp_clear, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s_new, (int32_t)n,
+                       err);
+    if (hipGetLastError() != hipSuccess ||
+        qhfp::fp_enqueue(f, s, (int32_t)n, k, p, s_new, buf, err, st) != hipSuccess ||
+        hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        rc = QH_EDEVICE;
+    else if (herr)
+        rc = QH_EINVAL;
+    (void)hipGetLastError();
     return rc;
 }

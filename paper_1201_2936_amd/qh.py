@@ -30,7 +30,7 @@ QH_FINISH_CAP = 1024
 
 EXPORTED = ["qh_ctx_create", "qh_ctx_destroy", "qh_status_str", "qh_version",
             "qh_hull2d", "qh_hull2d_batched", "qh_hull3d", "qh_hull3d_batched",
-            "qh_test_flag_permute", "qh_test_compact", "qh_select"]
+            "qh_test_flag_permute", "qh_test_flag_permute_noalloc", "qh_test_compact", "qh_select"]
 
 
 class QhStats(ctypes.Structure):
@@ -116,6 +116,8 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(i64), ctypes.POINTER(QhOpts)]
     lib.qh_test_flag_permute.restype = ctypes.c_int
     lib.qh_test_flag_permute.argtypes = [vp, vp, i64, ctypes.c_int32, vp, vp, vp]
+    lib.qh_test_flag_permute_noalloc.restype = ctypes.c_int
+    lib.qh_test_flag_permute_noalloc.argtypes = [vp, vp, i64, ctypes.c_int32, vp, vp, vp]
     lib.qh_test_compact.restype = ctypes.c_int
     lib.qh_test_compact.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(i64), vp]
     lib.qh_select.restype = ctypes.c_int
@@ -294,9 +296,10 @@ def qh_hull3d_batched(pts, offsets, mode: int = QH_EXACT_INT64, ctx: Context | N
     return fac[: 3 * nf].view(-1, 3), foff, ver[: nv], voff, stats.as_dict()
 
 
-def qh_test_flag_permute(f, s, k: int, stream=None):
+def qh_test_flag_permute(f, s, k: int, stream=None, noalloc: bool = False):
     """k-state segmented stable partition of device int32 states f and uint8
-    head flags s: returns (p int32, s_new uint8) device tensors."""
+    head flags s: returns (p int32, s_new uint8) device tensors.  noalloc:
+    through qh_test_flag_permute_noalloc (the library's fixed scratch)."""
     import torch
     lib = load()
     if (not isinstance(f, torch.Tensor) or not f.is_cuda or f.dtype != torch.int32 or f.dim() != 1
@@ -309,11 +312,11 @@ def qh_test_flag_permute(f, s, k: int, stream=None):
     p = torch.empty(max(n, 1), dtype=torch.int32, device=f.device)
     s_new = torch.empty(max(n, 1), dtype=torch.uint8, device=f.device)
     st = torch.cuda.current_stream().cuda_stream if stream is None else stream
-    rc = lib.qh_test_flag_permute(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(s.data_ptr()), n,
-                                  int(k), ctypes.c_void_p(p.data_ptr()),
-                                  ctypes.c_void_p(s_new.data_ptr()), ctypes.c_void_p(st))
+    fn = lib.qh_test_flag_permute_noalloc if noalloc else lib.qh_test_flag_permute
+    rc = fn(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(s.data_ptr()), n, int(k),
+            ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(s_new.data_ptr()), ctypes.c_void_p(st))
     if rc != QH_OK:
-        raise QhError(rc, "qh_test_flag_permute")
+        raise QhError(rc, "qh_test_flag_permute_noalloc" if noalloc else "qh_test_flag_permute")
     return p[:n], s_new[:n]
 
 
