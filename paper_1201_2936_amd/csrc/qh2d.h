@@ -97,6 +97,8 @@ struct HullArgs {
     int32_t max_rounds;
     int32_t fin_cap;   // finish every segment in one block once none is larger (0: off)
     int32_t fin_segs;  // ... and there are at most this many segments
+    int32_t grid_split;  // blocks of the split and of the round after it (0: the
+    int32_t grid_ro1;    // round kernel's grid)
 };
 
 hipError_t launch_setup(const Ws2 &ws, const HullArgs &a, int grid, hipStream_t st);
@@ -105,8 +107,9 @@ hipError_t launch_round(const Ws2 &ws, const HullArgs &a, int mode, int32_t r, i
                         int grid_multi, hipStream_t st);
 hipError_t launch_segments(const Ws2 &ws, const HullArgs &a, int32_t r, int grid, hipStream_t st);
 hipError_t launch_output(const Ws2 &ws, const HullArgs &a, int32_t H, hipStream_t st);
-// resident blocks of the round kernel on the whole device
-hipError_t round_grid(int mode, int cus, int *grid);
+// resident blocks on the whole device of the split, the round after it and
+// the later rounds' kernel
+hipError_t round_grids(int mode, int cus, int (&grids)[3]);
 // resident blocks of the extremes kernel
 hipError_t extremes_grid(int cus, int *grid);
 

@@ -1491,6 +1491,64 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
     }
 }
 
+// the 8-bit field c of a packed counter
+__device__ __forceinline__ uint32_t field8(uint32_t v, uint32_t c) { return (v >> (8u * c)) & 0xffu; }
+
+// a copy of a wave-uniform value in a vector register (so that a per-lane
+// select between two such values needs no scalar operand)
+__device__ __forceinline__ int32_t vcopy(int32_t s) {
+    int32_t v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t o = shfl_xor_u64(v, m);
+        v = o > v ? o : v;
+    }
+    return uniform_u64(v);
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t o = shfl_xor_u64(v, m);
+        v = o < v ? o : v;
+    }
+    return uniform_u64(v);
+}
+
+// The wave's best point of each class so far in the run: distance W, tie key
+// T (its low 32 bits are the index), and (FP32 filter) the estimate below
+// which a point cannot reach W.  Offered the lanes' candidates of class k
+// (cand: exact distance d > 0 and tie key tk).
+struct WaveBest {
+    uint64_t W[4], T[4];
+    float tau[4];
+    uint32_t C[4];
+};
+
+__device__ __forceinline__ void wave_offer(WaveBest &wb, int k, bool cand, uint64_t d, uint64_t tk, float B) {
+    if (!__ballot(cand)) return;
+    const uint64_t dm = wave_max_u64(cand ? d : 0ull);
+    const uint64_t tm = wave_min_u64((cand && d == dm) ? tk : ~0ull);
+    if (dm > wb.W[k] || (dm == wb.W[k] && tm < wb.T[k])) {
+        wb.W[k] = dm;
+        wb.T[k] = tm;
+        // E < fl(fl(W) - 2B) implies d < W (the estimate's error is below
+        // 4/5 of B, and fl(W) and the difference round by less than B/5)
+        wb.tau[k] = __fsub_rn((float)dm, 2.f * B);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // the first split, read-only
 // ---------------------------------------------------------------------------
@@ -1575,7 +1633,7 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
     Control *ctl = ws.ctl;
     const int n = ctl->rs[0].n[0];
     const int ntiles = (n + kTile - 1) / kTile;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
     if (fin_mode(ctl, 0, a)) return;  // the multi-segment kernel finishes the segments
     const int T = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
     if (blockIdx.x == 0 && tid == 0) {
@@ -1585,18 +1643,57 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
     }
     const int tb = blockIdx.x * T, te = min(tb + T, ntiles);
     const float c2 = MODE ? coord_c2(ctl) : 0.f;
-    RunBest rb[2] = {rb_none(), rb_none()};
+    // each wave's best point of each child in the run (uniform values); a
+    // lane's point is compared exactly only when it reaches it
+    WaveBest wb;
+    auto wb_reset = [&]() {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            wb.W[k] = 0;
+            wb.T[k] = ~0ull;
+            wb.tau[k] = -INFINITY;
+            wb.C[k] = 0;
+        }
+    };
+    wb_reset();
     int cur = -1, run0 = 0, run_lo = 0, run_hi = 0, seg_st = 0, seg_en = 0;
     uint32_t acc0 = 0, acc1 = 0, ntests = 0, nfall = 0, ncand = 0;
 
+    auto close_run = [&]() __attribute__((always_inline)) {
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                RunBest r;
+                r.k1 = wb.W[k];
+                r.k2 = wb.T[k];
+                r.cnt = (int32_t)wb.C[k];
+                sm->wrb[wv][k] = r;
+            }
+        }
+        __syncthreads();
+        if (tid < 2) {
+            RunBest m = sm->wrb[0][tid];
+#pragma unroll
+            for (int w = 1; w < kNW; ++w) rb_merge(m, sm->wrb[w][tid]);
+            Best b;
+            b.key1 = m.k1;
+            b.key2 = m.k2;
+            b.cnt = m.cnt;
+            b.idx = m.k1 ? (int32_t)(uint32_t)m.k2 : 0;
+            b.x = b.y = 0;  // filled in by the segment kernel for the winner
+            if (seg_st >= run_lo && seg_en <= run_hi) ws.adir[cur * 2 + tid] = b;
+            ws.recF[run0 * 2 + tid] = b;
+            ws.recL[run0 * 2 + tid] = b;
+        }
+        __syncthreads();
+        wb_reset();
+        cur = -1;
+    };
     // one tile whose points are in X, Y (valid mask vm)
     auto process = [&](int tile, const TileGeo &ti, const int32_t (&X)[kItems], const int32_t (&Y)[kItems],
                        uint32_t vm) __attribute__((always_inline)) {
         const int lo = tile * kTile, hi = min(lo + kTile, n);
-        if (cur >= 0 && (!ti.single || ti.seg != cur)) {
-            close_run_records<2>(ws, rb, sm->wrb, cur, 0, 0, run0, seg_st >= run_lo && seg_en <= run_hi);
-            cur = -1;
-        }
+        if (cur >= 0 && (!ti.single || ti.seg != cur)) close_run();
         if (!ti.single) return;  // the multi-segment kernel takes it
         if (cur < 0) {
             cur = ti.seg;
@@ -1618,17 +1715,21 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
                 const bool o0 = valid && d > 0, o1 = valid && d < 0;
                 m0 |= (o0 ? 1u : 0u) << i;
                 m1 |= (o1 ? 1u : 0u) << i;
-                const int32_t idx = fast_pos_init(lo, i);
-                rb_offer_nb(rb[0], o0, (uint64_t)d, X[i], Y[i], idx, ex, ey);
-                rb_offer_nb(rb[1], o1, (uint64_t)(-d), X[i], Y[i], idx, -ex, -ey);
+                const uint64_t dd = (uint64_t)(o0 ? d : -d);
+                const bool need = (o0 && dd >= wb.W[0]) || (o1 && dd >= wb.W[1]);
+                if (__ballot(need)) {
+                    const int32_t idx = fast_pos_init(lo, i);
+                    const uint64_t tk = tie_key(X[i], Y[i], idx, o0 ? ex : -ex, o0 ? ey : -ey);
+                    wave_offer(wb, 0, need && o0, dd, tk, 0.f);
+                    wave_offer(wb, 1, need && o1, dd, tk, 0.f);
+                }
             }
         } else {
-            // FP32 estimates with one bound for every point; the child's
-            // farthest point is among the items whose estimate is within twice
-            // the bound of the wave's largest estimate in that child
+            // FP32 estimates with one bound for every point; a point is
+            // compared exactly when its estimate reaches its child's
+            // threshold (its exact distance may then reach the child's best)
             const float B = static_bound(ex, ey, c2);
             float E[kItems];
-            float l0 = -INFINITY, l1 = -INFINITY;
             uint32_t und = 0;
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
@@ -1639,8 +1740,6 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
                 m0 |= (p0 ? 1u : 0u) << i;
                 m1 |= (n0 ? 1u : 0u) << i;
                 und |= (valid && !p0 && !n0 ? 1u : 0u) << i;
-                l0 = p0 ? fmaxf(l0, e) : l0;
-                l1 = n0 ? fmaxf(l1, -e) : l1;
             }
             ntests += (uint32_t)__popc(vm);
             // undecided signs (rare): exact, and always argmax candidates
@@ -1654,28 +1753,26 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
                 }
                 nfall += (uint32_t)__popc(und);
             }
-            const float t0 = __fsub_rn(wave_max_f_dpp(l0), 2.f * B);
-            const float t1 = __fsub_rn(wave_max_f_dpp(l1), 2.f * B);
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
                 const bool forced = (und >> i) & 1u;
-                const bool c0 = ((m0 >> i) & 1u) && (forced || E[i] >= t0);
-                const bool c1 = ((m1 >> i) & 1u) && (forced || -E[i] >= t1);
+                const bool c0 = ((m0 >> i) & 1u) && (forced || E[i] >= wb.tau[0]);
+                const bool c1 = ((m1 >> i) & 1u) && (forced || -E[i] >= wb.tau[1]);
                 if (!__ballot(c0 || c1)) continue;
-                if (c0 || c1) {
-                    ++ncand;
-                    const int64_t d = cross_i64(X[i], Y[i], ax, ay, bx, by);
-                    const int32_t idx = fast_pos_init(lo, i);
-                    if (c0) rb_offer(rb[0], (uint64_t)d, X[i], Y[i], idx, ex, ey);
-                    else rb_offer(rb[1], (uint64_t)(-d), X[i], Y[i], idx, -ex, -ey);
-                }
+                ncand += (c0 || c1) ? 1u : 0u;
+                const int64_t d = cross_i64(X[i], Y[i], ax, ay, bx, by);
+                const uint64_t dd = (uint64_t)(c0 ? d : -d);
+                const uint64_t tk = tie_key(X[i], Y[i], fast_pos_init(lo, i), c0 ? ex : -ex, c0 ? ey : -ey);
+                wave_offer(wb, 0, c0, dd, tk, B);
+                wave_offer(wb, 1, c1, dd, tk, B);
             }
         }
         const uint32_t lc0 = (uint32_t)__popc(m0), lc1 = (uint32_t)__popc(m1);
-        rb[0].cnt += (int32_t)lc0;
-        rb[1].cnt += (int32_t)lc1;
         acc0 += lc0;
         acc1 += lc1;
+        const uint32_t w = wave_sum(lc0 | (lc1 << 16));
+        wb.C[0] += w & 0xffffu;
+        wb.C[1] += w >> 16;
     };
     // software pipelined: the next tile's record and points are requested
     // before this tile is classified (no stores, so no wait orders them)
@@ -1705,10 +1802,10 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
         process(tile + 1, tc, XB, YB, vmB);
         tc = tn;
     }
-    if (cur >= 0) close_run_records<2>(ws, rb, sm->wrb, cur, 0, 0, run0, seg_st >= run_lo && seg_en <= run_hi);
+    if (cur >= 0) close_run();
     // survivors of the split (counted, not written) per child
     const uint32_t s0 = wave_sum(acc0), s1 = wave_sum(acc1);
-    if (lane_id() == 0 && (s0 | s1)) {
+    if (lane == 0 && (s0 | s1)) {
         atomicAdd(&ctl->nacc[0][0], s0);
         atomicAdd(&ctl->nacc[0][1], s1);
     }
@@ -1762,16 +1859,16 @@ __device__ __forceinline__ TileGeo2 ro1_record(const Ws2 &ws, int lt) {
     return ti;
 }
 
-// the 8-bit field c of a packed counter
-__device__ __forceinline__ uint32_t field8(uint32_t v, uint32_t c) { return (v >> (8u * c)) & 0xffu; }
-
 // Items are classified into four classes, k = 2 side + child (0: side 0 /
 // child 0, 1: side 0 / child 1, 2: side 1 / child 0, 3: side 1 / child 1),
 // 4 = dropped; three bits per item in one register.  The survivors of a tile
 // are staged in LDS grouped by class (each lane's items in item order at the
 // lane's offset within its wave's share), then written out in order: class
 // k goes to region (k & 1), side 0 from the start of the tile's slot, side 1
-// so that it ends at the slot's end.
+// so that it ends at the slot's end.  Each wave keeps the best point of
+// every class of the run as uniform values; a lane's point is compared
+// exactly only when it reaches its class's best (FP32 filter: when its
+// estimate reaches the class's threshold), which soon becomes rare.
 template <int MODE>
 __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a, char *smem) {
     Ro1Smem *sm = reinterpret_cast<Ro1Smem *>(smem);
@@ -1791,7 +1888,17 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
     }
     const int tb = blockIdx.x * T, te = min(tb + T, nt);
     const float c2 = MODE ? coord_c2(ctl) : 0.f;
-    RunBest rb[4] = {rb_none(), rb_none(), rb_none(), rb_none()};
+    WaveBest wb;
+    auto wb_reset = [&]() {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            wb.W[k] = 0;
+            wb.T[k] = ~0ull;
+            wb.tau[k] = -INFINITY;
+            wb.C[k] = 0;
+        }
+    };
+    wb_reset();
     int cur = -1, run0 = 0, run_lo = 0, run_hi = 0, seg_st = 0, seg_en = 0;
     uint32_t acc0 = 0, acc1 = 0, ntests = 0, nfall = 0, ncand = 0;
     bool oob = false;
@@ -1801,7 +1908,36 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
         ti.single = 0;
         if (tile < te) ti = ro1_record(ws, tile);
         if (cur >= 0 && (!ti.single || ti.seg != cur)) {
-            close_run_records<4>(ws, rb, sm->wrb, cur, S0, nt, run0, seg_st >= run_lo && seg_en <= run_hi);
+            // the run ends: the waves' bests merged into its records
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    RunBest r;
+                    r.k1 = wb.W[k];
+                    r.k2 = wb.T[k];
+                    r.cnt = (int32_t)wb.C[k];
+                    sm->wrb[wv][k] = r;
+                }
+            }
+            __syncthreads();
+            if (tid < 4) {
+                RunBest m = sm->wrb[0][tid];
+#pragma unroll
+                for (int w = 1; w < kNW; ++w) rb_merge(m, sm->wrb[w][tid]);
+                Best b;
+                b.key1 = m.k1;
+                b.key2 = m.k2;
+                b.cnt = m.cnt;
+                b.idx = m.k1 ? (int32_t)(uint32_t)m.k2 : 0;
+                b.x = b.y = 0;  // filled in by the segment kernel for the winner
+                const int sd = tid >> 1, c = tid & 1;
+                const int g = (sd ? S0 : 0) + cur, rt = (sd ? nt : 0) + run0;
+                if (seg_st >= run_lo && seg_en <= run_hi) ws.adir[g * 2 + c] = b;
+                ws.recF[rt * 2 + c] = b;
+                ws.recL[rt * 2 + c] = b;
+            }
+            __syncthreads();
+            wb_reset();
             cur = -1;
         }
         if (!ti.single) continue;  // past the last tile, or the multi-segment kernel takes it
@@ -1816,62 +1952,78 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
         run_hi = hi;
         int32_t X[kItems], Y[kItems];
         const uint32_t vm = load_input_wave(a, lo, hi, X, Y);
-        // side line a -> b; child edges per side: side 0 a -> f0 -> b, side 1
-        // b -> f1 -> a
+        // Relative to a (q = p - a): the side is the sign of q x (b - a); side
+        // 0's children are q x E00 and q x E01 - K01, side 1's q x E10 - K10
+        // and q x E11, with E00 = f0 - a, E01 = b - f0, E10 = f1 - b,
+        // E11 = a - f1, K01 = E00 x E01, K10 = (b - a) x E10 (the cross
+        // products of Algorithm 1's tests, regrouped)
         const int ax = ti.ax, ay = ti.ay, bx = ti.bx, by = ti.by;
+        const int esx = bx - ax, esy = by - ay;
         const int e00x = ti.f0x - ax, e00y = ti.f0y - ay, e01x = bx - ti.f0x, e01y = by - ti.f0y;
         const int e10x = ti.f1x - bx, e10y = ti.f1y - by, e11x = ax - ti.f1x, e11y = ay - ti.f1y;
         uint32_t cl = 0;  // class of item i in bits 3i .. 3i + 2
         if (MODE == 0) {
+            const int64_t nk01 = -((int64_t)e00x * e01y - (int64_t)e00y * e01x);
+            const int64_t nk10 = -((int64_t)esx * e10y - (int64_t)esy * e10x);
+            // the per-side values as vector-register copies
+            const int32_t v00x = vcopy(e00x), v00y = vcopy(e00y), v10x = vcopy(e10x), v10y = vcopy(e10y);
+            const int32_t v01x = vcopy(e01x), v01y = vcopy(e01y), v11x = vcopy(e11x), v11y = vcopy(e11y);
+            const int32_t k01l = vcopy((int32_t)(uint32_t)nk01), k01h = vcopy((int32_t)(uint32_t)(nk01 >> 32));
+            const int32_t k10l = vcopy((int32_t)(uint32_t)nk10), k10h = vcopy((int32_t)(uint32_t)(nk10 >> 32));
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
                 const bool valid = (vm >> i) & 1u;
-                const int32_t x = X[i], y = Y[i];
-                const int64_t ds = cross_i64(x, y, ax, ay, bx, by);
+                const int32_t qx = X[i] - ax, nqy = ay - Y[i];
+                const int64_t ds = (int64_t)((uint64_t)((int64_t)qx * esy) + (uint64_t)((int64_t)nqy * esx));
                 const bool s1 = ds < 0, live = valid && ds != 0;
-                const int ux = s1 ? bx : ax, uy = s1 ? by : ay;
-                const int fx = s1 ? ti.f1x : ti.f0x, fy = s1 ? ti.f1y : ti.f0y;
-                const int c0x = s1 ? e10x : e00x, c0y = s1 ? e10y : e00y;
-                const int c1x = s1 ? e11x : e01x, c1y = s1 ? e11y : e01y;
-                const int64_t d0 = (int64_t)(x - ux) * (int64_t)c0y - (int64_t)(y - uy) * (int64_t)c0x;
-                const int64_t d1 = (int64_t)(x - fx) * (int64_t)c1y - (int64_t)(y - fy) * (int64_t)c1x;
+                const int32_t a0x = s1 ? v10x : v00x, a0y = s1 ? v10y : v00y;
+                const int32_t a1x = s1 ? v11x : v01x, a1y = s1 ? v11y : v01y;
+                const int64_t nk0 = (int64_t)(((uint64_t)(uint32_t)(s1 ? k10h : 0) << 32) | (uint32_t)(s1 ? k10l : 0));
+                const int64_t nk1 = (int64_t)(((uint64_t)(uint32_t)(s1 ? 0 : k01h) << 32) | (uint32_t)(s1 ? 0 : k01l));
+                const int64_t d0 = (int64_t)((uint64_t)((int64_t)qx * a0y) + (uint64_t)((int64_t)nqy * a0x) + (uint64_t)nk0);
+                const int64_t d1 = (int64_t)((uint64_t)((int64_t)qx * a1y) + (uint64_t)((int64_t)nqy * a1x) + (uint64_t)nk1);
                 const bool o0 = live && d0 > 0, o1 = live && !o0 && d1 > 0;
                 const uint32_t k = (o0 || o1) ? (s1 ? 2u : 0u) + (o1 ? 1u : 0u) : 4u;
                 cl |= k << (3 * i);
-                const uint64_t dsel = (uint64_t)(o0 ? d0 : d1);
-                // the full comparison only for lanes whose distance reaches
-                // the running best of their class (fewer and fewer as a run
-                // goes on), the whole wave skipping it when none does
-                const bool need = (k == 0 && dsel >= rb[0].k1) || (k == 1 && dsel >= rb[1].k1) ||
-                                  (k == 2 && dsel >= rb[2].k1) || (k == 3 && dsel >= rb[3].k1);
+                const uint64_t d = (uint64_t)(o0 ? d0 : d1);
+                const bool need = (k == 0 && d >= wb.W[0]) || (k == 1 && d >= wb.W[1]) ||
+                                  (k == 2 && d >= wb.W[2]) || (k == 3 && d >= wb.W[3]);
                 if (__ballot(need)) {
-                    const uint64_t tk = tie_key(x, y, fast_pos_init(lo, i), o0 ? c0x : c1x, o0 ? c0y : c1y);
-                    rb_offer_k(rb[0], k == 0, dsel, tk);
-                    rb_offer_k(rb[1], k == 1, dsel, tk);
-                    rb_offer_k(rb[2], k == 2, dsel, tk);
-                    rb_offer_k(rb[3], k == 3, dsel, tk);
+                    const uint64_t tk = tie_key(X[i], Y[i], fast_pos_init(lo, i), o0 ? a0x : a1x, o0 ? a0y : a1y);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) wave_offer(wb, kk, need && k == (uint32_t)kk, d, tk, 0.f);
                 }
             }
         } else {
-            const float Bs = static_bound(bx - ax, by - ay, c2);
+            const float Bs = static_bound(esx, esy, c2);
             const float Bk[4] = {static_bound(e00x, e00y, c2), static_bound(e01x, e01y, c2),
                                  static_bound(e10x, e10y, c2), static_bound(e11x, e11y, c2)};
-            float E[kItems];
-            float l[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+            const float fesx = (float)esx, fesy = (float)esy;
+            // per-side values as vector-register copies: the child edges, the
+            // offsets of u and f from a, the bounds
+            const int32_t v00x = vcopy(e00x), v00y = vcopy(e00y), v10x = vcopy(e10x), v10y = vcopy(e10y);
+            const int32_t v01x = vcopy(e01x), v01y = vcopy(e01y), v11x = vcopy(e11x), v11y = vcopy(e11y);
+            const int32_t vesx = vcopy(esx), vesy = vcopy(esy);
+            const int32_t vf0x = vcopy(e00x), vf0y = vcopy(e00y);
+            const int32_t vf1x = vcopy(ti.f1x - ax), vf1y = vcopy(ti.f1y - ay);
+            const float vb00 = __int_as_float(vcopy(__float_as_int(Bk[0]))), vb10 = __int_as_float(vcopy(__float_as_int(Bk[2])));
+            const float vb01 = __int_as_float(vcopy(__float_as_int(Bk[1]))), vb11 = __int_as_float(vcopy(__float_as_int(Bk[3])));
             uint32_t und = 0;
+            float E[kItems];
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
                 const bool valid = (vm >> i) & 1u;
-                const int32_t x = X[i], y = Y[i];
-                const float es = cross_f32_nb(x, y, ax, ay, bx - ax, by - ay);
+                const int32_t qx = X[i] - ax, qy = Y[i] - ay;
+                const float es = __fsub_rn(__fmul_rn((float)qx, fesy), __fmul_rn((float)qy, fesx));
                 const bool s1 = es < -Bs, sure = s1 || es > Bs;
-                const int ux = s1 ? bx : ax, uy = s1 ? by : ay;
-                const int fx = s1 ? ti.f1x : ti.f0x, fy = s1 ? ti.f1y : ti.f0y;
-                const int c0x = s1 ? e10x : e00x, c0y = s1 ? e10y : e00y;
-                const int c1x = s1 ? e11x : e01x, c1y = s1 ? e11y : e01y;
-                const float B0 = s1 ? Bk[2] : Bk[0], B1 = s1 ? Bk[3] : Bk[1];
-                const float e0 = cross_f32_nb(x, y, ux, uy, c0x, c0y);
-                const float e1 = cross_f32_nb(x, y, fx, fy, c1x, c1y);
+                // u - a: 0 or b - a; f - a: f0 - a or f1 - a
+                const int32_t d0x = qx - (s1 ? vesx : 0), d0y = qy - (s1 ? vesy : 0);
+                const int32_t d1x = qx - (s1 ? vf1x : vf0x), d1y = qy - (s1 ? vf1y : vf0y);
+                const int32_t a0x = s1 ? v10x : v00x, a0y = s1 ? v10y : v00y;
+                const int32_t a1x = s1 ? v11x : v01x, a1y = s1 ? v11y : v01y;
+                const float B0 = s1 ? vb10 : vb00, B1 = s1 ? vb11 : vb01;
+                const float e0 = __fsub_rn(__fmul_rn((float)d0x, (float)a0y), __fmul_rn((float)d0y, (float)a0x));
+                const float e1 = __fsub_rn(__fmul_rn((float)d1x, (float)a1y), __fmul_rn((float)d1y, (float)a1x));
                 // 0, 1: child; 2: dropped; 3: undecided
                 uint32_t st = e0 > B0 ? 0u : (!(e0 < -B0) ? 3u : (e1 > B1 ? 1u : (e1 < -B1 ? 2u : 3u)));
                 st = !valid ? 2u : (!sure ? 3u : st);
@@ -1880,14 +2032,9 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
                 und |= (st == 3 ? 1u : 0u) << i;
                 const float e = st == 0 ? e0 : e1;
                 E[i] = e;
-                l[0] = k == 0 ? fmaxf(l[0], e) : l[0];
-                l[1] = k == 1 ? fmaxf(l[1], e) : l[1];
-                l[2] = k == 2 ? fmaxf(l[2], e) : l[2];
-                l[3] = k == 3 ? fmaxf(l[3], e) : l[3];
                 ntests += valid ? (sure ? (e0 > B0 ? 2u : 3u) : 1u) : 0u;
             }
-            // undecided items (rare): the whole classification in int64; their
-            // exact distances make them argmax candidates
+            // undecided items (rare): the whole classification in int64
             if (__ballot(und != 0)) {
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
@@ -1905,32 +2052,28 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
                 }
                 nfall += (uint32_t)__popc(und);
             }
-            float t[4];
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) t[kk] = __fsub_rn(wave_max_f_dpp(l[kk]), 2.f * Bk[kk]);
+            // candidates: estimates at or above their class's threshold, and
+            // the items decided exactly; their exact distances to the waves'
+            // bests
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
                 const uint32_t k = (cl >> (3 * i)) & 7u;
                 const bool forced = (und >> i) & 1u;
-                const float th = (k & 2u) ? ((k & 1u) ? t[3] : t[2]) : ((k & 1u) ? t[1] : t[0]);
-                const bool c = k < 4 && (forced || E[i] >= th);
-                if (!__ballot(c)) continue;
-                if (c) {
-                    ++ncand;
-                    const bool s1 = (k & 2u) != 0, in0 = (k & 1u) == 0;
-                    const int32_t x = X[i], y = Y[i];
-                    const int ux = s1 ? bx : ax, uy = s1 ? by : ay;
-                    const int fx = s1 ? ti.f1x : ti.f0x, fy = s1 ? ti.f1y : ti.f0y;
-                    const int cx = in0 ? (s1 ? e10x : e00x) : (s1 ? e11x : e01x);
-                    const int cy = in0 ? (s1 ? e10y : e00y) : (s1 ? e11y : e01y);
-                    const int px0 = in0 ? ux : fx, py0 = in0 ? uy : fy;
-                    const int64_t d = (int64_t)(x - px0) * (int64_t)cy - (int64_t)(y - py0) * (int64_t)cx;
-                    const uint64_t tk = tie_key(x, y, fast_pos_init(lo, i), cx, cy);
-                    rb_offer_k(rb[0], k == 0, (uint64_t)d, tk);
-                    rb_offer_k(rb[1], k == 1, (uint64_t)d, tk);
-                    rb_offer_k(rb[2], k == 2, (uint64_t)d, tk);
-                    rb_offer_k(rb[3], k == 3, (uint64_t)d, tk);
-                }
+                const bool need = k < 4 && (forced || (k == 0 && E[i] >= wb.tau[0]) || (k == 1 && E[i] >= wb.tau[1]) ||
+                                            (k == 2 && E[i] >= wb.tau[2]) || (k == 3 && E[i] >= wb.tau[3]));
+                if (!__ballot(need)) continue;
+                ncand += need ? 1u : 0u;
+                const bool s1 = (k & 2u) != 0, in0 = (k & 1u) == 0;
+                const int32_t x = X[i], y = Y[i];
+                const int ux = s1 ? bx : ax, uy = s1 ? by : ay;
+                const int fx = s1 ? ti.f1x : ti.f0x, fy = s1 ? ti.f1y : ti.f0y;
+                const int cx = in0 ? (s1 ? e10x : e00x) : (s1 ? e11x : e01x);
+                const int cy = in0 ? (s1 ? e10y : e00y) : (s1 ? e11y : e01y);
+                const int px0 = in0 ? ux : fx, py0 = in0 ? uy : fy;
+                const int64_t d = (int64_t)(x - px0) * (int64_t)cy - (int64_t)(y - py0) * (int64_t)cx;
+                const uint64_t tk = tie_key(x, y, fast_pos_init(lo, i), cx, cy);
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) wave_offer(wb, kk, need && k == (uint32_t)kk, (uint64_t)d, tk, Bk[kk]);
             }
         }
         // per-lane counts of the four classes (8-bit fields), their prefix in
@@ -1941,36 +2084,37 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
             const uint32_t k = (cl >> (3 * i)) & 7u;
             cnt += k < 4 ? (1u << (8u * k)) : 0u;
         }
-        rb[0].cnt += (int32_t)field8(cnt, 0);
-        rb[1].cnt += (int32_t)field8(cnt, 1);
-        rb[2].cnt += (int32_t)field8(cnt, 2);
-        rb[3].cnt += (int32_t)field8(cnt, 3);
         const uint32_t c01 = field8(cnt, 0) | (field8(cnt, 1) << 16), c23 = field8(cnt, 2) | (field8(cnt, 3) << 16);
         const uint32_t i01 = wave_incl_sum(c01), i23 = wave_incl_sum(c23);
-        if (lane == kWave - 1) {
-            sm->wcnt[wv][0] = i01 & 0xffffu;
-            sm->wcnt[wv][1] = i01 >> 16;
-            sm->wcnt[wv][2] = i23 & 0xffffu;
-            sm->wcnt[wv][3] = i23 >> 16;
+        const uint32_t w01 = wave_read(i01, kWave - 1), w23 = wave_read(i23, kWave - 1);
+        wb.C[0] += w01 & 0xffffu;
+        wb.C[1] += w01 >> 16;
+        wb.C[2] += w23 & 0xffffu;
+        wb.C[3] += w23 >> 16;
+        if (lane == 0) {
+            sm->wcnt[wv][0] = w01 & 0xffffu;
+            sm->wcnt[wv][1] = w01 >> 16;
+            sm->wcnt[wv][2] = w23 & 0xffffu;
+            sm->wcnt[wv][3] = w23 >> 16;
         }
         __syncthreads();
-        uint32_t tot[4], wb[4];
+        uint32_t tot[4], wbase[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             tot[k] = 0;
-            wb[k] = 0;
+            wbase[k] = 0;
 #pragma unroll
             for (int w = 0; w < kNW; ++w) {
                 const uint32_t c = sm->wcnt[w][k];
-                wb[k] += (w < wv) ? c : 0u;
+                wbase[k] += (w < wv) ? c : 0u;
                 tot[k] += c;
             }
         }
         const uint32_t cs1 = tot[0], cs2 = cs1 + tot[1], cs3 = cs2 + tot[2], S = cs3 + tot[3];
         // staging offsets of this lane's first item of each class
         const uint32_t e01 = i01 - c01, e23 = i23 - c23;
-        const uint32_t lb0 = wb[0] + (e01 & 0xffffu), lb1 = cs1 + wb[1] + (e01 >> 16);
-        const uint32_t lb2 = cs2 + wb[2] + (e23 & 0xffffu), lb3 = cs3 + wb[3] + (e23 >> 16);
+        const uint32_t lb0 = wbase[0] + (e01 & 0xffffu), lb1 = cs1 + wbase[1] + (e01 >> 16);
+        const uint32_t lb2 = cs2 + wbase[2] + (e23 & 0xffffu), lb3 = cs3 + wbase[3] + (e23 >> 16);
         uint32_t run = 0;  // the lane's items staged so far per class (8-bit fields)
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
@@ -3229,14 +3373,15 @@ hipError_t launch_round(const Ws2 &ws, const HullArgs &a, int mode, int32_t r, i
                         int grid_multi, hipStream_t st) {
     // round 0: the read-only split; round 1: one pass over the input for both
     // of the split's children; later rounds: the survivors through the pieces
+    const int gs = a.grid_split > 0 ? a.grid_split : grid, g1 = a.grid_ro1 > 0 ? a.grid_ro1 : grid;
     if (mode == 0) {
-        if (r == 0) hipLaunchKernelGGL(k_split<0>, dim3(grid), dim3(kBlock), 0, st, ws, a);
-        else if (r == 1) hipLaunchKernelGGL(k_round_ro1<0>, dim3(grid), dim3(kBlock), 0, st, ws, a);
+        if (r == 0) hipLaunchKernelGGL(k_split<0>, dim3(gs), dim3(kBlock), 0, st, ws, a);
+        else if (r == 1) hipLaunchKernelGGL(k_round_ro1<0>, dim3(g1), dim3(kBlock), 0, st, ws, a);
         else hipLaunchKernelGGL(k_round<0>, dim3(grid), dim3(kBlock), 0, st, ws, a, r);
         hipLaunchKernelGGL(k_round_multi<0>, dim3(grid_multi), dim3(kBlock), 0, st, ws, a, r);
     } else {
-        if (r == 0) hipLaunchKernelGGL(k_split<1>, dim3(grid), dim3(kBlock), 0, st, ws, a);
-        else if (r == 1) hipLaunchKernelGGL(k_round_ro1<1>, dim3(grid), dim3(kBlock), 0, st, ws, a);
+        if (r == 0) hipLaunchKernelGGL(k_split<1>, dim3(gs), dim3(kBlock), 0, st, ws, a);
+        else if (r == 1) hipLaunchKernelGGL(k_round_ro1<1>, dim3(g1), dim3(kBlock), 0, st, ws, a);
         else hipLaunchKernelGGL(k_round<1>, dim3(grid), dim3(kBlock), 0, st, ws, a, r);
         hipLaunchKernelGGL(k_round_multi<1>, dim3(grid_multi), dim3(kBlock), 0, st, ws, a, r);
     }
@@ -3288,23 +3433,19 @@ hipError_t extremes_grid(int cus, int *grid) {
     return hipSuccess;
 }
 
-hipError_t round_grid(int mode, int cus, int *grid) {
-    // one grid for the split, the round after it and the later rounds: the
-    // smallest residency of the three kernels
+hipError_t round_grids(int mode, int cus, int (&grids)[3]) {
     const void *f[3] = {mode == 0 ? reinterpret_cast<const void *>(&k_split<0>)
                                   : reinterpret_cast<const void *>(&k_split<1>),
                         mode == 0 ? reinterpret_cast<const void *>(&k_round_ro1<0>)
                                   : reinterpret_cast<const void *>(&k_round_ro1<1>),
                         mode == 0 ? reinterpret_cast<const void *>(&k_round<0>)
                                   : reinterpret_cast<const void *>(&k_round<1>)};
-    int per = INT32_MAX;
     for (int j = 0; j < 3; ++j) {
         int pj = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pj, f[j], kBlock, 0);
         if (e != hipSuccess) return e;
-        per = std::min(per, pj);
+        grids[j] = std::max(1, pj) * cus;
     }
-    *grid = std::max(1, per) * cus;
     return hipSuccess;
 }
 

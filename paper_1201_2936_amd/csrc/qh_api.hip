@@ -143,8 +143,14 @@ qh_status ctx_init(qh_ctx *c) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
         cus > 0)
         c->cus = cus;
-    for (int m = 0; m < 2; ++m)
-        if (round_grid(m, c->cus, &c->grid[m]) != hipSuccess || c->grid[m] <= 0) return QH_EDEVICE;
+    for (int m = 0; m < 2; ++m) {
+        int g[3];
+        if (round_grids(m, c->cus, g) != hipSuccess) return QH_EDEVICE;
+        c->grid_pre[m][0] = g[0];
+        c->grid_pre[m][1] = g[1];
+        c->grid[m] = g[2];
+        if (g[0] <= 0 || g[1] <= 0 || g[2] <= 0) return QH_EDEVICE;
+    }
     if (extremes_grid(c->cus, &c->grid_ext) != hipSuccess || c->grid_ext <= 0) return QH_EDEVICE;
     if (hipHostMalloc((void **)&c->ctl_host, sizeof(Control), hipHostMallocDefault) != hipSuccess)
         return QH_ENOMEM;
@@ -258,6 +264,10 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
     args.fin_cap = (o && (o->flags & QH_FLAG_NO_FINISH)) ? 0 : kFinCap;
     args.fin_segs = cfg.fin_segs;
     const int grid = cfg.grid;
+    // the split and the round after it at their own residency, scaled like
+    // the round kernel's grid
+    args.grid_split = (int32_t)std::max<int64_t>(1, (int64_t)c->grid_pre[mode][0] * grid / std::max(1, c->grid[mode]));
+    args.grid_ro1 = (int32_t)std::max<int64_t>(1, (int64_t)c->grid_pre[mode][1] * grid / std::max(1, c->grid[mode]));
     int64_t syncs = 0;
     int r = 0;
     Timing tm{c, timing, {}};

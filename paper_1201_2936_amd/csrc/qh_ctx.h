@@ -50,6 +50,7 @@ struct qh_ctx {
     int64_t *single_hoff = nullptr;   // device int64[2]
     std::vector<hipEvent_t> ev;       // timing events (pairs)
     int grid[2] = {0, 0};             // resident blocks of the round kernel, per mode
+    int grid_pre[2][2] = {{0, 0}, {0, 0}};  // ... of the split and of the round after it
     int grid_ext = 0;                 // resident blocks of the extremes kernel
     int hint_rounds = 0;              // rounds the last 2D call needed (first batch size)
     qh3::Ctx3 *c3 = nullptr;          // 3D workspace, made on the first 3D call
