@@ -1027,6 +1027,64 @@ __device__ __forceinline__ bool fin_mode(const Control *ctl, int r, const HullAr
 }
 
 
+// the 8-bit field c of a packed counter
+__device__ __forceinline__ uint32_t field8(uint32_t v, uint32_t c) { return (v >> (8u * c)) & 0xffu; }
+
+// a copy of a wave-uniform value in a vector register (so that a per-lane
+// select between two such values needs no scalar operand)
+__device__ __forceinline__ int32_t vcopy(int32_t s) {
+    int32_t v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t o = shfl_xor_u64(v, m);
+        v = o > v ? o : v;
+    }
+    return uniform_u64(v);
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t o = shfl_xor_u64(v, m);
+        v = o < v ? o : v;
+    }
+    return uniform_u64(v);
+}
+
+// The wave's best point of each class so far in the run: distance W, tie key
+// T (its low 32 bits are the index), and (FP32 filter) the estimate below
+// which a point cannot reach W.  Offered the lanes' candidates of class k
+// (cand: exact distance d > 0 and tie key tk).
+struct WaveBest {
+    uint64_t W[4], T[4];
+    float tau[4];
+    uint32_t C[4];
+};
+
+__device__ __forceinline__ void wave_offer(WaveBest &wb, int k, bool cand, uint64_t d, uint64_t tk, float B) {
+    if (!__ballot(cand)) return;
+    const uint64_t dm = wave_max_u64(cand ? d : 0ull);
+    const uint64_t tm = wave_min_u64((cand && d == dm) ? tk : ~0ull);
+    if (dm > wb.W[k] || (dm == wb.W[k] && tm < wb.T[k])) {
+        wb.W[k] = dm;
+        wb.T[k] = tm;
+        // E < fl(fl(W) - 2B) implies d < W (the estimate's error is below
+        // 4/5 of B, and fl(W) and the difference round by less than B/5)
+        wb.tau[k] = __fsub_rn((float)dm, 2.f * B);
+    }
+}
+
 // a tile's record with its segment's geometry (u, f, v) when one segment
 // covers it
 struct TileGeo {
@@ -1209,10 +1267,21 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
         ctl->maxseg[q] = 0;
     }
     const int tb = blockIdx.x * T, te = min(tb + T, ntiles);
-    // A run: consecutive one-segment tiles of one segment in this block.  Its
-    // argmax of each child stays in the lanes' registers (r0, r1) and is
-    // reduced once, when the run ends.
-    RunBest r0 = rb_none(), r1 = rb_none();
+    const float c2 = MODE ? coord_c2(ctl) : 0.f;
+    // A run: consecutive one-segment tiles of one segment in this block.
+    // Each wave keeps the best point of each child of the run as uniform
+    // values; a lane's point is compared exactly only when it reaches it.
+    WaveBest wb;
+    auto wb_reset = [&]() {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            wb.W[k] = 0;
+            wb.T[k] = ~0ull;
+            wb.tau[k] = -INFINITY;
+            wb.C[k] = 0;
+        }
+    };
+    wb_reset();
     int cur = -1, run0 = 0, run_lo = 0, run_hi = 0, seg_st = 0, seg_en = 0;
     // the current tile's record and, when prefetched, its points
     TileGeo tc;
@@ -1238,12 +1307,16 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
         if (past) ti.single = 0;
         const int gseg = (R ? S0 : 0) + ti.seg;
         if (cur >= 0 && (!ti.single || gseg != cur)) {
-            // the run ends: reduce it, record it at its first tile
-            wave_rb63(r0);
-            wave_rb63(r1);
-            if (lane == kWave - 1) {
-                sm->wrb[wv][0] = r0;
-                sm->wrb[wv][1] = r1;
+            // the run ends: merge the waves' bests, record it at its first tile
+            if (lane == 0) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    RunBest rr;
+                    rr.k1 = wb.W[c];
+                    rr.k2 = wb.T[c];
+                    rr.cnt = (int32_t)wb.C[c];
+                    sm->wrb[wv][c] = rr;
+                }
             }
             __syncthreads();
             if (tid < 2) {
@@ -1261,8 +1334,7 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
                 ws.recL[run0 * 2 + tid] = b;
             }
             __syncthreads();
-            r0 = rb_none();
-            r1 = rb_none();
+            wb_reset();
             cur = -1;
         }
         if (past) return true;
@@ -1331,75 +1403,67 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
                     const bool o0 = valid && d0 > 0;
                     const bool o1 = valid && !o0 && d1 > 0;
                     stb |= (o0 ? 0u : (o1 ? 1u : 2u)) << (2 * i);
-                    rb_offer_nb(r0, o0, (uint64_t)d0, X[i], Y[i], I[i], e0x, e0y);
-                    rb_offer_nb(r1, o1, (uint64_t)d1, X[i], Y[i], I[i], e1x, e1y);
+                    const uint64_t d = (uint64_t)(o0 ? d0 : d1);
+                    const bool need = (o0 & (d >= wb.W[0])) | (o1 & (d >= wb.W[1]));
+                    if (__ballot(need)) {
+                        const uint64_t tk = tie_key(X[i], Y[i], I[i], o0 ? e0x : e1x, o0 ? e0y : e1y);
+                        wave_offer(wb, 0, need && o0, d, tk, 0.f);
+                        wave_offer(wb, 1, need && o1, d, tk, 0.f);
+                    }
                 }
             } else {
-                // FP32 pass: the state where both signs it needs are certain,
-                // the upper bound U of the distance to the point's own edge,
-                // and the best lower bound per child
-                float l0 = -INFINITY, l1 = -INFINITY;
-                float U[kItems];
+                // FP32 with one bound per child edge for every point (the
+                // largest coordinate bounds the differences); undecided items
+                // are redone in int64 and are argmax candidates; a decided
+                // survivor is one when its estimate reaches its child's
+                // threshold
+                const float B0 = static_bound(e0x, e0y, c2), B1 = static_bound(e1x, e1y, c2);
+                uint32_t und = 0, cand = 0;
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
-                    float B0, B1;
-                    const float e0 = cross_f32(X[i], Y[i], ux, uy, fx, fy, B0);
-                    const float e1 = cross_f32(X[i], Y[i], fx, fy, vx, vy, B1);
-                    const bool p0 = e0 > B0, n0 = e0 < -B0, p1 = e1 > B1, n1 = e1 < -B1;
-                    uint32_t sti = p0 ? 0u : (!n0 ? 3u : (p1 ? 1u : (n1 ? 2u : 3u)));
-                    sti = ((vm >> i) & 1u) ? sti : 2u;
+                    const bool valid = (vm >> i) & 1u;
+                    const float e0 = cross_f32_nb(X[i], Y[i], ux, uy, e0x, e0y);
+                    const float e1 = cross_f32_nb(X[i], Y[i], fx, fy, e1x, e1y);
+                    uint32_t sti = e0 > B0 ? 0u : (!(e0 < -B0) ? 3u : (e1 > B1 ? 1u : (e1 < -B1 ? 2u : 3u)));
+                    sti = valid ? sti : 2u;
                     stb |= sti << (2 * i);
-                    U[i] = p0 ? __fadd_rn(e0, 2.f * B0) : __fadd_rn(e1, 2.f * B1);
-                    l0 = sti == 0 ? fmaxf(l0, __fsub_rn(e0, 2.f * B0)) : l0;
-                    l1 = sti == 1 ? fmaxf(l1, __fsub_rn(e1, 2.f * B1)) : l1;
-                    // pin the item's results here, so that its FP32 temporaries
-                    // die now instead of being carried past the exact pass
-                    asm volatile("" : "+v"(U[i]), "+v"(l0), "+v"(l1));
-                    __builtin_amdgcn_sched_barrier(0);
+                    und |= (sti == 3 ? 1u : 0u) << i;
+                    const bool c = ((sti == 0) & (e0 >= wb.tau[0])) | ((sti == 1) & (e1 >= wb.tau[1]));
+                    cand |= (c ? 1u : 0u) << i;
                 }
                 // exact pass over the undecided items (rare): both signs in int64
-                const uint32_t und = stb & (stb >> 1) & 0x5555u;
                 if (__ballot(und != 0)) {
 #pragma unroll
                     for (int i = 0; i < kItems; ++i) {
-                        if (!((und >> (2 * i)) & 1u)) continue;
-                        // opaque copies: the FP32 values are recomputed here
-                        // rather than kept live from the pass above
-                        int32_t x = X[i], y = Y[i];
-                        asm volatile("" : "+v"(x), "+v"(y));
-                        float B0, B1;
-                        const float e0 = cross_f32(x, y, ux, uy, fx, fy, B0);
-                        const float e1 = cross_f32(x, y, fx, fy, vx, vy, B1);
+                        if (!((und >> i) & 1u)) continue;
+                        const int32_t x = X[i], y = Y[i];
+                        const float e0 = cross_f32_nb(x, y, ux, uy, e0x, e0y);
                         const bool o0 = cross_i64(x, y, ux, uy, fx, fy) > 0;
                         const bool o1 = !o0 && cross_i64(x, y, fx, fy, vx, vy) > 0;
-                        nfall += ((e0 > B0 || e0 < -B0) ? 0u : 1u) +
-                                 ((!o0 && !(e1 > B1 || e1 < -B1)) ? 1u : 0u);
+                        nfall += ((e0 > B0 || e0 < -B0) ? 0u : 1u) + (o0 ? 0u : 1u);
                         stb ^= ((o0 ? 0u : (o1 ? 1u : 2u)) ^ 3u) << (2 * i);
-                        U[i] = INFINITY;  // always a candidate: decided exactly
                     }
                 }
-                // only points whose upper bound reaches the wave's best lower
-                // bound of their child can be its argmax
-                const float M0 = wave_max_f_dpp(l0), M1 = wave_max_f_dpp(l1);
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
                     const uint32_t sti = (stb >> (2 * i)) & 3u;
-                    const bool c = sti < 2 && U[i] >= (sti == 0 ? M0 : M1);
-                    if (!__ballot(c)) continue;
-                    ncand += c ? 1u : 0u;
-                    if (c && sti == 0)
-                        rb_offer(r0, (uint64_t)cross_i64(X[i], Y[i], ux, uy, fx, fy), X[i], Y[i], I[i], e0x, e0y);
-                    if (c && sti == 1)
-                        rb_offer(r1, (uint64_t)cross_i64(X[i], Y[i], fx, fy, vx, vy), X[i], Y[i], I[i], e1x, e1y);
+                    const bool any = ((und | cand) >> i) & 1u;
+                    const bool c0 = (sti == 0) & any, c1 = (sti == 1) & any;
+                    if (!__ballot(c0 || c1)) continue;
+                    ncand += (c0 || c1) ? 1u : 0u;
+                    const int64_t d = c0 ? cross_i64(X[i], Y[i], ux, uy, fx, fy) : cross_i64(X[i], Y[i], fx, fy, vx, vy);
+                    const uint64_t tk = tie_key(X[i], Y[i], I[i], c0 ? e0x : e1x, c0 ? e0y : e1y);
+                    wave_offer(wb, 0, c0, (uint64_t)d, tk, B0);
+                    wave_offer(wb, 1, c1, (uint64_t)d, tk, B1);
                 }
             }
             // the lane's survivors per child: fields 00 and 01 of stb
             const uint32_t lc0 = (uint32_t)__popc(~(stb | (stb >> 1)) & 0x5555u);
             const uint32_t lc1 = (uint32_t)__popc(stb & ~(stb >> 1) & 0x5555u);
             if (MODE != 0) ntests += 2u * (uint32_t)__popc(vm) - lc0;
-            r0.cnt += (int32_t)lc0;
-            r1.cnt += (int32_t)lc1;
             const uint32_t wt = wave_sum(lc0 | (lc1 << 16));
+            wb.C[0] += wt & 0xffffu;
+            wb.C[1] += wt >> 16;
             if (lane == 0) sm->wcnt[buf][wv] = wt;
             if (pre) {
                 int32_t *pvs = sm->pvs[buf ^ 1], *pps = sm->pps[buf ^ 1];
@@ -1488,64 +1552,6 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
             atomicAdd(&ctl->filter_fallbacks, (unsigned long long)stat[1]);
             atomicAdd(&ctl->candidates, (unsigned long long)stat[2]);
         }
-    }
-}
-
-// the 8-bit field c of a packed counter
-__device__ __forceinline__ uint32_t field8(uint32_t v, uint32_t c) { return (v >> (8u * c)) & 0xffu; }
-
-// a copy of a wave-uniform value in a vector register (so that a per-lane
-// select between two such values needs no scalar operand)
-__device__ __forceinline__ int32_t vcopy(int32_t s) {
-    int32_t v;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
-    return v;
-}
-
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const uint64_t o = shfl_xor_u64(v, m);
-        v = o > v ? o : v;
-    }
-    return uniform_u64(v);
-}
-
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const uint64_t o = shfl_xor_u64(v, m);
-        v = o < v ? o : v;
-    }
-    return uniform_u64(v);
-}
-
-// The wave's best point of each class so far in the run: distance W, tie key
-// T (its low 32 bits are the index), and (FP32 filter) the estimate below
-// which a point cannot reach W.  Offered the lanes' candidates of class k
-// (cand: exact distance d > 0 and tie key tk).
-struct WaveBest {
-    uint64_t W[4], T[4];
-    float tau[4];
-    uint32_t C[4];
-};
-
-__device__ __forceinline__ void wave_offer(WaveBest &wb, int k, bool cand, uint64_t d, uint64_t tk, float B) {
-    if (!__ballot(cand)) return;
-    const uint64_t dm = wave_max_u64(cand ? d : 0ull);
-    const uint64_t tm = wave_min_u64((cand && d == dm) ? tk : ~0ull);
-    if (dm > wb.W[k] || (dm == wb.W[k] && tm < wb.T[k])) {
-        wb.W[k] = dm;
-        wb.T[k] = tm;
-        // E < fl(fl(W) - 2B) implies d < W (the estimate's error is below
-        // 4/5 of B, and fl(W) and the difference round by less than B/5)
-        wb.tau[k] = __fsub_rn((float)dm, 2.f * B);
     }
 }
 
@@ -1716,7 +1722,7 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
                 m0 |= (o0 ? 1u : 0u) << i;
                 m1 |= (o1 ? 1u : 0u) << i;
                 const uint64_t dd = (uint64_t)(o0 ? d : -d);
-                const bool need = (o0 && dd >= wb.W[0]) || (o1 && dd >= wb.W[1]);
+                const bool need = (o0 & (dd >= wb.W[0])) | (o1 & (dd >= wb.W[1]));
                 if (__ballot(need)) {
                     const int32_t idx = fast_pos_init(lo, i);
                     const uint64_t tk = tie_key(X[i], Y[i], idx, o0 ? ex : -ex, o0 ? ey : -ey);
@@ -1729,14 +1735,13 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
             // compared exactly when its estimate reaches its child's
             // threshold (its exact distance may then reach the child's best)
             const float B = static_bound(ex, ey, c2);
-            float E[kItems];
-            uint32_t und = 0;
+            uint32_t und = 0, cand = 0;
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
                 const bool valid = (vm >> i) & 1u;
                 const float e = cross_f32_nb(X[i], Y[i], ax, ay, ex, ey);
-                E[i] = e;
                 const bool p0 = valid && e > B, n0 = valid && e < -B;
+                cand |= (((p0 & (e >= wb.tau[0])) | (n0 & (-e >= wb.tau[1]))) ? 1u : 0u) << i;
                 m0 |= (p0 ? 1u : 0u) << i;
                 m1 |= (n0 ? 1u : 0u) << i;
                 und |= (valid && !p0 && !n0 ? 1u : 0u) << i;
@@ -1755,9 +1760,8 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
             }
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
-                const bool forced = (und >> i) & 1u;
-                const bool c0 = ((m0 >> i) & 1u) && (forced || E[i] >= wb.tau[0]);
-                const bool c1 = ((m1 >> i) & 1u) && (forced || -E[i] >= wb.tau[1]);
+                const bool any = ((und | cand) >> i) & 1u;
+                const bool c0 = ((m0 >> i) & 1u) & any, c1 = ((m1 >> i) & 1u) & any;
                 if (!__ballot(c0 || c1)) continue;
                 ncand += (c0 || c1) ? 1u : 0u;
                 const int64_t d = cross_i64(X[i], Y[i], ax, ay, bx, by);
@@ -1986,8 +1990,9 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
                 const uint32_t k = (o0 || o1) ? (s1 ? 2u : 0u) + (o1 ? 1u : 0u) : 4u;
                 cl |= k << (3 * i);
                 const uint64_t d = (uint64_t)(o0 ? d0 : d1);
-                const bool need = (k == 0 && d >= wb.W[0]) || (k == 1 && d >= wb.W[1]) ||
-                                  (k == 2 && d >= wb.W[2]) || (k == 3 && d >= wb.W[3]);
+                // (bitwise: no short-circuit branches)
+                const bool need = ((k == 0) & (d >= wb.W[0])) | ((k == 1) & (d >= wb.W[1])) |
+                                  ((k == 2) & (d >= wb.W[2])) | ((k == 3) & (d >= wb.W[3]));
                 if (__ballot(need)) {
                     const uint64_t tk = tie_key(X[i], Y[i], fast_pos_init(lo, i), o0 ? a0x : a1x, o0 ? a0y : a1y);
 #pragma unroll
@@ -2008,8 +2013,7 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
             const int32_t vf1x = vcopy(ti.f1x - ax), vf1y = vcopy(ti.f1y - ay);
             const float vb00 = __int_as_float(vcopy(__float_as_int(Bk[0]))), vb10 = __int_as_float(vcopy(__float_as_int(Bk[2])));
             const float vb01 = __int_as_float(vcopy(__float_as_int(Bk[1]))), vb11 = __int_as_float(vcopy(__float_as_int(Bk[3])));
-            uint32_t und = 0;
-            float E[kItems];
+            uint32_t und = 0, cand = 0;  // undecided items; estimates at their class's threshold
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
                 const bool valid = (vm >> i) & 1u;
@@ -2031,7 +2035,9 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
                 cl |= k << (3 * i);
                 und |= (st == 3 ? 1u : 0u) << i;
                 const float e = st == 0 ? e0 : e1;
-                E[i] = e;
+                const bool c = ((k == 0) & (e >= wb.tau[0])) | ((k == 1) & (e >= wb.tau[1])) |
+                               ((k == 2) & (e >= wb.tau[2])) | ((k == 3) & (e >= wb.tau[3]));
+                cand |= (c ? 1u : 0u) << i;
                 ntests += valid ? (sure ? (e0 > B0 ? 2u : 3u) : 1u) : 0u;
             }
             // undecided items (rare): the whole classification in int64
@@ -2058,9 +2064,7 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
                 const uint32_t k = (cl >> (3 * i)) & 7u;
-                const bool forced = (und >> i) & 1u;
-                const bool need = k < 4 && (forced || (k == 0 && E[i] >= wb.tau[0]) || (k == 1 && E[i] >= wb.tau[1]) ||
-                                            (k == 2 && E[i] >= wb.tau[2]) || (k == 3 && E[i] >= wb.tau[3]));
+                const bool need = (k < 4) & (((und | cand) >> i) & 1u);
                 if (!__ballot(need)) continue;
                 ncand += need ? 1u : 0u;
                 const bool s1 = (k & 2u) != 0, in0 = (k & 1u) == 0;
@@ -3312,7 +3316,7 @@ __global__ __launch_bounds__(kBlock) void k_extremes_final(Ws2 ws, HullArgs a) {
 
 // (the exact form fits in 128 registers: four waves per SIMD)
 template <int MODE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 4 : 1)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 4 : 3)))
 void k_round(Ws2 ws, HullArgs a, int32_t r) {
     __shared__ FastSmem sm;
     if (ws.ctl->setup_error) return;
@@ -3327,7 +3331,8 @@ __global__ __launch_bounds__(kBlock) void k_split(Ws2 ws, HullArgs a) {
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_round_ro1(Ws2 ws, HullArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 4 : 1)))
+void k_round_ro1(Ws2 ws, HullArgs a) {
     __shared__ Ro1Smem sm;
     if (ws.ctl->setup_error) return;
     phase_round_ro1<MODE>(ws, a, reinterpret_cast<char *>(&sm));
