@@ -5,16 +5,17 @@ independent 2D point sets (sizes log-uniform in [256, 2^20], 511,371,962
 points in total, each uniform in a disk of radius 2^20), every instance an
 initial segment of one set of rounds (extremes, first split, every round,
 output), with the points already resident in device memory.  The headline
-form is the FP32 filter with exact int64 fallback (bit-exact); the plain
-exact-int64 form is timed beside it on the same data.
+is the faster of the two forms on this GPU, the plain exact-int64 form; the
+FP32 filter with exact int64 fallback (bit-exact, the same output) is timed
+beside it on the same data.
 
-Prints ONE JSON line.  ``roofline`` describes the round (k_round for the tiles
-covered by one segment and k_round_multi for the others, launched together
-for the first split and once per later round; in the last round, once no
-segment holds more than 1,024 points, k_round_multi finishes every segment
-with one workgroup each), which moves nearly all the bytes: algorithmic bytes
-per round over the round's average duration, timed with HIP events around the
-pair of launches on the stream they run on.  ``traffic`` is the counter-
+Prints ONE JSON line.  ``roofline`` describes the round kernels (k_split for
+the first split, k_round_ro1 for the round after it, k_round for the later
+rounds, each with k_round_multi for the tiles that hold several segments; in
+the last round, once no segment holds more than 1,024 points, k_round_multi
+finishes every segment with one workgroup each), which move nearly all the
+bytes: algorithmic bytes per round over the round's average duration, timed
+with HIP events around the pair of launches on the stream they run on.  ``traffic`` is the counter-
 measured HBM traffic per round from the committed rocprofv3 summary, null when
 the kernel sources changed since it was taken.
 ``cpu_baseline`` is the oracle (plain single-threaded C Quickhull) on the
@@ -244,22 +245,26 @@ def batched_leg(steps: int, warmup: int):
     def run(mode):
         return qh.qh_hull2d_batched(pts, off, mode=mode, ctx=ctx)
 
-    sec_f, (idx_f, hoff_f, st_f) = time_steps(lambda: run(qh.QH_FP32_FILTER), steps, warmup)
-    sec_x, (idx_x, hoff_x, _) = time_steps(lambda: run(qh.QH_EXACT_INT64), max(3, min(steps, 10)), 1)
+    # the headline form (exact int64) and the FP32 filter beside it
+    sec_x, (idx_x, hoff_x, st_x) = time_steps(lambda: run(qh.QH_EXACT_INT64), steps, warmup)
+    sec_f, (idx_f, hoff_f, st_f) = time_steps(lambda: run(qh.QH_FP32_FILTER), max(3, min(steps, 10)), 1)
     same = bool(torch.equal(idx_f, idx_x) and torch.equal(hoff_f, hoff_x))
 
     # the launch configuration picked by the autotuner, the launches replayed
     # from captured graphs (fixed output buffers, a stream of its own)
-    tuned = tuned_graph_leg(lambda **kw: qh.qh_hull2d_batched(pts, off, mode=qh.QH_FP32_FILTER, **kw),
-                            lambda o: (o[0], o[1]), (idx_f, hoff_f), max(3, min(steps, 10)),
+    tuned = tuned_graph_leg(lambda **kw: qh.qh_hull2d_batched(pts, off, mode=qh.QH_EXACT_INT64, **kw),
+                            lambda o: (o[0], o[1]), (idx_x, hoff_x), max(3, min(steps, 10)),
                             [torch.empty(max(N, 1), dtype=torch.int32, device="cuda"),
-                             torch.empty_like(hoff_f)], ["out", "hull_offsets"])
+                             torch.empty_like(hoff_x)], ["out", "hull_offsets"])
 
     # per-launch kernel timing (HIP events around every launch, on the
     # stream the kernels run on): a separate pass of the same call
-    timed = [qh.qh_hull2d_batched(pts, off, mode=qh.QH_FP32_FILTER, ctx=ctx, timing=True)[2]
+    timed = [qh.qh_hull2d_batched(pts, off, mode=qh.QH_EXACT_INT64, ctx=ctx, timing=True)[2]
              for _ in range(3)]
     roof, bpl, avg_ms = round_roofline(timed, load_traffic(WORKLOAD))
+    timed_f = [qh.qh_hull2d_batched(pts, off, mode=qh.QH_FP32_FILTER, ctx=ctx, timing=True)[2]
+               for _ in range(3)]
+    roof_f, _, avg_ms_f = round_roofline(timed_f, None)
     nt = len(timed)
 
     def tavg(key):
@@ -270,14 +275,14 @@ def batched_leg(steps: int, warmup: int):
                for i in range(k)]
     sctx = qh.Context()
     for i in range(min(k, 64)):
-        qh.qh_hull2d(singles[i], mode=qh.QH_FP32_FILTER, ctx=sctx)
+        qh.qh_hull2d(singles[i], mode=qh.QH_EXACT_INT64, ctx=sctx)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     seq_ok = True
-    hoff_host = hoff_f.cpu().numpy()
-    idx_host = idx_f.cpu().numpy()
+    hoff_host = hoff_x.cpu().numpy()
+    idx_host = idx_x.cpu().numpy()
     for i in range(k):
-        one, _ = qh.qh_hull2d(singles[i], mode=qh.QH_FP32_FILTER, ctx=sctx)
+        one, _ = qh.qh_hull2d(singles[i], mode=qh.QH_EXACT_INT64, ctx=sctx)
         if i % 64 == 0:
             seq_ok &= np.array_equal(one.cpu().numpy(), idx_host[hoff_host[i]:hoff_host[i + 1]])
     torch.cuda.synchronize()
@@ -292,14 +297,19 @@ def batched_leg(steps: int, warmup: int):
     del singles, pts, off
     torch.cuda.empty_cache()
     part = {
-        "value": round(N / sec_f / 1e6, 3),
-        "ms_per_step": round(sec_f * 1e3, 4),
+        "value": round(N / sec_x / 1e6, 3),
+        "ms_per_step": round(sec_x * 1e3, 4),
         "config": {"workload": WORKLOAD, "instances": k, "n_total": N, "dims": 2,
                    "sizes": "log-uniform in [256, 2^20] (seed 5)",
-                   "coords": "int32 uniform in the disk of radius 2^20", "form": "fp32_filter",
+                   "coords": "int32 uniform in the disk of radius 2^20", "form": "exact_int64",
                    "call": "qh_hull2d_batched"},
-        "exact_int64": {"value": round(N / sec_x / 1e6, 3), "unit": "Mpoints/s",
-                        "ms_per_step": round(sec_x * 1e3, 4), "dtype": "i64"},
+        "fp32_filter": {"value": round(N / sec_f / 1e6, 3), "unit": "Mpoints/s",
+                        "ms_per_step": round(sec_f * 1e3, 4), "dtype": "f32+i64",
+                        "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"])
+                        if st_f["filter_tests"] else 0.0,
+                        "argmax_candidates": int(st_f["argmax_candidates"]),
+                        "round_kernel_avg_launch_us": round(avg_ms_f * 1e3, 2),
+                        "roofline": roof_f},
         "autotuned_graph": tuned,
         "sequential_single_calls": {"value": round(N / sec_seq / 1e6, 3), "unit": "Mpoints/s",
                                     "ms": round(sec_seq * 1e3, 1), "calls": k,
@@ -309,13 +319,12 @@ def batched_leg(steps: int, warmup: int):
         "hull_vertices": int(hoff_host[-1]),
         "parity_vs_oracle_sample": None,
         "parity_vs_oracle": None,
-        "rounds": int(st_f["rounds"]),
-        "fallback_rate": (st_f["filter_fallbacks"] / st_f["filter_tests"]) if st_f["filter_tests"] else 0.0,
-        "argmax_candidates": int(st_f["argmax_candidates"]),
-        "round_kernel": {"name": "k_round + k_round_multi (first split, later rounds, last round finishing "
-                                 "small segments)",
+        "rounds": int(st_x["rounds"]),
+        "round_kernel": {"name": "k_split, k_round_ro1, k_round, each with k_round_multi (the first split, "
+                                 "the round after it, the later rounds; the last round finishing small "
+                                 "segments)",
                          "launches_per_step": tavg("round_launches"), "avg_launch_us": round(avg_ms * 1e3, 2),
-                         "bytes_per_launch": round(bpl), "grid_blocks": int(st_f["grid_blocks"]),
+                         "bytes_per_launch": round(bpl), "grid_blocks": int(st_x["grid_blocks"]),
                          "first_split_us": round(tavg("split_ms") * 1e3, 1)},
         "device_time_us": {"all_kernels": round(tavg("kernel_ms") * 1e3, 1),
                            "rounds": round(tavg("round_kernel_ms") * 1e3, 1),
@@ -342,14 +351,15 @@ def square_leg(steps: int):
     ctx = qh.Context()
     sec, (idx_f, st_f) = time_steps(lambda: qh.qh_hull2d(pts, mode=qh.QH_FP32_FILTER, ctx=ctx), steps, 3)
     sec_x, (idx_x, _) = time_steps(lambda: qh.qh_hull2d(pts, mode=qh.QH_EXACT_INT64, ctx=ctx), steps, 3)
-    tuned = tuned_graph_leg(lambda **kw: qh.qh_hull2d(pts, mode=qh.QH_FP32_FILTER, **kw),
-                            lambda o: (o[0],), (idx_f,), steps,
+    tuned = tuned_graph_leg(lambda **kw: qh.qh_hull2d(pts, mode=qh.QH_EXACT_INT64, **kw),
+                            lambda o: (o[0],), (idx_x,), steps,
                             [torch.empty(max(n, 1), dtype=torch.int32, device="cuda")], ["out"])
-    timed = [qh.qh_hull2d(pts, mode=qh.QH_FP32_FILTER, ctx=ctx, timing=True)[1] for _ in range(steps)]
+    # the round kernels' roofline in the faster (exact) form
+    timed = [qh.qh_hull2d(pts, mode=qh.QH_EXACT_INT64, ctx=ctx, timing=True)[1] for _ in range(steps)]
     roof, bpl, avg_ms = round_roofline(timed, load_traffic(SQUARE))
     nt = len(timed)
     split_ms = sum(s["split_ms"] for s in timed) / nt
-    split_bytes = 8 * n + 12 * timed[0]["split_points_out"]
+    split_bytes = 8 * n  # the split reads the input and writes nothing
     check = (pts_np, idx_f.cpu().numpy(), idx_x.cpu().numpy())
     ctx.close()
     del pts
@@ -569,7 +579,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+i64",
+        "dtype": "i64",
         "data": "synthetic",
         "config": head.pop("config"),
         "roofline": head.pop("roofline"),

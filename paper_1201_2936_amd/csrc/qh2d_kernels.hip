@@ -469,6 +469,8 @@ __device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a
         __syncthreads();
     }
     if (threadIdx.x < 64) ctl->cspan_slot[threadIdx.x] = (uint32_t)kCoordMax2D;
+    for (int i = threadIdx.x; i < 4 * kAccSlots; i += blockDim.x) (&ctl->nacc[0][0][0])[i] = 0;
+    for (int i = threadIdx.x; i < 3 * kAccSlots; i += blockDim.x) (&ctl->fstat[0][0])[i] = 0;
     if (threadIdx.x == 0) {
         RoundState z = {};
         ctl->rs[1] = z;
@@ -487,7 +489,6 @@ __device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a
         ctl->points_in = ctl->points_out = ctl->first_in = ctl->first_out = 0;
         ctl->second_in = ctl->second_out = 0;
         ctl->cspan = (uint32_t)kCoordMax2D;
-        ctl->filter_tests = ctl->filter_fallbacks = ctl->candidates = 0;
         ctl->rounds_with_work = 0;
         ctl->H = 0;
         ctl->h_total = 0;
@@ -495,8 +496,6 @@ __device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a
         ctl->maxseg[1] = 0;
         ctl->fin_ids = 0;
         ctl->fin_round = -1;
-        ctl->nacc[0][0] = ctl->nacc[0][1] = 0;
-        ctl->nacc[1][0] = ctl->nacc[1][1] = 0;
     }
 }
 
@@ -1044,28 +1043,56 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// one DPP step of a 64-bit reduction: lanes whose source is outside their
+// row, or whose row is masked off, receive the identity (lo, hi)
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v, uint32_t idl, uint32_t idh) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)idl, (int)(uint32_t)v, Ctrl, RowMask, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)idh, (int)(uint32_t)(v >> 32), Ctrl, RowMask, 0xf, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// maximum / minimum over the wave (row shifts and row broadcasts, no LDS;
+// complete in lane 63, returned as a uniform value)
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const uint64_t o = shfl_xor_u64(v, m);
-        v = o > v ? o : v;
-    }
-    return uniform_u64(v);
+    uint64_t o;
+    o = dpp_u64<0x111, 0xf>(v, 0u, 0u); v = o > v ? o : v;
+    o = dpp_u64<0x112, 0xf>(v, 0u, 0u); v = o > v ? o : v;
+    o = dpp_u64<0x114, 0xf>(v, 0u, 0u); v = o > v ? o : v;
+    o = dpp_u64<0x118, 0xf>(v, 0u, 0u); v = o > v ? o : v;
+    o = dpp_u64<0x142, 0xa>(v, 0u, 0u); v = o > v ? o : v;
+    o = dpp_u64<0x143, 0xc>(v, 0u, 0u); v = o > v ? o : v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, kWave - 1);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), kWave - 1);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const uint64_t o = shfl_xor_u64(v, m);
-        v = o < v ? o : v;
-    }
-    return uniform_u64(v);
+    const uint32_t ff = 0xffffffffu;
+    uint64_t o;
+    o = dpp_u64<0x111, 0xf>(v, ff, ff); v = o < v ? o : v;
+    o = dpp_u64<0x112, 0xf>(v, ff, ff); v = o < v ? o : v;
+    o = dpp_u64<0x114, 0xf>(v, ff, ff); v = o < v ? o : v;
+    o = dpp_u64<0x118, 0xf>(v, ff, ff); v = o < v ? o : v;
+    o = dpp_u64<0x142, 0xa>(v, ff, ff); v = o < v ? o : v;
+    o = dpp_u64<0x143, 0xc>(v, ff, ff); v = o < v ? o : v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, kWave - 1);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), kWave - 1);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // The wave's best point of each class so far in the run: distance W, tie key
 // T (its low 32 bits are the index), and (FP32 filter) the estimate below
 // which a point cannot reach W.  Offered the lanes' candidates of class k
 // (cand: exact distance d > 0 and tie key tk).
+// bit i set when item i's two-bit class field (bits 2i, 2i + 1) is 2 or 3
+__device__ __forceinline__ uint32_t stb_dropped_mask(uint32_t stb) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) m |= ((stb >> (2 * i + 1)) & 1u) << i;
+    return m;
+}
+
 struct WaveBest {
     uint64_t W[4], T[4];
     float tau[4];
@@ -1394,6 +1421,10 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
             // one segment covers the tile: uniform geometry, every wave on its own
             const int ux = ti.ux, uy = ti.uy, fx = ti.fx, fy = ti.fy, vx = ti.vx, vy = ti.vy;
             const int e0x = fx - ux, e0y = fy - uy, e1x = vx - fx, e1y = vy - fy;
+            // items that may be a child's farthest point: resolved once per
+            // tile and child below
+            uint32_t fl = 0;
+            float B0 = 0.f, B1 = 0.f;
             if (MODE == 0) {
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
@@ -1405,11 +1436,7 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
                     stb |= (o0 ? 0u : (o1 ? 1u : 2u)) << (2 * i);
                     const uint64_t d = (uint64_t)(o0 ? d0 : d1);
                     const bool need = (o0 & (d >= wb.W[0])) | (o1 & (d >= wb.W[1]));
-                    if (__ballot(need)) {
-                        const uint64_t tk = tie_key(X[i], Y[i], I[i], o0 ? e0x : e1x, o0 ? e0y : e1y);
-                        wave_offer(wb, 0, need && o0, d, tk, 0.f);
-                        wave_offer(wb, 1, need && o1, d, tk, 0.f);
-                    }
+                    fl |= (need ? 1u : 0u) << i;
                 }
             } else {
                 // FP32 with one bound per child edge for every point (the
@@ -1417,7 +1444,8 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
                 // are redone in int64 and are argmax candidates; a decided
                 // survivor is one when its estimate reaches its child's
                 // threshold
-                const float B0 = static_bound(e0x, e0y, c2), B1 = static_bound(e1x, e1y, c2);
+                B0 = static_bound(e0x, e0y, c2);
+                B1 = static_bound(e1x, e1y, c2);
                 uint32_t und = 0, cand = 0;
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
@@ -1444,18 +1472,35 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
                         stb ^= ((o0 ? 0u : (o1 ? 1u : 2u)) ^ 3u) << (2 * i);
                     }
                 }
+                // (undecided items may have been dropped by the exact pass)
+                fl = (und | cand) & ~stb_dropped_mask(stb);
+            }
+            if (__ballot(fl != 0)) {
+                // each lane's best flagged item of each child, then the wave's;
+                // the edges are made opaque so that the distances are
+                // recomputed here, not kept alive from the classification
+                int gux = ux, guy = uy, gfx = fx, gfy = fy, g0x = e0x, g0y = e0y, g1x = e1x, g1y = e1y;
+                asm volatile("" : "+s"(gux), "+s"(guy), "+s"(gfx), "+s"(gfy), "+s"(g0x), "+s"(g0y), "+s"(g1x),
+                             "+s"(g1y));
+                uint64_t bd[2] = {0, 0}, bt[2] = {~0ull, ~0ull};
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
-                    const uint32_t sti = (stb >> (2 * i)) & 3u;
-                    const bool any = ((und | cand) >> i) & 1u;
-                    const bool c0 = (sti == 0) & any, c1 = (sti == 1) & any;
-                    if (!__ballot(c0 || c1)) continue;
-                    ncand += (c0 || c1) ? 1u : 0u;
-                    const int64_t d = c0 ? cross_i64(X[i], Y[i], ux, uy, fx, fy) : cross_i64(X[i], Y[i], fx, fy, vx, vy);
-                    const uint64_t tk = tie_key(X[i], Y[i], I[i], c0 ? e0x : e1x, c0 ? e0y : e1y);
-                    wave_offer(wb, 0, c0, (uint64_t)d, tk, B0);
-                    wave_offer(wb, 1, c1, (uint64_t)d, tk, B1);
+                    if (!((fl >> i) & 1u)) continue;
+                    const bool c1 = ((stb >> (2 * i)) & 3u) == 1u;
+                    const int px0 = c1 ? gfx : gux, py0 = c1 ? gfy : guy;
+                    const int cx = c1 ? g1x : g0x, cy = c1 ? g1y : g0y;
+                    const uint64_t d = (uint64_t)((int64_t)(X[i] - px0) * (int64_t)cy - (int64_t)(Y[i] - py0) * (int64_t)cx);
+                    const uint64_t tk = tie_key(X[i], Y[i], I[i], cx, cy);
+                    const uint64_t od = c1 ? bd[1] : bd[0], ot = c1 ? bt[1] : bt[0];
+                    const bool better = d > od || (d == od && tk < ot);
+                    bd[0] = (better && !c1) ? d : bd[0];
+                    bt[0] = (better && !c1) ? tk : bt[0];
+                    bd[1] = (better && c1) ? d : bd[1];
+                    bt[1] = (better && c1) ? tk : bt[1];
                 }
+                if (MODE != 0) ncand += (uint32_t)__popc(fl);
+                wave_offer(wb, 0, bd[0] != 0, bd[0], bt[0], B0);
+                wave_offer(wb, 1, bd[1] != 0, bd[1], bt[1], B1);
             }
             // the lane's survivors per child: fields 00 and 01 of stb
             const uint32_t lc0 = (uint32_t)__popc(~(stb | (stb >> 1)) & 0x5555u);
@@ -1534,8 +1579,8 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
     }
     if (oob) atomicOr(&ctl->error, kErrInternal);
     if (tid == 0 && (acc0 | acc1)) {
-        atomicAdd(&ctl->nacc[p][0], acc0);
-        atomicAdd(&ctl->nacc[p][1], acc1);
+        atomicAdd(&ctl->nacc[p][0][blockIdx.x % kAccSlots], acc0);
+        atomicAdd(&ctl->nacc[p][1][blockIdx.x % kAccSlots], acc1);
     }
     if (MODE != 0) {
         if (tid == 0) { stat[0] = 0; stat[1] = 0; stat[2] = 0; }
@@ -1548,9 +1593,9 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
         }
         __syncthreads();
         if (tid == 0 && stat[0]) {
-            atomicAdd(&ctl->filter_tests, (unsigned long long)stat[0]);
-            atomicAdd(&ctl->filter_fallbacks, (unsigned long long)stat[1]);
-            atomicAdd(&ctl->candidates, (unsigned long long)stat[2]);
+            atomicAdd(&ctl->fstat[0][blockIdx.x % kAccSlots], (unsigned long long)stat[0]);
+            atomicAdd(&ctl->fstat[1][blockIdx.x % kAccSlots], (unsigned long long)stat[1]);
+            atomicAdd(&ctl->fstat[2][blockIdx.x % kAccSlots], (unsigned long long)stat[2]);
         }
     }
 }
@@ -1627,9 +1672,9 @@ __device__ __forceinline__ void flush_filter_stats(Control *ctl, uint32_t *stat,
     }
     __syncthreads();
     if (tid == 0 && stat[0]) {
-        atomicAdd(&ctl->filter_tests, (unsigned long long)stat[0]);
-        atomicAdd(&ctl->filter_fallbacks, (unsigned long long)stat[1]);
-        atomicAdd(&ctl->candidates, (unsigned long long)stat[2]);
+        atomicAdd(&ctl->fstat[0][blockIdx.x % kAccSlots], (unsigned long long)stat[0]);
+        atomicAdd(&ctl->fstat[1][blockIdx.x % kAccSlots], (unsigned long long)stat[1]);
+        atomicAdd(&ctl->fstat[2][blockIdx.x % kAccSlots], (unsigned long long)stat[2]);
     }
 }
 
@@ -1713,6 +1758,8 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
         const int ax = ti.ux, ay = ti.uy, bx = ti.fx, by = ti.fy;
         const int ex = bx - ax, ey = by - ay;
         uint32_t m0 = 0, m1 = 0;  // the items of child 0 / child 1
+        uint32_t fl = 0;          // items that may be a child's farthest point
+        float B = 0.f;
         if (MODE == 0) {
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
@@ -1723,18 +1770,13 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
                 m1 |= (o1 ? 1u : 0u) << i;
                 const uint64_t dd = (uint64_t)(o0 ? d : -d);
                 const bool need = (o0 & (dd >= wb.W[0])) | (o1 & (dd >= wb.W[1]));
-                if (__ballot(need)) {
-                    const int32_t idx = fast_pos_init(lo, i);
-                    const uint64_t tk = tie_key(X[i], Y[i], idx, o0 ? ex : -ex, o0 ? ey : -ey);
-                    wave_offer(wb, 0, need && o0, dd, tk, 0.f);
-                    wave_offer(wb, 1, need && o1, dd, tk, 0.f);
-                }
+                fl |= (need ? 1u : 0u) << i;
             }
         } else {
             // FP32 estimates with one bound for every point; a point is
             // compared exactly when its estimate reaches its child's
             // threshold (its exact distance may then reach the child's best)
-            const float B = static_bound(ex, ey, c2);
+            B = static_bound(ex, ey, c2);
             uint32_t und = 0, cand = 0;
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
@@ -1758,18 +1800,33 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
                 }
                 nfall += (uint32_t)__popc(und);
             }
+            // (undecided items may have been dropped by the exact pass)
+            fl = (und | cand) & (m0 | m1);
+        }
+        if (__ballot(fl != 0)) {
+            // each lane's best flagged item of each child, then the wave's;
+            // the edge is made opaque so that the distances are recomputed
+            // here, not kept alive from the classification above
+            int gax = ax, gay = ay, gex = ex, gey = ey;
+            asm volatile("" : "+s"(gax), "+s"(gay), "+s"(gex), "+s"(gey));
+            uint64_t bd[2] = {0, 0}, bt[2] = {~0ull, ~0ull};
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
-                const bool any = ((und | cand) >> i) & 1u;
-                const bool c0 = ((m0 >> i) & 1u) & any, c1 = ((m1 >> i) & 1u) & any;
-                if (!__ballot(c0 || c1)) continue;
-                ncand += (c0 || c1) ? 1u : 0u;
-                const int64_t d = cross_i64(X[i], Y[i], ax, ay, bx, by);
-                const uint64_t dd = (uint64_t)(c0 ? d : -d);
-                const uint64_t tk = tie_key(X[i], Y[i], fast_pos_init(lo, i), c0 ? ex : -ex, c0 ? ey : -ey);
-                wave_offer(wb, 0, c0, dd, tk, B);
-                wave_offer(wb, 1, c1, dd, tk, B);
+                if (!((fl >> i) & 1u)) continue;
+                const bool c1 = (m1 >> i) & 1u;
+                const int64_t d = (int64_t)(X[i] - gax) * (int64_t)gey - (int64_t)(Y[i] - gay) * (int64_t)gex;
+                const uint64_t dd = (uint64_t)(c1 ? -d : d);
+                const uint64_t tk = tie_key(X[i], Y[i], fast_pos_init(lo, i), c1 ? -gex : gex, c1 ? -gey : gey);
+                const uint64_t od = c1 ? bd[1] : bd[0], ot = c1 ? bt[1] : bt[0];
+                const bool better = dd > od || (dd == od && tk < ot);
+                bd[0] = (better && !c1) ? dd : bd[0];
+                bt[0] = (better && !c1) ? tk : bt[0];
+                bd[1] = (better && c1) ? dd : bd[1];
+                bt[1] = (better && c1) ? tk : bt[1];
             }
+            if (MODE != 0) ncand += (uint32_t)__popc(fl);
+            wave_offer(wb, 0, bd[0] != 0, bd[0], bt[0], B);
+            wave_offer(wb, 1, bd[1] != 0, bd[1], bt[1], B);
         }
         const uint32_t lc0 = (uint32_t)__popc(m0), lc1 = (uint32_t)__popc(m1);
         acc0 += lc0;
@@ -1810,8 +1867,9 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
     // survivors of the split (counted, not written) per child
     const uint32_t s0 = wave_sum(acc0), s1 = wave_sum(acc1);
     if (lane == 0 && (s0 | s1)) {
-        atomicAdd(&ctl->nacc[0][0], s0);
-        atomicAdd(&ctl->nacc[0][1], s1);
+        const int sl = (blockIdx.x * kNW + wv) % kAccSlots;
+        atomicAdd(&ctl->nacc[0][0][sl], s0);
+        atomicAdd(&ctl->nacc[0][1][sl], s1);
     }
     if (MODE != 0) flush_filter_stats(ctl, sm->stat, ntests, nfall, ncand);
 }
@@ -1831,6 +1889,10 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
 // so that they end at the slot's end (a tile has at most kTile points on
 // both sides together); for the piece table they are the pieces of tile t
 // and of tile nt + t, the tiles of region 0 and region 1 of this round.
+// the low bit of each item's three-bit field
+constexpr uint32_t kLow3 = 0x249249u & ((1u << (3 * kItems)) - 1u);
+static_assert(3 * kItems <= 24, "three-bit class fields");
+
 struct Ro1Smem {
     uint32_t stat[4];
     RunBest wrb[kNW][4];
@@ -1966,6 +2028,8 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
         const int e00x = ti.f0x - ax, e00y = ti.f0y - ay, e01x = bx - ti.f0x, e01y = by - ti.f0y;
         const int e10x = ti.f1x - bx, e10y = ti.f1y - by, e11x = ax - ti.f1x, e11y = ay - ti.f1y;
         uint32_t cl = 0;  // class of item i in bits 3i .. 3i + 2
+        uint32_t fl = 0;  // FP32 filter: argmax candidates (bit 3i)
+        float Bk[4] = {0.f, 0.f, 0.f, 0.f};
         if (MODE == 0) {
             const int64_t nk01 = -((int64_t)e00x * e01y - (int64_t)e00y * e01x);
             const int64_t nk10 = -((int64_t)esx * e10y - (int64_t)esy * e10x);
@@ -1993,6 +2057,9 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
                 // (bitwise: no short-circuit branches)
                 const bool need = ((k == 0) & (d >= wb.W[0])) | ((k == 1) & (d >= wb.W[1])) |
                                   ((k == 2) & (d >= wb.W[2])) | ((k == 3) & (d >= wb.W[3]));
+                // offered at once: the wave's bests rise item by item, and
+                // with four classes that keeps the offers fewer than
+                // flagging them for a pass per tile
                 if (__ballot(need)) {
                     const uint64_t tk = tie_key(X[i], Y[i], fast_pos_init(lo, i), o0 ? a0x : a1x, o0 ? a0y : a1y);
 #pragma unroll
@@ -2001,8 +2068,10 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
             }
         } else {
             const float Bs = static_bound(esx, esy, c2);
-            const float Bk[4] = {static_bound(e00x, e00y, c2), static_bound(e01x, e01y, c2),
-                                 static_bound(e10x, e10y, c2), static_bound(e11x, e11y, c2)};
+            Bk[0] = static_bound(e00x, e00y, c2);
+            Bk[1] = static_bound(e01x, e01y, c2);
+            Bk[2] = static_bound(e10x, e10y, c2);
+            Bk[3] = static_bound(e11x, e11y, c2);
             const float fesx = (float)esx, fesy = (float)esy;
             // per-side values as vector-register copies: the child edges, the
             // offsets of u and f from a, the bounds
@@ -2059,25 +2128,38 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
                 nfall += (uint32_t)__popc(und);
             }
             // candidates: estimates at or above their class's threshold, and
-            // the items decided exactly; their exact distances to the waves'
-            // bests
+            // the items decided exactly
 #pragma unroll
-            for (int i = 0; i < kItems; ++i) {
-                const uint32_t k = (cl >> (3 * i)) & 7u;
-                const bool need = (k < 4) & (((und | cand) >> i) & 1u);
-                if (!__ballot(need)) continue;
-                ncand += need ? 1u : 0u;
-                const bool s1 = (k & 2u) != 0, in0 = (k & 1u) == 0;
-                const int32_t x = X[i], y = Y[i];
-                const int ux = s1 ? bx : ax, uy = s1 ? by : ay;
-                const int fx = s1 ? ti.f1x : ti.f0x, fy = s1 ? ti.f1y : ti.f0y;
-                const int cx = in0 ? (s1 ? e10x : e00x) : (s1 ? e11x : e01x);
-                const int cy = in0 ? (s1 ? e10y : e00y) : (s1 ? e11y : e01y);
-                const int px0 = in0 ? ux : fx, py0 = in0 ? uy : fy;
-                const int64_t d = (int64_t)(x - px0) * (int64_t)cy - (int64_t)(y - py0) * (int64_t)cx;
-                const uint64_t tk = tie_key(x, y, fast_pos_init(lo, i), cx, cy);
+            for (int i = 0; i < kItems; ++i) fl |= (((und | cand) >> i) & 1u) << (3 * i);
+        }
+        if (MODE != 0 && __ballot(fl != 0)) {
+            // each lane's best flagged item of each class (exact distances to
+            // the child edge), then the wave's
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) wave_offer(wb, kk, need && k == (uint32_t)kk, (uint64_t)d, tk, Bk[kk]);
+            for (int kk = 0; kk < 4; ++kk) {
+                // bit 3i: item i is flagged and of class kk
+                const uint32_t x = cl ^ ((uint32_t)kk * kLow3);
+                const uint32_t fc = fl & ~(x | (x >> 1) | (x >> 2)) & kLow3;
+                if (!__ballot(fc != 0)) continue;
+                if (MODE != 0) ncand += (uint32_t)__popc(fc);
+                int px0 = kk == 0 ? ax : kk == 1 ? ti.f0x : kk == 2 ? bx : ti.f1x;
+                int py0 = kk == 0 ? ay : kk == 1 ? ti.f0y : kk == 2 ? by : ti.f1y;
+                int cx = kk == 0 ? e00x : kk == 1 ? e01x : kk == 2 ? e10x : e11x;
+                int cy = kk == 0 ? e00y : kk == 1 ? e01y : kk == 2 ? e10y : e11y;
+                // opaque: the distances are recomputed here, not kept alive
+                // from the classification
+                asm volatile("" : "+s"(px0), "+s"(py0), "+s"(cx), "+s"(cy));
+                uint64_t bd = 0, bt = ~0ull;
+#pragma unroll
+                for (int i = 0; i < kItems; ++i) {
+                    if (!((fc >> (3 * i)) & 1u)) continue;
+                    const uint64_t d = (uint64_t)((int64_t)(X[i] - px0) * (int64_t)cy - (int64_t)(Y[i] - py0) * (int64_t)cx);
+                    const uint64_t tk = tie_key(X[i], Y[i], fast_pos_init(lo, i), cx, cy);
+                    const bool better = d > bd || (d == bd && tk < bt);
+                    bd = better ? d : bd;
+                    bt = better ? tk : bt;
+                }
+                wave_offer(wb, kk, bd != 0, bd, bt, Bk[kk]);
             }
         }
         // per-lane counts of the four classes (8-bit fields), their prefix in
@@ -2162,8 +2244,8 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
     }
     if (oob) atomicOr(&ctl->error, kErrInternal);
     if (tid == 0 && (acc0 | acc1)) {
-        atomicAdd(&ctl->nacc[1][0], acc0);
-        atomicAdd(&ctl->nacc[1][1], acc1);
+        atomicAdd(&ctl->nacc[1][0][blockIdx.x % kAccSlots], acc0);
+        atomicAdd(&ctl->nacc[1][1][blockIdx.x % kAccSlots], acc1);
     }
     if (MODE != 0) flush_filter_stats(ctl, sm->stat, ntests, nfall, ncand);
 }
@@ -2452,8 +2534,8 @@ __device__ __forceinline__ void phase_round_multi(const Ws2 &ws, const HullArgs 
     }
     if (oob) atomicOr(&ctl->error, kErrInternal);
     if (tid == 0 && (acc0 | acc1)) {
-        atomicAdd(&ctl->nacc[p][0], acc0);
-        atomicAdd(&ctl->nacc[p][1], acc1);
+        atomicAdd(&ctl->nacc[p][0][blockIdx.x % kAccSlots], acc0);
+        atomicAdd(&ctl->nacc[p][1][blockIdx.x % kAccSlots], acc1);
     }
     if (MODE != 0) {
         if (tid == 0) { stat[0] = 0; stat[1] = 0; stat[2] = 0; }
@@ -2466,9 +2548,9 @@ __device__ __forceinline__ void phase_round_multi(const Ws2 &ws, const HullArgs 
         }
         __syncthreads();
         if (tid == 0 && stat[0]) {
-            atomicAdd(&ctl->filter_tests, (unsigned long long)stat[0]);
-            atomicAdd(&ctl->filter_fallbacks, (unsigned long long)stat[1]);
-            atomicAdd(&ctl->candidates, (unsigned long long)stat[2]);
+            atomicAdd(&ctl->fstat[0][blockIdx.x % kAccSlots], (unsigned long long)stat[0]);
+            atomicAdd(&ctl->fstat[1][blockIdx.x % kAccSlots], (unsigned long long)stat[1]);
+            atomicAdd(&ctl->fstat[2][blockIdx.x % kAccSlots], (unsigned long long)stat[2]);
         }
     }
 }
@@ -2815,7 +2897,7 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
     const int nt0 = (rs->n[0] + kTile - 1) / kTile;
     const int nt1 = (rs->n[1] + kTile - 1) / kTile;
     // survivors of this round per region (summed by the round kernel's blocks)
-    const int An0 = (int)ctl->nacc[p][0], An1 = (int)ctl->nacc[p][1];
+    const int An0 = (int)wave_sum(ctl->nacc[p][0][lane_id()]), An1 = (int)wave_sum(ctl->nacc[p][1][lane_id()]);
     // The split (r = 0) keeps no point: its children are the instances'
     // input ranges (both regions of the next round are the input), and every
     // child is made, even an empty one, so that every input tile has its
@@ -2833,9 +2915,11 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             RoundState z = {};
             z.hbase = hbase + (int32_t)ctl->fin_ids;
             *rn = z;
-            ctl->nacc[q][0] = 0;
-            ctl->nacc[q][1] = 0;
             ctl->fin_round = r;
+        }
+        if (blockIdx.x == 0 && tid < kAccSlots) {
+            ctl->nacc[q][0][tid] = 0;
+            ctl->nacc[q][1][tid] = 0;
         }
         return;
     }
@@ -2844,8 +2928,6 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
         rn->piece_ctr = 0;
         rn->n[0] = Nn0;
         rn->n[1] = Nn1;
-        ctl->nacc[q][0] = 0;
-        ctl->nacc[q][1] = 0;
         const unsigned long long nin = (unsigned long long)(rs->n[0] + rs->n[1]);
         if (nin) {
             if (ro0) {
@@ -2860,6 +2942,10 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
             }
             ctl->rounds_with_work += 1ull;
         }
+    }
+    if (blockIdx.x == 0 && tid < kAccSlots) {
+        ctl->nacc[q][0][tid] = 0;
+        ctl->nacc[q][1][tid] = 0;
     }
     for (int i = blockIdx.x * kSegBlock + tid; i < 2 * nsegt + 4 && i < ws.s4cap; i += gridDim.x * kSegBlock) {
         ws.st4(q)[i] = 0;

@@ -411,9 +411,12 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
             stats->extremes_ms = ms[Timing::kExtremes];
             stats->segment_ms = ms[Timing::kSegments];
         }
-        stats->filter_tests = (int64_t)h.filter_tests;
-        stats->filter_fallbacks = (int64_t)h.filter_fallbacks;
-        stats->argmax_candidates = (int64_t)h.candidates;
+        unsigned long long fs[3] = {0, 0, 0};
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < kAccSlots; ++i) fs[j] += h.fstat[j][i];
+        stats->filter_tests = (int64_t)fs[0];
+        stats->filter_fallbacks = (int64_t)fs[1];
+        stats->argmax_candidates = (int64_t)fs[2];
         stats->max_segments = h.max_segments;
         stats->grid_blocks = grid;
         stats->host_syncs = syncs;

@@ -198,6 +198,8 @@ enum : int32_t {
     kErrInternal = 32,  // an internal index check failed
 };
 
+constexpr int kAccSlots = 64;
+
 struct Control {
     RoundState rs[2];
     int32_t error;
@@ -210,11 +212,14 @@ struct Control {
     unsigned long long first_out;     // survivors of the first split (counted, not written)
     unsigned long long second_in;     // input points read by the round after it
     unsigned long long second_out;    // survivors written by that round
-    unsigned long long filter_tests;
-    unsigned long long filter_fallbacks;
-    unsigned long long candidates;
+    // FP32-filter counters (tests, fallbacks, argmax candidates), spread
+    // over kAccSlots words each like nacc
+    unsigned long long fstat[3][64];
     unsigned long long rounds_with_work;
-    unsigned int nacc[2][2];          // survivors per region written by the round kernel, by parity
+    // survivors per region counted by the round kernels, by parity, spread
+    // over kAccSlots words each (the blocks add into the word of their number
+    // modulo kAccSlots, so that few additions meet at one address)
+    unsigned int nacc[2][2][64];
     int32_t tper[2];                  // tiles per block of the round kernel, by parity
     int32_t tper_ext;                 // tiles per block of the extremes kernel
     int32_t maxseg[2];                // largest segment of the round, by parity

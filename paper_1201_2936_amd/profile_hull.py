@@ -97,16 +97,24 @@ def summarize(args):
         copy_kib = args.copy_mb * 1024.0
         scale = {}
         per_kernel = {}
+        names = args.kernel.split(",")
+        heads = args.launch_kernels.split(",") if args.launch_kernels else names[:1]
         for ctr, path in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
             rows = _counter_rows(path, ctr)
             copies = [v for n, v in rows if "copyBuffer" in n or "copy" in _short(n).lower()]
             big = max(copies) if copies else 0.0
             scale[ctr] = copy_kib / big if big > 0 else None
-            names = args.kernel.split(",")
-            vals = [v for n, v in rows if any(_short(n).startswith(k) for k in names)]
-            # launches are counted on the first kernel name (one per round)
-            nl = len([1 for n, v in rows if _short(n).startswith(names[0])])
-            per_kernel[ctr] = (sum(vals), nl)
+            # the launches of the kernels that start a round, each with the
+            # other kernels of its round; from launch --from-launch on
+            groups = []
+            for n, v in rows:
+                sn = _short(n)
+                if any(sn.startswith(k) for k in heads):
+                    groups.append(v)
+                elif any(sn.startswith(k) for k in names) and groups:
+                    groups[-1] += v
+            groups = groups[args.from_launch:]
+            per_kernel[ctr] = (sum(groups), len(groups))
         f_kib, nf = per_kernel["FETCH_SIZE"]
         w_kib, nw = per_kernel["WRITE_SIZE"]
         fetch_b = f_kib * 1024 * scale["FETCH_SIZE"] / max(nf, 1)
@@ -119,15 +127,14 @@ def summarize(args):
             out["kernel_sha"] = args.kernel_sha
         # per launch of the first kernel name (one per round), the kernels of
         # that round added: KiB as read, in order
-        names = args.kernel.split(",")
         per_round = {}
         for ctr, path in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
             seq = []
             for n, v in _counter_rows(path, ctr):
                 sn = _short(n)
-                if sn.startswith(names[0]):
+                if any(sn.startswith(k) for k in heads):
                     seq.append(v)
-                elif any(sn.startswith(k) for k in names[1:]) and seq:
+                elif any(sn.startswith(k) for k in names) and seq:
                     seq[-1] += v
             per_round[ctr] = seq
         nr = min(len(per_round["FETCH_SIZE"]), len(per_round["WRITE_SIZE"]))
@@ -166,7 +173,11 @@ def main():
         sp.add_argument("--write")
         sp.add_argument("--kernel", default="k_round",
                         help="kernel name prefixes, comma-separated; bytes are summed and "
-                             "divided by the launches of the first")
+                             "divided by the launches of the first (or of --launch-kernels)")
+        sp.add_argument("--launch-kernels", default="",
+                        help="kernel name prefixes whose dispatches each start a round")
+        sp.add_argument("--from-launch", type=int, default=0,
+                        help="count the rounds from this launch on (skip a first call)")
         sp.add_argument("--copy-mb", type=int, default=256)
         sp.add_argument("--kernel-sha", default="")
         sp.add_argument("--out")
