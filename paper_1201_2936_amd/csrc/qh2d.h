@@ -92,7 +92,7 @@ struct HullArgs {
     int64_t *hull_offsets;
     int32_t n;
     int32_t k;
-    int32_t vec_ok;
+    int32_t vec_ok;      // the planes are 4-byte aligned: 4-point vector loads
     int32_t timing;
     int32_t max_rounds;
     int32_t fin_cap;   // finish every segment in one block once none is larger (0: off)

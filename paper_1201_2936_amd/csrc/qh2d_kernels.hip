@@ -41,6 +41,12 @@ namespace qh {
 // 5 eps also covers the rounding of the bound itself.
 constexpr float kErrC = 5.0f / 16777216.0f;
 constexpr int kNW = kBlock / kWave;
+
+// Four consecutive int32 coordinates.  Only 4-byte alignment is assumed: the
+// y plane starts n values after the x plane, and dword-aligned multi-dword
+// global loads are legal on gfx9 and later (one instruction still moves 16
+// bytes per lane).
+typedef int32_t i32x4u __attribute__((ext_vector_type(4), aligned(4)));
 constexpr int kQ = kItems / 4;
 
 // ---------------------------------------------------------------------------
@@ -613,8 +619,8 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
         for (int qq = 0; qq < kQ; ++qq) {
             const int v0 = lo + qq * kBlock * 4 + tid * 4;
             if (a.vec_ok && v0 + 3 < hi) {
-                const int4 p = *reinterpret_cast<const int4 *>(a.x + v0);
-                const int4 q = *reinterpret_cast<const int4 *>(a.y + v0);
+                const i32x4u p = *reinterpret_cast<const i32x4u *>(a.x + v0);
+                const i32x4u q = *reinterpret_cast<const i32x4u *>(a.y + v0);
                 X[qq * 4 + 0] = p.x; X[qq * 4 + 1] = p.y; X[qq * 4 + 2] = p.z; X[qq * 4 + 3] = p.w;
                 Y[qq * 4 + 0] = q.x; Y[qq * 4 + 1] = q.y; Y[qq * 4 + 2] = q.z; Y[qq * 4 + 3] = q.w;
             } else {
@@ -924,8 +930,8 @@ __device__ __forceinline__ void load_input(const HullArgs &a, int lo, int hi, in
     for (int qq = 0; qq < kQ; ++qq) {
         const int v0 = lo + qq * kBlock * 4 + tid * 4;
         if (a.vec_ok && v0 + 3 < hi) {
-            const int4 pa = *reinterpret_cast<const int4 *>(a.x + v0);
-            const int4 pb = *reinterpret_cast<const int4 *>(a.y + v0);
+            const i32x4u pa = *reinterpret_cast<const i32x4u *>(a.x + v0);
+            const i32x4u pb = *reinterpret_cast<const i32x4u *>(a.y + v0);
             X[qq * 4 + 0] = pa.x; X[qq * 4 + 1] = pa.y; X[qq * 4 + 2] = pa.z; X[qq * 4 + 3] = pa.w;
             Y[qq * 4 + 0] = pb.x; Y[qq * 4 + 1] = pb.y; Y[qq * 4 + 2] = pb.z; Y[qq * 4 + 3] = pb.w;
         } else {
@@ -1159,8 +1165,8 @@ __device__ __forceinline__ uint32_t load_input_wave(const HullArgs &a, int lo, i
     for (int qq = 0; qq < kQ; ++qq) {
         const int v0 = fast_pos_init(lo, qq * 4);
         if (a.vec_ok && v0 + 3 < hi) {
-            const int4 pa = *reinterpret_cast<const int4 *>(a.x + v0);
-            const int4 pb = *reinterpret_cast<const int4 *>(a.y + v0);
+            const i32x4u pa = *reinterpret_cast<const i32x4u *>(a.x + v0);
+            const i32x4u pb = *reinterpret_cast<const i32x4u *>(a.y + v0);
             X[qq * 4 + 0] = pa.x; X[qq * 4 + 1] = pa.y; X[qq * 4 + 2] = pa.z; X[qq * 4 + 3] = pa.w;
             Y[qq * 4 + 0] = pb.x; Y[qq * 4 + 1] = pb.y; Y[qq * 4 + 2] = pb.z; Y[qq * 4 + 3] = pb.w;
         } else {

@@ -260,7 +260,7 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
     args.hull_offsets = hull_offsets;
     args.n = (int32_t)n;
     args.k = k;
-    args.vec_ok = (((uintptr_t)pts & 15u) == 0 && (n & 3) == 0) ? 1 : 0;
+    args.vec_ok = ((uintptr_t)pts & 3u) == 0 ? 1 : 0;
     args.fin_cap = (o && (o->flags & QH_FLAG_NO_FINISH)) ? 0 : kFinCap;
     args.fin_segs = cfg.fin_segs;
     const int grid = cfg.grid;
