@@ -612,13 +612,13 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
         imx = -1;
     };
     // the points of a tile (4-point vectors where the input allows) and its record
-    auto load_tile = [&](int tile, int32_t (&X)[kItems], int32_t (&Y)[kItems], TileInfo &ti) {
+    auto load_tile = [&](int tile, int32_t (&X)[kItems], int32_t (&Y)[kItems], TileInfo &ti, bool whole) {
         const int lo = tile * kTile;
         const int hi = min(lo + kTile, n);
 #pragma unroll
         for (int qq = 0; qq < kQ; ++qq) {
             const int v0 = lo + qq * kBlock * 4 + tid * 4;
-            if (a.vec_ok && v0 + 3 < hi) {
+            if (whole || (a.vec_ok && v0 + 3 < hi)) {
                 const i32x4u p = *reinterpret_cast<const i32x4u *>(a.x + v0);
                 const i32x4u q = *reinterpret_cast<const i32x4u *>(a.y + v0);
                 X[qq * 4 + 0] = p.x; X[qq * 4 + 1] = p.y; X[qq * 4 + 2] = p.z; X[qq * 4 + 3] = p.w;
@@ -640,22 +640,12 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
         ti.start = scalar_load(rec + 2);
         ti.end = scalar_load(rec + 3);
     };
-    // software pipelined: the next tile's points are requested before this
-    // tile is reduced
-    int32_t Xn[kItems], Yn[kItems];
-    TileInfo tin = {};
-    if (tb < te) load_tile(tb, Xn, Yn, tin);
-    for (int tile = tb; tile < te; ++tile) {
+    // one tile's points: the run's extremes in registers, or several
+    // instances reduced per instance in LDS
+    auto reduce_tile = [&](int tile, const int32_t (&X)[kItems], const int32_t (&Y)[kItems], const TileInfo &ti)
+        __attribute__((always_inline)) {
         const int lo = tile * kTile;
         const int hi = min(lo + kTile, n);
-        int32_t X[kItems], Y[kItems];
-#pragma unroll
-        for (int i = 0; i < kItems; ++i) {
-            X[i] = Xn[i];
-            Y[i] = Yn[i];
-        }
-        const TileInfo ti = tin;
-        if (tile + 1 < te) load_tile(tile + 1, Xn, Yn, tin);
         const bool full = hi - lo == kTile;
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
@@ -682,7 +672,7 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
                 if (ck < kmn) { kmn = ck; imn = v; }
                 if (ck > kmx) { kmx = ck; imx = v; }
             }
-            continue;
+            return;
         }
         if (cur >= 0) {
             flush(tile);
@@ -766,6 +756,31 @@ __device__ __forceinline__ void phase_extremes(const Ws2 &ws, const HullArgs &a,
             }
             __syncthreads();
         }
+    };
+    // software pipelined over the full tiles: the next tile's points are
+    // requested before this tile is reduced, unconditionally (the last
+    // iteration reloads its own tile), so the wait for this tile's points
+    // never waits for them; the input's ragged last tile comes after the loop
+    const int tfe = max(tb, min(te, n / kTile));
+    int32_t Xn[kItems], Yn[kItems];
+    TileInfo tin = {};
+    if (tb < tfe) load_tile(tb, Xn, Yn, tin, true);
+    for (int tile = tb; tile < tfe; ++tile) {
+        int32_t X[kItems], Y[kItems];
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            X[i] = Xn[i];
+            Y[i] = Yn[i];
+        }
+        const TileInfo ti = tin;
+        load_tile(min(tile + 1, tfe - 1), Xn, Yn, tin, true);
+        reduce_tile(tile, X, Y, ti);
+    }
+    for (int tile = tfe; tile < te; ++tile) {
+        int32_t X[kItems], Y[kItems];
+        TileInfo ti;
+        load_tile(tile, X, Y, ti, false);
+        reduce_tile(tile, X, Y, ti);
     }
     if (cur >= 0) flush(te);
     const bool bad = span > 2u * (uint32_t)kCoordMax2D || nspan > 2u * (uint32_t)kCoordMax2D;
@@ -1158,6 +1173,21 @@ __device__ __forceinline__ int fast_pos_init(int lo, int i) {
     return lo + (int)(threadIdx.x / kWave) * 512 + (i >> 2) * 256 + lane_id() * 4 + (i & 3);
 }
 
+// A full tile's points, every lane's four-point vectors in range: no
+// per-lane conditions, so that loads of the next tile issued before this
+// one is classified need not wait for anything.
+__device__ __forceinline__ void load_full_wave(const HullArgs &a, int lo, int32_t (&X)[kItems],
+                                               int32_t (&Y)[kItems]) {
+#pragma unroll
+    for (int qq = 0; qq < kQ; ++qq) {
+        const int v0 = fast_pos_init(lo, qq * 4);
+        const i32x4u pa = *reinterpret_cast<const i32x4u *>(a.x + v0);
+        const i32x4u pb = *reinterpret_cast<const i32x4u *>(a.y + v0);
+        X[qq * 4 + 0] = pa.x; X[qq * 4 + 1] = pa.y; X[qq * 4 + 2] = pa.z; X[qq * 4 + 3] = pa.w;
+        Y[qq * 4 + 0] = pb.x; Y[qq * 4 + 1] = pb.y; Y[qq * 4 + 2] = pb.z; Y[qq * 4 + 3] = pb.w;
+    }
+}
+
 __device__ __forceinline__ uint32_t load_input_wave(const HullArgs &a, int lo, int hi,
                                                     int32_t (&X)[kItems], int32_t (&Y)[kItems]) {
     uint32_t vm = 0;
@@ -1486,8 +1516,8 @@ __device__ __forceinline__ void phase_round_fast(const Ws2 &ws, const HullArgs &
                 // the edges are made opaque so that the distances are
                 // recomputed here, not kept alive from the classification
                 int gux = ux, guy = uy, gfx = fx, gfy = fy, g0x = e0x, g0y = e0y, g1x = e1x, g1y = e1y;
-                asm volatile("" : "+s"(gux), "+s"(guy), "+s"(gfx), "+s"(gfy), "+s"(g0x), "+s"(g0y), "+s"(g1x),
-                             "+s"(g1y));
+                asm volatile("" : "+v"(gux), "+v"(guy), "+v"(gfx), "+v"(gfy), "+v"(g0x), "+v"(g0y), "+v"(g1x),
+                             "+v"(g1y));
                 uint64_t bd[2] = {0, 0}, bt[2] = {~0ull, ~0ull};
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
@@ -1750,6 +1780,11 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
     auto process = [&](int tile, const TileGeo &ti, const int32_t (&X)[kItems], const int32_t (&Y)[kItems],
                        uint32_t vm) __attribute__((always_inline)) {
         const int lo = tile * kTile, hi = min(lo + kTile, n);
+        // this tile's loads end here on every path (also for a tile that is
+        // skipped), so the loads issued for the next tile never count as
+        // pending where its registers are written again
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) asm volatile("" ::"v"(X[i]), "v"(Y[i]));
         if (cur >= 0 && (!ti.single || ti.seg != cur)) close_run();
         if (!ti.single) return;  // the multi-segment kernel takes it
         if (cur < 0) {
@@ -1814,7 +1849,7 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
             // the edge is made opaque so that the distances are recomputed
             // here, not kept alive from the classification above
             int gax = ax, gay = ay, gex = ex, gey = ey;
-            asm volatile("" : "+s"(gax), "+s"(gay), "+s"(gex), "+s"(gey));
+            asm volatile("" : "+v"(gax), "+v"(gay), "+v"(gex), "+v"(gey));
             uint64_t bd[2] = {0, 0}, bt[2] = {~0ull, ~0ull};
 #pragma unroll
             for (int i = 0; i < kItems; ++i) {
@@ -1841,33 +1876,38 @@ __device__ __forceinline__ void phase_split(const Ws2 &ws, const HullArgs &a, ch
         wb.C[0] += w & 0xffffu;
         wb.C[1] += w >> 16;
     };
-    // software pipelined: the next tile's record and points are requested
-    // before this tile is classified (no stores, so no wait orders them)
+    // software pipelined over the full tiles: the next tile's record and
+    // points are requested before this tile is classified, unconditionally
+    // (the last iteration reloads its own tile; a tile of several instances
+    // is loaded and skipped), so that the wait for this tile's points never
+    // waits for them; the input's ragged last tile comes after the loop
+    const int tfe = max(tb, min(te, n / kTile));
+    constexpr uint32_t kAll = (1u << kItems) - 1u;
     int32_t XA[kItems], YA[kItems], XB[kItems], YB[kItems];
-    uint32_t vmA = 0, vmB = 0;
     TileGeo tc;
     tc.single = 0;
-    if (tb < te) {
+    if (tb < tfe) {
         tc = tile_record(ws, 0, tb, ntiles);
-        if (tc.single) vmA = load_input_wave(a, tb * kTile, min(tb * kTile + kTile, n), XA, YA);
+        load_full_wave(a, tb * kTile, XA, YA);
     }
-    for (int tile = tb; tile < te; tile += 2) {
-        TileGeo tn;
-        tn.single = 0;
-        if (tile + 1 < te) {
-            tn = tile_record(ws, 0, tile + 1, ntiles);
-            if (tn.single) vmB = load_input_wave(a, (tile + 1) * kTile, min((tile + 2) * kTile, n), XB, YB);
-        }
-        process(tile, tc, XA, YA, vmA);
+    for (int tile = tb; tile < tfe; tile += 2) {
+        const int t1 = min(tile + 1, tfe - 1);
+        TileGeo tn = tile_record(ws, 0, t1, ntiles);
+        load_full_wave(a, t1 * kTile, XB, YB);
+        process(tile, tc, XA, YA, kAll);
+        if (tile + 1 >= tfe) break;
         tc = tn;
-        if (tile + 1 >= te) break;
-        tn.single = 0;
-        if (tile + 2 < te) {
-            tn = tile_record(ws, 0, tile + 2, ntiles);
-            if (tn.single) vmA = load_input_wave(a, (tile + 2) * kTile, min((tile + 3) * kTile, n), XA, YA);
-        }
-        process(tile + 1, tc, XB, YB, vmB);
+        const int t2 = min(tile + 2, tfe - 1);
+        tn = tile_record(ws, 0, t2, ntiles);
+        load_full_wave(a, t2 * kTile, XA, YA);
+        process(tile + 1, tc, XB, YB, kAll);
         tc = tn;
+    }
+    for (int tile = tfe; tile < te; ++tile) {
+        const TileGeo tl = tile_record(ws, 0, tile, ntiles);
+        int32_t X[kItems], Y[kItems];
+        const uint32_t vm = tl.single ? load_input_wave(a, tile * kTile, min(tile * kTile + kTile, n), X, Y) : 0u;
+        process(tile, tl, X, Y, vm);
     }
     if (cur >= 0) close_run();
     // survivors of the split (counted, not written) per child
@@ -2154,7 +2194,7 @@ __device__ __forceinline__ void phase_round_ro1(const Ws2 &ws, const HullArgs &a
                 int cy = kk == 0 ? e00y : kk == 1 ? e01y : kk == 2 ? e10y : e11y;
                 // opaque: the distances are recomputed here, not kept alive
                 // from the classification
-                asm volatile("" : "+s"(px0), "+s"(py0), "+s"(cx), "+s"(cy));
+                asm volatile("" : "+v"(px0), "+v"(py0), "+v"(cx), "+v"(cy));
                 uint64_t bd = 0, bt = ~0ull;
 #pragma unroll
                 for (int i = 0; i < kItems; ++i) {
