@@ -66,6 +66,13 @@ struct InitRes {
     int32_t pad[3];
 };
 
+// Totals of the scan of the new facets' counts (device -> host).
+struct ScanTot {
+    int64_t written;   // points in the new outside sets
+    int32_t nseg;      // facets with points
+    int32_t ntiles;    // apex tiles of those facets
+};
+
 struct Pool {
     int32_t *x, *y, *z, *idx;
 };
@@ -77,9 +84,18 @@ hipError_t launch_classify(int pass, const int32_t *ix, const int32_t *iy, const
                            int32_t ntiles, const FacetRec *fac, uint32_t *counts,
                            uint32_t *cursor, const int64_t *range, int mode,
                            unsigned long long *filter_ctr, hipStream_t st);
-hipError_t launch_apex(Pool pool, const SegRec *seg, int32_t nseg, int32_t ntiles,
-                       const FacetRec *fac, ApexKey *tile_keys, ApexKey *seg_keys,
-                       hipStream_t st);
+// The outside-set ranges of the nf new facets from pass 1's counts:
+// range[j] = top + (points of facets before j); the facets with points in
+// facet order as seg records; cursor[j] = 0; totals in *tot (all of its
+// fields written).  part: 3 * ceil(nf / kScanChunk) words of scratch.
+constexpr int kScanChunk = kBlock * 8;
+hipError_t launch_scan(const uint32_t *counts, int32_t nf, int64_t top, int64_t *range, SegRec *seg,
+                       uint32_t *cursor, uint32_t *part, ScanTot *tot, hipStream_t st);
+// The apex of each facet of seg[0 .. tot->nseg) over tot->ntiles tiles;
+// nseg_max and ntiles_max bound those and size the grids.
+hipError_t launch_apex(Pool pool, const SegRec *seg, int32_t nseg_max, int32_t ntiles_max,
+                       const ScanTot *tot, const FacetRec *fac, ApexKey *tile_keys,
+                       ApexKey *seg_keys, hipStream_t st);
 hipError_t launch_gather(Pool in, Pool out, const SegRec *seg, int32_t nseg, int32_t ntiles,
                          const int64_t *dst, hipStream_t st);
 size_t init_scratch_bytes(int grid);

@@ -106,7 +106,7 @@ struct HBuf {
 struct Ctx3 {
     DBuf pool[2];      // point pools: x, y, z, idx planes of pool_cap each
     int64_t pool_cap = 0;
-    DBuf fac, src, seg, counts, cursor, range, tkeys, skeys, gdst, init, filt, ilist;
+    DBuf fac, src, seg, counts, cursor, range, tkeys, skeys, gdst, init, filt, ilist, scan;
     HBuf up, down;
     std::vector<hipEvent_t> ev;
     Topo topo;                         // facet table (kept for its capacity)
@@ -131,6 +131,7 @@ void ctx3_free(qh3::Ctx3 *c3) {
     c3->init.release();
     c3->filt.release();
     c3->ilist.release();
+    c3->scan.release();
     c3->up.release();
     c3->down.release();
     for (hipEvent_t e : c3->ev) (void)hipEventDestroy(e);
@@ -238,21 +239,33 @@ qh_status Run::classify(const std::vector<SrcRec> &srcs_in, int from_input, int3
         s.tile0 = tiles;
         tiles += (s.len + kTile - 1) / kTile;
     }
+    // the new outside sets never pass the pool's end: every classified point
+    // is written at most once, after the live data
+    if (top + total > w->pool_cap) return QH_ECAPACITY;
     // staging (pinned, written only after the previous round's last wait):
-    // up = [facet records | sources | ranges | apex segments],
-    // down = [counts | apex keys]
+    // up = [facet records | sources], down = [counts | apex keys | totals]
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const int64_t nseg_max = std::min<int64_t>(nf, total);
+    const int64_t tiles_max = nseg_max + total / kTile;
+    const int32_t nchunk = (nf + kScanChunk - 1) / kScanChunk;
     const size_t fb = sizeof(FacetRec) * (size_t)nf, sb = sizeof(SrcRec) * srcs.size();
-    const size_t rb = sizeof(int64_t) * (size_t)nf, gb = sizeof(SegRec) * (size_t)nf;
-    const size_t o_src = al(fb), o_rng = o_src + al(sb), o_seg = o_rng + al(rb);
-    QH3_TRY(w->up.want(o_seg + al(gb)));
+    const size_t o_src = al(fb);
+    QH3_TRY(w->up.want(o_src + al(sb)));
     const size_t o_key = al(sizeof(uint32_t) * (size_t)nf);
-    QH3_TRY(w->down.want(o_key + sizeof(ApexKey) * (size_t)nf + 256));
+    const size_t o_tot = o_key + al(sizeof(ApexKey) * (size_t)nseg_max);
+    QH3_TRY(w->down.want(o_tot + sizeof(ScanTot) + 256));
     QH3_TRY(w->fac.want(fb));
     QH3_TRY(w->src.want(sb));
     QH3_TRY(w->counts.want(sizeof(uint32_t) * (size_t)nf));
     QH3_TRY(w->cursor.want(sizeof(uint32_t) * (size_t)nf));
-    QH3_TRY(w->range.want(rb));
+    QH3_TRY(w->range.want(sizeof(int64_t) * (size_t)nf));
+    QH3_TRY(w->seg.want(sizeof(SegRec) * (size_t)std::max<int64_t>(1, nseg_max)));
+    QH3_TRY(w->tkeys.want(sizeof(ApexKey) * (size_t)std::max<int64_t>(1, tiles_max)));
+    QH3_TRY(w->skeys.want(sizeof(ApexKey) * (size_t)std::max<int64_t>(1, nseg_max)));
+    const size_t o_stot = al(sizeof(uint32_t) * 3 * (size_t)std::max(1, nchunk));
+    QH3_TRY(w->scan.want(o_stot + sizeof(ScanTot)));
+    uint32_t *dpart = w->scan.as<uint32_t>();
+    ScanTot *dtot = reinterpret_cast<ScanTot *>(w->scan.as<char>() + o_stot);
     FacetRec *hf = w->up.as<FacetRec>();
     W->run(nf, 4096, [&](int64_t lo, int64_t hi, int) {
         for (int64_t j = lo; j < hi; ++j) hf[j] = to_rec(Tp, Tp.F[first + j]);
@@ -262,106 +275,87 @@ qh_status Run::classify(const std::vector<SrcRec> &srcs_in, int from_input, int3
     QH3_TRY(hipMemcpyAsync(w->fac.p, hf, fb, hipMemcpyHostToDevice, st));
     QH3_TRY(hipMemcpyAsync(w->src.p, hs, sb, hipMemcpyHostToDevice, st));
     QH3_TRY(hipMemsetAsync(w->counts.p, 0, sizeof(uint32_t) * (size_t)nf, st));
-    QH3_TRY(hipMemsetAsync(w->cursor.p, 0, sizeof(uint32_t) * (size_t)nf, st));
     const Pool in = pool(cur);
+    // pass 1 counts per new facet; the scan makes the ranges and the apex
+    // list on the device; pass 2 scatters; the apex step follows, and the
+    // host waits once, for the counts, the apexes and the totals
     QH3_TRY(ev_begin(0));
     QH3_TRY(launch_classify(1, x, y, z, from_input, in, in, w->src.as<SrcRec>(), (int32_t)srcs.size(),
                             tiles, w->fac.as<FacetRec>(), w->counts.as<uint32_t>(),
                             w->cursor.as<uint32_t>(), w->range.as<int64_t>(), mode,
                             w->filt.as<unsigned long long>(), st));
-    QH3_TRY(ev_end());
-    ++launches;
-    uint32_t *hc = w->down.as<uint32_t>();
-    QH3_TRY(hipMemcpyAsync(hc, w->counts.p, sizeof(uint32_t) * (size_t)nf, hipMemcpyDeviceToHost, st));
-    QH3_TRY(hipStreamSynchronize(st));
-    ++syncs;
-    pts_in += total;
-
-    // ranges of the new outside sets, after the live data, and the list of
-    // new facets with points (prefix sums over chunks, on the host threads)
-    int64_t *hr = reinterpret_cast<int64_t *>(w->up.as<char>() + o_rng);
-    constexpr int32_t kChunk = 8192;
-    const int32_t nchunk = (nf + kChunk - 1) / kChunk;
-    std::vector<int64_t> cpts((size_t)nchunk + 1, 0);
-    std::vector<int32_t> cseg((size_t)nchunk + 1, 0), ctil((size_t)nchunk + 1, 0);
-    W->run(nchunk, 1, [&](int64_t lo, int64_t hi, int) {
-        for (int64_t c = lo; c < hi; ++c) {
-            int64_t np = 0;
-            int32_t ng = 0, nt = 0;
-            for (int32_t j = (int32_t)c * kChunk; j < std::min<int32_t>(nf, (int32_t)(c + 1) * kChunk); ++j) {
-                np += hc[j];
-                if (hc[j]) {
-                    ++ng;
-                    nt += (int32_t)((hc[j] + kTile - 1) / kTile);
-                }
-            }
-            cpts[c + 1] = np;
-            cseg[c + 1] = ng;
-            ctil[c + 1] = nt;
-        }
-    });
-    for (int32_t c = 0; c < nchunk; ++c) {
-        cpts[c + 1] += cpts[c];
-        cseg[c + 1] += cseg[c];
-        ctil[c + 1] += ctil[c];
-    }
-    const int64_t written = cpts[nchunk];
-    const int32_t seg_tiles = ctil[nchunk];
-    std::vector<SegRec> segs((size_t)cseg[nchunk]);
-    W->run(nchunk, 1, [&](int64_t lo, int64_t hi, int) {
-        for (int64_t c = lo; c < hi; ++c) {
-            int64_t at = top + cpts[c];
-            int32_t q = cseg[c], tl = ctil[c];
-            for (int32_t j = (int32_t)c * kChunk; j < std::min<int32_t>(nf, (int32_t)(c + 1) * kChunk); ++j) {
-                const int32_t id = first + j;
-                Tp.len[id] = (int32_t)hc[j];
-                Tp.start[id] = at;
-                hr[j] = at;
-                if (hc[j]) {
-                    SegRec sg;
-                    sg.start = at;
-                    sg.len = (int32_t)hc[j];
-                    sg.facet = j;
-                    sg.tile0 = tl;
-                    sg.pad = 0;
-                    tl += (sg.len + kTile - 1) / kTile;
-                    segs[q++] = sg;
-                }
-                at += hc[j];
-            }
-        }
-    });
-    if (top + written > w->pool_cap) return QH_ECAPACITY;  // cannot happen after compaction
-    QH3_TRY(hipMemcpyAsync(w->range.p, hr, sizeof(int64_t) * (size_t)nf, hipMemcpyHostToDevice, st));
-    QH3_TRY(ev_begin(0));
+    QH3_TRY(launch_scan(w->counts.as<uint32_t>(), nf, top, w->range.as<int64_t>(), w->seg.as<SegRec>(),
+                        w->cursor.as<uint32_t>(), dpart, dtot, st));
     QH3_TRY(launch_classify(2, x, y, z, from_input, in, in, w->src.as<SrcRec>(), (int32_t)srcs.size(),
                             tiles, w->fac.as<FacetRec>(), w->counts.as<uint32_t>(),
                             w->cursor.as<uint32_t>(), w->range.as<int64_t>(), mode,
                             w->filt.as<unsigned long long>(), st));
     QH3_TRY(ev_end());
-    ++launches;
+    launches += 5;
+    QH3_TRY(ev_begin(1));
+    QH3_TRY(launch_apex(in, w->seg.as<SegRec>(), (int32_t)nseg_max, (int32_t)tiles_max, dtot,
+                        w->fac.as<FacetRec>(), w->tkeys.as<ApexKey>(), w->skeys.as<ApexKey>(), st));
+    QH3_TRY(ev_end());
+    if (nseg_max > 0) launches += 2;
+    uint32_t *hc = w->down.as<uint32_t>();
+    ApexKey *hk = reinterpret_cast<ApexKey *>(w->down.as<char>() + o_key);
+    ScanTot *htot = reinterpret_cast<ScanTot *>(w->down.as<char>() + o_tot);
+    QH3_TRY(hipMemcpyAsync(hc, w->counts.p, sizeof(uint32_t) * (size_t)nf, hipMemcpyDeviceToHost, st));
+    if (nseg_max > 0)
+        QH3_TRY(hipMemcpyAsync(hk, w->skeys.p, sizeof(ApexKey) * (size_t)nseg_max, hipMemcpyDeviceToHost, st));
+    QH3_TRY(hipMemcpyAsync(htot, dtot, sizeof(ScanTot), hipMemcpyDeviceToHost, st));
+    QH3_TRY(hipStreamSynchronize(st));
+    ++syncs;
+    pts_in += total;
+
+    // the host's copy of the facet table: each new facet's range (the same
+    // prefix sums, over chunks on the host threads) and the facets with
+    // points in facet order, as the device listed them
+    constexpr int32_t kChunk = 8192;
+    const int32_t nhc = (nf + kChunk - 1) / kChunk;
+    std::vector<int64_t> cpts((size_t)nhc + 1, 0);
+    std::vector<int32_t> cseg((size_t)nhc + 1, 0);
+    W->run(nhc, 1, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t c = lo; c < hi; ++c) {
+            int64_t np = 0;
+            int32_t ng = 0;
+            for (int32_t j = (int32_t)c * kChunk; j < std::min<int32_t>(nf, (int32_t)(c + 1) * kChunk); ++j) {
+                np += hc[j];
+                ng += hc[j] ? 1 : 0;
+            }
+            cpts[c + 1] = np;
+            cseg[c + 1] = ng;
+        }
+    });
+    for (int32_t c = 0; c < nhc; ++c) {
+        cpts[c + 1] += cpts[c];
+        cseg[c + 1] += cseg[c];
+    }
+    const int64_t written = cpts[nhc];
+    const int32_t ns = cseg[nhc];
+    // (with no new facet the scan did not run and wrote no totals)
+    const ScanTot dt = nf > 0 ? *htot : ScanTot{0, 0, 0};
+    if (written != dt.written || ns != dt.nseg || written > total) return QH_EDEVICE;
+    std::vector<int32_t> segf((size_t)ns);
+    W->run(nhc, 1, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t c = lo; c < hi; ++c) {
+            int64_t at = top + cpts[c];
+            int32_t q = cseg[c];
+            for (int32_t j = (int32_t)c * kChunk; j < std::min<int32_t>(nf, (int32_t)(c + 1) * kChunk); ++j) {
+                const int32_t id = first + j;
+                Tp.len[id] = (int32_t)hc[j];
+                Tp.start[id] = at;
+                if (hc[j]) segf[q++] = j;
+                at += hc[j];
+            }
+        }
+    });
     top += written;
     pts_out += written;
+    apex_pts += written;
 
     // apex of every new facet with points
-    const int32_t ns = (int32_t)segs.size();
     if (ns) {
-        QH3_TRY(w->seg.want(sizeof(SegRec) * (size_t)ns));
-        QH3_TRY(w->tkeys.want(sizeof(ApexKey) * (size_t)seg_tiles));
-        QH3_TRY(w->skeys.want(sizeof(ApexKey) * (size_t)ns));
-        SegRec *hsg = reinterpret_cast<SegRec *>(w->up.as<char>() + o_seg);
-        std::copy(segs.begin(), segs.end(), hsg);
-        QH3_TRY(hipMemcpyAsync(w->seg.p, hsg, sizeof(SegRec) * (size_t)ns, hipMemcpyHostToDevice, st));
-        QH3_TRY(ev_begin(1));
-        QH3_TRY(launch_apex(in, w->seg.as<SegRec>(), ns, seg_tiles, w->fac.as<FacetRec>(),
-                            w->tkeys.as<ApexKey>(), w->skeys.as<ApexKey>(), st));
-        QH3_TRY(ev_end());
-        launches += 2;
-        ApexKey *hk = reinterpret_cast<ApexKey *>(w->down.as<char>() + o_key);
-        QH3_TRY(hipMemcpyAsync(hk, w->skeys.p, sizeof(ApexKey) * (size_t)ns, hipMemcpyDeviceToHost, st));
-        QH3_TRY(hipStreamSynchronize(st));
-        ++syncs;
-        apex_pts += written;
         std::atomic<int> bad{0};
         W->run(ns, 4096, [&](int64_t lo, int64_t hi, int) {
             for (int64_t s = lo; s < hi; ++s) {
@@ -370,14 +364,12 @@ qh_status Run::classify(const std::vector<SrcRec> &srcs_in, int from_input, int3
                 if (k.idx < 0 || k.idx >= n || k.d <= 0)
                     bad.store(1);
                 else
-                    Tp.set_apex(first + segs[s].facet, k.idx, k.x, k.y, k.z);
+                    Tp.set_apex(first + segf[s], k.idx, k.x, k.y, k.z);
             }
         });
         if (bad.load()) return QH_EDEVICE;
-    } else {
-        QH3_TRY(hipStreamSynchronize(st));
     }
-    for (const SegRec &sg : segs) Tp.active.push_back(first + sg.facet);
+    for (int32_t j : segf) Tp.active.push_back(first + j);
     return QH_OK;
 }
 

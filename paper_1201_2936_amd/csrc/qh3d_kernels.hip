@@ -629,10 +629,10 @@ __device__ __forceinline__ void wave_best(ApexKey &k) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k3_apex_tiles(Pool pool, const SegRec *seg, int32_t nseg,
-                                                        int32_t ntiles, const FacetRec *fac,
-                                                        ApexKey *tile_keys) {
+__global__ __launch_bounds__(kBlock) void k3_apex_tiles(Pool pool, const SegRec *seg, const ScanTot *tot,
+                                                        const FacetRec *fac, ApexKey *tile_keys) {
     __shared__ ApexKey lds[kBlock / kWave];
+    const int32_t nseg = tot->nseg, ntiles = tot->ntiles;
     for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int32_t s = find_range(seg, nseg, t);
         const SegRec sg = seg[s];
@@ -671,11 +671,11 @@ __global__ __launch_bounds__(kBlock) void k3_apex_tiles(Pool pool, const SegRec 
 }
 
 // one wave per facet: the best of its tiles
-__global__ __launch_bounds__(kBlock) void k3_apex_merge(const SegRec *seg, int32_t nseg,
+__global__ __launch_bounds__(kBlock) void k3_apex_merge(const SegRec *seg, const ScanTot *tot,
                                                         const ApexKey *tile_keys,
                                                         ApexKey *seg_keys) {
     const int32_t s = (int32_t)((blockIdx.x * kBlock + threadIdx.x) / kWave);
-    if (s >= nseg) return;
+    if (s >= tot->nseg) return;
     const SegRec sg = seg[s];
     const int32_t nt = (sg.len + kTile - 1) / kTile;
     ApexKey best = akey_empty();
@@ -684,16 +684,117 @@ __global__ __launch_bounds__(kBlock) void k3_apex_merge(const SegRec *seg, int32
     if (lane_id() == 0) seg_keys[s] = best;
 }
 
-hipError_t launch_apex(Pool pool, const SegRec *seg, int32_t nseg, int32_t ntiles,
-                       const FacetRec *fac, ApexKey *tile_keys, ApexKey *seg_keys,
-                       hipStream_t st) {
-    if (nseg <= 0) return hipSuccess;
-    const int grid = ntiles < 65536 ? ntiles : 65536;
-    hipLaunchKernelGGL(k3_apex_tiles, dim3(grid), dim3(kBlock), 0, st, pool, seg, nseg, ntiles, fac,
-                       tile_keys);
-    const int gm = (int)(((int64_t)nseg * kWave + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k3_apex_merge, dim3(gm), dim3(kBlock), 0, st, seg, nseg, tile_keys,
-                       seg_keys);
+hipError_t launch_apex(Pool pool, const SegRec *seg, int32_t nseg_max, int32_t ntiles_max,
+                       const ScanTot *tot, const FacetRec *fac, ApexKey *tile_keys,
+                       ApexKey *seg_keys, hipStream_t st) {
+    if (nseg_max <= 0 || ntiles_max <= 0) return hipSuccess;
+    const int grid = ntiles_max < 65536 ? ntiles_max : 65536;
+    hipLaunchKernelGGL(k3_apex_tiles, dim3(grid), dim3(kBlock), 0, st, pool, seg, tot, fac, tile_keys);
+    const int gm = (int)(((int64_t)nseg_max * kWave + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k3_apex_merge, dim3(gm), dim3(kBlock), 0, st, seg, tot, tile_keys, seg_keys);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// outside-set ranges of the new facets: an exclusive scan of pass 1's counts
+// ---------------------------------------------------------------------------
+// The compact step of the flagPermute (Sections 4.1-4.2): facet j's points go
+// to [top + P_j, top + P_j + c_j), P_j the count of the facets before it, and
+// the facets with points are listed in facet order for the apex step, each
+// with the first of its tiles.  Three launches and no host wait: per-chunk
+// sums, their scan in one block, each chunk's own scan.  A thread owns eight
+// consecutive facets of a chunk.
+__device__ __forceinline__ void scan_vals(const uint32_t *counts, int32_t nf, int32_t j0, uint32_t (&c)[8],
+                                          uint32_t (&sum)[3]) {
+    sum[0] = sum[1] = sum[2] = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        c[i] = j0 + i < nf ? counts[j0 + i] : 0u;
+        sum[0] += c[i];
+        sum[1] += c[i] ? 1u : 0u;
+        sum[2] += (c[i] + kTile - 1) / kTile;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k3_scan_part(const uint32_t *counts, int32_t nf, uint32_t *part) {
+    __shared__ uint32_t scratch[3 * (kBlock / kWave)];
+    uint32_t c[8], v[3], tot[3];
+    scan_vals(counts, nf, blockIdx.x * kScanChunk + threadIdx.x * 8, c, v);
+    qh::block_excl_scan<kBlock, 3>(v, tot, scratch);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x + 0] = tot[0];
+        part[3 * blockIdx.x + 1] = tot[1];
+        part[3 * blockIdx.x + 2] = tot[2];
+    }
+}
+
+// one block: the chunk sums become exclusive prefixes (each thread a run of
+// consecutive chunks)
+__global__ __launch_bounds__(kBlock) void k3_scan_top(uint32_t *part, int32_t nchunk, ScanTot *out) {
+    __shared__ uint32_t scratch[3 * (kBlock / kWave)];
+    const int32_t per = (nchunk + kBlock - 1) / kBlock;
+    const int32_t c0 = min(nchunk, (int32_t)threadIdx.x * per), c1 = min(nchunk, c0 + per);
+    uint32_t v[3] = {0, 0, 0}, tot[3];
+    for (int32_t c = c0; c < c1; ++c) {
+        v[0] += part[3 * c + 0];
+        v[1] += part[3 * c + 1];
+        v[2] += part[3 * c + 2];
+    }
+    qh::block_excl_scan<kBlock, 3>(v, tot, scratch);
+    for (int32_t c = c0; c < c1; ++c) {
+        const uint32_t a0 = part[3 * c + 0], a1 = part[3 * c + 1], a2 = part[3 * c + 2];
+        part[3 * c + 0] = v[0];
+        part[3 * c + 1] = v[1];
+        part[3 * c + 2] = v[2];
+        v[0] += a0;
+        v[1] += a1;
+        v[2] += a2;
+    }
+    if (threadIdx.x == 0) {
+        out->written = (int64_t)tot[0];
+        out->nseg = (int32_t)tot[1];
+        out->ntiles = (int32_t)tot[2];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k3_scan_apply(const uint32_t *counts, int32_t nf, int64_t top,
+                                                        const uint32_t *part, int64_t *range, SegRec *seg,
+                                                        uint32_t *cursor) {
+    __shared__ uint32_t scratch[3 * (kBlock / kWave)];
+    const int32_t j0 = blockIdx.x * kScanChunk + threadIdx.x * 8;
+    uint32_t c[8], v[3], tot[3];
+    scan_vals(counts, nf, j0, c, v);
+    qh::block_excl_scan<kBlock, 3>(v, tot, scratch);
+    int64_t at = top + (int64_t)part[3 * blockIdx.x + 0] + v[0];
+    int32_t q = (int32_t)(part[3 * blockIdx.x + 1] + v[1]);
+    int32_t tl = (int32_t)(part[3 * blockIdx.x + 2] + v[2]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if (j0 + i >= nf) break;
+        range[j0 + i] = at;
+        cursor[j0 + i] = 0;  // pass 2's per-facet write positions start at 0
+        if (c[i]) {
+            SegRec sg;
+            sg.start = at;
+            sg.len = (int32_t)c[i];
+            sg.facet = j0 + i;
+            sg.tile0 = tl;
+            sg.pad = 0;
+            seg[q++] = sg;
+            tl += (int32_t)((c[i] + kTile - 1) / kTile);
+        }
+        at += c[i];
+    }
+}
+
+hipError_t launch_scan(const uint32_t *counts, int32_t nf, int64_t top, int64_t *range, SegRec *seg,
+                       uint32_t *cursor, uint32_t *part, ScanTot *tot, hipStream_t st) {
+    const int32_t nchunk = (nf + kScanChunk - 1) / kScanChunk;
+    if (nchunk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k3_scan_part, dim3(nchunk), dim3(kBlock), 0, st, counts, nf, part);
+    hipLaunchKernelGGL(k3_scan_top, dim3(1), dim3(kBlock), 0, st, part, nchunk, tot);
+    hipLaunchKernelGGL(k3_scan_apply, dim3(nchunk), dim3(kBlock), 0, st, counts, nf, top, part, range, seg,
+                       cursor);
     return hipGetLastError();
 }
 

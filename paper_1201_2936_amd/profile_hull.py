@@ -187,7 +187,7 @@ def main():
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="square_16m",
-                    help="a single-hull workload, or batched_disks (one batched call per step)")
+                    help="a single-hull workload (2D or 3D), or batched_disks (one batched call per step)")
     ap.add_argument("--mode", type=int, default=1, help="0 exact int64, 1 FP32 filter")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--copy-mb", type=int, default=0, help="also run one device copy of this size")
@@ -214,15 +214,18 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(f"copy of {args.copy_mb} MiB done", flush=True)
+    dims = pts.shape[0]
     for i in range(args.steps):
-        if off is None:
+        if dims == 3:
+            _, idx, st = qh.qh_hull3d(pts, mode=args.mode, ctx=ctx)
+        elif off is None:
             idx, st = qh.qh_hull2d(pts, mode=args.mode, ctx=ctx)
         else:
             idx, _, st = qh.qh_hull2d_batched(pts, off, mode=args.mode, ctx=ctx)
         torch.cuda.synchronize()
         print(f"hull {i}: h={idx.numel()} rounds={st['rounds']} "
-              f"round_kernel_bytes={st['round_kernel_bytes']} launches={st['round_launches']}",
-              flush=True)
+              f"round_kernel_bytes={st['round_kernel_bytes']} launches={st['round_launches']} "
+              f"host_syncs={st['host_syncs']}", flush=True)
     ctx.close()
 
 
