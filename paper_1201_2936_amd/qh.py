@@ -6,8 +6,10 @@ library is missing this module raises: there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqh.so")
@@ -139,21 +141,38 @@ def version() -> str:
     return load().qh_version().decode()
 
 
+# Contexts still open when the interpreter exits are closed by an exit hook,
+# while the HIP runtime is certainly alive, not by their finalizers during
+# interpreter teardown.
+_open_contexts = weakref.WeakSet()
+
+
+def _close_open_contexts():
+    for c in list(_open_contexts):
+        c.close()
+
+
+atexit.register(_close_open_contexts)
+
+
 class Context:
     """A workspace context (device memory reused across calls)."""
 
     def __init__(self):
+        self.ptr = None
         lib = load()
         p = ctypes.c_void_p()
         st = lib.qh_ctx_create(ctypes.byref(p))
         if st != QH_OK:
             raise QhError(st, "qh_ctx_create")
         self.ptr = p
+        _open_contexts.add(self)
 
     def close(self):
         if self.ptr is not None and self.ptr.value:
             load().qh_ctx_destroy(self.ptr)
         self.ptr = None
+        _open_contexts.discard(self)
 
     def __del__(self):
         try:
