@@ -99,6 +99,32 @@ def test_grid_duplicates_collinear(qhm, ctx, mode, seed):
         assert got.tolist() == oracle.hull2d(pts).tolist()
 
 
+def _range_edge_points(seed, C, n):
+    """Snapped points of the circle of radius C (many hull vertices, nearly
+    collinear triples) and points of its disk, with the four points of the
+    axes at distance C; with C = 2^22 - 1 the differences reach 2^23 - 2,
+    the end of the 24-bit product range."""
+    rng = np.random.default_rng(seed)
+    P = [workloads.circle(rng, n // 2, C).astype(np.int64),
+         workloads.disk(rng, n - n // 2 - 4, C).astype(np.int64),
+         np.array([[-C, C, 0, 0], [0, 0, -C, C]], np.int64)]
+    pts = np.concatenate(P, axis=1)
+    pts = pts[:, rng.permutation(pts.shape[1])]
+    return np.ascontiguousarray(pts.astype(np.int32))
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("C", [(1 << 22) - 1, 1 << 22, (1 << 30) - 1])
+def test_coordinate_range_edges(qhm, ctx, mode, C):
+    # |c| < 2^22 takes the 24-bit product path of the exact form, larger
+    # coordinates the 64-bit one; both must give the oracle's output
+    for seed in range(3):
+        pts = _range_edge_points(seed, C, 60000 + 1001 * seed)
+        _say(f"range edges C={C} seed={seed} n={pts.shape[1]} mode={mode}")
+        got, _ = _gpu_hull(qhm, ctx, pts, mode)
+        assert got.tolist() == oracle.hull2d(pts).tolist()
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_many_segments(qhm, ctx, mode):
     # every point on a parabola is a vertex: segments shrink to single points
