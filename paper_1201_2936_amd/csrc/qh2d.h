@@ -99,12 +99,14 @@ struct HullArgs {
     int32_t fin_segs;  // ... and there are at most this many segments
     int32_t grid_split;  // blocks of the split and of the round after it (0: the
     int32_t grid_ro1;    // round kernel's grid)
+    int32_t fin_from;    // first round whose finishing kernel is launched (earlier
+                         // rounds never finish: their segments go on as rounds)
 };
 
 hipError_t launch_setup(const Ws2 &ws, const HullArgs &a, int grid, hipStream_t st);
 hipError_t launch_extremes(const Ws2 &ws, const HullArgs &a, int grid, hipStream_t st);
 hipError_t launch_round(const Ws2 &ws, const HullArgs &a, int mode, int32_t r, int grid,
-                        int grid_multi, hipStream_t st);
+                        int grid_multi, int grid_fin, hipStream_t st);
 hipError_t launch_segments(const Ws2 &ws, const HullArgs &a, int32_t r, int grid, hipStream_t st);
 hipError_t launch_output(const Ws2 &ws, const HullArgs &a, int32_t H, hipStream_t st);
 // resident blocks on the whole device of the split, the round after it and

@@ -1039,7 +1039,7 @@ __device__ __forceinline__ int64_t child_d(int32_t x, int32_t y, uint32_t st, co
 // alike by every kernel of the round.  Never in round 1, whose segments are
 // the split's children, kept as input ranges rather than as points.
 __device__ __forceinline__ bool fin_mode(const Control *ctl, int r, const HullArgs &a) {
-    if (r == 1) return false;
+    if (r == 1 || r < a.fin_from) return false;
     const int p = r & 1;
     const RoundState &rs = ctl->rs[p];
     const int S = rs.s[0] + rs.s[1];
@@ -3490,20 +3490,25 @@ void k_round_ro1(Ws2 ws, HullArgs a) {
     phase_round_ro1<MODE>(ws, a, reinterpret_cast<char *>(&sm));
 }
 
-union MultiSmem {
-    RoundSmem round;
-    FinSmem fin;
-};
-
+// The multi-segment kernel needs about 37 KB of LDS, the finishing pass
+// about 73 KB; in one kernel the larger size would hold the multi-segment
+// kernel to two workgroups per CU in every round.  So the finishing pass is
+// a kernel of its own, launched from round fin_from on (the round the
+// context's last call finished in; 0 on a first call) and leaving at once
+// unless the round finishes; rounds before fin_from do not finish.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_round_multi(Ws2 ws, HullArgs a, int32_t r) {
-    __shared__ MultiSmem sm;
+    __shared__ RoundSmem sm;
     if (ws.ctl->setup_error) return;
-    if (fin_mode(ws.ctl, r, a)) {
-        phase_finish(ws, a, r, &sm.fin);
-        return;
-    }
-    phase_round_multi<MODE>(ws, a, r, reinterpret_cast<char *>(&sm.round));
+    if (fin_mode(ws.ctl, r, a)) return;  // the finishing kernel takes the round
+    phase_round_multi<MODE>(ws, a, r, reinterpret_cast<char *>(&sm));
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish(Ws2 ws, HullArgs a, int32_t r) {
+    __shared__ FinSmem sm;
+    if (ws.ctl->setup_error) return;
+    if (!fin_mode(ws.ctl, r, a)) return;
+    phase_finish(ws, a, r, &sm);
 }
 
 __global__ __launch_bounds__(kSegBlock) void k_segments(Ws2 ws, HullArgs a, int32_t r) {
@@ -3527,7 +3532,7 @@ hipError_t launch_extremes(const Ws2 &ws, const HullArgs &a, int grid, hipStream
 }
 
 hipError_t launch_round(const Ws2 &ws, const HullArgs &a, int mode, int32_t r, int grid,
-                        int grid_multi, hipStream_t st) {
+                        int grid_multi, int grid_fin, hipStream_t st) {
     // round 0: the read-only split; round 1: one pass over the input for both
     // of the split's children; later rounds: the survivors through the pieces
     const int gs = a.grid_split > 0 ? a.grid_split : grid, g1 = a.grid_ro1 > 0 ? a.grid_ro1 : grid;
@@ -3542,6 +3547,8 @@ hipError_t launch_round(const Ws2 &ws, const HullArgs &a, int mode, int32_t r, i
         else hipLaunchKernelGGL(k_round<1>, dim3(grid), dim3(kBlock), 0, st, ws, a, r);
         hipLaunchKernelGGL(k_round_multi<1>, dim3(grid_multi), dim3(kBlock), 0, st, ws, a, r);
     }
+    if (a.fin_cap > 0 && r >= a.fin_from)
+        hipLaunchKernelGGL(k_finish, dim3(std::max(1, grid_fin)), dim3(kBlock), 0, st, ws, a, r);
     return hipGetLastError();
 }
 

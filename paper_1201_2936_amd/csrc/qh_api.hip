@@ -263,7 +263,13 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
     args.vec_ok = ((uintptr_t)pts & 3u) == 0 ? 1 : 0;
     args.fin_cap = (o && (o->flags & QH_FLAG_NO_FINISH)) ? 0 : kFinCap;
     args.fin_segs = cfg.fin_segs;
+    // a call of the same shape as the last one starts the finishing kernel
+    // where that call finished; any other call from round 0
+    args.fin_from = (c->fin_hint_n == n && c->fin_hint_k == k && c->fin_hint_mode == mode) ? c->fin_hint : 0;
     const int grid = cfg.grid;
+    // the finishing kernel: at most its resident count of workgroups (two per
+    // CU), each finishing segments one after the other
+    const int grid_fin = std::max(1, std::min(cfg.fin_segs, 2 * c->cus));
     // the split and the round after it at their own residency, scaled like
     // the round kernel's grid
     args.grid_split = (int32_t)std::max<int64_t>(1, (int64_t)c->grid_pre[mode][0] * grid / std::max(1, c->grid[mode]));
@@ -295,7 +301,7 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
             }
             for (int rr = r0; rr < r0 + len; ++rr) {
                 if (!ok(tm.before(st, rr == 0 ? Timing::kSplit : Timing::kRound)) ||
-                    !ok(launch_round(ws, args, mode, rr, grid, cfg.grid_multi, st)) || !ok(tm.after(st)))
+                    !ok(launch_round(ws, args, mode, rr, grid, cfg.grid_multi, grid_fin, st)) || !ok(tm.after(st)))
                     return e;
                 if (!ok(tm.before(st, Timing::kSegments)) || !ok(launch_segments(ws, args, rr, grid_seg, st)) ||
                     !ok(tm.after(st)))
@@ -378,6 +384,10 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
         const Control &hc = *c->ctl_host;
         const int need = hc.fin_round >= 0 ? hc.fin_round + 1 : (int)hc.rounds_with_work;
         c->hint_rounds = std::max(1, std::min(need, 64));
+        c->fin_hint = hc.fin_round >= 0 ? hc.fin_round : 0;
+        c->fin_hint_n = n;
+        c->fin_hint_k = k;
+        c->fin_hint_mode = mode;
     }
     QH_TRY(tm.before(st, Timing::kOutput));
     QH_TRY(launch_output(c->ws, args, H, st));
@@ -498,7 +508,7 @@ qh_status run2d_tuned(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *o
     const int mode = o ? (int)o->mode : 0;
     if (mode != QH_EXACT_INT64 && mode != QH_FP32_FILTER) return QH_EINVAL;
     if (o && (o->flags & QH_FLAG_GRAPH) && !o->stream) return QH_EINVAL;
-    const QhLaunch dflt = {c->grid[mode], 2 * c->cus, 2 * (2 * c->cus)};
+    const QhLaunch dflt = {c->grid[mode], 4 * c->cus, 2 * (2 * c->cus)};
     if (!o || !(o->flags & QH_FLAG_AUTOTUNE))
         return run2d(c, pts, n, offsets, k, hull_idx, hull_offsets, h_total, single_off, o, dflt, 0);
     const uint64_t key = size_class(mode, n, k);
@@ -519,7 +529,7 @@ qh_status run2d_tuned(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *o
     for (int gm = 1; gm <= 2; ++gm)
         for (int mm = 2; mm <= 4; mm += 2)
             for (int fp = 1; fp <= 4; fp *= 2) {
-                const QhLaunch cand = {c->grid[mode] * gm, mm * c->cus, fp * mm * c->cus};
+                const QhLaunch cand = {c->grid[mode] * gm, mm * c->cus, fp * 2 * c->cus};
                 for (int rep = 0; rep < 2; ++rep) {
                     const auto t0 = std::chrono::steady_clock::now();
                     qh_status s = run2d(c, pts, n, offsets, k, hull_idx, hull_offsets, h_total, single_off,

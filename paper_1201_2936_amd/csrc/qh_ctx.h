@@ -53,6 +53,10 @@ struct qh_ctx {
     int grid_pre[2][2] = {{0, 0}, {0, 0}};  // ... of the split and of the round after it
     int grid_ext = 0;                 // resident blocks of the extremes kernel
     int hint_rounds = 0;              // rounds the last 2D call needed (first batch size)
+    int fin_hint = 0;                 // the round it finished in (0: none or unknown),
+    int64_t fin_hint_n = -1;          // ... for this point count,
+    int32_t fin_hint_k = -1;          // ... instance count
+    int fin_hint_mode = -1;           // ... and arithmetic
     qh3::Ctx3 *c3 = nullptr;          // 3D workspace, made on the first 3D call
     std::vector<unsigned char> gkey;  // launch arguments of the cached graphs
     std::vector<QhGraph> graphs;

@@ -196,6 +196,24 @@ def test_finish_round_reported(qhm, ctx, mode):
             assert st["finish_round"] >= 1
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_finish_hint_same_shape(qhm, ctx, mode):
+    """A call of the same shape as the context's last one launches the
+    finishing kernel only from the round that call finished in; inputs that
+    could finish earlier, later or never must still give the oracle's hull."""
+    n = 40000
+    rng = workloads.rng_for(77)
+    sets = [workloads.disk(rng, n, 1 << 20),
+            workloads.circle(rng, n, 1 << 20),
+            workloads.disk(rng, n, 1 << 20),
+            workloads.small_collinear(3, n, 400),
+            workloads.disk(rng, n, 1 << 20)]
+    for i, pts in enumerate(sets):
+        _say(f"finish hint call {i} n={n} mode={mode}")
+        got, st = _gpu_hull(qhm, ctx, np.ascontiguousarray(pts), mode)
+        assert got.tolist() == oracle.hull2d(pts).tolist()
+
+
 def test_deterministic_and_no_ctx(qhm):
     pts = workloads.disk(workloads.rng_for(13), 50000, 1 << 20)
     t = torch.from_numpy(pts).to("cuda")
