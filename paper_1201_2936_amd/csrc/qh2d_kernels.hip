@@ -3496,8 +3496,10 @@ void k_round_ro1(Ws2 ws, HullArgs a) {
 // a kernel of its own, launched from round fin_from on (the round the
 // context's last call finished in; 0 on a first call) and leaving at once
 // unless the round finishes; rounds before fin_from do not finish.
+// (the filter form held to 128 registers: four waves per SIMD, as the exact)
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_round_multi(Ws2 ws, HullArgs a, int32_t r) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 1 : 4)))
+void k_round_multi(Ws2 ws, HullArgs a, int32_t r) {
     __shared__ RoundSmem sm;
     if (ws.ctl->setup_error) return;
     if (fin_mode(ws.ctl, r, a)) return;  // the finishing kernel takes the round
