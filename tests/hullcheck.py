@@ -96,6 +96,20 @@ def monotone_chain(pts) -> list:
     return [low[p] for p in chain]
 
 
+def _lowest_index_per_point(pts):
+    """For every point, the lowest index carrying its coordinates."""
+    x = pts[0].astype(np.int64)
+    y = pts[1].astype(np.int64)
+    n = len(x)
+    order = np.lexsort((np.arange(n), y, x))
+    xs, ys = x[order], y[order]
+    start = np.ones(n, bool)
+    start[1:] = (xs[1:] != xs[:-1]) | (ys[1:] != ys[:-1])
+    low = np.empty(n, np.int64)
+    low[order] = order[start][np.cumsum(start) - 1]
+    return low
+
+
 def _orient(ax, ay, bx, by, px, py):
     """(b - a) x (p - a): > 0 when p is strictly left of a -> b."""
     return (bx - ax) * (py - ay) - (by - ay) * (px - ax)
@@ -117,9 +131,7 @@ def check_hull2d(pts, idx) -> None:
     x, y = pts[0], pts[1]
     vx, vy = x[idx], y[idx]
     # lowest index among exact duplicates
-    low = _lowest_index_of_coords(pts)
-    for i in range(h):
-        assert low[(int(vx[i]), int(vy[i]))] == int(idx[i]), "not the lowest duplicate index"
+    assert (_lowest_index_per_point(pts)[idx] == idx).all(), "not the lowest duplicate index"
     # start at the lexicographic minimum
     lex = np.lexsort((y, x))
     first = lex[0]

@@ -17,8 +17,6 @@ Nothing here calls the oracle or the library.
 """
 from __future__ import annotations
 
-from collections import defaultdict
-
 import numpy as np
 
 from hullcheck import monotone_chain
@@ -63,75 +61,67 @@ def brute_vertices3d(pts):
     return sorted(verts)
 
 
-def _planes_equal(n1, n2):
-    c = np.cross(n1, n2)
-    return not c.any() and int(np.dot(n1, n2)) > 0
-
-
 def check_hull3d(pts, facets, verts, sample=None):
     """Assert the invariants above.  ``sample``: check only these point
-    indices against every facet (None = all points)."""
+    indices against every facet (None = all points).  Array operations
+    throughout: facet planes are compared by their primitive normals (the
+    normal divided by the gcd of its components), which are equal exactly
+    when the planes have the same outward direction."""
     P = np.asarray(pts, np.int64)
     F = np.asarray(facets, np.int64).reshape(-1, 3)
     V = np.asarray(verts, np.int64)
+    n = P.shape[1]
     assert len(V) >= 4 and len(F) == 2 * len(V) - 4
     assert (np.diff(V) > 0).all(), "vertices not ascending"
-    assert set(F.ravel().tolist()) == set(V.tolist()), "facet corners != vertex set"
+    assert np.array_equal(np.unique(F.ravel()), V), "facet corners != vertex set"
     A = P[:, F[:, 0]].T
     B = P[:, F[:, 1]].T
     C = P[:, F[:, 2]].T
     N = np.cross(B - A, C - A)
     assert N.any(axis=1).all(), "zero-area facet"
     off = np.einsum("ij,ij->i", N, A)
-    idx = np.arange(P.shape[1]) if sample is None else np.asarray(sample)
+    idx = np.arange(n) if sample is None else np.asarray(sample)
     for s in range(0, len(idx), 4096):
         q = P[:, idx[s:s + 4096]]
         d = N @ q - off[:, None]
         assert (d <= 0).all(), "a point lies outside a facet"
-    # closed oriented 2-manifold
-    edges = {}
-    for f, (a, b, c) in enumerate(F.tolist()):
-        for u, w in ((a, b), (b, c), (c, a)):
-            assert (u, w) not in edges, "directed edge used twice"
-            edges[(u, w)] = f
-    for (u, w) in edges:
-        assert (w, u) in edges, "edge without its reverse"
-    E = len(edges) // 2
+    # closed oriented 2-manifold: each directed edge once, with its reverse
+    u = F.ravel()
+    w = F[:, [1, 2, 0]].ravel()
+    key = np.sort(u * n + w)
+    assert (np.diff(key) > 0).all(), "directed edge used twice"
+    rev = w * n + u
+    pos = np.searchsorted(key, rev)
+    assert (pos < len(key)).all() and (key[np.minimum(pos, len(key) - 1)] == rev).all(), \
+        "edge without its reverse"
+    E = len(key) // 2
     assert len(V) - E + len(F) == 2, "Euler characteristic"
+    # the facet planes by primitive outward normal
+    g = np.gcd.reduce(np.abs(N), axis=1)
+    prim = N // g[:, None]
+    _, pid = np.unique(prim, axis=0, return_inverse=True)
+    pid = pid.ravel()
     # every vertex is extreme: >= 3 distinct planes around it
-    inc = defaultdict(list)
-    for f, tri in enumerate(F.tolist()):
-        for v in tri:
-            inc[v].append(f)
-    for v, fs in inc.items():
-        reps = []
-        for f in fs:
-            if not any(_planes_equal(N[f], N[r]) for r in reps):
-                reps.append(f)
-            if len(reps) >= 3:
-                break
-        assert len(reps) >= 3, f"vertex {v} is not extreme"
+    pairs = np.unique(u * (pid.max() + 1) + np.repeat(pid, 3))
+    verts_of_pairs = pairs // (pid.max() + 1)
+    vv, cnt = np.unique(verts_of_pairs, return_counts=True)
+    assert np.array_equal(vv, V) and (cnt >= 3).all(), "a vertex is not extreme"
     # lowest index among duplicates
-    low = _lowest_index3(P)
-    for v in V.tolist():
-        assert low[(int(P[0, v]), int(P[1, v]), int(P[2, v]))] == v, "not the lowest index"
-    # canonical triangulation: each face fanned from its lowest vertex
-    parent = list(range(len(F)))
-
-    def find(i):
-        while parent[i] != i:
-            parent[i] = parent[parent[i]]
-            i = parent[i]
-        return i
-
-    for (u, w), f in edges.items():
-        g = edges[(w, u)]
-        if _planes_equal(N[f], N[g]):
-            parent[find(f)] = find(g)
-    faces = defaultdict(list)
-    for f in range(len(F)):
-        faces[find(f)].append(f)
-    for fs in faces.values():
-        lowest = min(int(v) for f in fs for v in F[f])
-        assert all(int(F[f, 0]) == lowest for f in fs), "face not fanned from its lowest vertex"
-    assert [tuple(t) for t in F.tolist()] == sorted(tuple(t) for t in F.tolist()), "facets not sorted"
+    order = np.lexsort((np.arange(n), P[2], P[1], P[0]))
+    Ps = P[:, order]
+    start = np.ones(n, bool)
+    start[1:] = (Ps[:, 1:] != Ps[:, :-1]).any(axis=0)
+    grp = np.cumsum(start) - 1
+    low_of_grp = order[start]
+    lowest = np.empty(n, np.int64)
+    lowest[order] = low_of_grp[grp]
+    assert (lowest[V] == V).all(), "not the lowest index"
+    # canonical triangulation: each face (the facets of one plane) fanned from
+    # its lowest vertex
+    minv = np.full(pid.max() + 1, np.iinfo(np.int64).max)
+    np.minimum.at(minv, np.repeat(pid, 3), u)
+    assert (F[:, 0] == minv[pid]).all(), "face not fanned from its lowest vertex"
+    dF = F[1:] - F[:-1]
+    first = np.argmax(dF != 0, axis=1)
+    lead = dF[np.arange(len(dF)), first]
+    assert ((lead > 0) | (dF == 0).all(axis=1)).all(), "facets not sorted"
