@@ -219,6 +219,35 @@ struct alignas(64) Facet {
 };
 static_assert(sizeof(Facet) == 64, "a facet is one cache line");
 
+// a[i] += a[i - 1] for i = 1 .. len - 1 (an inclusive prefix sum in place),
+// in chunks on the host threads: chunk sums, their scan, then each chunk
+inline void prefix_sum(Workers &W, int32_t *a, int64_t len) {
+    const int64_t chunk = 1 << 16;
+    const int64_t nc = (len + chunk - 1) / chunk;
+    if (nc <= 1) {
+        for (int64_t i = 1; i < len; ++i) a[i] += a[i - 1];
+        return;
+    }
+    std::vector<int64_t> tot((size_t)nc, 0);
+    W.run(nc, 1, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t c = lo; c < hi; ++c) {
+            int32_t *p = a + c * chunk;
+            const int64_t m = std::min(chunk, len - c * chunk);
+            for (int64_t i = 1; i < m; ++i) p[i] += p[i - 1];
+            tot[(size_t)c] = p[m - 1];
+        }
+    });
+    for (int64_t c = 1; c < nc; ++c) tot[(size_t)c] += tot[(size_t)c - 1];
+    W.run(nc - 1, 1, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t c = lo + 1; c < hi + 1; ++c) {
+            int32_t *p = a + c * chunk;
+            const int32_t add = (int32_t)tot[(size_t)c - 1];
+            const int64_t m = std::min(chunk, len - c * chunk);
+            for (int64_t i = 0; i < m; ++i) p[i] += add;
+        }
+    });
+}
+
 enum { kTopoOk = 0, kTopoBroken = 1, kTopoNoMem = 2 };
 
 struct P3 {
@@ -552,7 +581,7 @@ struct Topo {
             for (int64_t i = lo; i < hi; ++i)
                 for (int k = 0; k < 3; ++k) __atomic_fetch_add(&deg[F[alive[i]].v[k] + 1], 1, __ATOMIC_RELAXED);
         });
-        for (int32_t i = 0; i < n; ++i) deg[i + 1] += deg[i];
+        prefix_sum(W, deg.data(), (int64_t)n + 1);
         std::vector<int32_t> inc(deg[n]);
         {
             std::vector<int32_t> fill(deg.begin(), deg.end() - 1);
@@ -579,9 +608,27 @@ struct Topo {
                 isv[v] = np >= 3;
             }
         });
-        verts.clear();
-        for (int32_t v = 0; v < n; ++v)
-            if (isv[v]) verts.push_back(v);
+        {
+            // the vertices in ascending order: per-chunk counts, then fills
+            const int64_t ch = 1 << 16, nc = ((int64_t)n + ch - 1) / ch;
+            std::vector<int32_t> vc((size_t)nc + 1, 0);
+            W.run(nc, 1, [&](int64_t lo, int64_t hi, int) {
+                for (int64_t c = lo; c < hi; ++c) {
+                    int32_t k = 0;
+                    for (int64_t v = c * ch; v < std::min<int64_t>(n, (c + 1) * ch); ++v) k += isv[v];
+                    vc[(size_t)c + 1] = k;
+                }
+            });
+            for (int64_t c = 0; c < nc; ++c) vc[(size_t)c + 1] += vc[(size_t)c];
+            verts.resize((size_t)vc[(size_t)nc]);
+            W.run(nc, 1, [&](int64_t lo, int64_t hi, int) {
+                for (int64_t c = lo; c < hi; ++c) {
+                    int32_t o = vc[(size_t)c];
+                    for (int64_t v = c * ch; v < std::min<int64_t>(n, (c + 1) * ch); ++v)
+                        if (isv[v]) verts[(size_t)o++] = (int32_t)v;
+                }
+            });
+        }
         // faces: coplanar neighbour pairs (found in parallel) are joined by
         // union-find; a facet with no coplanar neighbour is a face by itself
         std::vector<uint8_t> cop((size_t)na, 0);
@@ -717,7 +764,7 @@ struct Topo {
                 for (size_t i = 0; i < v.size(); i += 3) __atomic_fetch_add(&cnt[v[i] + 1], 1, __ATOMIC_RELAXED);
             }
         });
-        for (int32_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+        prefix_sum(W, cnt.data(), (int64_t)n + 1);
         tri.resize(3 * nt);
         {
             std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
