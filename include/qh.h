@@ -62,12 +62,15 @@ enum {
     QH_FLAG_NO_FINISH = 2u, /* 2D: run every level of the recursion as a
                                round of the round kernels.  By default, once
                                no segment holds more than QH_FINISH_CAP
-                               points and there are at most two segments per
-                               workgroup of the multi-segment kernel, one
+                               points and the round's segments are few
+                               enough (qh_stats.finish_segments), one
                                workgroup per segment completes that segment's
                                recursion in on-chip memory (the same levels
                                and the same rules as the rounds, so the same
-                               output) */
+                               output).  A call of the same point count,
+                               instance count and arithmetic as the context's
+                               previous call starts finishing no earlier than
+                               the round that call finished in */
     QH_FLAG_GRAPH = 4u,     /* 2D: replay the call's launches from HIP graphs
                                that the context captured on an earlier call
                                with the same arguments, buffers and workspace
