@@ -559,8 +559,8 @@ def main():
     ap.add_argument("--no-square", action="store_true", help="skip the 16.7M-point square leg")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the hulls of one batch "
-              "on one MI355X); --gpus must be 1", file=sys.stderr)
+        print("bench.py: measures one GPU only (every hull of the batch on one "
+              "MI355X); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     from paper_1201_2936_amd import qh
