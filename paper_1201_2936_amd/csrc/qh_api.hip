@@ -508,7 +508,7 @@ qh_status run2d_tuned(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *o
     const int mode = o ? (int)o->mode : 0;
     if (mode != QH_EXACT_INT64 && mode != QH_FP32_FILTER) return QH_EINVAL;
     if (o && (o->flags & QH_FLAG_GRAPH) && !o->stream) return QH_EINVAL;
-    const QhLaunch dflt = {c->grid[mode], 4 * c->cus, 2 * (2 * c->cus)};
+    const QhLaunch dflt = {c->grid[mode], 4 * c->cus, 16 * c->cus};
     if (!o || !(o->flags & QH_FLAG_AUTOTUNE))
         return run2d(c, pts, n, offsets, k, hull_idx, hull_offsets, h_total, single_off, o, dflt, 0);
     const uint64_t key = size_class(mode, n, k);
@@ -529,7 +529,7 @@ qh_status run2d_tuned(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *o
     for (int gm = 1; gm <= 2; ++gm)
         for (int mm = 2; mm <= 4; mm += 2)
             for (int fp = 1; fp <= 4; fp *= 2) {
-                const QhLaunch cand = {c->grid[mode] * gm, mm * c->cus, fp * 2 * c->cus};
+                const QhLaunch cand = {c->grid[mode] * gm, mm * c->cus, fp * 4 * c->cus};
                 for (int rep = 0; rep < 2; ++rep) {
                     const auto t0 = std::chrono::steady_clock::now();
                     qh_status s = run2d(c, pts, n, offsets, k, hull_idx, hull_offsets, h_total, single_off,
