@@ -67,7 +67,12 @@ enum {
                                workgroup per segment completes that segment's
                                recursion in on-chip memory (the same levels
                                and the same rules as the rounds, so the same
-                               output).  A call of the same point count,
+                               output); or, from the third round on, once no
+                               segment holds more than QH_FINISH_CAP / 2
+                               points and the round's points are few enough,
+                               each workgroup completes runs of consecutive
+                               segments of up to QH_FINISH_CAP / 2 points
+                               together.  A call of the same point count,
                                instance count and arithmetic as the context's
                                previous call starts finishing no earlier than
                                the round that call finished in */
@@ -136,7 +141,7 @@ typedef struct qh_stats {
     double host_output_ms;      /* ... of which the output (vertex test and
                                    canonical triangulation) */
     int64_t finish_round;       /* 2D: the round whose segments were finished
-                                   by one workgroup each (-1: none) */
+                                   in on-chip memory (-1: none) */
     int64_t multi_blocks;       /* 2D: blocks of a multi-segment-kernel launch */
     int64_t finish_segments;    /* 2D: most segments that a round may finish
                                    (one workgroup each, in turn) */
@@ -146,6 +151,9 @@ typedef struct qh_stats {
                                    the call (0 once the size class is tuned) */
     int64_t degenerate_instances; /* qh_hull3d_batched: instances without a hull
                                    (fewer than four affinely independent points) */
+    int64_t finish_runs;        /* 2D: 1 if the finishing round took runs of
+                                   consecutive small segments together, 0 if
+                                   one segment per workgroup (or none) */
 } qh_stats;
 
 typedef struct qh_opts {

@@ -13,6 +13,8 @@ constexpr int kPieceItems = 8;           // tile counts per thread of the piece 
 constexpr int kSegBlock = 256;           // segments per tile of the segment phase
 constexpr int kRankSmallCap = 8192;      // hull ids ranked inside one block's LDS (64 KB)
 constexpr int kFinCap = 1024;            // points of a segment one block finishes in LDS
+constexpr int kFinUnit = kFinCap / 2;     // points of a run of small segments finished together
+constexpr int kFinUnitsPerBlock = 8;      // runs per finishing block that a round may need
 constexpr int32_t kCoordMax2D = (1 << 30) - 1;
 constexpr int kMaxStamps = 256;
 
@@ -101,6 +103,9 @@ struct HullArgs {
     int32_t grid_ro1;    // round kernel's grid)
     int32_t fin_from;    // first round whose finishing kernel is launched (earlier
                          // rounds never finish: their segments go on as rounds)
+    int32_t fin_pts;     // or finish runs of segments, kFinUnit points per block at
+                         // a time, once none is larger and the round holds at most
+                         // this many points (0: off)
 };
 
 hipError_t launch_setup(const Ws2 &ws, const HullArgs &a, int grid, hipStream_t st);

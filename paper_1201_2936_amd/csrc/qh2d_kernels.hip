@@ -502,6 +502,7 @@ __device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a
         ctl->maxseg[1] = 0;
         ctl->fin_ids = 0;
         ctl->fin_round = -1;
+        ctl->fin_runs = 0;
     }
 }
 
@@ -1035,15 +1036,27 @@ __device__ __forceinline__ int64_t child_d(int32_t x, int32_t y, uint32_t st, co
 
 // Round r ends the recursion in one pass when no segment has more than
 // fin_cap points and there are at most fin_segs segments (a workgroup takes
-// one segment at a time: many small segments go faster as rounds); decided
-// alike by every kernel of the round.  Never in round 1, whose segments are
-// the split's children, kept as input ranges rather than as points.
-__device__ __forceinline__ bool fin_mode(const Control *ctl, int r, const HullArgs &a) {
-    if (r == 1 || r < a.fin_from) return false;
+// one segment at a time), or, from round 2 on, when no segment has more
+// than kFinUnit points and the round holds at most fin_pts points (a
+// workgroup takes runs of consecutive segments of up to kFinUnit points
+// together); decided alike by every kernel of the round.  Never in round 1,
+// whose segments are the split's children, kept as input ranges rather than
+// as points.
+__device__ __forceinline__ bool fin_each(const Control *ctl, int r, const HullArgs &a) {
     const int p = r & 1;
     const RoundState &rs = ctl->rs[p];
     const int S = rs.s[0] + rs.s[1];
-    return a.fin_cap > 0 && S > 0 && S <= a.fin_segs && ctl->maxseg[p] <= a.fin_cap;
+    return S <= a.fin_segs && ctl->maxseg[p] <= a.fin_cap;
+}
+
+__device__ __forceinline__ bool fin_mode(const Control *ctl, int r, const HullArgs &a) {
+    if (r == 1 || r < a.fin_from || a.fin_cap <= 0) return false;
+    const int p = r & 1;
+    const RoundState &rs = ctl->rs[p];
+    const int S = rs.s[0] + rs.s[1];
+    if (S <= 0) return false;
+    if (fin_each(ctl, r, a)) return true;
+    return r >= 2 && ctl->maxseg[p] <= kFinUnit && (int64_t)rs.n[0] + rs.n[1] <= (int64_t)a.fin_pts;
 }
 
 
@@ -2648,6 +2661,7 @@ struct FinSmem {
             uint64_t kmax[kFinCap];                     // argmax: distance, then tie key
             uint64_t kmin[kFinCap];
             uint32_t cnt[kFinCap];                      // child sizes c0 | c1 << 16
+            int32_t sin[kFinCap];                       // its instance
             int32_t vx[kFinCap + 4], vy[kFinCap + 4];   // vertices: coordinates,
             int32_t vi[kFinCap + 4], vg[kFinCap + 4];   // input index, hull id
         } w;
@@ -2656,17 +2670,28 @@ struct FinSmem {
     int32_t s_base, s_ns, s_m;
 };
 
-// one segment of round p: its points, its edge u -> v and apex f
-__device__ void finish_segment(const Ws2 &ws, const HullArgs &a, int p, int R, int s, bool init,
-                               int nt0, int nt1, int hbase, FinSmem *sm) {
+// segments s0 .. s0 + M - 1 of round p in region R (consecutive, so their
+// points are one range; M = 1 in the first split, where the points are the
+// instance's input range): their points, edges u -> v and apexes f.  The
+// levels treat the segments as the sub-segments of one
+__device__ void finish_unit(const Ws2 &ws, const HullArgs &a, int p, int R, int s0, int M, bool init,
+                            int nt0, int nt1, int hbase, FinSmem *sm) {
     Control *ctl = ws.ctl;
     const int tid = threadIdx.x;
-    const SegGeo G = ws.geo(p, R)[s];
-    const SegTop Tp = ws.top(p, R)[s];
-    const int len = G.len, start = G.start;
-    if (len < 1 || len > kFinCap) {  // the caller's bound: never
-        if (tid == 0) atomicOr(&ctl->error, kErrInternal);
+    const SegGeo G0 = ws.geo(p, R)[s0];
+    const SegGeo GL = ws.geo(p, R)[s0 + M - 1];
+    const int start = G0.start, len = GL.start + GL.len - G0.start;
+    // vertex slots: u and v of segment j at 2j and 2j + 1, then the apexes
+    // of each level in order (at most one per point)
+    if (M < 1 || M > kBlock || (init && M != 1) || len < 1 || len > kFinCap || 2 * M + len > kFinCap + 4) {
+        if (tid == 0) atomicOr(&ctl->error, kErrInternal);  // the caller's bounds: never
         return;
+    }
+    SegGeo G;
+    SegTop Tp;
+    if (tid < M) {
+        G = ws.geo(p, R)[s0 + tid];
+        Tp = ws.top(p, R)[s0 + tid];
     }
     // the points into buffer 0
     if (init) {
@@ -2722,18 +2747,30 @@ __device__ void finish_segment(const Ws2 &ws, const HullArgs &a, int p, int R, i
         }
         if (bad) atomicOr(&ctl->error, kErrInternal);
     }
-    // vertex slots: 0 = u, 1 = v, then the apexes of each level in order
-    const bool same = G.fx == G.ux && G.fy == G.uy;  // first split of a one-point instance
-    if (tid == 0) {
-        sm->w.vx[0] = G.ux; sm->w.vy[0] = G.uy; sm->w.vg[0] = Tp.uc;
-        sm->w.vx[1] = G.vx; sm->w.vy[1] = G.vy; sm->w.vg[1] = Tp.vc;
-        sm->w.vx[2] = G.fx; sm->w.vy[2] = G.fy; sm->w.vi[2] = Tp.fidx;
-        sm->w.sst[0] = 0;
-        sm->w.suv[0] = 0u | (1u << 16);
+    // first split of a one-point instance: u = f
+    const bool same = M == 1 && G0.fx == G0.ux && G0.fy == G0.uy;
+    if (tid < M) {
+        const int u = 2 * tid, v = u + 1, f = 2 * M + tid;
+        sm->w.vx[u] = G.ux; sm->w.vy[u] = G.uy; sm->w.vg[u] = Tp.uc;
+        sm->w.vx[v] = G.vx; sm->w.vy[v] = G.vy; sm->w.vg[v] = Tp.vc;
+        sm->w.vx[f] = G.fx; sm->w.vy[f] = G.fy; sm->w.vi[f] = Tp.fidx;
+        sm->w.sst[tid] = G.start - start;
+        sm->w.suv[tid] = (uint32_t)u | ((uint32_t)v << 16);
+        sm->w.sin[tid] = Tp.inst;
+        if (G.len < 1) atomicOr(&ctl->error, kErrInternal);
     }
-    for (int j = tid; j < len; j += kBlock) sm->w.sid[0][j] = 0;
     __syncthreads();
-    int b = 0, m = len, ns = 1, nv = 2;
+    // each point's segment: the last one starting at or before it
+    for (int j = tid; j < len; j += kBlock) {
+        int lo = 0, hi = M - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sm->w.sst[mid] <= j) lo = mid; else hi = mid - 1;
+        }
+        sm->w.sid[0][j] = (uint16_t)lo;
+    }
+    __syncthreads();
+    int b = 0, m = len, ns = M, nv = 2 * M;
     for (int level = 0; ns > 0; ++level) {
         const int32_t *X = b ? sm->w.px1 : sm->px0;
         const int32_t *Y = b ? sm->w.py1 : sm->py0;
@@ -2806,7 +2843,7 @@ __device__ void finish_segment(const Ws2 &ws, const HullArgs &a, int p, int R, i
                 sm->w.vg[at] = gid;
                 if (gid < ws.hcap) {
                     ws.V[gid] = sm->w.vi[at];
-                    ws.hinst[gid] = Tp.inst;
+                    ws.hinst[gid] = sm->w.sin[t];
                     ws.nxt[gid] = sm->w.vg[v];
                     ws.nxt[sm->w.vg[u]] = gid;
                 } else {
@@ -2838,12 +2875,14 @@ __device__ void finish_segment(const Ws2 &ws, const HullArgs &a, int p, int R, i
         // order (a scan over contiguous chunks of sub-segments)
         const int c0s = tid * kFinChunk, c1s = min(c0s + kFinChunk, ns);
         uint32_t cc[kFinChunk], uvs[kFinChunk];
+        int32_t ins[kFinChunk];
         uint32_t loc = 0;  // new sub-segments | their points << 16
 #pragma unroll
         for (int k = 0; k < kFinChunk; ++k) {
             const int t = c0s + k;
             cc[k] = t < c1s ? sm->w.cnt[t] : 0u;
             uvs[k] = t < c1s ? sm->w.suv[t] : 0u;
+            ins[k] = t < c1s ? sm->w.sin[t] : 0;
             const uint32_t a0 = cc[k] & 0xffffu, a1 = cc[k] >> 16;
             loc += (a0 > 0 ? 1u : 0u) + (a1 > 0 ? 1u : 0u) + ((a0 + a1) << 16);
         }
@@ -2858,8 +2897,16 @@ __device__ void finish_segment(const Ws2 &ws, const HullArgs &a, int p, int R, i
             const uint32_t u = uvs[k] & 0xffffu, v = uvs[k] >> 16, f = (uint32_t)(nv + t);
             uint32_t id0 = 0xffffu, id1 = 0xffffu;
             const uint32_t st0 = npt, st1 = npt + a0;
-            if (a0 > 0) { id0 = nid; sm->w.sst[nid] = (int)st0; sm->w.suv[nid] = u | (f << 16); ++nid; }
-            if (a1 > 0) { id1 = nid; sm->w.sst[nid] = (int)st1; sm->w.suv[nid] = f | (v << 16); ++nid; }
+            if (a0 > 0) {
+                id0 = nid;
+                sm->w.sst[nid] = (int)st0; sm->w.suv[nid] = u | (f << 16); sm->w.sin[nid] = ins[k];
+                ++nid;
+            }
+            if (a1 > 0) {
+                id1 = nid;
+                sm->w.sst[nid] = (int)st1; sm->w.suv[nid] = f | (v << 16); sm->w.sin[nid] = ins[k];
+                ++nid;
+            }
             npt += a0 + a1;
             // where each child's points go (read by the scatter below)
             sm->w.kmax[t] = (uint64_t)st0 | ((uint64_t)st1 << 32);
@@ -2903,10 +2950,45 @@ __device__ void phase_finish(const Ws2 &ws, const HullArgs &a, int r, FinSmem *s
     const int S0 = rs->s[0], S1 = rs->s[1];
     const int nt0 = (rs->n[0] + kTile - 1) / kTile, nt1 = (rs->n[1] + kTile - 1) / kTile;
     const int hbase = rs->hbase;
-    for (int g = blockIdx.x; g < S0 + S1; g += gridDim.x) {
-        const int R = g < S0 ? 0 : 1;
-        finish_segment(ws, a, p, R, R ? g - S0 : g, r == 0, nt0, nt1, hbase, sm);
-        __syncthreads();
+    if (fin_each(ctl, r, a)) {
+        for (int g = blockIdx.x; g < S0 + S1; g += gridDim.x) {
+            const int R = g < S0 ? 0 : 1;
+            finish_unit(ws, a, p, R, R ? g - S0 : g, 1, r == 0, nt0, nt1, hbase, sm);
+            __syncthreads();
+        }
+        return;
+    }
+    // many small segments: each block takes a range of the segments (in
+    // table order, region 0 then 1) and finishes them in runs: the next
+    // segments of a region (at most kBlock) that hold at most kFinUnit points
+    // together, always at least one (no segment is larger)
+    const int tid = threadIdx.x;
+    const int S = S0 + S1;
+    const int Q = (S + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int glo = min(S, (int)blockIdx.x * Q), ghi = min(S, glo + Q);
+    for (int R = 0; R < 2; ++R) {
+        const int off = R ? S0 : 0, SR = R ? S1 : S0;
+        int s = max(glo - off, 0);
+        const int se = min(ghi - off, SR);
+        while (s < se) {
+            const int st = ws.geo(p, R)[s].start;
+            const int cand = min(kBlock, se - s);
+            bool fits = false;
+            if (tid < cand) {
+                const SegGeo G = ws.geo(p, R)[s + tid];
+                fits = G.start + G.len - st <= kFinUnit;
+            }
+            // the segments are consecutive, so their ends rise: the ones that
+            // fit are a prefix
+            const int M = __syncthreads_count(fits);
+            if (M < 1) {
+                if (tid == 0) atomicOr(&ctl->error, kErrInternal);
+                return;
+            }
+            finish_unit(ws, a, p, R, s, M, false, nt0, nt1, hbase, sm);
+            __syncthreads();
+            s += M;
+        }
     }
 }
 
@@ -2976,12 +3058,13 @@ __device__ __forceinline__ void phase_segments(const Ws2 &ws, const HullArgs &a,
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
 
     if (fin_mode(ctl, r, a)) {
-        // the segments were finished by the multi-segment kernel: no next round
+        // the segments were finished by the finishing kernel: no next round
         if (blockIdx.x == 0 && tid == 0) {
             RoundState z = {};
             z.hbase = hbase + (int32_t)ctl->fin_ids;
             *rn = z;
             ctl->fin_round = r;
+            ctl->fin_runs = fin_each(ctl, r, a) ? 0 : 1;
         }
         if (blockIdx.x == 0 && tid < kAccSlots) {
             ctl->nacc[q][0][tid] = 0;

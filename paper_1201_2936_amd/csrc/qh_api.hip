@@ -270,6 +270,7 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
     // the finishing kernel: at most its resident count of workgroups (two per
     // CU), each finishing segments one after the other
     const int grid_fin = std::max(1, std::min(cfg.fin_segs, 2 * c->cus));
+    args.fin_pts = args.fin_cap > 0 ? kFinUnitsPerBlock * kFinUnit * grid_fin : 0;
     // the split and the round after it at their own residency, scaled like
     // the round kernel's grid
     args.grid_split = (int32_t)std::max<int64_t>(1, (int64_t)c->grid_pre[mode][0] * grid / std::max(1, c->grid[mode]));
@@ -431,6 +432,7 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
         stats->grid_blocks = grid;
         stats->host_syncs = syncs;
         stats->finish_round = h.fin_round;
+        stats->finish_runs = h.fin_round >= 0 ? h.fin_runs : 0;
         stats->multi_blocks = cfg.grid_multi;
         stats->finish_segments = args.fin_cap > 0 ? cfg.fin_segs : 0;
         stats->graph_launches = graph_launches;

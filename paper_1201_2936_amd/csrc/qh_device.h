@@ -225,6 +225,7 @@ struct Control {
     int32_t maxseg[2];                // largest segment of the round, by parity
     uint32_t fin_ids;                 // hull ids taken by the finishing pass
     int32_t fin_round;                // the round that finished every segment (-1: none)
+    int32_t fin_runs;                 // ... in runs of small segments (1) or one by one (0)
     int32_t H;                        // compact hull ids used
     long long h_total;                // hull vertices of all instances
     int32_t nstamps;

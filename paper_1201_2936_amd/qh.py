@@ -63,6 +63,7 @@ class QhStats(ctypes.Structure):
         ("graph_launches", ctypes.c_int64),
         ("tuned_configs", ctypes.c_int64),
         ("degenerate_instances", ctypes.c_int64),
+        ("finish_runs", ctypes.c_int64),
     ]
 
     def as_dict(self):

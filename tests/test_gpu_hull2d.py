@@ -335,6 +335,39 @@ def test_batched_many_tiny_instances(qhm, ctx, mode):
     assert got.tolist() == want.tolist()
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_batched_finish_runs(qhm, ctx, mode):
+    """Thousands of instances: the rounds soon hold tens of thousands of small
+    segments, which the finishing kernel takes in runs of consecutive
+    segments (runs that end at region and workgroup boundaries, circles whose
+    every point is a vertex, collinear and duplicate points); the second call
+    of the same shape starts finishing where the first one did."""
+    rng = np.random.default_rng(4242)
+    insts = []
+    for i in range(2500):
+        kind = i % 10
+        n = int(np.exp(rng.uniform(np.log(16), np.log(20000))))
+        if kind < 7:
+            insts.append(workloads.disk(rng, n, 1 << 20))
+        elif kind == 7:
+            insts.append(workloads.circle(rng, min(n, 3000), 1 << 20))
+        elif kind == 8:
+            insts.append(workloads.small_collinear(int(rng.integers(1 << 30)), min(n, 500)))
+        else:
+            insts.append(workloads.small_grid(int(rng.integers(1 << 30)), min(n, 4000), 9))
+    pts, offsets = _concat(insts)
+    _say(f"batched finish runs k=2500 N={offsets[-1]} mode={mode}")
+    want, want_off = oracle.hull2d_batched(pts, offsets)
+    for call in range(2):
+        got, got_off, st = _gpu_batched(qhm, ctx, pts, offsets, mode)
+        assert got_off.tolist() == want_off.tolist()
+        assert got.tolist() == want.tolist()
+        if mode & 2:
+            assert st["finish_round"] == -1 and st["finish_runs"] == 0
+        else:
+            assert st["finish_round"] >= 2 and st["finish_runs"] == 1
+
+
 def _polygon_instance(rng, m, r):
     """m vertices of a strictly convex polygon (a regular m-gon of radius r,
     rounded to the grid) and 3m points strictly inside, shuffled."""
