@@ -2656,7 +2656,8 @@ struct FinSmem {
         struct {
             int32_t px1[kFinCap], py1[kFinCap], pi1[kFinCap];  // point buffer 1
             uint16_t sid[2][kFinCap];                   // sub-segment of every point
-            int32_t sst[kFinCap + 1];                   // sub-segment starts
+            int32_t sst[kFinCap + 4];                   // segment starts (set-up), then
+                                                        // each vertex slot's successor
             uint32_t suv[kFinCap];                      // its ends: vertex slots u | v << 16
             uint64_t kmax[kFinCap];                     // argmax: distance, then tie key
             uint64_t kmin[kFinCap];
@@ -2749,6 +2750,7 @@ __device__ void finish_unit(const Ws2 &ws, const HullArgs &a, int p, int R, int 
     }
     // first split of a one-point instance: u = f
     const bool same = M == 1 && G0.fx == G0.ux && G0.fy == G0.uy;
+    const bool defer = !same;
     if (tid < M) {
         const int u = 2 * tid, v = u + 1, f = 2 * M + tid;
         sm->w.vx[u] = G.ux; sm->w.vy[u] = G.uy; sm->w.vg[u] = Tp.uc;
@@ -2827,11 +2829,25 @@ __device__ void finish_unit(const Ws2 &ws, const HullArgs &a, int p, int R, int 
                 sm->w.vi[at] = pi[k];
             }
         }
-        // B. hull ids of the apexes, linked between their edge's ends
+        // B. the apexes join the hull between their edge's ends: as links
+        // between vertex slots, given hull ids when the levels end (one
+        // claim on the global id counter per call, not one per level), or,
+        // for the one-point instance of a first split, at once
+        if (defer) {
+            for (int t = tid; t < ns; t += kBlock) {
+                const uint32_t uv = sm->w.suv[t];
+                const int u = (int)(uv & 0xffffu), v = (int)(uv >> 16);
+                const int at = nv + t;
+                sm->w.sst[at] = v;
+                sm->w.sst[u] = at;
+                sm->w.vg[at] = sm->w.sin[t];  // the instance, until the ids are known
+                sm->w.cnt[t] = 0;
+            }
+        }
         const bool link = !(level == 0 && same);
-        if (tid == 0) sm->s_base = link ? (int)atomicAdd(&ctl->fin_ids, (unsigned)ns) : 0;
+        if (!defer && tid == 0) sm->s_base = link ? (int)atomicAdd(&ctl->fin_ids, (unsigned)ns) : 0;
         __syncthreads();
-        for (int t = tid; t < ns; t += kBlock) {
+        for (int t = tid; t < ns && !defer; t += kBlock) {
             const uint32_t uv = sm->w.suv[t];
             const int u = (int)(uv & 0xffffu), v = (int)(uv >> 16);
             const int at = nv + t;
@@ -2899,12 +2915,12 @@ __device__ void finish_unit(const Ws2 &ws, const HullArgs &a, int p, int R, int 
             const uint32_t st0 = npt, st1 = npt + a0;
             if (a0 > 0) {
                 id0 = nid;
-                sm->w.sst[nid] = (int)st0; sm->w.suv[nid] = u | (f << 16); sm->w.sin[nid] = ins[k];
+                sm->w.suv[nid] = u | (f << 16); sm->w.sin[nid] = ins[k];
                 ++nid;
             }
             if (a1 > 0) {
                 id1 = nid;
-                sm->w.sst[nid] = (int)st1; sm->w.suv[nid] = f | (v << 16); sm->w.sin[nid] = ins[k];
+                sm->w.suv[nid] = f | (v << 16); sm->w.sin[nid] = ins[k];
                 ++nid;
             }
             npt += a0 + a1;
@@ -2938,6 +2954,31 @@ __device__ void finish_unit(const Ws2 &ws, const HullArgs &a, int p, int R, int 
             ns = 0;
         }
         __syncthreads();
+    }
+    if (!defer) return;
+    // the hull ids of the apexes (slots 2M .. nv - 1, in slot order) and the
+    // links: every apex and every segment's u (its new successor); the v
+    // ends keep theirs
+    const int na = nv - 2 * M;
+    if (tid == 0) sm->s_base = na > 0 ? (int)atomicAdd(&ctl->fin_ids, (unsigned)na) : 0;
+    __syncthreads();
+    const int gb = hbase + sm->s_base;
+    for (int sl = tid; sl < nv; sl += kBlock) {
+        if (sl < 2 * M && (sl & 1)) continue;
+        const int nx = sm->w.sst[sl];
+        const int gn = nx < 2 * M ? sm->w.vg[nx] : gb + (nx - 2 * M);
+        if (sl < 2 * M) {
+            ws.nxt[sm->w.vg[sl]] = gn;
+            continue;
+        }
+        const int gid = gb + (sl - 2 * M);
+        if (gid < ws.hcap && gn < ws.hcap) {
+            ws.V[gid] = sm->w.vi[sl];
+            ws.hinst[gid] = sm->w.vg[sl];
+            ws.nxt[gid] = gn;
+        } else {
+            atomicOr(&ctl->error, kErrHullCap);
+        }
     }
 }
 
