@@ -12,8 +12,8 @@ beside it on the same data.
 Prints ONE JSON line.  ``roofline`` describes the round kernels (k_split for
 the first split, k_round_ro1 for the round after it, k_round for the later
 rounds, each with k_round_multi for the tiles that hold several segments; in
-the last round, once no segment holds more than 1,024 points, k_round_multi
-finishes every segment with one workgroup each), which move nearly all the
+the last round k_finish completes the remaining small segments in LDS, one
+workgroup per segment or per run of consecutive segments), which move nearly all the
 bytes: algorithmic bytes per round over the round's average duration, timed
 with HIP events around the pair of launches on the stream they run on.  ``traffic`` is the counter-
 measured HBM traffic per round from the committed rocprofv3 summary, null when
