@@ -320,9 +320,11 @@ def batched_leg(steps: int, warmup: int):
         "parity_vs_oracle_sample": None,
         "parity_vs_oracle": None,
         "rounds": int(st_x["rounds"]),
-        "round_kernel": {"name": "k_split, k_round_ro1, k_round, each with k_round_multi (the first split, "
-                                 "the round after it, the later rounds; the last round finishing small "
-                                 "segments)",
+        "finish_round": int(st_x["finish_round"]),
+        "finish_runs": int(st_x["finish_runs"]),
+        "round_kernel": {"name": "k_split, k_round_ro1, k_round, each with k_round_multi and k_finish (the "
+                                 "first split, the round after it, the later rounds; the last round "
+                                 "finishing small segments)",
                          "launches_per_step": tavg("round_launches"), "avg_launch_us": round(avg_ms * 1e3, 2),
                          "bytes_per_launch": round(bpl), "grid_blocks": int(st_x["grid_blocks"]),
                          "first_split_us": round(tavg("split_ms") * 1e3, 1)},

@@ -214,6 +214,23 @@ def test_finish_hint_same_shape(qhm, ctx, mode):
         assert got.tolist() == oracle.hull2d(pts).tolist()
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_circle_300k_finish(qhm, ctx, mode):
+    """One instance of 300,000 grid points on a circle (174,915 of them hull
+    vertices): segments shrink by half a round, so the round that first
+    holds no segment above QH_FINISH_CAP points holds few enough of them to
+    finish them one per workgroup (runs of segments need many more, which
+    batches of instances give)."""
+    pts = workloads.circle(workloads.rng_for(91), 300000, (1 << 30) - 1)
+    _say(f"circle 300k mode={mode}")
+    got, st = _gpu_hull(qhm, ctx, pts, mode)
+    assert got.tolist() == oracle.hull2d(pts).tolist()
+    if mode & 2:
+        assert st["finish_round"] == -1 and st["finish_runs"] == 0
+    else:
+        assert st["finish_round"] >= 2 and st["finish_runs"] == 0
+
+
 def test_deterministic_and_no_ctx(qhm):
     pts = workloads.disk(workloads.rng_for(13), 50000, 1 << 20)
     t = torch.from_numpy(pts).to("cuda")
