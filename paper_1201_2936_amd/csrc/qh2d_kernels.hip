@@ -2967,12 +2967,10 @@ __device__ void finish_unit(const Ws2 &ws, const HullArgs &a, int p, int R, int 
         if (sl < 2 * M && (sl & 1)) continue;
         const int nx = sm->w.sst[sl];
         const int gn = nx < 2 * M ? sm->w.vg[nx] : gb + (nx - 2 * M);
-        if (sl < 2 * M) {
-            ws.nxt[sm->w.vg[sl]] = gn;
-            continue;
-        }
-        const int gid = gb + (sl - 2 * M);
-        if (gid < ws.hcap && gn < ws.hcap) {
+        const int gid = sl < 2 * M ? sm->w.vg[sl] : gb + (sl - 2 * M);
+        if (sl < 2 * M && gn < ws.hcap) {
+            ws.nxt[gid] = gn;
+        } else if (sl >= 2 * M && gid < ws.hcap && gn < ws.hcap) {
             ws.V[gid] = sm->w.vi[sl];
             ws.hinst[gid] = sm->w.vg[sl];
             ws.nxt[gid] = gn;

@@ -268,7 +268,8 @@ qh_status run2d(qh_ctx *c, const int32_t *pts, int64_t n, const int64_t *offsets
     args.fin_from = (c->fin_hint_n == n && c->fin_hint_k == k && c->fin_hint_mode == mode) ? c->fin_hint : 0;
     const int grid = cfg.grid;
     // the finishing kernel: at most its resident count of workgroups (two per
-    // CU), each finishing segments one after the other
+    // CU), each finishing segments, or runs of small segments, one after the
+    // other
     const int grid_fin = std::max(1, std::min(cfg.fin_segs, 2 * c->cus));
     args.fin_pts = args.fin_cap > 0 ? kFinUnitsPerBlock * kFinUnit * grid_fin : 0;
     // the split and the round after it at their own residency, scaled like
