@@ -429,7 +429,10 @@ __device__ __forceinline__ void ml_append(const Ws2 &ws, int p, RoundState *rsp,
 // ---------------------------------------------------------------------------
 // set-up
 // ---------------------------------------------------------------------------
-// block 0: compact the non-empty instances into the first segment table
+// block 0: compact the non-empty instances into the first segment table.
+// Each thread takes kInstPer consecutive instances per pass (their offsets
+// requested together), one block scan per pass
+constexpr int kInstPer = 16;
 __device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a, char *smem) {
     if (blockIdx.x != 0) return;
     ScanSmem *sm = reinterpret_cast<ScanSmem *>(smem);
@@ -437,23 +440,37 @@ __device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a
     const int k = a.k;
     if (threadIdx.x == 0) { sm->carry = 0; sm->bad = 0; sm->maxlen = 0; }
     __syncthreads();
-    for (int base = 0; base < k; base += kBlock) {
-        const int i = base + (int)threadIdx.x;
-        int64_t lo = 0, hi = 0;
-        bool ne = false;
-        if (i < k) {
-            lo = a.offsets[i];
-            hi = a.offsets[i + 1];
-            if (lo < 0 || hi < lo || hi > a.n || (i == 0 && lo != 0) || (i == k - 1 && hi != a.n))
-                atomicOr(&sm->bad, 1);
-            ne = hi > lo;
-            if (ne) atomicMax(&sm->maxlen, (int)min<int64_t>(hi - lo, INT32_MAX));
+    for (int base = 0; base < k; base += kBlock * kInstPer) {
+        const int i0 = base + (int)threadIdx.x * kInstPer;
+        int64_t off[kInstPer + 1];
+#pragma unroll
+        for (int j = 0; j <= kInstPer; ++j) off[j] = i0 + j <= k ? a.offsets[i0 + j] : 0;
+        uint32_t cnt = 0;
+        bool bad = false;
+        int mx = 0;
+#pragma unroll
+        for (int j = 0; j < kInstPer; ++j) {
+            const int i = i0 + j;
+            if (i >= k) continue;
+            const int64_t lo = off[j], hi = off[j + 1];
+            if (lo < 0 || hi < lo || hi > a.n || (i == 0 && lo != 0) || (i == k - 1 && hi != a.n)) bad = true;
+            if (hi > lo) {
+                ++cnt;
+                mx = max(mx, (int)min<int64_t>(hi - lo, INT32_MAX));
+            }
         }
-        uint32_t v[1] = {ne ? 1u : 0u}, tot[1];
+        if (bad) atomicOr(&sm->bad, 1);
+        if (mx > 0) atomicMax(&sm->maxlen, mx);
+        uint32_t v[1] = {cnt}, tot[1];
         block_excl_scan<kBlock, 1>(v, tot, sm->scratch);
-        const uint32_t j = (uint32_t)sm->carry + v[0];
-        if (i < k) {
-            ws.inst_rank[i] = ne ? (int32_t)j : -1;
+        uint32_t jn = (uint32_t)sm->carry + v[0];
+#pragma unroll
+        for (int j = 0; j < kInstPer; ++j) {
+            const int i = i0 + j;
+            if (i >= k) continue;
+            const int64_t lo = off[j], hi = off[j + 1];
+            const bool ne = hi > lo;
+            ws.inst_rank[i] = ne ? (int32_t)jn : -1;
             ws.nxt[i] = -1;
             ws.nxt[k + i] = -1;
             if (ne) {
@@ -461,13 +478,14 @@ __device__ __forceinline__ void phase_instances(const Ws2 &ws, const HullArgs &a
                 g.start = (int32_t)lo;
                 g.len = (int32_t)(hi - lo);
                 g.ux = g.uy = g.fx = g.fy = g.vx = g.vy = 0;
-                ws.geo(0, 0)[j] = g;
+                ws.geo(0, 0)[jn] = g;
                 SegTop t;
                 t.fidx = 0;
                 t.uc = i;
                 t.vc = i;
                 t.inst = i;
-                ws.top(0, 0)[j] = t;
+                ws.top(0, 0)[jn] = t;
+                ++jn;
             }
         }
         __syncthreads();
