@@ -127,6 +127,36 @@ def test_autotune_keeps_output(qhm, mode):
     ctx.close()
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_graph_replays_finish_runs(qhm, mode):
+    """2,000 small disks: the last round finishes runs of small segments;
+    replayed from graphs with the contents changed in place between calls."""
+    rng = np.random.default_rng(606)
+    sizes = np.floor(np.exp(rng.uniform(np.log(64), np.log(8000), size=2000))).astype(np.int64)
+    base, off = workloads.batched_disks(len(sizes), sizes)
+    sets = [base, np.ascontiguousarray(base[::-1]), np.ascontiguousarray(-base)]
+    ctx = qhm.Context()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        buf = torch.empty(base.shape, dtype=torch.int32, device="cuda")
+        offs = torch.from_numpy(off).to("cuda")
+        out = torch.empty(base.shape[1], dtype=torch.int32, device="cuda")
+        hoff = torch.empty(len(sizes) + 1, dtype=torch.int64, device="cuda")
+        for rep in range(5):
+            pts = sets[rep % len(sets)]
+            _say(f"graph finish runs mode={mode} replay={rep}")
+            buf.copy_(torch.from_numpy(pts))
+            got, got_off, stats = qhm.qh_hull2d_batched(buf, offs, mode=mode, ctx=ctx, graph=True,
+                                                        out=out, hull_offsets=hoff,
+                                                        stream=st.cuda_stream)
+            want, want_off = oracle.hull2d_batched(pts, off)
+            assert got_off.cpu().tolist() == want_off.tolist(), rep
+            assert got.cpu().tolist() == want.tolist(), rep
+            assert stats["finish_runs"] == 1, rep
+            torch.cuda.synchronize()
+    ctx.close()
+
+
 def test_autotune_batched_with_graph(qhm):
     sizes = np.array([256, 3000, 40000, 1 << 16, 777, 12345], np.int64)
     pts, off = workloads.batched_disks(len(sizes), sizes)
